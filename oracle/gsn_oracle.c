@@ -1,0 +1,417 @@
+/*
+ * gsn_oracle.c -- plain FP64 CPU oracle for the generalised Schroedinger-Newton
+ * split-step solver of Ferreira, Silva, Bertolami, Gomes & Guerreiro,
+ * "Using numerical methods from nonlocal optics to simulate the dynamics of
+ * N-body systems in alternative theories of gravity" (arXiv:1909.08354).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct reference
+ * the HIP solver is checked against.  Only the test-suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load it; the product path never does.
+ * It shares no code, header, table or constant generator with the GPU library.
+ *
+ * What is computed (paper Sec. II, Eq. (1)-(2) and the optics form Eq. (3);
+ * Sec. III for the method: symmetric split-step Fourier for Eq. (1) and a
+ * spectral solve for Eq. (2)):
+ *
+ *     i d(psi)/dz = -a lap(psi) - (g |psi|^2 + phi) psi,
+ *     phi_hat(k)  = K(k) rho_hat(k),   rho = |psi|^2,
+ *     K(k)        = c_N/|k|^2 [k != 0] + c_Y/(|k|^2 + m_Y^2) + c_0.
+ *
+ * This is Eq. (1) with A = -a, B = -1, G(rho) = -g rho, i.e. Eq. (3) with
+ * k = k0 = 1 and Delta n = g rho + phi.  The kernel family is the Fourier form
+ * of Eq. (2), Eq. (4), Eq. (5), and the constant-coefficient Fourier form of the
+ * modified Poisson equation Eq. (8) / Eq. (12) (Newtonian 1/k^2 plus a Yukawa
+ * correction plus a contact term).  The k = 0 Newtonian term is dropped (a
+ * periodic Poisson problem needs a neutral source); the Yukawa and contact
+ * k = 0 terms are kept.
+ *
+ * Discretisation: C-order grid [n0][n1][n2] (last axis contiguous), periodic,
+ * x_j = -L/2 + j L/N, k_j = 2 pi j'/L with j' = j for j < N/2 else j - N.
+ * Forward DFT  X_k = sum_x x_x exp(-i k.x)   (unnormalised);
+ * inverse DFT  x_x = (1/P) sum_k X_k exp(+i k.x).
+ *
+ * One symmetric step (Strang):  psi <- L(dz/2) N(dz) L(dz/2) psi with
+ *   L(h): psi <- IDFT[ exp(-i a |k|^2 h) DFT psi ]
+ *   N(h): rho = |psi|^2; phi = Re IDFT[ K DFT rho ]; psi <- psi exp(i (g rho + phi) h)
+ * The nonlinear sub-step is exact because rho is unchanged by a pointwise phase.
+ *
+ * The FFT is an iterative radix-2 transform with twiddles from direct FP64
+ * cos/sin of 2 pi m / n (never a recurrence).  Multi-dimensional transforms are
+ * applied axis by axis.  OpenMP threads run independent 1-D lines in parallel;
+ * results do not depend on the thread count.
+ */
+#define _GNU_SOURCE
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+typedef double _Complex cx;
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_ENOMEM 2
+
+typedef struct {
+    int ndim;
+    int n[3];
+    double L[3];
+    long long P;      /* total number of points */
+    long long stride[3];
+} grid_t;
+
+static int is_pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+static int grid_init(grid_t *g, int ndim, const int *n, const double *L)
+{
+    if (ndim < 1 || ndim > 3 || !n) return ORC_EINVAL;
+    g->ndim = ndim;
+    g->P = 1;
+    for (int d = 0; d < ndim; d++) {
+        if (!is_pow2(n[d])) return ORC_EINVAL;
+        if (L && !(L[d] > 0.0)) return ORC_EINVAL;
+        g->n[d] = n[d];
+        g->L[d] = L ? L[d] : 1.0;
+        g->P *= n[d];
+    }
+    long long s = 1;
+    for (int d = ndim - 1; d >= 0; d--) { g->stride[d] = s; s *= n[d]; }
+    return ORC_OK;
+}
+
+static int nthreads_or_default(int nthreads)
+{
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+}
+
+/* wavenumber of DFT index j on an axis with N points and length L */
+static double wavenumber(int j, int N, double L)
+{
+    int jj = (j < N / 2) ? j : j - N;
+    return 2.0 * M_PI * (double)jj / L;
+}
+
+/* |k|^2 of the point with flat index q */
+static double k_squared(const grid_t *g, long long q)
+{
+    double k2 = 0.0;
+    for (int d = 0; d < g->ndim; d++) {
+        int j = (int)((q / g->stride[d]) % g->n[d]);
+        double k = wavenumber(j, g->n[d], g->L[d]);
+        k2 += k * k;
+    }
+    return k2;
+}
+
+/* K(k) of Eq. (2) in Fourier form, kp = {c_N, c_Y, m_Y, c_0} */
+static double kernel_value(double k2, const double *kp)
+{
+    double K = kp[3];
+    if (kp[1] != 0.0) K += kp[1] / (k2 + kp[2] * kp[2]);
+    if (k2 > 0.0) K += kp[0] / k2;
+    return K;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1-D radix-2 FFT                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* tw[m] = exp(sign * 2 pi i m / n), m < n/2, each from cos/sin directly */
+static cx *make_twiddles(int n, int sign)
+{
+    int h = n / 2 > 0 ? n / 2 : 1;
+    cx *tw = (cx *)malloc(sizeof(cx) * (size_t)h);
+    if (!tw) return NULL;
+    for (int m = 0; m < h; m++) {
+        double ang = 2.0 * M_PI * (double)m / (double)n;
+        tw[m] = cos(ang) + (double)sign * sin(ang) * I;
+    }
+    return tw;
+}
+
+/* in-place unnormalised DFT of one contiguous line: bit reversal, then
+   log2(n) butterfly stages of growing length */
+static void fft_line(cx *a, int n, const cx *tw)
+{
+    for (int i = 1, j = 0; i < n; i++) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) { cx t = a[i]; a[i] = a[j]; a[j] = t; }
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        int half = len / 2, step = n / len;
+        for (int i = 0; i < n; i += len) {
+            for (int j = 0; j < half; j++) {
+                cx u = a[i + j];
+                cx v = a[i + j + half] * tw[j * step];
+                a[i + j] = u + v;
+                a[i + j + half] = u - v;
+            }
+        }
+    }
+}
+
+/* transform every line along axis d; sign -1 forward, +1 inverse (no scale) */
+static int fft_axis(cx *data, const grid_t *g, int d, int sign, int nthreads)
+{
+    int n = g->n[d];
+    if (n == 1) return ORC_OK;
+    long long stride = g->stride[d];
+    long long nlines = g->P / n;
+    cx *tw = make_twiddles(n, sign);
+    if (!tw) return ORC_ENOMEM;
+    int err = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        cx *line = (cx *)malloc(sizeof(cx) * (size_t)n);
+        if (!line) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (long long q = 0; q < nlines; q++) {
+                long long outer = q / stride, inner = q % stride;
+                cx *base = data + outer * stride * n + inner;
+                for (int j = 0; j < n; j++) line[j] = base[(long long)j * stride];
+                fft_line(line, n, tw);
+                for (int j = 0; j < n; j++) base[(long long)j * stride] = line[j];
+            }
+            free(line);
+        }
+    }
+    free(tw);
+    return err ? ORC_ENOMEM : ORC_OK;
+}
+
+/* full N-D transform; sign -1: unnormalised forward, +1: inverse with 1/P */
+static int fft_nd(cx *data, const grid_t *g, int sign, int nthreads)
+{
+    for (int d = 0; d < g->ndim; d++) {
+        int e = fft_axis(data, g, d, sign, nthreads);
+        if (e) return e;
+    }
+    if (sign > 0) {
+        double s = 1.0 / (double)g->P;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (long long q = 0; q < g->P; q++) data[q] *= s;
+    }
+    return ORC_OK;
+}
+
+int orc_fft(double *data, int ndim, const int *n, int sign, int nthreads)
+{
+    grid_t g;
+    if (!data || (sign != -1 && sign != 1) || grid_init(&g, ndim, n, NULL)) return ORC_EINVAL;
+    return fft_nd((cx *)data, &g, sign, nthreads_or_default(nthreads));
+}
+
+/* brute-force O(P^2) DFT, same normalisation as orc_fft; for pinning only.
+   The phase sum_d k_d x_d / n_d is reduced exactly in integers modulo P. */
+int orc_dft_brute(const double *in, double *out, int ndim, const int *n, int sign)
+{
+    grid_t g;
+    if (!in || !out || (sign != -1 && sign != 1) || grid_init(&g, ndim, n, NULL)) return ORC_EINVAL;
+    const cx *a = (const cx *)in;
+    cx *b = (cx *)out;
+    long long P = g.P;
+    for (long long kq = 0; kq < P; kq++) {
+        cx acc = 0.0;
+        for (long long xq = 0; xq < P; xq++) {
+            long long m = 0;
+            for (int d = 0; d < ndim; d++) {
+                long long kd = (kq / g.stride[d]) % g.n[d];
+                long long xd = (xq / g.stride[d]) % g.n[d];
+                m += ((kd * xd) % g.n[d]) * (P / g.n[d]);
+            }
+            m %= P;
+            double ang = 2.0 * M_PI * (double)m / (double)P;
+            acc += a[xq] * (cos(ang) + (double)sign * sin(ang) * I);
+        }
+        b[kq] = (sign > 0) ? acc / (double)P : acc;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* potential, sub-steps, evolution                                          */
+/* ------------------------------------------------------------------------ */
+
+/* phi = Re IDFT[ K DFT rho ] into tmp (complex scratch of P entries) */
+static int potential_into(cx *tmp, const double *rho, const double *Kk,
+                          const grid_t *g, int nt)
+{
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) tmp[q] = rho[q];
+    int e = fft_nd(tmp, g, -1, nt);
+    if (e) return e;
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) tmp[q] *= Kk[q];
+    return fft_nd(tmp, g, +1, nt);
+}
+
+int orc_potential(const double *rho, double *phi, int ndim, const int *n,
+                  const double *L, const double *kp, int nthreads)
+{
+    grid_t g;
+    if (!rho || !phi || !kp || grid_init(&g, ndim, n, L)) return ORC_EINVAL;
+    if (kp[1] != 0.0 && !(kp[2] > 0.0)) return ORC_EINVAL;
+    int nt = nthreads_or_default(nthreads);
+    cx *tmp = (cx *)malloc(sizeof(cx) * (size_t)g.P);
+    double *Kk = (double *)malloc(sizeof(double) * (size_t)g.P);
+    int e = ORC_ENOMEM;
+    if (tmp && Kk) {
+        for (long long q = 0; q < g.P; q++) Kk[q] = kernel_value(k_squared(&g, q), kp);
+        e = potential_into(tmp, rho, Kk, &g, nt);
+        if (!e)
+            for (long long q = 0; q < g.P; q++) phi[q] = creal(tmp[q]);
+    }
+    free(tmp);
+    free(Kk);
+    return e;
+}
+
+/* kinetic sub-step L(h) with a precomputed propagator table prop[q] */
+static int kinetic_step(cx *psi, const cx *prop, const grid_t *g, int nt)
+{
+    int e = fft_nd(psi, g, -1, nt);
+    if (e) return e;
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) psi[q] *= prop[q];
+    return fft_nd(psi, g, +1, nt);
+}
+
+/* nonlinear sub-step N(h): psi <- psi exp(i (g rho + phi) h) */
+static int nonlinear_step(cx *psi, cx *tmp, double *rho, const double *Kk,
+                          double gloc, double h, const grid_t *g, int nt)
+{
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) {
+        double re = creal(psi[q]), im = cimag(psi[q]);
+        rho[q] = re * re + im * im;
+    }
+    int e = potential_into(tmp, rho, Kk, g, nt);
+    if (e) return e;
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) {
+        double th = (gloc * rho[q] + creal(tmp[q])) * h;
+        psi[q] *= cos(th) + sin(th) * I;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Evolve psi (interleaved complex128, C-order) by nsteps symmetric steps.
+ *   kp = {c_N, c_Y, m_Y, c_0};  a = kinetic coefficient; g = local coefficient.
+ *   merged = 0: each step is literally L(dz/2) N(dz) L(dz/2).
+ *   merged = 1: L(dz/2) [N(dz) L(dz)]^(n-1) N(dz) L(dz/2), algebraically the
+ *               same product of operators (L(h1) L(h2) = L(h1 + h2) exactly).
+ * Returns 0 on success.
+ */
+int orc_evolve(double *psi_io, int ndim, const int *n, const double *L,
+               const double *kp, double a, double gloc, double dz,
+               long long nsteps, int merged, int nthreads)
+{
+    grid_t g;
+    if (!psi_io || !kp || grid_init(&g, ndim, n, L) || nsteps < 0) return ORC_EINVAL;
+    if (kp[1] != 0.0 && !(kp[2] > 0.0)) return ORC_EINVAL;
+    if (!isfinite(dz) || !isfinite(a) || !isfinite(gloc)) return ORC_EINVAL;
+    if (nsteps == 0) return ORC_OK;
+    int nt = nthreads_or_default(nthreads);
+    cx *psi = (cx *)psi_io;
+    size_t P = (size_t)g.P;
+    cx *half = (cx *)malloc(sizeof(cx) * P);
+    cx *full = (cx *)malloc(sizeof(cx) * P);
+    cx *tmp = (cx *)malloc(sizeof(cx) * P);
+    double *Kk = (double *)malloc(sizeof(double) * P);
+    double *rho = (double *)malloc(sizeof(double) * P);
+    int e = ORC_ENOMEM;
+    if (!half || !full || !tmp || !Kk || !rho) goto done;
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g.P; q++) {
+        double k2 = k_squared(&g, q);
+        double th_h = -a * k2 * dz * 0.5, th_f = -a * k2 * dz;
+        half[q] = cos(th_h) + sin(th_h) * I;
+        full[q] = cos(th_f) + sin(th_f) * I;
+        Kk[q] = kernel_value(k2, kp);
+    }
+    if (!merged) {
+        for (long long s = 0; s < nsteps; s++) {
+            if ((e = kinetic_step(psi, half, &g, nt))) goto done;
+            if ((e = nonlinear_step(psi, tmp, rho, Kk, gloc, dz, &g, nt))) goto done;
+            if ((e = kinetic_step(psi, half, &g, nt))) goto done;
+        }
+    } else {
+        if ((e = kinetic_step(psi, half, &g, nt))) goto done;
+        for (long long s = 0; s < nsteps; s++) {
+            if ((e = nonlinear_step(psi, tmp, rho, Kk, gloc, dz, &g, nt))) goto done;
+            if ((e = kinetic_step(psi, s + 1 < nsteps ? full : half, &g, nt))) goto done;
+        }
+    }
+    e = ORC_OK;
+done:
+    free(half);
+    free(full);
+    free(tmp);
+    free(Kk);
+    free(rho);
+    return e;
+}
+
+/*
+ * Observables of psi: out = {M, E_kin, E_loc, E_nl, E_total} with
+ *   M     = dV sum |psi|^2
+ *   E_kin = a dV / P sum_k |k|^2 |psi_hat_k|^2      (= a dV sum |grad psi|^2)
+ *   E_loc = -(g/2) dV sum rho^2
+ *   E_nl  = -(1/2) dV sum rho phi
+ * E_total is the Hamiltonian of the equation above: its variation with
+ * respect to conj(psi) is -a lap(psi) - g rho psi - phi psi.
+ */
+int orc_observables(const double *psi_in, int ndim, const int *n, const double *L,
+                    const double *kp, double a, double gloc, double *out, int nthreads)
+{
+    grid_t g;
+    if (!psi_in || !kp || !out || grid_init(&g, ndim, n, L)) return ORC_EINVAL;
+    if (kp[1] != 0.0 && !(kp[2] > 0.0)) return ORC_EINVAL;
+    int nt = nthreads_or_default(nthreads);
+    const cx *psi = (const cx *)psi_in;
+    size_t P = (size_t)g.P;
+    double dV = 1.0;
+    for (int d = 0; d < g.ndim; d++) dV *= g.L[d] / g.n[d];
+    cx *tmp = (cx *)malloc(sizeof(cx) * P);
+    double *Kk = (double *)malloc(sizeof(double) * P);
+    double *rho = (double *)malloc(sizeof(double) * P);
+    int e = ORC_ENOMEM;
+    if (!tmp || !Kk || !rho) goto done;
+    double mass = 0.0, ekin = 0.0, eloc = 0.0, enl = 0.0;
+    for (long long q = 0; q < g.P; q++) {
+        double re = creal(psi[q]), im = cimag(psi[q]);
+        rho[q] = re * re + im * im;
+        mass += rho[q];
+        eloc += rho[q] * rho[q];
+        tmp[q] = psi[q];
+        Kk[q] = kernel_value(k_squared(&g, q), kp);
+    }
+    if ((e = fft_nd(tmp, &g, -1, nt))) goto done;
+    for (long long q = 0; q < g.P; q++) {
+        double re = creal(tmp[q]), im = cimag(tmp[q]);
+        ekin += k_squared(&g, q) * (re * re + im * im);
+    }
+    if ((e = potential_into(tmp, rho, Kk, &g, nt))) goto done;
+    for (long long q = 0; q < g.P; q++) enl += rho[q] * creal(tmp[q]);
+    out[0] = dV * mass;
+    out[1] = a * dV / (double)g.P * ekin;
+    out[2] = -0.5 * gloc * dV * eloc;
+    out[3] = -0.5 * dV * enl;
+    out[4] = out[1] + out[2] + out[3];
+    e = ORC_OK;
+done:
+    free(tmp);
+    free(Kk);
+    free(rho);
+    return e;
+}
+
+int orc_max_threads(void) { return omp_get_max_threads(); }

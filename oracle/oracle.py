@@ -1,0 +1,126 @@
+"""ctypes wrapper around the FP64 CPU oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``.  The product path never imports
+this module, and this module imports nothing from the product package.
+
+Conventions (arXiv:1909.08354 Sec. II Eq. (1)-(3), Sec. III):
+  * arrays are numpy complex128 in C order, shape ``n`` (slowest axis first);
+  * ``kern`` = (c_N, c_Y, m_Y, c_0): K(k) = c_N/|k|^2 [k != 0]
+    + c_Y/(|k|^2 + m_Y^2) + c_0;
+  * ``a`` kinetic coefficient (1/2 for Eq. (3) with k = k0 = 1),
+    ``g`` local (Kerr) coefficient, ``dz`` the step.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b  # type: ignore
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.orc_fft.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, ctypes.c_int]
+    lib.orc_dft_brute.argtypes = [dp, dp, ctypes.c_int, ip, ctypes.c_int]
+    lib.orc_potential.argtypes = [dp, dp, ctypes.c_int, ip, dp, dp, ctypes.c_int]
+    lib.orc_evolve.argtypes = [dp, ctypes.c_int, ip, dp, dp, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_longlong,
+                               ctypes.c_int, ctypes.c_int]
+    lib.orc_observables.argtypes = [dp, ctypes.c_int, ip, dp, dp, ctypes.c_double,
+                                    ctypes.c_double, dp, ctypes.c_int]
+    lib.orc_max_threads.argtypes = []
+    for f in ("orc_fft", "orc_dft_brute", "orc_potential", "orc_evolve",
+              "orc_observables", "orc_max_threads"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _shape_args(shape, L=None):
+    n = (ctypes.c_int * len(shape))(*[int(s) for s in shape])
+    if L is None:
+        return n, None
+    Larr = np.ascontiguousarray(np.asarray(L, dtype=np.float64).reshape(len(shape)))
+    return n, Larr
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def max_threads():
+    return _load().orc_max_threads()
+
+
+def fft(x, inverse=False, nthreads=0):
+    """Unnormalised forward DFT (exp(-i k.x)); inverse carries 1/P."""
+    a = np.array(x, dtype=np.complex128, order="C", copy=True)
+    n, _ = _shape_args(a.shape)
+    _check(_load().orc_fft(_dptr(a), a.ndim, n, 1 if inverse else -1, nthreads), "fft")
+    return a
+
+
+def dft_brute(x, inverse=False):
+    """O(P^2) DFT with the same normalisation as :func:`fft` (pin only)."""
+    a = np.ascontiguousarray(x, dtype=np.complex128)
+    out = np.empty_like(a)
+    n, _ = _shape_args(a.shape)
+    _check(_load().orc_dft_brute(_dptr(a), _dptr(out), a.ndim, n, 1 if inverse else -1),
+           "dft_brute")
+    return out
+
+
+def potential(rho, L, kern, nthreads=0):
+    """phi = Re IDFT[K DFT rho] for a real density on a periodic box."""
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    phi = np.empty_like(r)
+    n, Larr = _shape_args(r.shape, L)
+    k = np.ascontiguousarray(kern, dtype=np.float64)
+    _check(_load().orc_potential(_dptr(r), _dptr(phi), r.ndim, n, _dptr(Larr), _dptr(k),
+                                 nthreads), "potential")
+    return phi
+
+
+def evolve(psi, L, kern, a, g, dz, nsteps, merged=True, nthreads=0):
+    """nsteps symmetric split steps of the equation; returns a new array."""
+    p = np.array(psi, dtype=np.complex128, order="C", copy=True)
+    n, Larr = _shape_args(p.shape, L)
+    k = np.ascontiguousarray(kern, dtype=np.float64)
+    _check(_load().orc_evolve(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a), float(g),
+                              float(dz), int(nsteps), 1 if merged else 0, nthreads), "evolve")
+    return p
+
+
+def observables(psi, L, kern, a, g, nthreads=0):
+    """dict(mass, kinetic, local, nonlocal, total) of psi."""
+    p = np.ascontiguousarray(psi, dtype=np.complex128)
+    n, Larr = _shape_args(p.shape, L)
+    k = np.ascontiguousarray(kern, dtype=np.float64)
+    out = np.zeros(5)
+    _check(_load().orc_observables(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a),
+                                   float(g), _dptr(out), nthreads), "observables")
+    return {"mass": out[0], "kinetic": out[1], "local": out[2], "nonlocal": out[3],
+            "total": out[4]}
+
+
+def rel_l2(x, ref):
+    """||x - ref||_2 / ||ref||_2 in FP64."""
+    x = np.asarray(x, dtype=np.complex128)
+    ref = np.asarray(ref, dtype=np.complex128)
+    return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel()))

@@ -1,0 +1,153 @@
+"""Seeded synthetic initial states and workload recipes.
+
+This module holds only input generation: grid coordinates, Gaussian lumps with
+phase-gradient velocities and seeded random draws.  It contains none of the
+solver's arithmetic, so both the HIP path and the CPU oracle can be fed from it.
+
+The paper starts its simulations from a Gaussian distribution of the number
+density (Sec. IV) and reaches a fluid velocity through the Madelung form
+psi = sqrt(rho) exp(i S / nu), v = grad S (Sec. II, before Eq. (15)); a lump
+moving with velocity v is therefore exp(-|x - c|^2 / w^2) exp(i v.(x - c)) with
+nu = 1.  The paper gives no grid, box or duration, so every workload here is
+synthetic; the recipes are listed in WORKLOADS.
+
+Conventions: C-order arrays, slowest axis first; x_j = -L/2 + j L/N on each
+axis; ``waist`` w is the optics convention psi = A exp(-r^2 / w^2); lumps use
+minimum-image displacements on the periodic box.
+"""
+import numpy as np
+
+
+def axis_coords(N, L):
+    """Cell coordinates x_j = -L/2 + j L/N, j = 0..N-1."""
+    return -0.5 * L + np.arange(N, dtype=np.float64) * (L / N)
+
+
+def _min_image(d, L):
+    return (d + 0.5 * L) % L - 0.5 * L
+
+
+def gaussian(n, L, waist, amplitude=1.0, center=None, velocity=None):
+    """Separable Gaussian lump amplitude*exp(-|x-c|^2/w^2)*exp(i v.(x-c))."""
+    nd = len(n)
+    center = np.zeros(nd) if center is None else np.asarray(center, dtype=np.float64)
+    velocity = np.zeros(nd) if velocity is None else np.asarray(velocity, dtype=np.float64)
+    out = np.array(amplitude, dtype=np.complex128)
+    for ax in range(nd):
+        x = axis_coords(n[ax], L[ax])
+        d = _min_image(x - center[ax], L[ax])
+        f = np.exp(-(d * d) / (waist * waist)) * np.exp(1j * velocity[ax] * d)
+        shape = [1] * nd
+        shape[ax] = n[ax]
+        out = out * f.reshape(shape)
+    return np.ascontiguousarray(np.broadcast_to(out, tuple(n)), dtype=np.complex128)
+
+
+def lumps(n, L, centers, waists, velocities, amplitude=1.0):
+    """Sum of Gaussian lumps (complex128)."""
+    psi = np.zeros(tuple(n), dtype=np.complex128)
+    for c, w, v in zip(centers, waists, velocities):
+        psi += gaussian(n, L, w, amplitude, c, v)
+    return psi
+
+
+def phase_noise(psi, size, seed):
+    """psi * exp(i size xi), xi i.i.d. U[-1, 1] per grid point from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    xi = rng.uniform(-1.0, 1.0, size=psi.shape)
+    return psi * np.exp(1j * size * xi)
+
+
+def random_lumps(rng, n, L, count, waist_range, vel_range=0.5):
+    """Draw ``count`` lumps in the order: centre, waist, velocity (per lump)."""
+    nd = len(n)
+    cs, ws, vs = [], [], []
+    for _ in range(count):
+        cs.append(rng.uniform(0.0, 1.0, size=nd) * np.asarray(L, dtype=np.float64))
+        ws.append(rng.uniform(*waist_range))
+        vs.append(rng.uniform(-vel_range, vel_range, size=nd))
+    return cs, ws, vs
+
+
+def to_c64(psi):
+    """The bits both sides start from: the HIP path gets complex64 ..."""
+    return np.ascontiguousarray(psi, dtype=np.complex64)
+
+
+def as_oracle_input(psi):
+    """... and the oracle gets complex128(complex64(psi)), so IC rounding is shared."""
+    return np.ascontiguousarray(to_c64(psi), dtype=np.complex128)
+
+
+# --------------------------------------------------------------------------
+# workload recipes (every one synthetic; see module docstring)
+# kern = (c_N, c_Y, m_Y, c_0); a = 1/2 (Eq. (3) with k = k0 = 1)
+# --------------------------------------------------------------------------
+WORKLOADS = {
+    "gsn2d_128_kerr_newton": dict(
+        n=(128, 128), L=(40.0, 40.0), kern=(1.0, 0.0, 0.0, 0.0), a=0.5, g=-0.5,
+        dz=1e-3, steps=200, seed=1909,
+        ic="gaussian A=1 w=3 centred, phase noise 1e-3*U[-1,1]"),
+    "gsn3d_256_newton_yukawa": dict(
+        n=(256, 256, 256), L=(256.0, 256.0, 256.0), kern=(1.0, 0.3, 0.1, 0.0), a=0.5,
+        g=0.0, dz=5e-4, steps=1000, seed=2, ic="gaussian A=1 w=6 centred, real"),
+    "gsn2d_batch64_sweep": dict(
+        count=64, sizes=(256, 512, 1024), a=0.5, g=-0.5, dz=1e-3, steps=500, seed=3,
+        ic="1-4 lumps, centres U[0,L)^2, w U[2,6], v U[-0.5,0.5]^2; c_Y U[0,1], m_Y U[0.05,0.5]"),
+    "gsn3d_512_lumps": dict(
+        n=(512, 512, 512), L=(512.0, 512.0, 512.0), kern=(1.0, 0.3, 0.1, 0.0), a=0.5,
+        g=0.0, dz=2.5e-4, steps=2000, seed=4,
+        ic="8 lumps, centres U[0,512)^3, w U[4,10], v U[-0.5,0.5]^3"),
+    "gsn2d_512_corrector": dict(
+        n=(512, 512), L=(512.0, 512.0), kern=(1.0, 0.0, 0.0, 0.0), a=0.5, g=-0.5,
+        dz_fine=5e-3, ratio=8, train_seeds=(10000, 12000), heldout_seeds=(20000, 20100),
+        ic="1-4 lumps, centres U[0,L)^2, w U[2,6], v U[-0.5,0.5]^2"),
+}
+
+
+def gaussian_2d_128(seed=None):
+    """128^2 on [-20,20)^2: Gaussian A=1 w=3 with 1e-3 phase noise."""
+    w = WORKLOADS["gsn2d_128_kerr_newton"]
+    psi = gaussian(w["n"], w["L"], 3.0)
+    return phase_noise(psi, 1e-3, w["seed"] if seed is None else seed)
+
+
+def gaussian_3d_256(n=None):
+    """Centred real Gaussian cloud, waist 6 grid units (dx = 1)."""
+    w = WORKLOADS["gsn3d_256_newton_yukawa"]
+    n = w["n"] if n is None else n
+    return gaussian(n, tuple(float(v) for v in n), 6.0)
+
+
+def lumps_3d(n=(512, 512, 512), seed=4, count=8):
+    """``count`` lumps, waist U[4,10], velocities U[-0.5,0.5]^3 (dx = 1)."""
+    rng = np.random.default_rng(seed)
+    L = tuple(float(v) for v in n)
+    cs, ws, vs = random_lumps(rng, n, L, count, (4.0, 10.0))
+    return lumps(n, L, cs, ws, vs)
+
+
+def batch_sweep(count=64, seed=3, sizes=(256, 512, 1024)):
+    """Instances of the batched sweep, in draw order size, c_Y, m_Y, lump count,
+    then per lump centre, waist, velocity.  Returns a list of dicts."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        N = int(sizes[rng.integers(0, len(sizes))])
+        cY = float(rng.uniform(0.0, 1.0))
+        mY = float(rng.uniform(0.05, 0.5))
+        nl = int(rng.integers(1, 5))
+        n, L = (N, N), (float(N), float(N))
+        cs, ws, vs = random_lumps(rng, n, L, nl, (2.0, 6.0))
+        out.append(dict(n=n, L=L, kern=(1.0, cY, mY, 0.0), a=0.5, g=-0.5, dz=1e-3,
+                        psi=lumps(n, L, cs, ws, vs)))
+    return out
+
+
+def corrector_state(seed, n=(512, 512)):
+    """One seeded 2-D lump state for the learned-corrector workload."""
+    rng = np.random.default_rng(seed)
+    L = tuple(float(v) for v in n)
+    nl = int(rng.integers(1, 5))
+    cs, ws, vs = random_lumps(rng, n, L, nl, (2.0, 6.0))
+    return lumps(n, L, cs, ws, vs)
