@@ -1,0 +1,139 @@
+/*
+ * gsn.h -- C ABI of the MI355X (gfx950) split-step Schroedinger-Newton solver.
+ *
+ * The library advances the generalised Schroedinger-Newton system of
+ * arXiv:1909.08354 (Sec. II, Eq. (1)-(2)) in its optics form, Eq. (3) with
+ * k = k0 = 1:
+ *
+ *     i d(psi)/dz = -a lap(psi) - (g |psi|^2 + phi) psi,
+ *     phi_hat(k)  = K(k) rho_hat(k),  rho = |psi|^2,
+ *     K(k)        = c_newton/|k|^2 [k != 0] + c_yukawa/(|k|^2 + m_yukawa^2) + c_contact,
+ *
+ * i.e. Eq. (1) with A = -a, B = -1, G(rho) = -g rho, and the Fourier form of
+ * Eq. (2) / Eq. (4) / Eq. (5) / Eq. (8) with constant coefficients (Newtonian
+ * 1/k^2 plus its Yukawa-type correction plus a contact term; Eq. (12) with
+ * alpha = 0 is c_newton = gamma, c_contact = -beta).  The time step is the
+ * symmetric split-step Fourier method with a spectral solve for the potential
+ * (Sec. III).  The Newtonian k = 0 term is dropped; the uniform part K(0) <rho>
+ * of the potential is a pure global phase that is accumulated in FP64 and
+ * applied when psi is read.
+ *
+ * Grid: 2-D or 3-D, C order (slowest axis first, last axis contiguous),
+ * periodic, every extent a power of two in [8, 2048]; x_j = -L/2 + j L/N.
+ * psi is complex, interleaved (re, im), P = prod(n) elements.
+ *
+ * Precision: psi, rho and phi are stored in HBM as complex64/float; all FFT
+ * arithmetic, phases and multipliers run in FP64 in registers; mass, energy
+ * and the k = 0 potential term are FP64 reductions.
+ *
+ * Conventions shared by every call:
+ *   - every function returns gsn_status; nothing throws, nothing aborts;
+ *   - gsn_last_error() returns a thread-local message for the last failure;
+ *   - arguments are validated before any HIP call;
+ *   - no call keeps a caller pointer after it returns, except the workspace
+ *     given to gsn_create / gsn_batch_create / gsn_corrector_create, which the
+ *     caller owns and must keep alive (and unused by others) until destroy;
+ *   - work is queued on the stream given at creation (NULL = default stream);
+ *     calls documented as synchronising wait for that stream;
+ *   - one host thread per handle at a time.
+ */
+#ifndef GSN_H
+#define GSN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSN_OK = 0,
+    GSN_EINVAL = 1,        /* bad argument (null pointer, bad size, non-finite value) */
+    GSN_EUNSUPPORTED = 2,  /* valid but not supported (extent not a power of two in range) */
+    GSN_EWORKSPACE = 3,    /* workspace too small or misaligned (needs 256-byte alignment) */
+    GSN_EHIP = 4,          /* a HIP runtime call failed; see gsn_last_error() */
+    GSN_ENONFINITE = 5,    /* the fused FP64 mass became NaN or Inf */
+    GSN_ESTATE = 6         /* call out of order (e.g. step before psi/coefficients are set) */
+} gsn_status;
+
+typedef enum { GSN_C64 = 0, GSN_C128 = 1 } gsn_dtype;
+
+typedef struct gsn_grid_ *gsn_grid;
+
+/* K(k) = c_newton/|k|^2 [k != 0] + c_yukawa/(|k|^2 + m_yukawa^2) + c_contact
+   (Eq. (2) in Fourier form; Eq. (4)-(5) give the Yukawa family with
+   m_yukawa = 1/sigma or sqrt(2q/nu); Eq. (8) gives Newton plus Yukawa). */
+typedef struct {
+    double c_newton;
+    double c_yukawa;
+    double m_yukawa;   /* must be > 0 when c_yukawa != 0 */
+    double c_contact;
+} gsn_kernel;
+
+/* Bytes of device workspace gsn_create needs for this grid (ndim 2 or 3,
+   n[] in C order).  Includes psi, the half-spectrum of rho/phi, an energy
+   scratch copy of psi, FP64 reduction partials and FP64 tables. */
+gsn_status gsn_workspace_bytes(int ndim, const int32_t n[], size_t *bytes);
+
+/* Create a solver on the current HIP device.  d_workspace: device pointer,
+   256-byte aligned, at least gsn_workspace_bytes() bytes, owned by the caller.
+   L[]: box lengths > 0 (C order).  hip_stream: a hipStream_t or NULL.
+   Defaults after creation: a = 1/2, g = 0, dz = 0 (must be set), kernel = 0. */
+gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], const double L[],
+                      void *d_workspace, size_t bytes, void *hip_stream);
+gsn_status gsn_destroy(gsn_grid grid);
+
+/* Set the nonlocal kernel (see gsn_kernel).  All values finite. */
+gsn_status gsn_set_kernel(gsn_grid grid, const gsn_kernel *kernel);
+
+/* Set the kinetic coefficient a (Eq. (3): 1/2), the local coefficient g
+   (Kerr; Eq. (16) with n = 2 gives g = -2w) and the step dz (finite, != 0). */
+gsn_status gsn_set_coefficients(gsn_grid grid, double a_kin, double g_local, double dz);
+
+/* Load psi (P complex values, C order) from host (src_on_device = 0) or
+   device memory, as complex64 or complex128.  Resets the global phase and the
+   step count.  Synchronising for host sources. */
+gsn_status gsn_set_psi(gsn_grid grid, const void *src, int src_on_device, int dtype);
+
+/* Advance nsteps >= 0 symmetric split steps (Sec. III):
+   L(dz/2) [N(dz) L(dz)]^(nsteps-1) N(dz) L(dz/2).  Asynchronous on the stream;
+   a non-finite fused mass is reported by the next synchronising call. */
+gsn_status gsn_step(gsn_grid grid, int64_t nsteps);
+
+/* Wait for queued work; returns GSN_ENONFINITE if any step's mass was not finite. */
+gsn_status gsn_sync(gsn_grid grid);
+
+/* Copy psi (with the accumulated global phase applied in FP64) to host or
+   device memory as complex64 or complex128.  Synchronising. */
+gsn_status gsn_get_psi(gsn_grid grid, void *dst, int dst_on_device, int dtype);
+
+/* FP64 mass M = dV sum |psi|^2 of the current state.  Synchronising. */
+gsn_status gsn_mass(gsn_grid grid, double *mass);
+
+/* FP64 energy of the current state (the Hamiltonian of the equation):
+   e[0] total, e[1] kinetic a dV/P sum |k|^2 |psi_hat|^2, e[2] local
+   -(g/2) dV sum rho^2, e[3] nonlocal -(1/2) dV sum rho phi.  Synchronising. */
+gsn_status gsn_energy(gsn_grid grid, double e[4]);
+
+/* Global phase accumulated since gsn_set_psi (FP64) and steps taken. */
+gsn_status gsn_phase(gsn_grid grid, double *theta, int64_t *steps);
+
+/* Per-pass timing: runs nsteps steady-state steps with HIP events around every
+   pass on the grid's stream and writes the average milliseconds per launch of
+   each pass into ms[] (npass entries, order as gsn_pass_name()).  The state is
+   advanced exactly as gsn_step(nsteps) would.  Synchronising. */
+gsn_status gsn_profile_passes(gsn_grid grid, int64_t nsteps, double *ms, int npass);
+int gsn_pass_count(gsn_grid grid);
+const char *gsn_pass_name(gsn_grid grid, int i);
+/* Model HBM bytes per point that pass i moves (reads + writes). */
+double gsn_pass_bytes_per_point(gsn_grid grid, int i);
+
+/* Human-readable message for the last failure on this thread. */
+const char *gsn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSN_H */

@@ -1,0 +1,851 @@
+// gsn_api.hip -- host side of the C ABI declared in include/gsn.h.
+//
+// Owns argument validation, the layout of the caller's workspace, the FP64
+// tables (twiddles, per-axis |k|^2 and kinetic factors, all generated on the
+// host with double cos/sin), the per-step pass schedule and its launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gsn.h"
+#include "gsn_kernels.hpp"
+
+using namespace gsn;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static gsn_status fail(gsn_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(GSN_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+extern "C" const char *gsn_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------ kernel tables per N
+struct NKernels {
+    int E, TPL, lm_lines, em_lines;
+    void (*em_fwd)(EmArgs);
+    void (*em_inv)(EmArgs);
+    void (*density)(EmArgs);
+    void (*phase)(EmArgs);
+    void (*phase_energy)(EmArgs);
+    void (*lm_fwd)(LmArgs);
+    void (*lm_inv)(LmArgs);
+    void (*lm_kin)(LmArgs);
+    void (*lm_kern)(LmArgs);
+    void (*lm_kin_energy)(LmArgs);
+    int lm_threads() const { return lm_lines * TPL; }
+    int em_threads() const { return em_lines * TPL; }
+};
+
+template <int N> struct Cfg {
+    static constexpr int E = N < 16 ? N : 16;
+    static constexpr int TPL = N / E;
+    static constexpr int LM_LINES = N <= 64 ? 64 : N == 128 ? 32 : N <= 512 ? 16 : N == 1024 ? 8 : 4;
+    static constexpr int EM_LINES = (256 / TPL) > 64 ? 64 : (256 / TPL) < 1 ? 1 : 256 / TPL;
+};
+
+template <int N> static NKernels make_kernels()
+{
+    using C = Cfg<N>;
+    constexpr int E = C::E, LL = C::LM_LINES, EL = C::EM_LINES;
+    NKernels k;
+    k.E = E;
+    k.TPL = C::TPL;
+    k.lm_lines = LL;
+    k.em_lines = EL;
+    k.em_fwd = k_em_fft<N, E, EL, -1>;
+    k.em_inv = k_em_fft<N, E, EL, 1>;
+    k.density = k_density<N, E, EL>;
+    k.phase = k_phase<N, E, EL, false>;
+    k.phase_energy = k_phase<N, E, EL, true>;
+    k.lm_fwd = k_lm<N, E, LL, LM_FWD>;
+    k.lm_inv = k_lm<N, E, LL, LM_INV>;
+    k.lm_kin = k_lm<N, E, LL, LM_KIN>;
+    k.lm_kern = k_lm<N, E, LL, LM_KERN>;
+    k.lm_kin_energy = k_lm<N, E, LL, LM_KIN_ENERGY>;
+    return k;
+}
+
+static const NKernels *kernels_for(int N)
+{
+    switch (N) {
+    case 8: { static const NKernels k = make_kernels<8>(); return &k; }
+    case 16: { static const NKernels k = make_kernels<16>(); return &k; }
+    case 32: { static const NKernels k = make_kernels<32>(); return &k; }
+    case 64: { static const NKernels k = make_kernels<64>(); return &k; }
+    case 128: { static const NKernels k = make_kernels<128>(); return &k; }
+    case 256: { static const NKernels k = make_kernels<256>(); return &k; }
+    case 512: { static const NKernels k = make_kernels<512>(); return &k; }
+    case 1024: { static const NKernels k = make_kernels<1024>(); return &k; }
+    case 2048: { static const NKernels k = make_kernels<2048>(); return &k; }
+    default: return nullptr;
+    }
+}
+
+// ------------------------------------------------------------------ passes
+enum PassId {
+    P_ENTRY = 0, P_Y_FWD_PSI, P_KINETIC, P_Y_INV_PSI, P_DENSITY, P_Y_FWD_RHO, P_KERNEL,
+    P_Y_INV_PHI, P_PHASE, P_EXIT, P_COUNT
+};
+static const char *kPassNames[P_COUNT] = {
+    "x_entry_fft", "y_fwd_psi", "kinetic", "y_inv_psi", "x_density", "y_fwd_rho",
+    "kernel", "y_inv_phi", "x_phase", "x_exit_ifft"};
+
+struct Launch {
+    const void *fn;
+    dim3 grid, block;
+    bool em;
+    EmArgs ea;
+    LmArgs la;
+    int pass;
+};
+
+struct gsn_grid_ {
+    int ndim;
+    int n[3];
+    double L[3];
+    long long P;
+    int Nx, Ny, Nz;   // Nz = 1 in 2-D
+    hipStream_t stream;
+    int device;
+    // workspace carve-up
+    float2 *psi, *scratch, *half, *nyq;
+    double *mass_parts, *epart;
+    DevState *st;
+    double2 *tw[3];            // twiddles for x, y, z lengths
+    double *k2[3];             // |k_d|^2 tables
+    double2 *kinF[3], *kinH[3];
+    double *k2_unit;
+    double2 *kin_unit;
+    const NKernels *kx, *ky, *kz;
+    // parameters
+    double a, g, dz;
+    gsn_kernel kern;
+    bool have_dz, have_psi;
+    // launch schedules
+    std::vector<Launch> entry, kin_half, kin_full, nonlin, exit_, energy_rho, energy_kin;
+    int density_blocks;
+};
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t psi, scratch, half, nyq, mass_parts, epart, st, tables, total;
+    int density_blocks, em_blocks, lm_blocks_max;
+};
+
+static gsn_status validate_shape(int ndim, const int32_t n[])
+{
+    if (ndim != 2 && ndim != 3) return fail(GSN_EUNSUPPORTED, "ndim must be 2 or 3");
+    if (!n) return fail(GSN_EINVAL, "n is NULL");
+    for (int d = 0; d < ndim; ++d)
+        if (!is_pow2(n[d]) || n[d] < 8 || n[d] > 2048)
+            return fail(GSN_EUNSUPPORTED,
+                        "every extent must be a power of two in [8, 2048], got " + std::to_string(n[d]));
+    return GSN_OK;
+}
+
+static int lm_tiles_main(int nlines, int lines_per_tile, int nouter)
+{
+    return ((nlines + lines_per_tile - 1) / lines_per_tile) * nouter;
+}
+
+static Layout compute_layout(int ndim, const int32_t n[])
+{
+    Layout L{};
+    const int Nx = n[ndim - 1], Ny = n[ndim - 2], Nz = ndim == 3 ? n[0] : 1;
+    const long long P = (long long)Nx * Ny * Nz;
+    const long long rows = P / Nx;
+    const NKernels *kx = kernels_for(Nx), *ky = kernels_for(Ny), *kz = ndim == 3 ? kernels_for(Nz) : nullptr;
+    L.density_blocks = (int)((rows / 2 + kx->em_lines - 1) / kx->em_lines);
+    L.em_blocks = (int)((rows + kx->em_lines - 1) / kx->em_lines);
+    // largest LM grid of an energy pass: kinetic-energy pass over the last axis
+    int lmb = 0;
+    if (ndim == 3) lmb = lm_tiles_main(Nx, kz->lm_lines, Ny);
+    else lmb = lm_tiles_main(Nx, ky->lm_lines, 1);
+    L.lm_blocks_max = lmb;
+    size_t off = 0;
+    L.psi = off; off = align256(off + 8ull * P);
+    L.scratch = off; off = align256(off + 8ull * P);
+    L.half = off; off = align256(off + 8ull * (P / 2));
+    L.nyq = off; off = align256(off + 8ull * rows);
+    L.mass_parts = off; off = align256(off + 8ull * (size_t)(L.density_blocks > 1024 ? L.density_blocks : 1024));
+    size_t ep = 2ull * (size_t)L.density_blocks + (size_t)lmb + 1024;
+    L.epart = off; off = align256(off + 8ull * ep);
+    L.st = off; off = align256(off + sizeof(DevState));
+    L.tables = off;
+    size_t tb = 0;
+    for (int d = 0; d < ndim; ++d) tb += align256(16ull * n[d]) * 3 + align256(8ull * n[d]);
+    tb += 512;
+    off = align256(off + tb);
+    L.total = off;
+    return L;
+}
+
+extern "C" gsn_status gsn_workspace_bytes(int ndim, const int32_t n[], size_t *bytes)
+{
+    gsn_status s = validate_shape(ndim, n);
+    if (s) return s;
+    if (!bytes) return fail(GSN_EINVAL, "bytes is NULL");
+    *bytes = compute_layout(ndim, n).total;
+    return GSN_OK;
+}
+
+// ------------------------------------------------------------------ schedule construction
+static Seg seg_empty()
+{
+    Seg s;
+    std::memset(&s, 0, sizeof(s));
+    return s;
+}
+
+static Seg make_seg(float2 *ptr, long long es, long long ls, long long os, int nlines, int nouter,
+                    int lines_per_tile)
+{
+    Seg s = seg_empty();
+    s.ptr = ptr;
+    s.es = es;
+    s.ls = ls;
+    s.os = os;
+    s.nlines = nlines;
+    s.ngroups = (nlines + lines_per_tile - 1) / lines_per_tile;
+    s.ntiles = s.ngroups * nouter;
+    return s;
+}
+
+static LmArgs lm_base(gsn_grid g, const double2 *tw, double scale)
+{
+    LmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.tw = tw;
+    a.scale = scale;
+    a.kin1 = a.kin2 = a.kinp = g->kin_unit;
+    a.k2_1 = a.k2_2 = a.k2_p = g->k2_unit;
+    a.st = g->st;
+    return a;
+}
+
+static Launch lm_launch(void (*fn)(LmArgs), const NKernels *k, const LmArgs &a, int pass)
+{
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    L.fn = (const void *)fn;
+    L.grid = dim3(a.s0.ntiles + a.s1.ntiles);
+    L.block = dim3(k->lm_threads());
+    L.em = false;
+    L.la = a;
+    L.pass = pass;
+    return L;
+}
+
+static Launch em_launch(void (*fn)(EmArgs), const NKernels *k, const EmArgs &a, int pass)
+{
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    L.fn = (const void *)fn;
+    L.grid = dim3((a.nlines + k->em_lines - 1) / k->em_lines);
+    L.block = dim3(k->em_threads());
+    L.em = true;
+    L.ea = a;
+    L.pass = pass;
+    return L;
+}
+
+static EmArgs em_base(gsn_grid g, float2 *psi)
+{
+    EmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.psi = psi;
+    a.half = g->half;
+    a.nyq = g->nyq;
+    a.tw = g->tw[g->ndim - 1];
+    a.scale = 1.0;
+    return a;
+}
+
+static double kernel_k0(const gsn_kernel &k)
+{
+    double v = k.c_contact;
+    if (k.c_yukawa != 0.0) v += k.c_yukawa / (k.m_yukawa * k.m_yukawa);
+    return v;
+}
+
+// Build every launch list from the current parameters (pointers never move).
+static void build_schedule(gsn_grid g)
+{
+    const int nd = g->ndim, Nx = g->Nx, Ny = g->Ny, Nz = g->Nz;
+    const int X = nd - 1, Y = nd - 2, Z = 0;   // table indices by axis
+    const long long rows = g->P / Nx;
+    const int H = Nx / 2;
+    g->entry.clear(); g->kin_half.clear(); g->kin_full.clear(); g->nonlin.clear();
+    g->exit_.clear(); g->energy_rho.clear(); g->energy_kin.clear();
+
+    // entry / exit along x
+    {
+        EmArgs a = em_base(g, g->psi);
+        a.nlines = (int)rows;
+        a.scale = 1.0;
+        g->entry.push_back(em_launch(g->kx->em_fwd, g->kx, a, P_ENTRY));
+        a.scale = 1.0 / Nx;
+        g->exit_.push_back(em_launch(g->kx->em_inv, g->kx, a, P_EXIT));
+    }
+    // kinetic sub-steps (psi, full grid)
+    for (int half = 0; half < 2; ++half) {
+        std::vector<Launch> &dst = half ? g->kin_half : g->kin_full;
+        double2 *const *kin = half ? g->kinH : g->kinF;
+        if (nd == 3) {
+            const NKernels *ky = g->ky, *kz = g->kz;
+            LmArgs a = lm_base(g, g->tw[Y], 1.0);
+            a.s0 = make_seg(g->psi, Nx, 1, (long long)Ny * Nx, Nx, Nz, ky->lm_lines);
+            dst.push_back(lm_launch(ky->lm_fwd, ky, a, P_Y_FWD_PSI));
+            LmArgs b = lm_base(g, g->tw[Z], 1.0 / ((double)Ny * Nz));
+            b.s0 = make_seg(g->psi, (long long)Ny * Nx, 1, Nx, Nx, Ny, kz->lm_lines);
+            b.s0.c1l = 1;  // c1 = x = line
+            b.s0.c2o = 1;  // c2 = y = outer
+            b.kin1 = kin[X];
+            b.kin2 = kin[Y];
+            b.kinp = kin[Z];
+            dst.push_back(lm_launch(kz->lm_kin, kz, b, P_KINETIC));
+            LmArgs c = lm_base(g, g->tw[Y], 1.0);
+            c.s0 = a.s0;
+            dst.push_back(lm_launch(ky->lm_inv, ky, c, P_Y_INV_PSI));
+        } else {
+            const NKernels *ky = g->ky;
+            LmArgs b = lm_base(g, g->tw[Y], 1.0 / (double)Ny);
+            b.s0 = make_seg(g->psi, Nx, 1, 0, Nx, 1, ky->lm_lines);
+            b.s0.c1l = 1;
+            b.kin1 = kin[X];
+            b.kinp = kin[Y];
+            dst.push_back(lm_launch(ky->lm_kin, ky, b, P_KINETIC));
+        }
+    }
+    // nonlinear sub-step
+    const double K0 = kernel_k0(g->kern);
+    for (int energy = 0; energy < 2; ++energy) {
+        std::vector<Launch> &dst = energy ? g->energy_rho : g->nonlin;
+        float2 *src = energy ? g->scratch : g->psi;
+        EmArgs d = em_base(g, src);
+        d.nlines = (int)(rows / 2);
+        d.partials = g->mass_parts;
+        dst.push_back(em_launch(g->kx->density, g->kx, d, P_DENSITY));
+        if (nd == 3) {
+            const NKernels *ky = g->ky, *kz = g->kz;
+            LmArgs e = lm_base(g, g->tw[Y], 1.0);
+            e.s0 = make_seg(g->half, H, 1, (long long)Ny * H, H, Nz, ky->lm_lines);
+            e.s1 = make_seg(g->nyq, 1, Ny, 0, Nz, 1, ky->lm_lines);
+            if (!energy) {
+                e.reduce = 1;
+                e.mass_parts = g->mass_parts;
+                e.nmass = g->density_blocks;
+                e.k0_dz_over_P = K0 * g->dz / (double)g->P;
+            }
+            dst.push_back(lm_launch(ky->lm_fwd, ky, e, P_Y_FWD_RHO));
+            LmArgs f = lm_base(g, g->tw[Z], 1.0 / ((double)Ny * Nz));
+            f.s0 = make_seg(g->half, (long long)Ny * H, 1, H, H, Ny, kz->lm_lines);
+            f.s0.c1l = 1;   // kx = line
+            f.s0.c2o = 1;   // ky = outer
+            f.s1 = make_seg(g->nyq, Ny, 1, 0, Ny, 1, kz->lm_lines);
+            f.s1.c1f = H;   // kx = Nyquist
+            f.s1.c2l = 1;   // ky = line
+            f.k2_1 = g->k2[X];
+            f.k2_2 = g->k2[Y];
+            f.k2_p = g->k2[Z];
+            f.cN = g->kern.c_newton;
+            f.cY = g->kern.c_yukawa;
+            f.mY2 = g->kern.m_yukawa * g->kern.m_yukawa;
+            f.c0 = g->kern.c_contact;
+            dst.push_back(lm_launch(kz->lm_kern, kz, f, P_KERNEL));
+            LmArgs gg = lm_base(g, g->tw[Y], 1.0);
+            gg.s0 = e.s0;
+            gg.s1 = e.s1;
+            dst.push_back(lm_launch(ky->lm_inv, ky, gg, P_Y_INV_PHI));
+        } else {
+            const NKernels *ky = g->ky;
+            LmArgs f = lm_base(g, g->tw[Y], 1.0 / (double)Ny);
+            f.s0 = make_seg(g->half, H, 1, 0, H, 1, ky->lm_lines);
+            f.s0.c1l = 1;
+            f.s1 = make_seg(g->nyq, 1, 0, 0, 1, 1, ky->lm_lines);
+            f.s1.c1f = H;
+            f.k2_1 = g->k2[X];
+            f.k2_p = g->k2[Y];
+            f.cN = g->kern.c_newton;
+            f.cY = g->kern.c_yukawa;
+            f.mY2 = g->kern.m_yukawa * g->kern.m_yukawa;
+            f.c0 = g->kern.c_contact;
+            if (!energy) {
+                f.reduce = 1;
+                f.mass_parts = g->mass_parts;
+                f.nmass = g->density_blocks;
+                f.k0_dz_over_P = K0 * g->dz / (double)g->P;
+            }
+            dst.push_back(lm_launch(ky->lm_kern, ky, f, P_KERNEL));
+        }
+        EmArgs h = em_base(g, src);
+        h.nlines = (int)(rows / 2);
+        h.g = g->g;
+        h.dz = g->dz;
+        h.partials = g->epart;
+        dst.push_back(em_launch(energy ? g->kx->phase_energy : g->kx->phase, g->kx, h, P_PHASE));
+    }
+    // kinetic energy: F_y (3-D) then the last-axis forward FFT with sum |k|^2 |psi_hat|^2
+    {
+        const int ep_off = 2 * g->density_blocks;
+        if (nd == 3) {
+            const NKernels *ky = g->ky, *kz = g->kz;
+            LmArgs a = lm_base(g, g->tw[Y], 1.0);
+            a.s0 = make_seg(g->scratch, Nx, 1, (long long)Ny * Nx, Nx, Nz, ky->lm_lines);
+            g->energy_kin.push_back(lm_launch(ky->lm_fwd, ky, a, P_Y_FWD_PSI));
+            LmArgs b = lm_base(g, g->tw[Z], 1.0);
+            b.s0 = make_seg(g->scratch, (long long)Ny * Nx, 1, Nx, Nx, Ny, kz->lm_lines);
+            b.s0.c1l = 1;
+            b.s0.c2o = 1;
+            b.k2_1 = g->k2[X];
+            b.k2_2 = g->k2[Y];
+            b.k2_p = g->k2[Z];
+            b.partials = g->epart + ep_off;
+            g->energy_kin.push_back(lm_launch(kz->lm_kin_energy, kz, b, P_KINETIC));
+        } else {
+            const NKernels *ky = g->ky;
+            LmArgs b = lm_base(g, g->tw[Y], 1.0);
+            b.s0 = make_seg(g->scratch, Nx, 1, 0, Nx, 1, ky->lm_lines);
+            b.s0.c1l = 1;
+            b.k2_1 = g->k2[X];
+            b.k2_p = g->k2[Y];
+            b.partials = g->epart + ep_off;
+            g->energy_kin.push_back(lm_launch(ky->lm_kin_energy, ky, b, P_KINETIC));
+        }
+    }
+}
+
+static hipError_t launch(const Launch &L, hipStream_t s)
+{
+    void *args[1];
+    EmArgs ea = L.ea;
+    LmArgs la = L.la;
+    if (L.em) args[0] = &ea;
+    else args[0] = &la;
+    return hipLaunchKernel(L.fn, L.grid, L.block, args, 0, s);
+}
+
+static gsn_status run_list(gsn_grid g, const std::vector<Launch> &v)
+{
+    for (const Launch &L : v) HIP_TRY(launch(L, g->stream));
+    return GSN_OK;
+}
+
+// ------------------------------------------------------------------ tables
+static double wavenumber(int j, int N, double L)
+{
+    const int jj = j < N / 2 ? j : j - N;
+    return 2.0 * M_PI * (double)jj / L;
+}
+
+static gsn_status upload(gsn_grid g, void *dst, const void *src, size_t bytes)
+{
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return GSN_OK;
+}
+
+static gsn_status upload_kinetic(gsn_grid g)
+{
+    for (int d = 0; d < g->ndim; ++d) {
+        const int N = g->n[d];
+        std::vector<double2> f(N), h(N);
+        for (int j = 0; j < N; ++j) {
+            const double k = wavenumber(j, N, g->L[d]);
+            const double thf = -g->a * k * k * g->dz, thh = 0.5 * thf;
+            f[j] = make_double2(std::cos(thf), std::sin(thf));
+            h[j] = make_double2(std::cos(thh), std::sin(thh));
+        }
+        gsn_status s = upload(g, g->kinF[d], f.data(), 16ull * N);
+        if (s) return s;
+        s = upload(g, g->kinH[d], h.data(), 16ull * N);
+        if (s) return s;
+    }
+    return GSN_OK;
+}
+
+static gsn_status upload_static_tables(gsn_grid g)
+{
+    for (int d = 0; d < g->ndim; ++d) {
+        const int N = g->n[d];
+        std::vector<double2> tw(N);
+        std::vector<double> k2(N);
+        for (int q = 0; q < N; ++q) {
+            const double ang = 2.0 * M_PI * (double)q / (double)N;
+            tw[q] = make_double2(std::cos(ang), -std::sin(ang));
+            const double k = wavenumber(q, N, g->L[d]);
+            k2[q] = k * k;
+        }
+        gsn_status s = upload(g, g->tw[d], tw.data(), 16ull * N);
+        if (s) return s;
+        s = upload(g, g->k2[d], k2.data(), 8ull * N);
+        if (s) return s;
+    }
+    const double zero = 0.0;
+    const double2 one = make_double2(1.0, 0.0);
+    gsn_status s = upload(g, g->k2_unit, &zero, 8);
+    if (s) return s;
+    return upload(g, g->kin_unit, &one, 16);
+}
+
+// ------------------------------------------------------------------ lifecycle
+extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], const double L[],
+                                 void *d_workspace, size_t bytes, void *hip_stream)
+{
+    if (!out) return fail(GSN_EINVAL, "out is NULL");
+    *out = nullptr;
+    gsn_status s = validate_shape(ndim, n);
+    if (s) return s;
+    if (!L) return fail(GSN_EINVAL, "L is NULL");
+    for (int d = 0; d < ndim; ++d)
+        if (!(std::isfinite(L[d]) && L[d] > 0.0)) return fail(GSN_EINVAL, "box lengths must be finite and > 0");
+    if (!d_workspace) return fail(GSN_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(GSN_EWORKSPACE, "workspace must be 256-byte aligned");
+    const Layout lay = compute_layout(ndim, n);
+    if (bytes < lay.total)
+        return fail(GSN_EWORKSPACE, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+
+    gsn_grid g = new (std::nothrow) gsn_grid_();
+    if (!g) return fail(GSN_EINVAL, "out of host memory");
+    g->ndim = ndim;
+    for (int d = 0; d < 3; ++d) { g->n[d] = d < ndim ? n[d] : 1; g->L[d] = d < ndim ? L[d] : 1.0; }
+    g->Nx = n[ndim - 1];
+    g->Ny = n[ndim - 2];
+    g->Nz = ndim == 3 ? n[0] : 1;
+    g->P = (long long)g->Nx * g->Ny * g->Nz;
+    g->stream = (hipStream_t)hip_stream;
+    g->kx = kernels_for(g->Nx);
+    g->ky = kernels_for(g->Ny);
+    g->kz = ndim == 3 ? kernels_for(g->Nz) : nullptr;
+    g->density_blocks = lay.density_blocks;
+    g->a = 0.5;
+    g->g = 0.0;
+    g->dz = 0.0;
+    std::memset(&g->kern, 0, sizeof(g->kern));
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return fail(GSN_EHIP, "hipGetDevice failed");
+    }
+    char *ws = (char *)d_workspace;
+    g->psi = (float2 *)(ws + lay.psi);
+    g->scratch = (float2 *)(ws + lay.scratch);
+    g->half = (float2 *)(ws + lay.half);
+    g->nyq = (float2 *)(ws + lay.nyq);
+    g->mass_parts = (double *)(ws + lay.mass_parts);
+    g->epart = (double *)(ws + lay.epart);
+    g->st = (DevState *)(ws + lay.st);
+    size_t off = lay.tables;
+    for (int d = 0; d < ndim; ++d) {
+        g->tw[d] = (double2 *)(ws + off); off += align256(16ull * n[d]);
+        g->kinF[d] = (double2 *)(ws + off); off += align256(16ull * n[d]);
+        g->kinH[d] = (double2 *)(ws + off); off += align256(16ull * n[d]);
+        g->k2[d] = (double *)(ws + off); off += align256(8ull * n[d]);
+    }
+    g->k2_unit = (double *)(ws + off); off += 256;
+    g->kin_unit = (double2 *)(ws + off); off += 256;
+    if ((s = upload_static_tables(g)) || (s = upload_kinetic(g))) {
+        delete g;
+        return s;
+    }
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, g->stream, g->st);
+    if (hipGetLastError() != hipSuccess) {
+        delete g;
+        return fail(GSN_EHIP, "reset kernel launch failed");
+    }
+    build_schedule(g);
+    *out = g;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_destroy(gsn_grid g)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    hipStreamSynchronize(g->stream);
+    delete g;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_set_kernel(gsn_grid g, const gsn_kernel *k)
+{
+    if (!g || !k) return fail(GSN_EINVAL, "NULL argument");
+    if (!std::isfinite(k->c_newton) || !std::isfinite(k->c_yukawa) || !std::isfinite(k->m_yukawa) ||
+        !std::isfinite(k->c_contact))
+        return fail(GSN_EINVAL, "kernel coefficients must be finite");
+    if (k->c_yukawa != 0.0 && !(k->m_yukawa > 0.0))
+        return fail(GSN_EINVAL, "m_yukawa must be > 0 when c_yukawa != 0");
+    g->kern = *k;
+    build_schedule(g);
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_set_coefficients(gsn_grid g, double a_kin, double g_local, double dz)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (!std::isfinite(a_kin) || !std::isfinite(g_local) || !std::isfinite(dz) || dz == 0.0)
+        return fail(GSN_EINVAL, "coefficients must be finite and dz != 0");
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->a = a_kin;
+    g->g = g_local;
+    g->dz = dz;
+    gsn_status s = upload_kinetic(g);
+    if (s) return s;
+    g->have_dz = true;
+    build_schedule(g);
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_set_psi(gsn_grid g, const void *src, int on_device, int dtype)
+{
+    if (!g || !src) return fail(GSN_EINVAL, "NULL argument");
+    if (dtype != GSN_C64 && dtype != GSN_C128) return fail(GSN_EINVAL, "dtype must be GSN_C64 or GSN_C128");
+    HIP_TRY(hipSetDevice(g->device));
+    const long long P = g->P;
+    if (dtype == GSN_C64) {
+        HIP_TRY(hipMemcpyAsync(g->psi, src, 8ull * P, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                               g->stream));
+    } else if (on_device) {
+        hipLaunchKernelGGL(k_from_c128, dim3(1024), dim3(256), 0, g->stream, (const double2 *)src, g->psi, P);
+        HIP_TRY(hipGetLastError());
+    } else {
+        std::vector<float2> tmp((size_t)P);
+        const double *s = (const double *)src;
+        for (long long i = 0; i < P; ++i) tmp[i] = make_float2((float)s[2 * i], (float)s[2 * i + 1]);
+        HIP_TRY(hipMemcpyAsync(g->psi, tmp.data(), 8ull * P, hipMemcpyHostToDevice, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+    }
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, g->stream, g->st);
+    HIP_TRY(hipGetLastError());
+    if (!on_device) HIP_TRY(hipStreamSynchronize(g->stream));
+    g->have_psi = true;
+    return GSN_OK;
+}
+
+static gsn_status ready(gsn_grid g)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
+    if (!g->have_dz) return fail(GSN_ESTATE, "coefficients (dz) not set");
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_step(gsn_grid g, int64_t nsteps)
+{
+    gsn_status s = ready(g);
+    if (s) return s;
+    if (nsteps < 0) return fail(GSN_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return GSN_OK;
+    HIP_TRY(hipSetDevice(g->device));
+    if ((s = run_list(g, g->entry)) || (s = run_list(g, g->kin_half))) return s;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        if ((s = run_list(g, g->nonlin))) return s;
+        if ((s = run_list(g, i + 1 < nsteps ? g->kin_full : g->kin_half))) return s;
+    }
+    return run_list(g, g->exit_);
+}
+
+static gsn_status read_state(gsn_grid g, DevState *st)
+{
+    HIP_TRY(hipMemcpyAsync(st, g->st, sizeof(DevState), hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_sync(gsn_grid g)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    HIP_TRY(hipSetDevice(g->device));
+    DevState st;
+    gsn_status s = read_state(g, &st);
+    if (s) return s;
+    if (st.nonfinite) return fail(GSN_ENONFINITE, "the fused FP64 mass became non-finite");
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_phase(gsn_grid g, double *theta, int64_t *steps)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    HIP_TRY(hipSetDevice(g->device));
+    DevState st;
+    gsn_status s = read_state(g, &st);
+    if (s) return s;
+    if (theta) *theta = st.theta;
+    if (steps) *steps = st.steps;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_get_psi(gsn_grid g, void *dst, int on_device, int dtype)
+{
+    if (!g || !dst) return fail(GSN_EINVAL, "NULL argument");
+    if (dtype != GSN_C64 && dtype != GSN_C128) return fail(GSN_EINVAL, "dtype must be GSN_C64 or GSN_C128");
+    if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
+    HIP_TRY(hipSetDevice(g->device));
+    const long long P = g->P;
+    if (on_device) {
+        if (dtype == GSN_C128) hipLaunchKernelGGL(k_readout<true>, dim3(1024), dim3(256), 0, g->stream, g->psi, dst, P, g->st);
+        else hipLaunchKernelGGL(k_readout<false>, dim3(1024), dim3(256), 0, g->stream, g->psi, dst, P, g->st);
+        HIP_TRY(hipGetLastError());
+    } else {
+        // through the scratch buffer (8 bytes per point) in chunks
+        const size_t esz = dtype == GSN_C128 ? 16 : 8;
+        const long long chunk = (long long)((8ull * P) / esz);
+        for (long long off = 0; off < P; off += chunk) {
+            const long long cnt = P - off < chunk ? P - off : chunk;
+            if (dtype == GSN_C128)
+                hipLaunchKernelGGL(k_readout<true>, dim3(1024), dim3(256), 0, g->stream, g->psi + off,
+                                   (void *)g->scratch, cnt, g->st);
+            else
+                hipLaunchKernelGGL(k_readout<false>, dim3(1024), dim3(256), 0, g->stream, g->psi + off,
+                                   (void *)g->scratch, cnt, g->st);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync((char *)dst + off * esz, g->scratch, cnt * esz, hipMemcpyDeviceToHost,
+                                   g->stream));
+            HIP_TRY(hipStreamSynchronize(g->stream));
+        }
+    }
+    return gsn_sync(g);
+}
+
+static double cell_volume(gsn_grid g)
+{
+    double dV = 1.0;
+    for (int d = 0; d < g->ndim; ++d) dV *= g->L[d] / g->n[d];
+    return dV;
+}
+
+static gsn_status sum_device(gsn_grid g, const double *dptr, int count, int stride, int offset,
+                             double *out)
+{
+    std::vector<double> h((size_t)count * stride);
+    HIP_TRY(hipMemcpyAsync(h.data(), dptr, 8ull * count * stride, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    double s = 0.0;
+    for (int i = 0; i < count; ++i) s += h[(size_t)i * stride + offset];
+    *out = s;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_mass(gsn_grid g, double *mass)
+{
+    if (!mass) return fail(GSN_EINVAL, "mass is NULL");
+    gsn_status s = g ? GSN_OK : fail(GSN_EINVAL, "grid is NULL");
+    if (s) return s;
+    if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
+    HIP_TRY(hipSetDevice(g->device));
+    const int nb = 1024;
+    hipLaunchKernelGGL(k_mass<256>, dim3(nb), dim3(256), 0, g->stream, g->psi, g->P, g->epart);
+    HIP_TRY(hipGetLastError());
+    double sum = 0.0;
+    if ((s = sum_device(g, g->epart, nb, 1, 0, &sum))) return s;
+    *mass = sum * cell_volume(g);
+    if ((s = gsn_sync(g))) return s;
+    if (!std::isfinite(*mass)) return fail(GSN_ENONFINITE, "mass is not finite");
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_energy(gsn_grid g, double e[4])
+{
+    if (!e) return fail(GSN_EINVAL, "e is NULL");
+    gsn_status s = g ? GSN_OK : fail(GSN_EINVAL, "grid is NULL");
+    if (s) return s;
+    if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, 8ull * g->P, hipMemcpyDeviceToDevice, g->stream));
+    for (const Launch &L : g->entry) {
+        Launch c = L;
+        c.ea.psi = g->scratch;
+        HIP_TRY(launch(c, g->stream));
+    }
+    if ((s = run_list(g, g->energy_rho))) return s;
+    if ((s = run_list(g, g->energy_kin))) return s;
+    const int nphase = (int)g->energy_rho.back().grid.x;
+    const int nkin = (int)g->energy_kin.back().grid.x;
+    double rho_sum = 0.0, rho_phi = 0.0, rho2 = 0.0, k2sum = 0.0;
+    if ((s = sum_device(g, g->mass_parts, g->density_blocks, 1, 0, &rho_sum))) return s;
+    if ((s = sum_device(g, g->epart, nphase, 2, 0, &rho_phi))) return s;
+    if ((s = sum_device(g, g->epart, nphase, 2, 1, &rho2))) return s;
+    if ((s = sum_device(g, g->epart + 2 * g->density_blocks, nkin, 1, 0, &k2sum))) return s;
+    const double dV = cell_volume(g), P = (double)g->P, K0 = kernel_k0(g->kern);
+    const double ekin = g->a * dV / P * k2sum;
+    const double eloc = -0.5 * g->g * dV * rho2;
+    const double enl = -0.5 * dV * (rho_phi + K0 * rho_sum * rho_sum / P);
+    e[0] = ekin + eloc + enl;
+    e[1] = ekin;
+    e[2] = eloc;
+    e[3] = enl;
+    return gsn_sync(g);
+}
+
+// ------------------------------------------------------------------ profiling
+extern "C" int gsn_pass_count(gsn_grid) { return P_COUNT; }
+
+extern "C" const char *gsn_pass_name(gsn_grid, int i)
+{
+    return (i >= 0 && i < P_COUNT) ? kPassNames[i] : "";
+}
+
+extern "C" double gsn_pass_bytes_per_point(gsn_grid g, int i)
+{
+    if (!g) return 0.0;
+    // reads + writes of complex64 psi (8 B), half spectrum (4 B per point)
+    switch (i) {
+    case P_ENTRY: case P_EXIT: case P_Y_FWD_PSI: case P_Y_INV_PSI: case P_KINETIC: return 16.0;
+    case P_DENSITY: return 12.0;
+    case P_Y_FWD_RHO: case P_KERNEL: case P_Y_INV_PHI: return 8.0;
+    case P_PHASE: return 20.0;
+    default: return 0.0;
+    }
+}
+
+extern "C" gsn_status gsn_profile_passes(gsn_grid g, int64_t nsteps, double *ms, int npass)
+{
+    gsn_status s = ready(g);
+    if (s) return s;
+    if (!ms || npass < P_COUNT || nsteps < 1) return fail(GSN_EINVAL, "bad profile arguments");
+    HIP_TRY(hipSetDevice(g->device));
+    std::vector<const Launch *> seq;
+    for (const Launch &L : g->entry) seq.push_back(&L);
+    for (const Launch &L : g->kin_half) seq.push_back(&L);
+    for (int64_t i = 0; i < nsteps; ++i) {
+        for (const Launch &L : g->nonlin) seq.push_back(&L);
+        for (const Launch &L : (i + 1 < nsteps ? g->kin_full : g->kin_half)) seq.push_back(&L);
+    }
+    for (const Launch &L : g->exit_) seq.push_back(&L);
+    std::vector<hipEvent_t> ev(seq.size() + 1);
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipEventRecord(ev[0], g->stream));
+    for (size_t i = 0; i < seq.size(); ++i) {
+        HIP_TRY(launch(*seq[i], g->stream));
+        HIP_TRY(hipEventRecord(ev[i + 1], g->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    std::vector<double> tot(P_COUNT, 0.0);
+    std::vector<int> cnt(P_COUNT, 0);
+    for (size_t i = 0; i < seq.size(); ++i) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+        tot[seq[i]->pass] += t;
+        cnt[seq[i]->pass] += 1;
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    for (int i = 0; i < P_COUNT; ++i) ms[i] = cnt[i] ? tot[i] / cnt[i] : 0.0;
+    return gsn_sync(g);
+}

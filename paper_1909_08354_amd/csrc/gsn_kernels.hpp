@@ -1,0 +1,367 @@
+// gsn_kernels.hpp -- the HBM passes of one split step on gfx950.
+//
+// State between passes is complex64 in HBM.  Each pass loads a tile of lines,
+// runs FFTs in FP64 registers (Stockham, LDS exchange as complex64), applies a
+// fused pointwise stage and stores the tile back.  Two tile shapes:
+//   * EM ("element-major", the contiguous x axis): a block owns whole rows;
+//     consecutive lanes hold consecutive points of a row.
+//   * LM ("line-major", strided y / z axes): a block owns LINES adjacent
+//     columns along x of one slice; consecutive lanes hold adjacent columns, so
+//     every load and store is a contiguous LINES*8-byte segment.
+//
+// Normalisation (F = unnormalised forward DFT, G = unnormalised inverse):
+//   psi_x = F_x psi is the state inside a run of steps;
+//   kinetic sub-step:  psi_x <- G_y G_z [M / (Ny Nz)] F_z F_y psi_x  (3-D)
+//                      psi_x <- G_y [M / Ny] F_y psi_x                (2-D)
+//   density:           rho_x = F_x |G_x psi_x / Nx|^2   (half spectrum)
+//   potential:         phi_x = G_y G_z [K / (Ny Nz)] F_z F_y rho_x
+//   phase:             psi_x <- F_x[ (G_x psi_x / Nx) exp(i (g rho + G_x phi_x / Nx) dz) ]
+// Powers of two make every scale exact.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "gsn_fft.hpp"
+
+namespace gsn {
+
+struct DevState {
+    double theta;      // accumulated global phase K(0) <rho> dz (FP64)
+    double mass_sum;   // sum |psi|^2 of the last nonlinear sub-step (no dV)
+    long long steps;   // nonlinear sub-steps taken since set_psi
+    int nonfinite;     // set when a fused mass was NaN/Inf
+    int pad;
+};
+
+// ---------------------------------------------------------------- EM passes
+struct EmArgs {
+    float2 *psi;          // rows of N complex
+    float2 *half;         // rows of N/2 complex (half spectrum, bins 0..N/2-1)
+    float2 *nyq;          // one complex per row (bin N/2)
+    const double2 *tw;    // exp(-2 pi i q / N), q < N
+    int nlines;           // rows (plain FFT) or row pairs (density / phase)
+    double scale;         // plain FFT output scale
+    double g, dz;         // phase stage
+    double *partials;     // per-block FP64 partials
+};
+
+template <int N, int E> struct EmShape {
+    static constexpr int TPL = N / E;
+};
+
+// Plain row FFT (entry/exit of a run of steps, energy evaluation).
+template <int N, int E, int LINES, int S>
+__global__ __launch_bounds__(LINES *(N / E)) void k_em_fft(EmArgs a)
+{
+    constexpr int TPL = N / E;
+    __shared__ float2 lds[LINES * EmLayout<N>::PITCH];
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    const int row = blockIdx.x * LINES + l;
+    const bool act = row < a.nlines;
+    const EmLayout<N> lay{l * EmLayout<N>::PITCH};
+    dc v[E];
+    float2 *p = a.psi + (long long)row * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+    fft<N, E, S>(v, t, lay, lds, a.tw);
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) p[t + TPL * e] = to_f2(scl(v[e], a.scale));
+    }
+}
+
+// Density pass: psi = G_x psi_x / N for two rows, rho = |psi|^2, FP64 partial
+// of sum rho, then one forward FFT of Z = rho_0 + i rho_1 and the split
+// X_0[k] = (Z[k] + conj Z[N-k]) / 2, X_1[k] = (Z[k] - conj Z[N-k]) / (2i).
+template <int N, int E, int LINES>
+__global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
+{
+    constexpr int TPL = N / E, NT = LINES * TPL;
+    __shared__ float2 lds[LINES * EmLayout<N>::PITCH];
+    __shared__ double sh[NT / 64 + 1];
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    const int pair = blockIdx.x * LINES + l;
+    const bool act = pair < a.nlines;
+    const EmLayout<N> lay{l * EmLayout<N>::PITCH};
+    const long long r0 = 2LL * pair, r1 = r0 + 1;
+    const double inv_n = 1.0 / N;
+    dc v[E], w[E];
+    const float2 *p0 = a.psi + r0 * N, *p1 = a.psi + r1 * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p0[t + TPL * e]) : mk(0.0, 0.0);
+    fft<N, E, 1>(v, t, lay, lds, a.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) w[e] = act ? from_f2(p1[t + TPL * e]) : mk(0.0, 0.0);
+    fft<N, E, 1>(w, t, lay, lds, a.tw);
+    double msum = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const double rho0 = norm2(v[e]) * (inv_n * inv_n);
+        const double rho1 = norm2(w[e]) * (inv_n * inv_n);
+        msum += rho0 + rho1;
+        v[e] = mk(rho0, rho1);
+    }
+    fft<N, E, -1>(v, t, lay, lds, a.tw);
+    // exchange Z so that bin k can see bin N-k
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[lay(t + TPL * e)] = to_f2(v[e]);
+    __syncthreads();
+    if (act) {
+        float2 *h0 = a.half + r0 * (N / 2), *h1 = a.half + r1 * (N / 2);
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            const int k = t + TPL * e;
+            const dc z = v[e];
+            const dc zc = conj(from_f2(lds[lay((N - k) & (N - 1))]));
+            const dc s = add(z, zc), d = sub(z, zc);
+            h0[k] = to_f2(scl(s, 0.5));
+            h1[k] = to_f2(mk(0.5 * d.y, -0.5 * d.x));
+        }
+        if (t == 0) {
+            const dc z = v[E / 2];   // bin N/2: both halves are real
+            a.nyq[r0] = make_float2((float)z.x, 0.0f);
+            a.nyq[r1] = make_float2((float)z.y, 0.0f);
+        }
+    }
+    const double bs = block_sum<NT>(msum, sh);
+    if (tid == 0) a.partials[blockIdx.x] = bs;
+}
+
+// Phase pass.  Rebuild the full x-spectrum of two phi rows from their half
+// spectra (X[N-k] = conj X[k]; DC and Nyquist real), one inverse FFT gives
+// phi_0 + i phi_1.  Then per row: psi = G_x psi_x / N, multiply by
+// exp(i (g |psi|^2 + phi) dz) in FP64, F_x, store.  ENERGY: instead of the
+// phase, accumulate sum rho*phi and sum rho^2 and store nothing.
+__device__ __forceinline__ void sincos_fp64(double th, double *s, double *c) { sincos(th, s, c); }
+
+template <int N, int E, int LINES, bool ENERGY>
+__global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
+{
+    constexpr int TPL = N / E, NT = LINES * TPL;
+    __shared__ float2 lds[LINES * EmLayout<N>::PITCH];
+    __shared__ double sh[NT / 64 + 1];
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    const int pair = blockIdx.x * LINES + l;
+    const bool act = pair < a.nlines;
+    const EmLayout<N> lay{l * EmLayout<N>::PITCH};
+    const long long r0 = 2LL * pair, r1 = r0 + 1;
+    const double inv_n = 1.0 / N;
+    dc z[E];
+    {
+        const float2 *h0 = a.half + r0 * (N / 2), *h1 = a.half + r1 * (N / 2);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            dc x0 = mk(0.0, 0.0), x1 = mk(0.0, 0.0);
+            if (act) {
+                if (e < E / 2) {
+                    const int k = t + TPL * e;
+                    x0 = from_f2(h0[k]);
+                    x1 = from_f2(h1[k]);
+                    if (k == 0) { x0.y = 0.0; x1.y = 0.0; }
+                } else if (e == E / 2 && t == 0) {
+                    x0 = mk((double)a.nyq[r0].x, 0.0);
+                    x1 = mk((double)a.nyq[r1].x, 0.0);
+                } else {
+                    const int kk = N - (t + TPL * e);
+                    x0 = conj(from_f2(h0[kk]));
+                    x1 = conj(from_f2(h1[kk]));
+                }
+            }
+            z[e] = mk(x0.x - x1.y, x0.y + x1.x);
+        }
+    }
+    fft<N, E, 1>(z, t, lay, lds, a.tw);
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        float2 *p = a.psi + (half ? r1 : r0) * N;
+        dc v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+        fft<N, E, 1>(v, t, lay, lds, a.tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const dc ps = scl(v[e], inv_n);
+            const double rho = norm2(ps);
+            const double phi = (half ? z[e].y : z[e].x) * inv_n;
+            if constexpr (ENERGY) {
+                acc0 += rho * phi;
+                acc1 += rho * rho;
+            } else {
+                double s, c;
+                sincos_fp64(fma(a.g, rho, phi) * a.dz, &s, &c);
+                v[e] = cmul(ps, mk(c, s));
+            }
+        }
+        if constexpr (!ENERGY) {
+            fft<N, E, -1>(v, t, lay, lds, a.tw);
+            if (act) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) p[t + TPL * e] = to_f2(v[e]);
+            }
+        }
+    }
+    if constexpr (ENERGY) {
+        const double b0 = block_sum<NT>(acc0, sh);
+        const double b1 = block_sum<NT>(acc1, sh);
+        if (tid == 0) {
+            a.partials[2 * blockIdx.x] = b0;
+            a.partials[2 * blockIdx.x + 1] = b1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- LM passes
+// A segment is a set of lines along the pass axis: line lg of outer slice o
+// starts at ptr + o*os + lg*ls, its points are es apart.  For the multiplier
+// stages the two other wavenumber indices of line (o, lg) are
+//   c1 = c1f + lg*c1l + o*c1o,  c2 = c2f + lg*c2l + o*c2o.
+struct Seg {
+    float2 *ptr;
+    long long es, ls, os;
+    int nlines, ngroups, ntiles;
+    int c1f, c1l, c1o, c2f, c2l, c2o;
+};
+
+enum LmMode { LM_FWD = 0, LM_INV = 1, LM_KIN = 2, LM_KERN = 3, LM_KIN_ENERGY = 4 };
+
+struct LmArgs {
+    Seg s0, s1;              // s1 used for tiles >= s0.ntiles (ntiles 0 if absent)
+    const double2 *tw;       // twiddles of the pass length
+    double scale;            // output scale (FWD / INV) or multiplier scale
+    const double2 *kin1, *kin2, *kinp;   // kinetic factor tables exp(-i a k_d^2 h)
+    const double *k2_1, *k2_2, *k2_p;    // k_d^2 tables
+    double cN, cY, mY2, c0;              // kernel K(k)
+    double *partials;                    // per-block FP64 partials (energy)
+    // fused end-of-step reduction in block 0 (after the density pass)
+    const double *mass_parts;
+    int nmass;
+    int reduce;
+    double k0_dz_over_P;
+    DevState *st;
+};
+
+template <int N, int E, int LINES, int MODE>
+__global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
+{
+    constexpr int TPL = N / E, NT = LINES * TPL;
+    __shared__ float2 lds[LINES * N];
+    __shared__ double sh[NT / 64 + 1];
+    const int tid = threadIdx.x, l = tid % LINES, t = tid / LINES;
+    int tile = blockIdx.x;
+    const bool second = tile >= a.s0.ntiles;
+    const Seg sg = second ? a.s1 : a.s0;
+    if (second) tile -= a.s0.ntiles;
+    const int o = tile / sg.ngroups, grp = tile - o * sg.ngroups;
+    const int lg = grp * LINES + l;
+    const bool act = lg < sg.nlines;
+    float2 *base = sg.ptr + (long long)o * sg.os + (long long)lg * sg.ls;
+    const LmLayout<LINES> lay{l};
+    dc v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        v[e] = act ? from_f2(base[(long long)(t + TPL * e) * sg.es]) : mk(0.0, 0.0);
+
+    if constexpr (MODE == LM_FWD || MODE == LM_INV) {
+        fft<N, E, MODE == LM_FWD ? -1 : 1>(v, t, lay, lds, a.tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = scl(v[e], a.scale);
+    } else {
+        // inactive lanes (lg >= nlines) read table entry 0, never past the end
+        const int c1 = act ? sg.c1f + lg * sg.c1l + o * sg.c1o : 0;
+        const int c2 = act ? sg.c2f + lg * sg.c2l + o * sg.c2o : 0;
+        fft<N, E, -1>(v, t, lay, lds, a.tw);
+        if constexpr (MODE == LM_KIN) {
+            const dc m12 = scl(cmul(from_d2(a.kin1[c1]), from_d2(a.kin2[c2])), a.scale);
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = cmul(v[e], cmul(m12, from_d2(a.kinp[t + TPL * e])));
+        } else if constexpr (MODE == LM_KERN) {
+            const double q12 = a.k2_1[c1] + a.k2_2[c2];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double k2 = q12 + a.k2_p[t + TPL * e];
+                double K = a.c0;
+                if (a.cY != 0.0) K += a.cY / (k2 + a.mY2);
+                if (k2 > 0.0) K += a.cN / k2;
+                else K = 0.0;   // k = 0: the uniform potential is a global phase
+                v[e] = scl(v[e], K * a.scale);
+            }
+        } else if constexpr (MODE == LM_KIN_ENERGY) {
+            const double q12 = a.k2_1[c1] + a.k2_2[c2];
+            double acc = 0.0;
+            if (act) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc += (q12 + a.k2_p[t + TPL * e]) * norm2(v[e]);
+            }
+            const double bs = block_sum<NT>(acc, sh);
+            if (tid == 0) a.partials[blockIdx.x] = bs;
+        }
+        if constexpr (MODE != LM_KIN_ENERGY) fft<N, E, 1>(v, t, lay, lds, a.tw);
+    }
+    if constexpr (MODE != LM_KIN_ENERGY) {
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) base[(long long)(t + TPL * e) * sg.es] = to_f2(v[e]);
+        }
+    }
+    if (a.reduce && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = tid; i < a.nmass; i += NT) s += a.mass_parts[i];
+        s = block_sum<NT>(s, sh);
+        if (tid == 0) {
+            a.st->mass_sum = s;
+            a.st->theta += a.k0_dz_over_P * s;
+            a.st->steps += 1;
+            if (!isfinite(s)) a.st->nonfinite = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- small kernels
+template <int NT>
+__global__ __launch_bounds__(NT) void k_mass(const float2 *__restrict__ psi, long long P, double *partials)
+{
+    __shared__ double sh[NT / 64 + 1];
+    double s = 0.0;
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < P; i += (long long)gridDim.x * NT) {
+        const float2 v = psi[i];
+        s += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    s = block_sum<NT>(s, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// dst = src * exp(i theta) in FP64, to complex64 or complex128
+template <bool C128>
+__global__ void k_readout(const float2 *__restrict__ src, void *dst, long long P, const DevState *st)
+{
+    double s, c;
+    sincos(st->theta, &s, &c);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < P;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float2 v = src[i];
+        const double re = c * v.x - s * v.y, im = s * v.x + c * v.y;
+        if constexpr (C128) ((double2 *)dst)[i] = make_double2(re, im);
+        else ((float2 *)dst)[i] = make_float2((float)re, (float)im);
+    }
+}
+
+__global__ void k_from_c128(const double2 *__restrict__ src, float2 *dst, long long P)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < P;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double2 v = src[i];
+        dst[i] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+__global__ void k_reset_state(DevState *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->theta = 0.0;
+        st->mass_sum = 0.0;
+        st->steps = 0;
+        st->nonfinite = 0;
+        st->pad = 0;
+    }
+}
+
+}  // namespace gsn

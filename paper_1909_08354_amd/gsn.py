@@ -1,0 +1,231 @@
+"""Thin ctypes binding of the C ABI in include/gsn.h (libgsn.so).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of
+libgsn.so.  PyTorch provides device memory (the caller-owned workspace and
+device-side psi buffers) and the stream.  If the library is missing, loading
+fails loudly; there is no CPU fallback.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgsn.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "gsn.h")
+
+GSN_OK, GSN_EINVAL, GSN_EUNSUPPORTED, GSN_EWORKSPACE, GSN_EHIP, GSN_ENONFINITE, GSN_ESTATE = range(7)
+GSN_C64, GSN_C128 = 0, 1
+STATUS_NAMES = {0: "GSN_OK", 1: "GSN_EINVAL", 2: "GSN_EUNSUPPORTED", 3: "GSN_EWORKSPACE",
+                4: "GSN_EHIP", 5: "GSN_ENONFINITE", 6: "GSN_ESTATE"}
+
+
+class GsnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class gsn_kernel(ctypes.Structure):
+    _fields_ = [("c_newton", ctypes.c_double), ("c_yukawa", ctypes.c_double),
+                ("m_yukawa", ctypes.c_double), ("c_contact", ctypes.c_double)]
+
+
+_lib = None
+vp = ctypes.c_void_p
+i32p = ctypes.POINTER(ctypes.c_int32)
+dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGNATURES = {
+    "gsn_workspace_bytes": [ctypes.c_int, i32p, ctypes.POINTER(ctypes.c_size_t)],
+    "gsn_create": [ctypes.POINTER(vp), ctypes.c_int, i32p, dp, vp, ctypes.c_size_t, vp],
+    "gsn_destroy": [vp],
+    "gsn_set_kernel": [vp, ctypes.POINTER(gsn_kernel)],
+    "gsn_set_coefficients": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "gsn_set_psi": [vp, vp, ctypes.c_int, ctypes.c_int],
+    "gsn_step": [vp, ctypes.c_int64],
+    "gsn_sync": [vp],
+    "gsn_get_psi": [vp, vp, ctypes.c_int, ctypes.c_int],
+    "gsn_mass": [vp, dp],
+    "gsn_energy": [vp, dp],
+    "gsn_phase": [vp, dp, ctypes.POINTER(ctypes.c_int64)],
+    "gsn_profile_passes": [vp, ctypes.c_int64, dp, ctypes.c_int],
+}
+
+
+def header_functions(path=HEADER):
+    """Names of every function declared in include/gsn.h."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsn_[a-z0-9_]+)\s*\(", txt)))
+
+
+def load(path=LIB_PATH):
+    """Load libgsn.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    for name, args in _SIGNATURES.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.gsn_last_error.argtypes = []
+    lib.gsn_last_error.restype = ctypes.c_char_p
+    lib.gsn_pass_count.argtypes = [vp]
+    lib.gsn_pass_count.restype = ctypes.c_int
+    lib.gsn_pass_name.argtypes = [vp, ctypes.c_int]
+    lib.gsn_pass_name.restype = ctypes.c_char_p
+    lib.gsn_pass_bytes_per_point.argtypes = [vp, ctypes.c_int]
+    lib.gsn_pass_bytes_per_point.restype = ctypes.c_double
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != GSN_OK:
+        raise GsnError(status, load().gsn_last_error().decode())
+    return status
+
+
+def _i32(seq):
+    return (ctypes.c_int32 * len(seq))(*[int(v) for v in seq])
+
+
+def _f64(seq):
+    return (ctypes.c_double * len(seq))(*[float(v) for v in seq])
+
+
+def gsn_workspace_bytes(n):
+    out = ctypes.c_size_t(0)
+    check(load().gsn_workspace_bytes(len(n), _i32(n), ctypes.byref(out)))
+    return out.value
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible to torch")
+    return torch
+
+
+def _ptr_and_flag(x):
+    """(pointer, on_device, dtype code, keepalive) for a numpy array or torch tensor."""
+    if isinstance(x, np.ndarray):
+        if x.dtype == np.complex64:
+            code = GSN_C64
+        elif x.dtype == np.complex128:
+            code = GSN_C128
+        else:
+            raise TypeError("psi must be complex64 or complex128")
+        x = np.ascontiguousarray(x)
+        return x.ctypes.data, 0, code, x
+    torch = _torch()
+    if x.dtype == torch.complex64:
+        code = GSN_C64
+    elif x.dtype == torch.complex128:
+        code = GSN_C128
+    else:
+        raise TypeError("psi must be complex64 or complex128")
+    x = x.contiguous()
+    return x.data_ptr(), 1 if x.is_cuda else 0, code, x
+
+
+class Grid:
+    """One periodic 2-D or 3-D grid on the current HIP device (gsn_create)."""
+
+    def __init__(self, n, L, stream=None):
+        torch = _torch()
+        lib = load()
+        self.n = tuple(int(v) for v in n)
+        self.L = tuple(float(v) for v in L)
+        self.P = int(np.prod(self.n))
+        nbytes = gsn_workspace_bytes(self.n)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = vp()
+        check(lib.gsn_create(ctypes.byref(h), len(self.n), _i32(self.n), _f64(self.L),
+                             vp(aligned), nbytes, vp(stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            check(load().gsn_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_kernel(self, c_newton=0.0, c_yukawa=0.0, m_yukawa=0.0, c_contact=0.0):
+        k = gsn_kernel(c_newton, c_yukawa, m_yukawa, c_contact)
+        check(load().gsn_set_kernel(self.h, ctypes.byref(k)))
+
+    def set_coefficients(self, a, g, dz):
+        check(load().gsn_set_coefficients(self.h, a, g, dz))
+
+    def set_psi(self, psi):
+        ptr, dev, code, keep = _ptr_and_flag(psi)
+        if tuple(keep.shape) != self.n:
+            raise ValueError(f"psi shape {tuple(keep.shape)} != grid {self.n}")
+        check(load().gsn_set_psi(self.h, vp(ptr), dev, code))
+        self._keep = keep
+
+    def step(self, nsteps):
+        check(load().gsn_step(self.h, int(nsteps)))
+
+    def sync(self):
+        check(load().gsn_sync(self.h))
+
+    def get_psi(self, dtype=np.complex128, device=False):
+        if device:
+            torch = _torch()
+            tdt = torch.complex128 if dtype == np.complex128 else torch.complex64
+            out = torch.empty(self.n, dtype=tdt, device="cuda")
+            check(load().gsn_get_psi(self.h, vp(out.data_ptr()), 1,
+                                     GSN_C128 if dtype == np.complex128 else GSN_C64))
+            return out
+        out = np.empty(self.n, dtype=dtype)
+        check(load().gsn_get_psi(self.h, vp(out.ctypes.data), 0,
+                                 GSN_C128 if dtype == np.complex128 else GSN_C64))
+        return out
+
+    def mass(self):
+        m = ctypes.c_double(0)
+        check(load().gsn_mass(self.h, ctypes.byref(m)))
+        return m.value
+
+    def energy(self):
+        e = (ctypes.c_double * 4)()
+        check(load().gsn_energy(self.h, e))
+        return {"total": e[0], "kinetic": e[1], "local": e[2], "nonlocal": e[3]}
+
+    def phase(self):
+        th = ctypes.c_double(0)
+        st = ctypes.c_int64(0)
+        check(load().gsn_phase(self.h, ctypes.byref(th), ctypes.byref(st)))
+        return th.value, st.value
+
+    def pass_names(self):
+        lib = load()
+        return [lib.gsn_pass_name(self.h, i).decode() for i in range(lib.gsn_pass_count(self.h))]
+
+    def pass_bytes_per_point(self):
+        lib = load()
+        return [lib.gsn_pass_bytes_per_point(self.h, i) for i in range(lib.gsn_pass_count(self.h))]
+
+    def profile_passes(self, nsteps):
+        lib = load()
+        npass = lib.gsn_pass_count(self.h)
+        ms = (ctypes.c_double * npass)()
+        check(lib.gsn_profile_passes(self.h, int(nsteps), ms, npass))
+        return dict(zip(self.pass_names(), list(ms)))

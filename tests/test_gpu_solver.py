@@ -1,0 +1,201 @@
+"""GPU parity of the HIP split-step solver against the FP64 oracle.
+
+Tolerances: the HIP path stores psi, rho and phi as complex64/float and does
+all arithmetic in FP64, so each pass adds one FP32 rounding (relative 6e-8 per
+value, unbiased).  Over n steps the relative L2 error grows like
+~1e-7 * sqrt(passes) and the norm drift stays ~1e-8; the targets asserted are
+the solver's stated bar: relative L2 <= 1e-5 and |M/M0 - 1| <= 1e-6 after up
+to 1000 steps (both against the FP64 oracle).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1909_08354_amd import gsn, inputs
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+NORM_DRIFT = 1e-6
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(psi0, L, kern, a, g, dz, steps, chunks=None):
+    grid = gsn.Grid(psi0.shape, L)
+    grid.set_kernel(*kern)
+    grid.set_coefficients(a, g, dz)
+    grid.set_psi(inputs.to_c64(psi0))
+    for c in (chunks or [steps]):
+        grid.step(c)
+    out = grid.get_psi(np.complex128)
+    return out, grid
+
+
+def lump_state(n, seed, count=2):
+    rng = np.random.default_rng(seed)
+    L = tuple(float(v) for v in n)
+    w = max(1.5, min(n) / 6.0)
+    cs, ws, vs = inputs.random_lumps(rng, n, L, count, (w, 1.5 * w))
+    psi = inputs.lumps(n, L, cs, ws, vs)
+    return inputs.phase_noise(psi, 1e-3, seed + 1), L
+
+
+def test_set_get_roundtrip_all_paths():
+    import torch
+    for n in [(64, 32), (8, 16, 32)]:
+        say("roundtrip", n)
+        psi, L = lump_state(n, 5)
+        ref = inputs.to_c64(psi)
+        grid = gsn.Grid(n, L)
+        for src in (ref, ref.astype(np.complex128), torch.from_numpy(ref).cuda(),
+                    torch.from_numpy(ref.astype(np.complex128)).cuda()):
+            grid.set_psi(src)
+            assert np.array_equal(grid.get_psi(np.complex64), ref)
+            assert np.array_equal(grid.get_psi(np.complex128), ref.astype(np.complex128))
+            assert np.array_equal(grid.get_psi(np.complex64, device=True).cpu().numpy(), ref)
+        grid.set_coefficients(0.5, 0.0, 1e-3)
+        grid.step(0)
+        assert np.array_equal(grid.get_psi(np.complex64), ref)
+
+
+@pytest.mark.parametrize("a", [0.5, 0.7])
+def test_free_gaussian_closed_form(a):
+    n, L, w, t, steps = (128, 128), (40.0, 40.0), 3.0, 0.2, 7
+    say("free gaussian a =", a)
+    psi0 = inputs.gaussian(n, L, w)
+    out, _ = run_gpu(psi0, L, (0, 0, 0, 0), a, 0.0, t / steps, steps)
+    y = inputs.axis_coords(n[0], L[0])[:, None]
+    x = inputs.axis_coords(n[1], L[1])[None, :]
+    exact = (1 + 4j * a * t / w ** 2) ** -1.0 * np.exp(-(x * x + y * y) / (w * w + 4j * a * t))
+    assert orc.rel_l2(out, exact) < 2e-6
+
+
+@pytest.mark.parametrize("n", [(16, 32), (8, 16, 32)])
+def test_plane_wave_global_phase(n):
+    """rho uniform: the whole potential is K(0)|A|^2, carried by the FP64
+    global phase; psi(t) = A exp(i(k0.x - a|k0|^2 t + (g + K(0))|A|^2 t))."""
+    say("plane wave", n)
+    L = tuple(10.0 + 2 * i for i in range(len(n)))
+    kern, a, g, A, dz, steps = (1.0, 0.7, 0.5, 0.25), 0.5, 1.3, 0.8 + 0.3j, 0.01, 37
+    coords = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    k0 = [2 * np.pi * m / Ld for m, Ld in zip((3, -2, 1), L)]
+    ph = sum(k * c for k, c in zip(k0, coords))
+    psi0 = A * np.exp(1j * ph)
+    out, grid = run_gpu(psi0, L, kern, a, g, dz, steps)
+    t = dz * steps
+    K0 = kern[1] / kern[2] ** 2 + kern[3]
+    exact = psi0 * np.exp(1j * (-a * sum(k * k for k in k0) * t + (g + K0) * abs(A) ** 2 * t))
+    assert orc.rel_l2(out, exact) < 2e-6
+    theta, nst = grid.phase()
+    assert nst == steps
+    assert abs(theta - K0 * abs(A) ** 2 * t) < 1e-6 * abs(K0 * abs(A) ** 2 * t)
+
+
+SHAPES = [(8, 8), (16, 64), (64, 16), (32, 128), (256, 8), (8, 256), (8, 2048), (2048, 8),
+          (8, 8, 8), (16, 8, 32), (32, 16, 8), (8, 32, 64), (64, 32, 16), (16, 16, 1024)]
+
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_parity_shapes(n):
+    say("parity", n)
+    psi0, L = lump_state(n, 11 + len(n))
+    kern, a, g, dz, steps = (1.0, 0.3, 0.4, 0.05), 0.5, -0.5, 2e-3, 20
+    out, grid = run_gpu(psi0, L, kern, a, g, dz, steps)
+    ref = orc.evolve(inputs.as_oracle_input(psi0), L, kern, a, g, dz, steps)
+    assert orc.rel_l2(ref, inputs.as_oracle_input(psi0)) > 1e-6   # the state moved
+    assert orc.rel_l2(out, ref) < REL_L2
+    m_ref = orc.observables(ref, L, kern, a, g)["mass"]
+    assert abs(grid.mass() / m_ref - 1) < NORM_DRIFT
+
+
+@pytest.mark.parametrize("steps", [200, 1000])
+def test_gaussian_128_kerr_newton(steps):
+    """128^2 on [-20,20)^2, Gaussian w=3 with 1e-3 phase noise, g=-0.5,
+    Newtonian kernel, dz=1e-3 (the small 2-D workload)."""
+    say("gaussian 128^2 steps", steps)
+    w = inputs.WORKLOADS["gsn2d_128_kerr_newton"]
+    psi0 = inputs.gaussian_2d_128()
+    out, grid = run_gpu(psi0, w["L"], w["kern"], w["a"], w["g"], w["dz"], steps)
+    ref = orc.evolve(inputs.as_oracle_input(psi0), w["L"], w["kern"], w["a"], w["g"], w["dz"], steps)
+    rel = orc.rel_l2(out, ref)
+    m0 = orc.observables(inputs.as_oracle_input(psi0), w["L"], w["kern"], w["a"], w["g"])["mass"]
+    drift = abs(grid.mass() / m0 - 1)
+    say(f"  rel_l2={rel:.3e} norm_drift={drift:.3e}")
+    assert rel < REL_L2
+    assert drift < NORM_DRIFT
+
+
+@pytest.mark.parametrize("n", [(64, 128), (16, 32, 64)])
+def test_energy_and_mass_match_oracle(n):
+    say("energy", n)
+    psi0, L = lump_state(n, 21)
+    kern, a, g, dz = (1.0, 0.3, 0.4, 0.05), 0.5, -0.5, 2e-3
+    out, grid = run_gpu(psi0, L, kern, a, g, dz, 10)
+    ref = orc.observables(out, L, kern, a, g)   # energy of the very same state
+    e = grid.energy()
+    scale = abs(ref["kinetic"]) + abs(ref["local"]) + abs(ref["nonlocal"])
+    for key in ("kinetic", "local", "nonlocal", "total"):
+        assert abs(e[key] - ref[key]) < 1e-6 * scale, (key, e[key], ref[key])
+    assert abs(grid.mass() / ref["mass"] - 1) < 1e-12
+
+
+def test_chunked_steps_match_single_run():
+    n = (64, 64)
+    psi0, L = lump_state(n, 31)
+    args = (L, (1.0, 0.2, 0.3, 0.0), 0.5, -0.5, 2e-3)
+    a, _ = run_gpu(psi0, *args, 50)
+    b, _ = run_gpu(psi0, *args, 50, chunks=[30, 20])
+    assert orc.rel_l2(a, b) < 1e-6
+
+
+def test_bitwise_determinism():
+    n = (32, 64, 16)
+    psi0, L = lump_state(n, 41)
+    args = (L, (1.0, 0.2, 0.3, 0.0), 0.5, -0.5, 2e-3, 15)
+    a, ga = run_gpu(psi0, *args)
+    b, gb = run_gpu(psi0, *args)
+    assert np.array_equal(a, b)
+    assert ga.energy() == gb.energy()
+
+
+def test_time_reversal():
+    n = (64, 32)
+    psi0, L = lump_state(n, 51)
+    grid = gsn.Grid(n, L)
+    grid.set_kernel(1.0, 0.2, 0.3, 0.0)
+    grid.set_coefficients(0.5, -0.5, 2e-3)
+    grid.set_psi(inputs.to_c64(psi0))
+    grid.step(100)
+    mid = grid.get_psi()
+    grid.set_coefficients(0.5, -0.5, -2e-3)
+    grid.step(100)
+    back = grid.get_psi()
+    assert orc.rel_l2(mid, psi0) > 1e-4
+    assert orc.rel_l2(back, inputs.as_oracle_input(psi0)) < 1e-5
+
+
+def test_nonfinite_is_reported():
+    n = (16, 16)
+    psi0, L = lump_state(n, 61)
+    psi0 = inputs.to_c64(psi0)
+    psi0[3, 4] = np.nan
+    grid = gsn.Grid(n, L)
+    grid.set_kernel(1.0)
+    grid.set_coefficients(0.5, -0.5, 1e-3)
+    grid.set_psi(psi0)
+    grid.step(2)
+    with pytest.raises(gsn.GsnError) as ei:
+        grid.sync()
+    assert ei.value.status == gsn.GSN_ENONFINITE
+
+
+def test_step_before_setup_is_rejected():
+    grid = gsn.Grid((16, 16), (1.0, 1.0))
+    with pytest.raises(gsn.GsnError) as ei:
+        grid.step(1)
+    assert ei.value.status == gsn.GSN_ESTATE
