@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Benchmark of the split-step Schroedinger-Newton hot path on one MI355X.
+
+Workload: one 3-D instance, 256^3 periodic grid (dx = 1), complex64 storage
+with FP64 arithmetic, centred Gaussian cloud of waist 6, Newtonian kernel plus
+a Yukawa correction 0.3/(k^2 + 0.1^2), g = 0, dz = 5e-4.  A "step" is one
+symmetric split step over the whole grid (8 HBM passes).  The timed region is
+one gsn_step(K) call with psi already resident in HBM.
+
+Prints ONE JSON line.  Besides throughput it reports the dominant pass's
+roofline (algorithmic bytes / HIP-event duration on the solver's stream), the
+norm and energy drift of the timed run, and the FP64 CPU oracle timed on a
+bounded sample on this host (a baseline, not a target).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+WORKLOAD = "gsn3d_256_newton_yukawa"
+
+
+def csrc_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1909_08354_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_pass):
+    """HBM bytes per launch from committed rocprofv3 counter runs, only when they
+    were taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+    except ValueError:
+        return None
+    if rec.get("csrc_hash") != csrc_hash():
+        return None
+    return rec.get("passes", {}).get(kernel_pass)
+
+
+def cpu_baseline(w, psi0_c128, budget_s=30.0):
+    """Oracle step rate on this host: time evolve(1) and evolve(3) on the same
+    input; the difference is two merged steps without table setup."""
+    from oracle import oracle as orc
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    args = (w["L"], w["kern"], w["a"], w["g"], w["dz"])
+    t0 = time.perf_counter()
+    orc.evolve(psi0_c128, *args, 1, nthreads=nthreads)
+    t1 = time.perf_counter()
+    if (t1 - t0) * 3 > budget_s:
+        per_step = t1 - t0
+        sample = "1 merged step incl. table setup (budget)"
+    else:
+        orc.evolve(psi0_c128, *args, 3, nthreads=nthreads)
+        t2 = time.perf_counter()
+        per_step = max((t2 - t1) - (t1 - t0), 1e-9) / 2
+        sample = "2 merged 256^3 steps (evolve(3) - evolve(1))"
+    P = int(np.prod(w["n"]))
+    return {"value": P / per_step, "unit": "grid-pt updates/s", "cores": nthreads,
+            "kind": "oracle", "sample": sample}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--autotune-iters", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the solver is single-GPU; multi-GPU sharding is design-only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1909_08354_amd import gsn, inputs
+
+    w = inputs.WORKLOADS[WORKLOAD]
+    n, L = w["n"], w["L"]
+    P = int(np.prod(n))
+    psi0 = inputs.gaussian_3d_256()
+    grid = gsn.Grid(n, L)
+    grid.set_kernel(*w["kern"])
+    grid.set_coefficients(w["a"], w["g"], w["dz"])
+    grid.set_psi(torch.from_numpy(inputs.to_c64(psi0)).cuda())
+    schedule = grid.autotune(args.autotune_iters) if args.autotune_iters > 0 else grid.schedule()
+    m0 = grid.mass()
+    e0 = grid.energy()
+
+    if args.warmup:
+        grid.step(args.warmup)
+    grid.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    grid.sync()
+    elapsed = t1 - t0
+    m1 = grid.mass()
+    e1 = grid.energy()
+    value = P * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # per-pass durations with HIP events on the solver's stream
+    prof = grid.profile_passes(args.profile_steps)
+    bpp = dict(zip(grid.pass_names(), grid.pass_bytes_per_point()))
+    steady = {k: v for k, v in prof.items() if k not in ("x_entry_fft", "x_exit_ifft")}
+    dom = max(steady, key=steady.get)
+    achieved = bpp[dom] * P / (steady[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
+    step_bytes = sum(bpp[k] for k in steady) * P
+    scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
+
+    line = {
+        "metric": "split-step grid-pt updates/s + %HBM peak; batched/corrected speedup at fixed err",
+        "value": value,
+        "unit": "grid-pt updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "storage": "c64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "grid": list(n), "dz": w["dz"],
+                   "kernel": {"c_newton": w["kern"][0], "c_yukawa": w["kern"][1],
+                              "m_yukawa": w["kern"][2]},
+                   "g": w["g"], "ic": w["ic"], "passes_per_step": len(steady)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bpp[dom] * P,
+                     "avg_launch_ms": steady[dom]},
+        "model_step_gbps": step_bytes / (ms_per_step * 1e-3) / 1e9,
+        "model_step_hbm_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "pass_ms": {k: round(v, 5) for k, v in prof.items()},
+        "schedule": schedule,
+        "norm_drift": abs(m1 / m0 - 1),
+        "energy_drift": abs(e1["total"] - e0["total"]) / scale,
+        "batched_speedup": None,
+        "corrected_speedup": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, inputs.as_oracle_input(psi0))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

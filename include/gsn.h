@@ -129,6 +129,21 @@ const char *gsn_pass_name(gsn_grid grid, int i);
 /* Model HBM bytes per point that pass i moves (reads + writes). */
 double gsn_pass_bytes_per_point(gsn_grid grid, int i);
 
+/* FFT schedule variants.  Every pass can run with 16 or 8 points per thread
+   (variant 0 "e16", variant 1 "e8"); this changes the Stockham radix plan,
+   the tile shape and the LDS footprint, never the result beyond rounding.
+   gsn_autotune times every variant of every pass of this grid (iters launches
+   each, on a scratch copy of psi: the state is not modified) and keeps the
+   fastest.  If the environment variable GSN_AUTOTUNE_CACHE names a file,
+   choices are read from it (key: GPU architecture, grid shape, pass) and new
+   ones appended.  Synchronising. */
+int gsn_variant_count(void);
+const char *gsn_variant_name(int v);
+gsn_status gsn_autotune(gsn_grid grid, int iters);
+/* Current variant of every pass (npass >= gsn_pass_count entries). */
+gsn_status gsn_get_schedule(gsn_grid grid, int *variants, int npass);
+gsn_status gsn_set_schedule(gsn_grid grid, const int *variants, int npass);
+
 /* Human-readable message for the last failure on this thread. */
 const char *gsn_last_error(void);
 

@@ -7,7 +7,11 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -51,16 +55,23 @@ struct NKernels {
     int em_threads() const { return em_lines * TPL; }
 };
 
-template <int N> struct Cfg {
-    static constexpr int E = N < 16 ? N : 16;
+// Schedule variants: E points per thread (16 or 8) for every pass kind.  The
+// EM tile holds 256/TPL rows (at most 64); the LM tile holds LINES columns
+// chosen so that a tile moves >= 64-byte contiguous segments per row.
+constexpr int kNumVariants = 2;
+static const char *kVariantNames[kNumVariants] = {"e16", "e8"};
+
+template <int N, int V> struct Cfg {
+    static constexpr int E0 = V == 0 ? 16 : 8;
+    static constexpr int E = N < E0 ? N : E0;
     static constexpr int TPL = N / E;
-    static constexpr int LM_LINES = N <= 64 ? 64 : N == 128 ? 32 : N <= 512 ? 16 : N == 1024 ? 8 : 4;
+    static constexpr int LM_LINES = TPL <= 4 ? 64 : TPL <= 8 ? 32 : TPL <= 32 ? 16 : TPL <= 64 ? 8 : 4;
     static constexpr int EM_LINES = (256 / TPL) > 64 ? 64 : (256 / TPL) < 1 ? 1 : 256 / TPL;
 };
 
-template <int N> static NKernels make_kernels()
+template <int N, int V> static NKernels make_kernels()
 {
-    using C = Cfg<N>;
+    using C = Cfg<N, V>;
     constexpr int E = C::E, LL = C::LM_LINES, EL = C::EM_LINES;
     NKernels k;
     k.E = E;
@@ -80,18 +91,25 @@ template <int N> static NKernels make_kernels()
     return k;
 }
 
-static const NKernels *kernels_for(int N)
+template <int N> static const NKernels *variant_table(int v)
 {
+    static const NKernels k[kNumVariants] = {make_kernels<N, 0>(), make_kernels<N, 1>()};
+    return &k[v];
+}
+
+static const NKernels *kernels_for(int N, int v = 0)
+{
+    if (v < 0 || v >= kNumVariants) v = 0;
     switch (N) {
-    case 8: { static const NKernels k = make_kernels<8>(); return &k; }
-    case 16: { static const NKernels k = make_kernels<16>(); return &k; }
-    case 32: { static const NKernels k = make_kernels<32>(); return &k; }
-    case 64: { static const NKernels k = make_kernels<64>(); return &k; }
-    case 128: { static const NKernels k = make_kernels<128>(); return &k; }
-    case 256: { static const NKernels k = make_kernels<256>(); return &k; }
-    case 512: { static const NKernels k = make_kernels<512>(); return &k; }
-    case 1024: { static const NKernels k = make_kernels<1024>(); return &k; }
-    case 2048: { static const NKernels k = make_kernels<2048>(); return &k; }
+    case 8: return variant_table<8>(v);
+    case 16: return variant_table<16>(v);
+    case 32: return variant_table<32>(v);
+    case 64: return variant_table<64>(v);
+    case 128: return variant_table<128>(v);
+    case 256: return variant_table<256>(v);
+    case 512: return variant_table<512>(v);
+    case 1024: return variant_table<1024>(v);
+    case 2048: return variant_table<2048>(v);
     default: return nullptr;
     }
 }
@@ -131,7 +149,8 @@ struct gsn_grid_ {
     double2 *kinF[3], *kinH[3];
     double *k2_unit;
     double2 *kin_unit;
-    const NKernels *kx, *ky, *kz;
+    int var[P_COUNT];          // schedule variant per pass
+    int max_density_blocks;    // over all variants (sizes the partial arrays)
     // parameters
     double a, g, dz;
     gsn_kernel kern;
@@ -172,13 +191,18 @@ static Layout compute_layout(int ndim, const int32_t n[])
     const int Nx = n[ndim - 1], Ny = n[ndim - 2], Nz = ndim == 3 ? n[0] : 1;
     const long long P = (long long)Nx * Ny * Nz;
     const long long rows = P / Nx;
-    const NKernels *kx = kernels_for(Nx), *ky = kernels_for(Ny), *kz = ndim == 3 ? kernels_for(Nz) : nullptr;
-    L.density_blocks = (int)((rows / 2 + kx->em_lines - 1) / kx->em_lines);
-    L.em_blocks = (int)((rows + kx->em_lines - 1) / kx->em_lines);
-    // largest LM grid of an energy pass: kinetic-energy pass over the last axis
+    // partial arrays are sized for the largest grid over all schedule variants
     int lmb = 0;
-    if (ndim == 3) lmb = lm_tiles_main(Nx, kz->lm_lines, Ny);
-    else lmb = lm_tiles_main(Nx, ky->lm_lines, 1);
+    for (int v = 0; v < kNumVariants; ++v) {
+        const NKernels *kx = kernels_for(Nx, v), *kl = kernels_for(ndim == 3 ? Nz : Ny, v);
+        const int db = (int)((rows / 2 + kx->em_lines - 1) / kx->em_lines);
+        if (db > L.density_blocks) L.density_blocks = db;
+        const int eb = (int)((rows + kx->em_lines - 1) / kx->em_lines);
+        if (eb > L.em_blocks) L.em_blocks = eb;
+        // kinetic-energy pass over the last axis
+        const int t = ndim == 3 ? lm_tiles_main(Nx, kl->lm_lines, Ny) : lm_tiles_main(Nx, kl->lm_lines, 1);
+        if (t > lmb) lmb = t;
+    }
     L.lm_blocks_max = lmb;
     size_t off = 0;
     L.psi = off; off = align256(off + 8ull * P);
@@ -293,6 +317,10 @@ static void build_schedule(gsn_grid g)
     const int X = nd - 1, Y = nd - 2, Z = 0;   // table indices by axis
     const long long rows = g->P / Nx;
     const int H = Nx / 2;
+    auto KX = [&](int pass) { return kernels_for(Nx, g->var[pass]); };
+    g->density_blocks = (int)((rows / 2 + KX(P_DENSITY)->em_lines - 1) / KX(P_DENSITY)->em_lines);
+    auto KY = [&](int pass) { return kernels_for(Ny, g->var[pass]); };
+    auto KZ = [&](int pass) { return kernels_for(Nz, g->var[pass]); };
     g->entry.clear(); g->kin_half.clear(); g->kin_full.clear(); g->nonlin.clear();
     g->exit_.clear(); g->energy_rho.clear(); g->energy_kin.clear();
 
@@ -301,16 +329,16 @@ static void build_schedule(gsn_grid g)
         EmArgs a = em_base(g, g->psi);
         a.nlines = (int)rows;
         a.scale = 1.0;
-        g->entry.push_back(em_launch(g->kx->em_fwd, g->kx, a, P_ENTRY));
+        g->entry.push_back(em_launch(KX(P_ENTRY)->em_fwd, KX(P_ENTRY), a, P_ENTRY));
         a.scale = 1.0 / Nx;
-        g->exit_.push_back(em_launch(g->kx->em_inv, g->kx, a, P_EXIT));
+        g->exit_.push_back(em_launch(KX(P_EXIT)->em_inv, KX(P_EXIT), a, P_EXIT));
     }
     // kinetic sub-steps (psi, full grid)
     for (int half = 0; half < 2; ++half) {
         std::vector<Launch> &dst = half ? g->kin_half : g->kin_full;
         double2 *const *kin = half ? g->kinH : g->kinF;
         if (nd == 3) {
-            const NKernels *ky = g->ky, *kz = g->kz;
+            const NKernels *ky = KY(P_Y_FWD_PSI), *kz = KZ(P_KINETIC), *ky2 = KY(P_Y_INV_PSI);
             LmArgs a = lm_base(g, g->tw[Y], 1.0);
             a.s0 = make_seg(g->psi, Nx, 1, (long long)Ny * Nx, Nx, Nz, ky->lm_lines);
             dst.push_back(lm_launch(ky->lm_fwd, ky, a, P_Y_FWD_PSI));
@@ -323,10 +351,10 @@ static void build_schedule(gsn_grid g)
             b.kinp = kin[Z];
             dst.push_back(lm_launch(kz->lm_kin, kz, b, P_KINETIC));
             LmArgs c = lm_base(g, g->tw[Y], 1.0);
-            c.s0 = a.s0;
-            dst.push_back(lm_launch(ky->lm_inv, ky, c, P_Y_INV_PSI));
+            c.s0 = make_seg(g->psi, Nx, 1, (long long)Ny * Nx, Nx, Nz, ky2->lm_lines);
+            dst.push_back(lm_launch(ky2->lm_inv, ky2, c, P_Y_INV_PSI));
         } else {
-            const NKernels *ky = g->ky;
+            const NKernels *ky = KY(P_KINETIC);
             LmArgs b = lm_base(g, g->tw[Y], 1.0 / (double)Ny);
             b.s0 = make_seg(g->psi, Nx, 1, 0, Nx, 1, ky->lm_lines);
             b.s0.c1l = 1;
@@ -343,9 +371,9 @@ static void build_schedule(gsn_grid g)
         EmArgs d = em_base(g, src);
         d.nlines = (int)(rows / 2);
         d.partials = g->mass_parts;
-        dst.push_back(em_launch(g->kx->density, g->kx, d, P_DENSITY));
+        dst.push_back(em_launch(KX(P_DENSITY)->density, KX(P_DENSITY), d, P_DENSITY));
         if (nd == 3) {
-            const NKernels *ky = g->ky, *kz = g->kz;
+            const NKernels *ky = KY(P_Y_FWD_RHO), *kz = KZ(P_KERNEL), *ky2 = KY(P_Y_INV_PHI);
             LmArgs e = lm_base(g, g->tw[Y], 1.0);
             e.s0 = make_seg(g->half, H, 1, (long long)Ny * H, H, Nz, ky->lm_lines);
             e.s1 = make_seg(g->nyq, 1, Ny, 0, Nz, 1, ky->lm_lines);
@@ -372,11 +400,11 @@ static void build_schedule(gsn_grid g)
             f.c0 = g->kern.c_contact;
             dst.push_back(lm_launch(kz->lm_kern, kz, f, P_KERNEL));
             LmArgs gg = lm_base(g, g->tw[Y], 1.0);
-            gg.s0 = e.s0;
-            gg.s1 = e.s1;
-            dst.push_back(lm_launch(ky->lm_inv, ky, gg, P_Y_INV_PHI));
+            gg.s0 = make_seg(g->half, H, 1, (long long)Ny * H, H, Nz, ky2->lm_lines);
+            gg.s1 = make_seg(g->nyq, 1, Ny, 0, Nz, 1, ky2->lm_lines);
+            dst.push_back(lm_launch(ky2->lm_inv, ky2, gg, P_Y_INV_PHI));
         } else {
-            const NKernels *ky = g->ky;
+            const NKernels *ky = KY(P_KERNEL);
             LmArgs f = lm_base(g, g->tw[Y], 1.0 / (double)Ny);
             f.s0 = make_seg(g->half, H, 1, 0, H, 1, ky->lm_lines);
             f.s0.c1l = 1;
@@ -401,13 +429,13 @@ static void build_schedule(gsn_grid g)
         h.g = g->g;
         h.dz = g->dz;
         h.partials = g->epart;
-        dst.push_back(em_launch(energy ? g->kx->phase_energy : g->kx->phase, g->kx, h, P_PHASE));
+        dst.push_back(em_launch(energy ? KX(P_PHASE)->phase_energy : KX(P_PHASE)->phase, KX(P_PHASE), h, P_PHASE));
     }
     // kinetic energy: F_y (3-D) then the last-axis forward FFT with sum |k|^2 |psi_hat|^2
     {
-        const int ep_off = 2 * g->density_blocks;
+        const int ep_off = 2 * g->max_density_blocks;
         if (nd == 3) {
-            const NKernels *ky = g->ky, *kz = g->kz;
+            const NKernels *ky = KY(P_Y_FWD_PSI), *kz = KZ(P_KINETIC);
             LmArgs a = lm_base(g, g->tw[Y], 1.0);
             a.s0 = make_seg(g->scratch, Nx, 1, (long long)Ny * Nx, Nx, Nz, ky->lm_lines);
             g->energy_kin.push_back(lm_launch(ky->lm_fwd, ky, a, P_Y_FWD_PSI));
@@ -421,7 +449,7 @@ static void build_schedule(gsn_grid g)
             b.partials = g->epart + ep_off;
             g->energy_kin.push_back(lm_launch(kz->lm_kin_energy, kz, b, P_KINETIC));
         } else {
-            const NKernels *ky = g->ky;
+            const NKernels *ky = KY(P_KINETIC);
             LmArgs b = lm_base(g, g->tw[Y], 1.0);
             b.s0 = make_seg(g->scratch, Nx, 1, 0, Nx, 1, ky->lm_lines);
             b.s0.c1l = 1;
@@ -532,10 +560,8 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
     g->Nz = ndim == 3 ? n[0] : 1;
     g->P = (long long)g->Nx * g->Ny * g->Nz;
     g->stream = (hipStream_t)hip_stream;
-    g->kx = kernels_for(g->Nx);
-    g->ky = kernels_for(g->Ny);
-    g->kz = ndim == 3 ? kernels_for(g->Nz) : nullptr;
-    g->density_blocks = lay.density_blocks;
+    for (int i = 0; i < P_COUNT; ++i) g->var[i] = 0;
+    g->max_density_blocks = lay.density_blocks;
     g->a = 0.5;
     g->g = 0.0;
     g->dz = 0.0;
@@ -782,7 +808,7 @@ extern "C" gsn_status gsn_energy(gsn_grid g, double e[4])
     if ((s = sum_device(g, g->mass_parts, g->density_blocks, 1, 0, &rho_sum))) return s;
     if ((s = sum_device(g, g->epart, nphase, 2, 0, &rho_phi))) return s;
     if ((s = sum_device(g, g->epart, nphase, 2, 1, &rho2))) return s;
-    if ((s = sum_device(g, g->epart + 2 * g->density_blocks, nkin, 1, 0, &k2sum))) return s;
+    if ((s = sum_device(g, g->epart + 2 * g->max_density_blocks, nkin, 1, 0, &k2sum))) return s;
     const double dV = cell_volume(g), P = (double)g->P, K0 = kernel_k0(g->kern);
     const double ekin = g->a * dV / P * k2sum;
     const double eloc = -0.5 * g->g * dV * rho2;
@@ -848,4 +874,144 @@ extern "C" gsn_status gsn_profile_passes(gsn_grid g, int64_t nsteps, double *ms,
     for (auto &e : ev) hipEventDestroy(e);
     for (int i = 0; i < P_COUNT; ++i) ms[i] = cnt[i] ? tot[i] / cnt[i] : 0.0;
     return gsn_sync(g);
+}
+
+// ------------------------------------------------------------------ schedule autotuning
+extern "C" int gsn_variant_count(void) { return kNumVariants; }
+
+extern "C" const char *gsn_variant_name(int v)
+{
+    return (v >= 0 && v < kNumVariants) ? kVariantNames[v] : "";
+}
+
+extern "C" gsn_status gsn_get_schedule(gsn_grid g, int *variants, int npass)
+{
+    if (!g || !variants || npass < P_COUNT) return fail(GSN_EINVAL, "bad schedule arguments");
+    for (int i = 0; i < P_COUNT; ++i) variants[i] = g->var[i];
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_set_schedule(gsn_grid g, const int *variants, int npass)
+{
+    if (!g || !variants || npass < P_COUNT) return fail(GSN_EINVAL, "bad schedule arguments");
+    for (int i = 0; i < P_COUNT; ++i)
+        if (variants[i] < 0 || variants[i] >= kNumVariants) return fail(GSN_EINVAL, "unknown schedule variant");
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    for (int i = 0; i < P_COUNT; ++i) g->var[i] = variants[i];
+    build_schedule(g);
+    return GSN_OK;
+}
+
+// The launch of pass p in the current step schedule, redirected from psi to the
+// scratch buffer and with the end-of-step reduction switched off, so timing it
+// leaves the solver state untouched.
+static bool timing_launch(gsn_grid g, int p, Launch *out)
+{
+    const std::vector<Launch> *lists[] = {&g->entry, &g->kin_full, &g->nonlin, &g->exit_};
+    for (const std::vector<Launch> *lst : lists)
+        for (const Launch &L : *lst)
+            if (L.pass == p) {
+                *out = L;
+                if (out->em) {
+                    if (out->ea.psi == g->psi) out->ea.psi = g->scratch;
+                } else {
+                    if (out->la.s0.ptr == g->psi) out->la.s0.ptr = g->scratch;
+                    out->la.reduce = 0;
+                }
+                return true;
+            }
+    return false;
+}
+
+static gsn_status time_launch(gsn_grid g, const Launch &L, int iters, double *ms)
+{
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    for (int i = 0; i < 2; ++i) HIP_TRY(launch(L, g->stream));
+    HIP_TRY(hipEventRecord(a, g->stream));
+    for (int i = 0; i < iters; ++i) HIP_TRY(launch(L, g->stream));
+    HIP_TRY(hipEventRecord(b, g->stream));
+    HIP_TRY(hipEventSynchronize(b));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, a, b));
+    HIP_TRY(hipEventDestroy(a));
+    HIP_TRY(hipEventDestroy(b));
+    *ms = (double)t / iters;
+    return GSN_OK;
+}
+
+static std::string cache_key(gsn_grid g, int p)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    std::ostringstream k;
+    k << arch << " " << g->ndim << "d";
+    for (int d = 0; d < g->ndim; ++d) k << (d ? "x" : " ") << g->n[d];
+    k << " " << kPassNames[p];
+    return k.str();
+}
+
+static std::map<std::string, int> read_cache(const char *path)
+{
+    std::map<std::string, int> m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t sp = line.rfind(' ');
+        if (sp == std::string::npos) continue;
+        const int v = std::atoi(line.c_str() + sp + 1);
+        if (v >= 0 && v < kNumVariants) m[line.substr(0, sp)] = v;
+    }
+    return m;
+}
+
+extern "C" gsn_status gsn_autotune(gsn_grid g, int iters)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (iters < 1 || iters > 10000) return fail(GSN_EINVAL, "iters must be in [1, 10000]");
+    HIP_TRY(hipSetDevice(g->device));
+    // realistic data for timing: a copy of psi (or zeros before psi is set)
+    if (g->have_psi)
+        HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, 8ull * g->P, hipMemcpyDeviceToDevice, g->stream));
+    else
+        HIP_TRY(hipMemsetAsync(g->scratch, 0, 8ull * g->P, g->stream));
+    const char *cpath = std::getenv("GSN_AUTOTUNE_CACHE");
+    std::map<std::string, int> cache;
+    if (cpath && *cpath) cache = read_cache(cpath);
+    std::vector<std::string> fresh;
+    for (int p = 0; p < P_COUNT; ++p) {
+        const std::string key = cache_key(g, p);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            g->var[p] = it->second;
+            continue;
+        }
+        int best = g->var[p];
+        double best_ms = 1e300;
+        bool present = false;
+        for (int v = 0; v < kNumVariants; ++v) {
+            g->var[p] = v;
+            build_schedule(g);
+            Launch L;
+            if (!timing_launch(g, p, &L)) break;
+            present = true;
+            double ms = 0.0;
+            gsn_status s = time_launch(g, L, iters, &ms);
+            if (s) return s;
+            if (ms < best_ms) { best_ms = ms; best = v; }
+        }
+        g->var[p] = best;
+        if (present) fresh.push_back(key + " " + std::to_string(best));
+    }
+    build_schedule(g);
+    if (cpath && *cpath && !fresh.empty()) {
+        std::ofstream f(cpath, std::ios::app);
+        for (const std::string &l : fresh) f << l << "\n";
+    }
+    return GSN_OK;
 }

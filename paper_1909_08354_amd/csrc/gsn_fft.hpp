@@ -168,14 +168,30 @@ template <int N, int E> struct Plan {
 // LDS addressing of one line.  Element-major lines (contiguous axis): one pad
 // per 16 points plus a line pitch of 16 (mod 32) float2.  Line-major tiles
 // (strided axes): position-major with the LINES lines of a tile adjacent.
-template <int N> struct EmLayout {
+// Synchronisation of an LDS exchange: a block barrier, or (when every line of
+// the tile lives inside one wavefront) a wavefront-scope fence plus a wave
+// barrier, which orders the wave's own LDS writes before its reads.
+template <bool WAVE> __device__ __forceinline__ void exchange_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <int N, int E = 16> struct EmLayout {
     static constexpr int S0 = N + N / 16;
     static constexpr int PITCH = (S0 % 32 == 0) ? S0 + 16 : S0;
     static constexpr int BYTES_PER_LINE = PITCH * 8;
+    static constexpr bool WAVE_LOCAL = (N / E) <= 64;   // a row within one wavefront
     int base;
     __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 4); }
 };
 template <int LINES> struct LmLayout {
+    static constexpr bool WAVE_LOCAL = false;
     int l;
     __device__ __forceinline__ int operator()(int pos) const { return pos * LINES + l; }
 };
@@ -219,10 +235,10 @@ __device__ __forceinline__ void fft_stages(dc (&v)[E], int t, const Lay &lay, fl
             }
         }
         if constexpr (!LAST) {
-            __syncthreads();
+            exchange_sync<Lay::WAVE_LOCAL>();
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = from_f2(lds[lay(t + TPL * e)]);
-            __syncthreads();
+            exchange_sync<Lay::WAVE_LOCAL>();
             fft_stages<N, E, S, ST + 1>(v, t, lay, lds, tw);
         }
     }

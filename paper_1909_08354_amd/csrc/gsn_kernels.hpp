@@ -52,11 +52,11 @@ template <int N, int E, int LINES, int S>
 __global__ __launch_bounds__(LINES *(N / E)) void k_em_fft(EmArgs a)
 {
     constexpr int TPL = N / E;
-    __shared__ float2 lds[LINES * EmLayout<N>::PITCH];
+    __shared__ float2 lds[LINES * EmLayout<N, E>::PITCH];
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
     const int row = blockIdx.x * LINES + l;
     const bool act = row < a.nlines;
-    const EmLayout<N> lay{l * EmLayout<N>::PITCH};
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     dc v[E];
     float2 *p = a.psi + (long long)row * N;
 #pragma unroll
@@ -75,35 +75,37 @@ template <int N, int E, int LINES>
 __global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
-    __shared__ float2 lds[LINES * EmLayout<N>::PITCH];
+    __shared__ float2 lds[LINES * EmLayout<N, E>::PITCH];
     __shared__ double sh[NT / 64 + 1];
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
     const int pair = blockIdx.x * LINES + l;
     const bool act = pair < a.nlines;
-    const EmLayout<N> lay{l * EmLayout<N>::PITCH};
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     const long long r0 = 2LL * pair, r1 = r0 + 1;
     const double inv_n = 1.0 / N;
-    dc v[E], w[E];
+    dc v[E];
+    double rho0[E];
     const float2 *p0 = a.psi + r0 * N, *p1 = a.psi + r1 * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p0[t + TPL * e]) : mk(0.0, 0.0);
     fft<N, E, 1>(v, t, lay, lds, a.tw);
 #pragma unroll
-    for (int e = 0; e < E; ++e) w[e] = act ? from_f2(p1[t + TPL * e]) : mk(0.0, 0.0);
-    fft<N, E, 1>(w, t, lay, lds, a.tw);
+    for (int e = 0; e < E; ++e) rho0[e] = norm2(v[e]) * (inv_n * inv_n);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p1[t + TPL * e]) : mk(0.0, 0.0);
+    fft<N, E, 1>(v, t, lay, lds, a.tw);
     double msum = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const double rho0 = norm2(v[e]) * (inv_n * inv_n);
-        const double rho1 = norm2(w[e]) * (inv_n * inv_n);
-        msum += rho0 + rho1;
-        v[e] = mk(rho0, rho1);
+        const double rho1 = norm2(v[e]) * (inv_n * inv_n);
+        msum += rho0[e] + rho1;
+        v[e] = mk(rho0[e], rho1);
     }
     fft<N, E, -1>(v, t, lay, lds, a.tw);
     // exchange Z so that bin k can see bin N-k
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[lay(t + TPL * e)] = to_f2(v[e]);
-    __syncthreads();
+    exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
     if (act) {
         float2 *h0 = a.half + r0 * (N / 2), *h1 = a.half + r1 * (N / 2);
 #pragma unroll
@@ -130,18 +132,61 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
 // phi_0 + i phi_1.  Then per row: psi = G_x psi_x / N, multiply by
 // exp(i (g |psi|^2 + phi) dz) in FP64, F_x, store.  ENERGY: instead of the
 // phase, accumulate sum rho*phi and sum rho^2 and store nothing.
-__device__ __forceinline__ void sincos_fp64(double th, double *s, double *c) { sincos(th, s, c); }
+// sin and cos in FP64: reduce th = k (pi/2) + r with |r| <= pi/4 (pi/2 split in
+// three parts, Cody-Waite), then the Taylor series of sin (to r^17) and cos (to
+// r^18), whose truncation error is below 1e-19 on |r| <= pi/4.  The reduction
+// is exact while |k| < 2^20 (|th| < 1.6e6); beyond that the absolute error
+// grows like |th| * 1e-16, which only matters for phases no step should reach.
+__host__ __device__ __forceinline__ void sincos_fp64(double th, double *s, double *c)
+{
+    constexpr double kTwoOverPi = 0.63661977236758134308;
+    // pi/2 = kP1 + kP2 + kP3 (+ 1e-37): kP1 and kP2 carry 33 significant bits
+    // each, so kf * kP1 and kf * kP2 are exact for |kf| < 2^20
+    constexpr double kP1 = 1.5707963267341256e+00;
+    constexpr double kP2 = 6.077100506303966e-11;
+    constexpr double kP3 = 2.0222662487959506e-21;
+    const double kf = rint(th * kTwoOverPi);
+    double r = fma(-kf, kP1, th);
+    r = fma(-kf, kP2, r);
+    r = fma(-kf, kP3, r);
+    const double r2 = r * r;
+    // sin r = r (1 - r^2/3! + r^4/5! - ... - r^16/17!)
+    double ps = -1.0 / 355687428096000.0;                 // -1/17!
+    ps = fma(ps, r2, 1.0 / 1307674368000.0);               //  1/15!
+    ps = fma(ps, r2, -1.0 / 6227020800.0);                 // -1/13!
+    ps = fma(ps, r2, 1.0 / 39916800.0);                    //  1/11!
+    ps = fma(ps, r2, -1.0 / 362880.0);                     // -1/9!
+    ps = fma(ps, r2, 1.0 / 5040.0);                        //  1/7!
+    ps = fma(ps, r2, -1.0 / 120.0);
+    ps = fma(ps, r2, 1.0 / 6.0);
+    const double sr = fma(-r * r2, ps, r);
+    // cos r = 1 - r^2/2! + r^4/4! - ... + r^18/18!
+    double pc = 1.0 / 6402373705728000.0;                  //  1/18!
+    pc = fma(pc, r2, -1.0 / 20922789888000.0);             // -1/16!
+    pc = fma(pc, r2, 1.0 / 87178291200.0);                 //  1/14!
+    pc = fma(pc, r2, -1.0 / 479001600.0);                  // -1/12!
+    pc = fma(pc, r2, 1.0 / 3628800.0);                     //  1/10!
+    pc = fma(pc, r2, -1.0 / 40320.0);                      // -1/8!
+    pc = fma(pc, r2, 1.0 / 720.0);                         //  1/6!
+    pc = fma(pc, r2, -1.0 / 24.0);                         // -1/4!
+    pc = fma(pc, r2, 0.5);                                 //  1/2!
+    const double cr = fma(-r2, pc, 1.0);
+    const int q = (int)(kf - 4.0 * floor(kf * 0.25));   // k mod 4 in [0, 4)
+    const double ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
+    *s = (q & 2) ? -ss : ss;
+    *c = ((q + 1) & 2) ? -cc : cc;
+}
 
 template <int N, int E, int LINES, bool ENERGY>
 __global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
-    __shared__ float2 lds[LINES * EmLayout<N>::PITCH];
+    __shared__ float2 lds[LINES * EmLayout<N, E>::PITCH];
     __shared__ double sh[NT / 64 + 1];
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
     const int pair = blockIdx.x * LINES + l;
     const bool act = pair < a.nlines;
-    const EmLayout<N> lay{l * EmLayout<N>::PITCH};
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     const long long r0 = 2LL * pair, r1 = r0 + 1;
     const double inv_n = 1.0 / N;
     dc z[E];
@@ -169,8 +214,15 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
         }
     }
     fft<N, E, 1>(z, t, lay, lds, a.tw);
-    double acc0 = 0.0, acc1 = 0.0;
+    // phi of both rows, kept as float (it is complex64-stored data already)
+    float phi0[E], phi1[E];
 #pragma unroll
+    for (int e = 0; e < E; ++e) {
+        phi0[e] = (float)(z[e].x * inv_n);
+        phi1[e] = (float)(z[e].y * inv_n);
+    }
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll 1
     for (int half = 0; half < 2; ++half) {
         float2 *p = a.psi + (half ? r1 : r0) * N;
         dc v[E];
@@ -181,7 +233,7 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
         for (int e = 0; e < E; ++e) {
             const dc ps = scl(v[e], inv_n);
             const double rho = norm2(ps);
-            const double phi = (half ? z[e].y : z[e].x) * inv_n;
+            const double phi = (double)(half ? phi1[e] : phi0[e]);
             if constexpr (ENERGY) {
                 acc0 += rho * phi;
                 acc1 += rho * rho;
@@ -274,14 +326,20 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = cmul(v[e], cmul(m12, from_d2(a.kinp[t + TPL * e])));
         } else if constexpr (MODE == LM_KERN) {
+            // K = c0 + (cN (k2 + m^2) + cY k2) / (k2 (k2 + m^2)), one reciprocal
+            // (hardware estimate refined by two Newton steps to FP64 accuracy)
             const double q12 = a.k2_1[c1] + a.k2_2[c2];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const double k2 = q12 + a.k2_p[t + TPL * e];
-                double K = a.c0;
-                if (a.cY != 0.0) K += a.cY / (k2 + a.mY2);
-                if (k2 > 0.0) K += a.cN / k2;
-                else K = 0.0;   // k = 0: the uniform potential is a global phase
+                const double km = k2 + a.mY2;
+                const double num = fma(a.cN, km, a.cY * k2);
+                const double den = k2 * km;
+                double r = __builtin_amdgcn_rcp(den);
+                r = fma(r, fma(-den, r, 1.0), r);
+                r = fma(r, fma(-den, r, 1.0), r);
+                // k = 0: the uniform potential is a global phase, not part of phi
+                const double K = k2 > 0.0 ? fma(num, r, a.c0) : 0.0;
                 v[e] = scl(v[e], K * a.scale);
             }
         } else if constexpr (MODE == LM_KIN_ENERGY) {

@@ -51,6 +51,9 @@ _SIGNATURES = {
     "gsn_energy": [vp, dp],
     "gsn_phase": [vp, dp, ctypes.POINTER(ctypes.c_int64)],
     "gsn_profile_passes": [vp, ctypes.c_int64, dp, ctypes.c_int],
+    "gsn_autotune": [vp, ctypes.c_int],
+    "gsn_get_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
+    "gsn_set_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
 }
 
 
@@ -81,6 +84,10 @@ def load(path=LIB_PATH):
     lib.gsn_pass_name.restype = ctypes.c_char_p
     lib.gsn_pass_bytes_per_point.argtypes = [vp, ctypes.c_int]
     lib.gsn_pass_bytes_per_point.restype = ctypes.c_double
+    lib.gsn_variant_count.argtypes = []
+    lib.gsn_variant_count.restype = ctypes.c_int
+    lib.gsn_variant_name.argtypes = [ctypes.c_int]
+    lib.gsn_variant_name.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -222,6 +229,26 @@ class Grid:
     def pass_bytes_per_point(self):
         lib = load()
         return [lib.gsn_pass_bytes_per_point(self.h, i) for i in range(lib.gsn_pass_count(self.h))]
+
+    def autotune(self, iters=20):
+        check(load().gsn_autotune(self.h, int(iters)))
+        return self.schedule()
+
+    def schedule(self):
+        lib = load()
+        npass = lib.gsn_pass_count(self.h)
+        v = (ctypes.c_int * npass)()
+        check(lib.gsn_get_schedule(self.h, v, npass))
+        return dict(zip(self.pass_names(), [lib.gsn_variant_name(i).decode() for i in v]))
+
+    def set_schedule(self, variants):
+        """variants: one variant index per pass, or a single index for all."""
+        lib = load()
+        npass = lib.gsn_pass_count(self.h)
+        if isinstance(variants, int):
+            variants = [variants] * npass
+        v = (ctypes.c_int * npass)(*variants)
+        check(lib.gsn_set_schedule(self.h, v, npass))
 
     def profile_passes(self, nsteps):
         lib = load()
