@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--autotune-iters", type=int, default=10)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -91,6 +93,12 @@ def main():
     import torch
     from paper_1909_08354_amd import gsn, inputs
 
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.WORKLOADS[WORKLOAD]
     n, L = w["n"], w["L"]
     P = int(np.prod(n))
@@ -154,6 +162,7 @@ def main():
         "model_step_hbm_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
         "pass_ms": {k: round(v, 5) for k, v in prof.items()},
         "schedule": schedule,
+        "nonlinear_mode": grid.nonlinear_mode(),
         "norm_drift": abs(m1 / m0 - 1),
         "energy_drift": abs(e1["total"] - e0["total"]) / scale,
         "batched_speedup": None,

@@ -140,6 +140,14 @@ double gsn_pass_bytes_per_point(gsn_grid grid, int i);
 int gsn_variant_count(void);
 const char *gsn_variant_name(int v);
 gsn_status gsn_autotune(gsn_grid grid, int iters);
+/* Nonlinear sub-step layout.  Mode 0: the phase pass recomputes psi from its
+   x-spectrum (the density pass writes only the rho half spectrum).  Mode 1:
+   the density pass also writes real-space psi in place, and the phase pass
+   reads it instead of transforming again (+8 bytes per point, two fewer FFTs
+   per pair of rows).  Both give the same result up to rounding; gsn_autotune
+   picks one by timing whole sub-steps. */
+gsn_status gsn_set_nonlinear_mode(gsn_grid grid, int mode);
+gsn_status gsn_get_nonlinear_mode(gsn_grid grid, int *mode);
 /* Current variant of every pass (npass >= gsn_pass_count entries). */
 gsn_status gsn_get_schedule(gsn_grid grid, int *variants, int npass);
 gsn_status gsn_set_schedule(gsn_grid grid, const int *variants, int npass);

@@ -44,7 +44,9 @@ struct NKernels {
     void (*em_fwd)(EmArgs);
     void (*em_inv)(EmArgs);
     void (*density)(EmArgs);
+    void (*density_store)(EmArgs);
     void (*phase)(EmArgs);
+    void (*phase_real)(EmArgs);
     void (*phase_energy)(EmArgs);
     void (*lm_fwd)(LmArgs);
     void (*lm_inv)(LmArgs);
@@ -80,9 +82,11 @@ template <int N, int V> static NKernels make_kernels()
     k.em_lines = EL;
     k.em_fwd = k_em_fft<N, E, EL, -1>;
     k.em_inv = k_em_fft<N, E, EL, 1>;
-    k.density = k_density<N, E, EL>;
-    k.phase = k_phase<N, E, EL, false>;
-    k.phase_energy = k_phase<N, E, EL, true>;
+    k.density = k_density<N, E, EL, false>;
+    k.density_store = k_density<N, E, EL, true>;
+    k.phase = k_phase<N, E, EL, false, false>;
+    k.phase_real = k_phase<N, E, EL, false, true>;
+    k.phase_energy = k_phase<N, E, EL, true, false>;
     k.lm_fwd = k_lm<N, E, LL, LM_FWD>;
     k.lm_inv = k_lm<N, E, LL, LM_INV>;
     k.lm_kin = k_lm<N, E, LL, LM_KIN>;
@@ -150,6 +154,7 @@ struct gsn_grid_ {
     double *k2_unit;
     double2 *kin_unit;
     int var[P_COUNT];          // schedule variant per pass
+    int store_psi;             // 1: density pass stores real-space psi for the phase pass
     int max_density_blocks;    // over all variants (sizes the partial arrays)
     // parameters
     double a, g, dz;
@@ -371,7 +376,9 @@ static void build_schedule(gsn_grid g)
         EmArgs d = em_base(g, src);
         d.nlines = (int)(rows / 2);
         d.partials = g->mass_parts;
-        dst.push_back(em_launch(KX(P_DENSITY)->density, KX(P_DENSITY), d, P_DENSITY));
+        const bool store = g->store_psi && !energy;
+        dst.push_back(em_launch(store ? KX(P_DENSITY)->density_store : KX(P_DENSITY)->density,
+                                KX(P_DENSITY), d, P_DENSITY));
         if (nd == 3) {
             const NKernels *ky = KY(P_Y_FWD_RHO), *kz = KZ(P_KERNEL), *ky2 = KY(P_Y_INV_PHI);
             LmArgs e = lm_base(g, g->tw[Y], 1.0);
@@ -429,7 +436,9 @@ static void build_schedule(gsn_grid g)
         h.g = g->g;
         h.dz = g->dz;
         h.partials = g->epart;
-        dst.push_back(em_launch(energy ? KX(P_PHASE)->phase_energy : KX(P_PHASE)->phase, KX(P_PHASE), h, P_PHASE));
+        dst.push_back(em_launch(energy ? KX(P_PHASE)->phase_energy
+                                       : store ? KX(P_PHASE)->phase_real : KX(P_PHASE)->phase,
+                                KX(P_PHASE), h, P_PHASE));
     }
     // kinetic energy: F_y (3-D) then the last-axis forward FFT with sum |k|^2 |psi_hat|^2
     {
@@ -561,6 +570,7 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
     g->P = (long long)g->Nx * g->Ny * g->Nz;
     g->stream = (hipStream_t)hip_stream;
     for (int i = 0; i < P_COUNT; ++i) g->var[i] = 0;
+    g->store_psi = 0;
     g->max_density_blocks = lay.density_blocks;
     g->a = 0.5;
     g->g = 0.0;
@@ -834,7 +844,7 @@ extern "C" double gsn_pass_bytes_per_point(gsn_grid g, int i)
     // reads + writes of complex64 psi (8 B), half spectrum (4 B per point)
     switch (i) {
     case P_ENTRY: case P_EXIT: case P_Y_FWD_PSI: case P_Y_INV_PSI: case P_KINETIC: return 16.0;
-    case P_DENSITY: return 12.0;
+    case P_DENSITY: return g->store_psi ? 20.0 : 12.0;
     case P_Y_FWD_RHO: case P_KERNEL: case P_Y_INV_PHI: return 8.0;
     case P_PHASE: return 20.0;
     default: return 0.0;
@@ -942,6 +952,37 @@ static gsn_status time_launch(gsn_grid g, const Launch &L, int iters, double *ms
     return GSN_OK;
 }
 
+// Time the nonlinear sub-step (density .. phase) on the scratch buffer.
+static gsn_status time_nonlinear(gsn_grid g, int iters, double *ms)
+{
+    std::vector<Launch> seq;
+    for (const Launch &L0 : g->nonlin) {
+        Launch L = L0;
+        if (L.em) {
+            if (L.ea.psi == g->psi) L.ea.psi = g->scratch;
+        } else {
+            if (L.la.s0.ptr == g->psi) L.la.s0.ptr = g->scratch;
+            L.la.reduce = 0;
+        }
+        seq.push_back(L);
+    }
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    for (const Launch &L : seq) HIP_TRY(launch(L, g->stream));
+    HIP_TRY(hipEventRecord(a, g->stream));
+    for (int i = 0; i < iters; ++i)
+        for (const Launch &L : seq) HIP_TRY(launch(L, g->stream));
+    HIP_TRY(hipEventRecord(b, g->stream));
+    HIP_TRY(hipEventSynchronize(b));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, a, b));
+    HIP_TRY(hipEventDestroy(a));
+    HIP_TRY(hipEventDestroy(b));
+    *ms = (double)t / iters;
+    return GSN_OK;
+}
+
 static std::string cache_key(gsn_grid g, int p)
 {
     hipDeviceProp_t prop;
@@ -952,7 +993,7 @@ static std::string cache_key(gsn_grid g, int p)
     std::ostringstream k;
     k << arch << " " << g->ndim << "d";
     for (int d = 0; d < g->ndim; ++d) k << (d ? "x" : " ") << g->n[d];
-    k << " " << kPassNames[p];
+    k << " " << (p < P_COUNT ? kPassNames[p] : "nonlinear_mode");
     return k.str();
 }
 
@@ -984,6 +1025,7 @@ extern "C" gsn_status gsn_autotune(gsn_grid g, int iters)
     std::map<std::string, int> cache;
     if (cpath && *cpath) cache = read_cache(cpath);
     std::vector<std::string> fresh;
+    g->store_psi = 0;
     for (int p = 0; p < P_COUNT; ++p) {
         const std::string key = cache_key(g, p);
         auto it = cache.find(key);
@@ -1008,10 +1050,62 @@ extern "C" gsn_status gsn_autotune(gsn_grid g, int iters)
         g->var[p] = best;
         if (present) fresh.push_back(key + " " + std::to_string(best));
     }
+    // nonlinear sub-step: recompute psi in the phase pass (mode 0), or store
+    // real-space psi in the density pass (mode 1, with its own variants of the
+    // two x passes); whole sub-steps are timed because the two passes change
+    // together
+    const std::string mkey = cache_key(g, P_COUNT);
+    auto mit = cache.find(mkey);
+    if (mit != cache.end()) {
+        g->store_psi = mit->second ? 1 : 0;
+    } else {
+        build_schedule(g);
+        double best_ms = 0.0;
+        gsn_status s = time_nonlinear(g, iters, &best_ms);
+        if (s) return s;
+        const int d0 = g->var[P_DENSITY], h0 = g->var[P_PHASE];
+        int bd = d0, bh = h0, bm = 0;
+        g->store_psi = 1;
+        for (int vd = 0; vd < kNumVariants; ++vd)
+            for (int vh = 0; vh < kNumVariants; ++vh) {
+                g->var[P_DENSITY] = vd;
+                g->var[P_PHASE] = vh;
+                build_schedule(g);
+                double ms = 0.0;
+                if ((s = time_nonlinear(g, iters, &ms))) return s;
+                if (ms < best_ms) { best_ms = ms; bd = vd; bh = vh; bm = 1; }
+            }
+        g->store_psi = bm;
+        g->var[P_DENSITY] = bm ? bd : d0;
+        g->var[P_PHASE] = bm ? bh : h0;
+        if (bm) {
+            fresh.push_back(cache_key(g, P_DENSITY) + " " + std::to_string(g->var[P_DENSITY]));
+            fresh.push_back(cache_key(g, P_PHASE) + " " + std::to_string(g->var[P_PHASE]));
+        }
+        fresh.push_back(mkey + " " + std::to_string(bm));
+    }
     build_schedule(g);
     if (cpath && *cpath && !fresh.empty()) {
         std::ofstream f(cpath, std::ios::app);
         for (const std::string &l : fresh) f << l << "\n";
     }
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_set_nonlinear_mode(gsn_grid g, int mode)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (mode != 0 && mode != 1) return fail(GSN_EINVAL, "mode must be 0 or 1");
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->store_psi = mode;
+    build_schedule(g);
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_get_nonlinear_mode(gsn_grid g, int *mode)
+{
+    if (!g || !mode) return fail(GSN_EINVAL, "NULL argument");
+    *mode = g->store_psi;
     return GSN_OK;
 }

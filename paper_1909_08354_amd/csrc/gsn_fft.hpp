@@ -183,12 +183,15 @@ template <bool WAVE> __device__ __forceinline__ void exchange_sync()
 }
 
 template <int N, int E = 16> struct EmLayout {
-    static constexpr int S0 = N + N / 16;
+    // one pad slot per E points: the first-stage writes (E consecutive
+    // positions per lane) then hit distinct banks across a wavefront
+    static constexpr int PAD_SHIFT = E >= 16 ? 4 : E == 8 ? 3 : E == 4 ? 2 : 1;
+    static constexpr int S0 = N + (N >> PAD_SHIFT);
     static constexpr int PITCH = (S0 % 32 == 0) ? S0 + 16 : S0;
     static constexpr int BYTES_PER_LINE = PITCH * 8;
     static constexpr bool WAVE_LOCAL = (N / E) <= 64;   // a row within one wavefront
     int base;
-    __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 4); }
+    __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> PAD_SHIFT); }
 };
 template <int LINES> struct LmLayout {
     static constexpr bool WAVE_LOCAL = false;

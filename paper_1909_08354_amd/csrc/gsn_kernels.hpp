@@ -71,7 +71,10 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_em_fft(EmArgs a)
 // Density pass: psi = G_x psi_x / N for two rows, rho = |psi|^2, FP64 partial
 // of sum rho, then one forward FFT of Z = rho_0 + i rho_1 and the split
 // X_0[k] = (Z[k] + conj Z[N-k]) / 2, X_1[k] = (Z[k] - conj Z[N-k]) / (2i).
-template <int N, int E, int LINES>
+//
+// STORE_PSI: also write psi (real space) back over the two psi_x rows, so the
+// phase pass can skip its two inverse x transforms (+8 bytes per point).
+template <int N, int E, int LINES, bool STORE_PSI>
 __global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
@@ -85,15 +88,27 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
     const double inv_n = 1.0 / N;
     dc v[E];
     double rho0[E];
-    const float2 *p0 = a.psi + r0 * N, *p1 = a.psi + r1 * N;
+    float2 *p0 = a.psi + r0 * N, *p1 = a.psi + r1 * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p0[t + TPL * e]) : mk(0.0, 0.0);
     fft<N, E, 1>(v, t, lay, lds, a.tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) rho0[e] = norm2(v[e]) * (inv_n * inv_n);
+    if constexpr (STORE_PSI) {
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) p0[t + TPL * e] = to_f2(scl(v[e], inv_n));
+        }
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p1[t + TPL * e]) : mk(0.0, 0.0);
     fft<N, E, 1>(v, t, lay, lds, a.tw);
+    if constexpr (STORE_PSI) {
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) p1[t + TPL * e] = to_f2(scl(v[e], inv_n));
+        }
+    }
     double msum = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -177,7 +192,10 @@ __host__ __device__ __forceinline__ void sincos_fp64(double th, double *s, doubl
     *c = ((q + 1) & 2) ? -cc : cc;
 }
 
-template <int N, int E, int LINES, bool ENERGY>
+//
+// REAL_IN: the psi rows already hold psi in real space (written by the density
+// pass with STORE_PSI), so the inverse x transform is skipped.
+template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
 __global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
@@ -228,10 +246,10 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
         dc v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
-        fft<N, E, 1>(v, t, lay, lds, a.tw);
+        if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const dc ps = scl(v[e], inv_n);
+            const dc ps = REAL_IN ? v[e] : scl(v[e], inv_n);
             const double rho = norm2(ps);
             const double phi = (double)(half ? phi1[e] : phi0[e]);
             if constexpr (ENERGY) {

@@ -54,6 +54,8 @@ _SIGNATURES = {
     "gsn_autotune": [vp, ctypes.c_int],
     "gsn_get_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
     "gsn_set_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
+    "gsn_set_nonlinear_mode": [vp, ctypes.c_int],
+    "gsn_get_nonlinear_mode": [vp, ctypes.POINTER(ctypes.c_int)],
 }
 
 
@@ -240,6 +242,14 @@ class Grid:
         v = (ctypes.c_int * npass)()
         check(lib.gsn_get_schedule(self.h, v, npass))
         return dict(zip(self.pass_names(), [lib.gsn_variant_name(i).decode() for i in v]))
+
+    def nonlinear_mode(self):
+        m = ctypes.c_int(0)
+        check(load().gsn_get_nonlinear_mode(self.h, ctypes.byref(m)))
+        return m.value
+
+    def set_nonlinear_mode(self, mode):
+        check(load().gsn_set_nonlinear_mode(self.h, int(mode)))
 
     def set_schedule(self, variants):
         """variants: one variant index per pass, or a single index for all."""
