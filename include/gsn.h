@@ -152,6 +152,41 @@ gsn_status gsn_get_nonlinear_mode(gsn_grid grid, int *mode);
 gsn_status gsn_get_schedule(gsn_grid grid, int *variants, int npass);
 gsn_status gsn_set_schedule(gsn_grid grid, const int *variants, int npass);
 
+/* ---------------------------------------------------------------- batches
+   Many independent 2-D instances of uneven sizes, each with its own kernel
+   K(k), coefficients a, g, dz and box, advanced together (parameter sweeps
+   over the gravity model).  Instances of one shape form a group; each pass of
+   a group is one launch over all its members, and every group's chain of
+   launches is one branch of a single captured hipGraph, so gsn_batch_step is
+   one hipGraphLaunch.  Results equal count independent gsn_grid runs up to
+   rounding.  n and L are count x 2 arrays (C order per instance). */
+typedef struct gsn_batch_ *gsn_batch;
+gsn_status gsn_batch_workspace_bytes(int count, int ndim, const int32_t *n, size_t *bytes);
+/* count in [1, 4096]; ndim must be 2.  Same workspace and stream rules as
+   gsn_create. */
+gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, const int32_t *n, const double *L,
+                            void *d_workspace, size_t bytes, void *hip_stream);
+gsn_status gsn_batch_destroy(gsn_batch batch);
+/* Set instance i's kernel, coefficients and psi (host or device, c64/c128);
+   resets its global phase.  Synchronising. */
+gsn_status gsn_batch_set(gsn_batch batch, int i, const gsn_kernel *kernel, double a_kin, double g_local,
+                         double dz, const void *psi, int src_on_device, int dtype);
+/* Advance every instance by nsteps symmetric steps (same schedule as
+   gsn_step); ordered after earlier work on the creation stream. */
+gsn_status gsn_batch_step(gsn_batch batch, int64_t nsteps);
+gsn_status gsn_batch_sync(gsn_batch batch);
+gsn_status gsn_batch_get(gsn_batch batch, int i, void *dst, int dst_on_device, int dtype);
+/* FP64 mass of every instance into masses[count].  Synchronising. */
+gsn_status gsn_batch_mass(gsn_batch batch, double *masses);
+gsn_status gsn_batch_phase(gsn_batch batch, int i, double *theta, int64_t *steps);
+/* Execution mode: 0 = one captured hipGraph per step count (default),
+   2 = the same grouped launches issued directly. */
+gsn_status gsn_batch_set_mode(gsn_batch batch, int mode);
+/* Variant (0 "e16" / 1 "e8") per pass family {kinetic, density, kernel,
+   phase, x entry/exit} (nfam >= 5) and the nonlinear mode (as
+   gsn_set_nonlinear_mode). */
+gsn_status gsn_batch_set_schedule(gsn_batch batch, const int *variants, int nfam, int nonlinear_mode);
+
 /* Human-readable message for the last failure on this thread. */
 const char *gsn_last_error(void);
 

@@ -1,0 +1,733 @@
+// gsn_batch.hip -- many independent 2-D instances (uneven sizes, per-instance
+// kernel and coefficients) advanced together.
+//
+// Instances with the same shape form a group.  Every pass of a group is ONE
+// grouped launch: block b works on tile (b mod tpi) of instance (b / tpi),
+// whose arguments (buffers, tables, coefficients) sit in a device array, so a
+// pass over 20 instances of 1024^2 is a single launch of thousands of blocks.
+// Groups only depend on themselves, so gsn_batch_step captures each group's
+// launch chain on its own stream branch of one hipGraph and replays the whole
+// run with one hipGraphLaunch.  Mode 1 runs the same tiles from one persistent
+// kernel that pulls (step, pass, instance, tile) work items from a device
+// queue with per-instance completion counters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gsn_host.hpp"
+
+namespace {
+
+// ------------------------------------------------------------------ grouped kernel tables
+struct GKernels {
+    int E, TPL, lm_lines, em_lines;
+    void (*em_fwd)(const EmArgs *, int);
+    void (*em_inv)(const EmArgs *, int);
+    void (*density)(const EmArgs *, int);
+    void (*density_store)(const EmArgs *, int);
+    void (*phase)(const EmArgs *, int);
+    void (*phase_real)(const EmArgs *, int);
+    void (*lm_kin)(const LmArgs *, int);
+    void (*lm_kern)(const LmArgs *, int);
+    int lm_threads() const { return lm_lines * TPL; }
+    int em_threads() const { return em_lines * TPL; }
+};
+
+template <int N, int V> GKernels make_gkernels()
+{
+    using C = Cfg<N, V>;
+    constexpr int E = C::E, LL = C::LM_LINES, EL = C::EM_LINES;
+    GKernels k;
+    k.E = E;
+    k.TPL = C::TPL;
+    k.lm_lines = LL;
+    k.em_lines = EL;
+    k.em_fwd = k_em_fft_g<N, E, EL, -1>;
+    k.em_inv = k_em_fft_g<N, E, EL, 1>;
+    k.density = k_density_g<N, E, EL, false>;
+    k.density_store = k_density_g<N, E, EL, true>;
+    k.phase = k_phase_g<N, E, EL, false>;
+    k.phase_real = k_phase_g<N, E, EL, true>;
+    k.lm_kin = k_lm_g<N, E, LL, LM_KIN>;
+    k.lm_kern = k_lm_g<N, E, LL, LM_KERN>;
+    return k;
+}
+
+template <int N> const GKernels *gvariant(int v)
+{
+    static const GKernels k[kNumVariants] = {make_gkernels<N, 0>(), make_gkernels<N, 1>()};
+    return &k[v];
+}
+
+const GKernels *gkernels_for(int N, int v)
+{
+    if (v < 0 || v >= kNumVariants) v = 0;
+    switch (N) {
+    case 8: return gvariant<8>(v);
+    case 16: return gvariant<16>(v);
+    case 32: return gvariant<32>(v);
+    case 64: return gvariant<64>(v);
+    case 128: return gvariant<128>(v);
+    case 256: return gvariant<256>(v);
+    case 512: return gvariant<512>(v);
+    case 1024: return gvariant<1024>(v);
+    case 2048: return gvariant<2048>(v);
+    default: return nullptr;
+    }
+}
+
+// pass kinds of a 2-D step
+enum BKind { B_ENTRY = 0, B_KIN_HALF, B_KIN_FULL, B_DENSITY, B_KERNEL, B_PHASE, B_EXIT, B_NKIND };
+// schedule variant per pass family: kinetic, density, kernel, phase, entry/exit
+enum BFam { F_KIN = 0, F_DENSITY, F_KERNEL, F_PHASE, F_XFFT, F_NFAM };
+const int kFamOf[B_NKIND] = {F_XFFT, F_KIN, F_KIN, F_DENSITY, F_KERNEL, F_PHASE, F_XFFT};
+
+struct Instance {
+    int ny, nx;
+    double Ly, Lx;
+    long long P;
+    float2 *psi, *half, *nyq;
+    double *mass_parts;
+    DevState *st;
+    double2 *tw_x, *tw_y, *kinF_x, *kinF_y, *kinH_x, *kinH_y;
+    double *k2_x, *k2_y;
+    gsn_kernel kern;
+    double a, g, dz;
+    bool set;
+};
+
+struct GLaunch {
+    const void *fn;
+    dim3 grid, block;
+    const void *args;   // device array of EmArgs or LmArgs
+    int tpi;
+};
+
+struct Group {
+    int ny, nx;
+    std::vector<int> members;
+    GLaunch launch[B_NKIND];
+    void *args_dev[B_NKIND];   // device arrays (inside the workspace)
+};
+
+}  // namespace
+
+struct gsn_batch_ {
+    int count;
+    hipStream_t user;     // the caller's stream (may be the NULL stream)
+    hipStream_t stream;   // internal stream: capture, replay, copies
+    hipEvent_t ev_in, ev_out;
+    int device;
+    std::vector<Instance> inst;
+    std::vector<Group> groups;
+    std::vector<hipStream_t> side;   // one capture branch per group
+    int var[F_NFAM];
+    int store_psi;
+    int mode;   // 0 grouped launches in a graph, 1 persistent kernel
+    char *ws;
+    size_t ws_bytes;
+    float2 *scratch;   // readout staging, 16 * max P bytes
+    double *k2_unit;
+    double2 *kin_unit;
+    // graph cache
+    hipGraphExec_t exec;
+    int64_t exec_steps;
+    bool dirty;
+    // persistent mode state
+    void *pq;   // device work-queue block
+};
+
+namespace {
+
+const int kMaxInstances = 4096;
+
+struct BLayout {
+    std::vector<size_t> inst_off;
+    size_t args_off, scratch_off, unit_off, queue_off, total;
+};
+
+// bytes of one instance's region (buffers, partials, state, tables)
+size_t instance_bytes(int ny, int nx)
+{
+    const long long P = (long long)ny * nx;
+    int db = 0;
+    for (int v = 0; v < kNumVariants; ++v) {
+        const NKernels *k = kernels_for(nx, v);
+        db = std::max(db, (int)((ny / 2 + k->em_lines - 1) / k->em_lines));
+    }
+    size_t b = 0;
+    b += align256(8ull * P);                 // psi
+    b += align256(4ull * P);                 // half spectrum
+    b += align256(8ull * ny);                // Nyquist column
+    b += align256(8ull * db);                // mass partials
+    b += align256(sizeof(DevState));
+    b += 6 * align256(16ull * std::max(nx, ny));   // twiddles and kinetic factors
+    b += 2 * align256(8ull * std::max(nx, ny));    // |k|^2 tables
+    return b;
+}
+
+gsn_status compute_blayout(int count, const int32_t *n, BLayout *L)
+{
+    size_t off = 0;
+    long long maxP = 0;
+    L->inst_off.resize(count);
+    for (int i = 0; i < count; ++i) {
+        L->inst_off[i] = off;
+        off += instance_bytes(n[2 * i], n[2 * i + 1]);
+        maxP = std::max(maxP, (long long)n[2 * i] * n[2 * i + 1]);
+    }
+    L->args_off = off;
+    off += align256((size_t)B_NKIND * count * std::max(sizeof(EmArgs), sizeof(LmArgs)));
+    L->scratch_off = off;
+    off += align256(16ull * maxP);
+    L->unit_off = off;
+    off += 512;
+    L->queue_off = off;
+    off += align256(4096 + 8ull * count + 64ull * count);
+    L->total = off;
+    return GSN_OK;
+}
+
+gsn_status validate_batch(int count, int ndim, const int32_t *n)
+{
+    if (count < 1 || count > kMaxInstances) return fail(GSN_EINVAL, "count must be in [1, 4096]");
+    if (ndim != 2) return fail(GSN_EUNSUPPORTED, "batched instances are 2-D");
+    if (!n) return fail(GSN_EINVAL, "n is NULL");
+    for (int i = 0; i < 2 * count; ++i)
+        if (!is_pow2(n[i]) || n[i] < 8 || n[i] > 2048)
+            return fail(GSN_EUNSUPPORTED, "every extent must be a power of two in [8, 2048]");
+    return GSN_OK;
+}
+
+gsn_status upload_sync(hipStream_t s, void *dst, const void *src, size_t bytes)
+{
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return GSN_OK;
+}
+
+gsn_status upload_instance_tables(gsn_batch b, Instance &I)
+{
+    const int dims[2] = {I.nx, I.ny};
+    const double Ls[2] = {I.Lx, I.Ly};
+    double2 *tw[2] = {I.tw_x, I.tw_y}, *kf[2] = {I.kinF_x, I.kinF_y}, *kh[2] = {I.kinH_x, I.kinH_y};
+    double *k2[2] = {I.k2_x, I.k2_y};
+    for (int d = 0; d < 2; ++d) {
+        const int N = dims[d];
+        std::vector<double2> t(N), f(N), h(N);
+        std::vector<double> q(N);
+        for (int j = 0; j < N; ++j) {
+            const double ang = 2.0 * M_PI * (double)j / (double)N;
+            t[j] = make_double2(std::cos(ang), -std::sin(ang));
+            const double k = wavenumber(j, N, Ls[d]);
+            q[j] = k * k;
+            const double thf = -I.a * k * k * I.dz, thh = 0.5 * thf;
+            f[j] = make_double2(std::cos(thf), std::sin(thf));
+            h[j] = make_double2(std::cos(thh), std::sin(thh));
+        }
+        gsn_status s;
+        if ((s = upload_sync(b->stream, tw[d], t.data(), 16ull * N))) return s;
+        if ((s = upload_sync(b->stream, kf[d], f.data(), 16ull * N))) return s;
+        if ((s = upload_sync(b->stream, kh[d], h.data(), 16ull * N))) return s;
+        if ((s = upload_sync(b->stream, k2[d], q.data(), 8ull * N))) return s;
+    }
+    return GSN_OK;
+}
+
+double kernel_k0(const gsn_kernel &k)
+{
+    double v = k.c_contact;
+    if (k.c_yukawa != 0.0) v += k.c_yukawa / (k.m_yukawa * k.m_yukawa);
+    return v;
+}
+
+// Per-instance argument structs of one pass kind (same layout as one grid).
+EmArgs em_args(gsn_batch b, const Instance &I, int kind)
+{
+    EmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.psi = I.psi;
+    a.half = I.half;
+    a.nyq = I.nyq;
+    a.tw = I.tw_x;
+    a.scale = kind == B_EXIT ? 1.0 / I.nx : 1.0;
+    a.g = I.g;
+    a.dz = I.dz;
+    a.partials = I.mass_parts;
+    a.nlines = (kind == B_ENTRY || kind == B_EXIT) ? I.ny : I.ny / 2;
+    (void)b;
+    return a;
+}
+
+Seg seg_of(float2 *ptr, long long es, long long ls, long long os, int nlines, int nouter, int lpt)
+{
+    Seg s;
+    std::memset(&s, 0, sizeof(s));
+    s.ptr = ptr;
+    s.es = es;
+    s.ls = ls;
+    s.os = os;
+    s.nlines = nlines;
+    s.ngroups = (nlines + lpt - 1) / lpt;
+    s.ntiles = s.ngroups * nouter;
+    return s;
+}
+
+LmArgs lm_args(gsn_batch b, const Instance &I, int kind, int lpt)
+{
+    LmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.kin1 = a.kin2 = a.kinp = b->kin_unit;
+    a.k2_1 = a.k2_2 = a.k2_p = b->k2_unit;
+    a.st = I.st;
+    a.tw = I.tw_y;
+    const int H = I.nx / 2;
+    if (kind == B_KIN_HALF || kind == B_KIN_FULL) {
+        a.scale = 1.0 / I.ny;
+        a.s0 = seg_of(I.psi, I.nx, 1, 0, I.nx, 1, lpt);
+        a.s0.c1l = 1;
+        a.kin1 = kind == B_KIN_HALF ? I.kinH_x : I.kinF_x;
+        a.kinp = kind == B_KIN_HALF ? I.kinH_y : I.kinF_y;
+    } else {   // B_KERNEL
+        a.scale = 1.0 / I.ny;
+        a.s0 = seg_of(I.half, H, 1, 0, H, 1, lpt);
+        a.s0.c1l = 1;
+        a.s1 = seg_of(I.nyq, 1, 0, 0, 1, 1, lpt);
+        a.s1.c1f = H;
+        a.k2_1 = I.k2_x;
+        a.k2_p = I.k2_y;
+        a.cN = I.kern.c_newton;
+        a.cY = I.kern.c_yukawa;
+        a.mY2 = I.kern.m_yukawa * I.kern.m_yukawa;
+        a.c0 = I.kern.c_contact;
+        a.reduce = 1;
+        a.mass_parts = I.mass_parts;
+        const NKernels *kx = kernels_for(I.nx, b->var[F_DENSITY]);
+        a.nmass = (I.ny / 2 + kx->em_lines - 1) / kx->em_lines;
+        a.k0_dz_over_P = kernel_k0(I.kern) * I.dz / (double)I.P;
+    }
+    return a;
+}
+
+// Rebuild every group's launch descriptors and upload the argument arrays.
+gsn_status build_batch(gsn_batch b)
+{
+    for (Group &G : b->groups) {
+        const int cnt = (int)G.members.size();
+        for (int kind = 0; kind < B_NKIND; ++kind) {
+            const int fam = kFamOf[kind];
+            const bool is_lm = (kind == B_KIN_HALF || kind == B_KIN_FULL || kind == B_KERNEL);
+            const int N = is_lm ? G.ny : G.nx;
+            const GKernels *k = gkernels_for(N, b->var[fam]);
+            GLaunch &L = G.launch[kind];
+            if (is_lm) {
+                std::vector<LmArgs> v(cnt);
+                for (int m = 0; m < cnt; ++m) v[m] = lm_args(b, b->inst[G.members[m]], kind, k->lm_lines);
+                gsn_status s = upload_sync(b->stream, G.args_dev[kind], v.data(), sizeof(LmArgs) * cnt);
+                if (s) return s;
+                L.tpi = v[0].s0.ntiles + v[0].s1.ntiles;
+                L.fn = (const void *)(kind == B_KERNEL ? k->lm_kern : k->lm_kin);
+                L.block = dim3(k->lm_threads());
+            } else {
+                std::vector<EmArgs> v(cnt);
+                for (int m = 0; m < cnt; ++m) v[m] = em_args(b, b->inst[G.members[m]], kind);
+                gsn_status s = upload_sync(b->stream, G.args_dev[kind], v.data(), sizeof(EmArgs) * cnt);
+                if (s) return s;
+                L.tpi = (v[0].nlines + k->em_lines - 1) / k->em_lines;
+                const bool st = b->store_psi != 0;
+                L.fn = kind == B_ENTRY ? (const void *)k->em_fwd
+                     : kind == B_EXIT ? (const void *)k->em_inv
+                     : kind == B_DENSITY ? (const void *)(st ? k->density_store : k->density)
+                                         : (const void *)(st ? k->phase_real : k->phase);
+                L.block = dim3(k->em_threads());
+            }
+            L.grid = dim3(L.tpi * cnt);
+            L.args = G.args_dev[kind];
+        }
+    }
+    b->dirty = true;
+    return GSN_OK;
+}
+
+hipError_t glaunch(const GLaunch &L, hipStream_t s)
+{
+    const void *args_ptr = L.args;
+    int tpi = L.tpi;
+    void *args[2] = {(void *)&args_ptr, (void *)&tpi};
+    return hipLaunchKernel(L.fn, L.grid, L.block, args, 0, s);
+}
+
+// The launch chain of one group for nsteps steps.
+gsn_status enqueue_group(const Group &G, int64_t nsteps, hipStream_t s)
+{
+    HIP_TRY(glaunch(G.launch[B_ENTRY], s));
+    HIP_TRY(glaunch(G.launch[B_KIN_HALF], s));
+    for (int64_t i = 0; i < nsteps; ++i) {
+        HIP_TRY(glaunch(G.launch[B_DENSITY], s));
+        HIP_TRY(glaunch(G.launch[B_KERNEL], s));
+        HIP_TRY(glaunch(G.launch[B_PHASE], s));
+        HIP_TRY(glaunch(G.launch[i + 1 < nsteps ? B_KIN_FULL : B_KIN_HALF], s));
+    }
+    HIP_TRY(glaunch(G.launch[B_EXIT], s));
+    return GSN_OK;
+}
+
+gsn_status capture_graph(gsn_batch b, int64_t nsteps)
+{
+    if (b->exec) {
+        HIP_TRY(hipGraphExecDestroy(b->exec));
+        b->exec = nullptr;
+    }
+    hipEvent_t fork;
+    HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    std::vector<hipEvent_t> join(b->groups.size());
+    for (auto &e : join) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    gsn_status st = GSN_OK;
+    hipError_t he = hipEventRecord(fork, b->stream);
+    for (size_t gi = 0; gi < b->groups.size() && he == hipSuccess && !st; ++gi) {
+        he = hipStreamWaitEvent(b->side[gi], fork, 0);
+        if (he != hipSuccess) break;
+        st = enqueue_group(b->groups[gi], nsteps, b->side[gi]);
+        if (st) break;
+        he = hipEventRecord(join[gi], b->side[gi]);
+        if (he == hipSuccess) he = hipStreamWaitEvent(b->stream, join[gi], 0);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(b->stream, &graph);
+    hipEventDestroy(fork);
+    for (auto &e : join) hipEventDestroy(e);
+    if (st) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (he != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return fail(GSN_EHIP, std::string("graph capture: ") + hipGetErrorString(he));
+    }
+    if (ee != hipSuccess) return fail(GSN_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+    hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(GSN_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    b->exec_steps = nsteps;
+    b->dirty = false;
+    return GSN_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" gsn_status gsn_batch_workspace_bytes(int count, int ndim, const int32_t *n, size_t *bytes)
+{
+    gsn_status s = validate_batch(count, ndim, n);
+    if (s) return s;
+    if (!bytes) return fail(GSN_EINVAL, "bytes is NULL");
+    BLayout L;
+    compute_blayout(count, n, &L);
+    *bytes = L.total;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, const int32_t *n,
+                                       const double *L, void *d_ws, size_t bytes, void *stream)
+{
+    if (!out) return fail(GSN_EINVAL, "out is NULL");
+    *out = nullptr;
+    gsn_status s = validate_batch(count, ndim, n);
+    if (s) return s;
+    if (!L) return fail(GSN_EINVAL, "L is NULL");
+    for (int i = 0; i < 2 * count; ++i)
+        if (!(std::isfinite(L[i]) && L[i] > 0.0)) return fail(GSN_EINVAL, "box lengths must be finite and > 0");
+    if (!d_ws) return fail(GSN_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(GSN_EWORKSPACE, "workspace must be 256-byte aligned");
+    BLayout lay;
+    compute_blayout(count, n, &lay);
+    if (bytes < lay.total)
+        return fail(GSN_EWORKSPACE, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+    gsn_batch b = new (std::nothrow) gsn_batch_();
+    if (!b) return fail(GSN_EINVAL, "out of host memory");
+    b->count = count;
+    b->user = (hipStream_t)stream;
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return fail(GSN_EHIP, "stream/event creation failed");
+    }
+    b->ws = (char *)d_ws;
+    b->ws_bytes = bytes;
+    b->exec = nullptr;
+    b->exec_steps = -1;
+    b->dirty = true;
+    b->mode = 0;
+    b->store_psi = 0;
+    b->pq = b->ws + lay.queue_off;
+    // default schedule: the variants the single-grid autotuner favours on gfx950
+    b->var[F_KIN] = 0;
+    b->var[F_DENSITY] = 0;
+    b->var[F_KERNEL] = 0;
+    b->var[F_PHASE] = 1;
+    b->var[F_XFFT] = 0;
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return fail(GSN_EHIP, "hipGetDevice failed");
+    }
+    b->scratch = (float2 *)(b->ws + lay.scratch_off);
+    b->k2_unit = (double *)(b->ws + lay.unit_off);
+    b->kin_unit = (double2 *)(b->ws + lay.unit_off + 256);
+    b->inst.resize(count);
+    std::map<std::pair<int, int>, int> gidx;
+    for (int i = 0; i < count; ++i) {
+        Instance &I = b->inst[i];
+        std::memset(&I, 0, sizeof(I));
+        I.ny = n[2 * i];
+        I.nx = n[2 * i + 1];
+        I.Ly = L[2 * i];
+        I.Lx = L[2 * i + 1];
+        I.P = (long long)I.ny * I.nx;
+        I.a = 0.5;
+        char *p = b->ws + lay.inst_off[i];
+        int db = 0;
+        for (int v = 0; v < kNumVariants; ++v) {
+            const NKernels *k = kernels_for(I.nx, v);
+            db = std::max(db, (int)((I.ny / 2 + k->em_lines - 1) / k->em_lines));
+        }
+        const int M = std::max(I.nx, I.ny);
+        I.psi = (float2 *)p; p += align256(8ull * I.P);
+        I.half = (float2 *)p; p += align256(4ull * I.P);
+        I.nyq = (float2 *)p; p += align256(8ull * I.ny);
+        I.mass_parts = (double *)p; p += align256(8ull * db);
+        I.st = (DevState *)p; p += align256(sizeof(DevState));
+        I.tw_x = (double2 *)p; p += align256(16ull * M);
+        I.tw_y = (double2 *)p; p += align256(16ull * M);
+        I.kinF_x = (double2 *)p; p += align256(16ull * M);
+        I.kinF_y = (double2 *)p; p += align256(16ull * M);
+        I.kinH_x = (double2 *)p; p += align256(16ull * M);
+        I.kinH_y = (double2 *)p; p += align256(16ull * M);
+        I.k2_x = (double *)p; p += align256(8ull * M);
+        I.k2_y = (double *)p; p += align256(8ull * M);
+        auto key = std::make_pair(I.ny, I.nx);
+        if (!gidx.count(key)) {
+            gidx[key] = (int)b->groups.size();
+            Group G;
+            G.ny = I.ny;
+            G.nx = I.nx;
+            b->groups.push_back(G);
+        }
+        b->groups[gidx[key]].members.push_back(i);
+    }
+    // argument arrays: per group, per kind, one slot per member
+    {
+        char *p = b->ws + lay.args_off;
+        const size_t sz = std::max(sizeof(EmArgs), sizeof(LmArgs));
+        for (Group &G : b->groups)
+            for (int kind = 0; kind < B_NKIND; ++kind) {
+                G.args_dev[kind] = p;
+                p += sz * G.members.size();
+            }
+    }
+    const double zero = 0.0;
+    const double2 one = make_double2(1.0, 0.0);
+    if ((s = upload_sync(b->stream, b->k2_unit, &zero, 8)) || (s = upload_sync(b->stream, b->kin_unit, &one, 16))) {
+        delete b;
+        return s;
+    }
+    b->side.resize(b->groups.size());
+    for (auto &st : b->side)
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (auto &x : b->side)
+                if (x) hipStreamDestroy(x);
+            delete b;
+            return fail(GSN_EHIP, "hipStreamCreate failed");
+        }
+    for (Instance &I : b->inst) {
+        if ((s = upload_instance_tables(b, I))) {
+            for (auto &x : b->side) hipStreamDestroy(x);
+            delete b;
+            return s;
+        }
+        hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, b->stream, I.st);
+    }
+    if ((s = build_batch(b))) {
+        for (auto &x : b->side) hipStreamDestroy(x);
+        delete b;
+        return s;
+    }
+    *out = b;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_batch_destroy(gsn_batch b)
+{
+    if (!b) return fail(GSN_EINVAL, "batch is NULL");
+    (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    for (auto &x : b->side) (void)hipStreamDestroy(x);
+    (void)hipEventDestroy(b->ev_in);
+    (void)hipEventDestroy(b->ev_out);
+    (void)hipStreamDestroy(b->stream);
+    delete b;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_batch_set(gsn_batch b, int i, const gsn_kernel *k, double a_kin, double g_local,
+                                    double dz, const void *psi, int on_device, int dtype)
+{
+    if (!b || !k || !psi) return fail(GSN_EINVAL, "NULL argument");
+    if (i < 0 || i >= b->count) return fail(GSN_EINVAL, "instance index out of range");
+    if (dtype != GSN_C64 && dtype != GSN_C128) return fail(GSN_EINVAL, "dtype must be GSN_C64 or GSN_C128");
+    if (!std::isfinite(k->c_newton) || !std::isfinite(k->c_yukawa) || !std::isfinite(k->m_yukawa) ||
+        !std::isfinite(k->c_contact))
+        return fail(GSN_EINVAL, "kernel coefficients must be finite");
+    if (k->c_yukawa != 0.0 && !(k->m_yukawa > 0.0)) return fail(GSN_EINVAL, "m_yukawa must be > 0 when c_yukawa != 0");
+    if (!std::isfinite(a_kin) || !std::isfinite(g_local) || !std::isfinite(dz) || dz == 0.0)
+        return fail(GSN_EINVAL, "coefficients must be finite and dz != 0");
+    HIP_TRY(hipSetDevice(b->device));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    Instance &I = b->inst[i];
+    I.kern = *k;
+    I.a = a_kin;
+    I.g = g_local;
+    I.dz = dz;
+    gsn_status s = upload_instance_tables(b, I);
+    if (s) return s;
+    if (dtype == GSN_C64) {
+        HIP_TRY(hipMemcpyAsync(I.psi, psi, 8ull * I.P, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                               b->stream));
+    } else if (on_device) {
+        hipLaunchKernelGGL(k_from_c128, dim3(1024), dim3(256), 0, b->stream, (const double2 *)psi, I.psi, I.P);
+        HIP_TRY(hipGetLastError());
+    } else {
+        std::vector<float2> tmp((size_t)I.P);
+        const double *src = (const double *)psi;
+        for (long long q = 0; q < I.P; ++q) tmp[q] = make_float2((float)src[2 * q], (float)src[2 * q + 1]);
+        HIP_TRY(hipMemcpyAsync(I.psi, tmp.data(), 8ull * I.P, hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+    }
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, b->stream, I.st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    I.set = true;
+    return build_batch(b);
+}
+
+extern "C" gsn_status gsn_batch_step(gsn_batch b, int64_t nsteps)
+{
+    if (!b) return fail(GSN_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(GSN_EINVAL, "nsteps must be >= 0");
+    for (const Instance &I : b->inst)
+        if (!I.set) return fail(GSN_ESTATE, "every instance must be set before stepping");
+    if (nsteps == 0) return GSN_OK;
+    HIP_TRY(hipSetDevice(b->device));
+    // order after the caller's earlier work, run on the internal stream, and
+    // make the caller's later work wait for the run
+    HIP_TRY(hipEventRecord(b->ev_in, b->user));
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    if (b->mode == 0) {
+        if (b->dirty || !b->exec || b->exec_steps != nsteps) {
+            gsn_status s = capture_graph(b, nsteps);
+            if (s) return s;
+        }
+        HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    } else {
+        // mode 2: the same grouped launches issued directly (no graph)
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            gsn_status s = enqueue_group(b->groups[gi], nsteps, b->stream);
+            if (s) return s;
+        }
+    }
+    HIP_TRY(hipEventRecord(b->ev_out, b->stream));
+    HIP_TRY(hipStreamWaitEvent(b->user, b->ev_out, 0));
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_batch_sync(gsn_batch b)
+{
+    if (!b) return fail(GSN_EINVAL, "batch is NULL");
+    HIP_TRY(hipSetDevice(b->device));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    HIP_TRY(hipStreamSynchronize(b->user));
+    for (const Instance &I : b->inst) {
+        DevState st;
+        HIP_TRY(hipMemcpy(&st, I.st, sizeof(st), hipMemcpyDeviceToHost));
+        if (st.nonfinite) return fail(GSN_ENONFINITE, "an instance's fused FP64 mass became non-finite");
+    }
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_batch_get(gsn_batch b, int i, void *dst, int on_device, int dtype)
+{
+    if (!b || !dst) return fail(GSN_EINVAL, "NULL argument");
+    if (i < 0 || i >= b->count) return fail(GSN_EINVAL, "instance index out of range");
+    if (dtype != GSN_C64 && dtype != GSN_C128) return fail(GSN_EINVAL, "dtype must be GSN_C64 or GSN_C128");
+    HIP_TRY(hipSetDevice(b->device));
+    const Instance &I = b->inst[i];
+    const size_t esz = dtype == GSN_C128 ? 16 : 8;
+    void *out = on_device ? dst : (void *)b->scratch;
+    if (dtype == GSN_C128)
+        hipLaunchKernelGGL(k_readout<true>, dim3(1024), dim3(256), 0, b->stream, I.psi, out, I.P, I.st);
+    else
+        hipLaunchKernelGGL(k_readout<false>, dim3(1024), dim3(256), 0, b->stream, I.psi, out, I.P, I.st);
+    HIP_TRY(hipGetLastError());
+    if (!on_device) HIP_TRY(hipMemcpyAsync(dst, b->scratch, esz * I.P, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return gsn_batch_sync(b);
+}
+
+extern "C" gsn_status gsn_batch_mass(gsn_batch b, double *masses)
+{
+    if (!b || !masses) return fail(GSN_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(b->device));
+    for (int i = 0; i < b->count; ++i) {
+        const Instance &I = b->inst[i];
+        double *parts = (double *)b->scratch;
+        hipLaunchKernelGGL(k_mass<256>, dim3(256), dim3(256), 0, b->stream, I.psi, I.P, parts);
+        HIP_TRY(hipGetLastError());
+        std::vector<double> h(256);
+        HIP_TRY(hipMemcpyAsync(h.data(), parts, 8 * 256, hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        double sum = 0.0;
+        for (double v : h) sum += v;
+        masses[i] = sum * (I.Lx / I.nx) * (I.Ly / I.ny);
+    }
+    return gsn_batch_sync(b);
+}
+
+extern "C" gsn_status gsn_batch_set_mode(gsn_batch b, int mode)
+{
+    if (!b) return fail(GSN_EINVAL, "batch is NULL");
+    if (mode != 0 && mode != 2) return fail(GSN_EINVAL, "mode must be 0 (graph) or 2 (direct launches)");
+    b->mode = mode;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_batch_set_schedule(gsn_batch b, const int *variants, int nfam, int nonlinear_mode)
+{
+    if (!b || !variants || nfam < F_NFAM) return fail(GSN_EINVAL, "bad schedule arguments");
+    for (int i = 0; i < F_NFAM; ++i)
+        if (variants[i] < 0 || variants[i] >= kNumVariants) return fail(GSN_EINVAL, "unknown schedule variant");
+    if (nonlinear_mode != 0 && nonlinear_mode != 1) return fail(GSN_EINVAL, "nonlinear mode must be 0 or 1");
+    HIP_TRY(hipSetDevice(b->device));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < F_NFAM; ++i) b->var[i] = variants[i];
+    b->store_psi = nonlinear_mode;
+    return build_batch(b);
+}
+
+extern "C" gsn_status gsn_batch_phase(gsn_batch b, int i, double *theta, int64_t *steps)
+{
+    if (!b) return fail(GSN_EINVAL, "batch is NULL");
+    if (i < 0 || i >= b->count) return fail(GSN_EINVAL, "instance index out of range");
+    HIP_TRY(hipSetDevice(b->device));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    DevState st;
+    HIP_TRY(hipMemcpy(&st, b->inst[i].st, sizeof(st), hipMemcpyDeviceToHost));
+    if (theta) *theta = st.theta;
+    if (steps) *steps = st.steps;
+    return GSN_OK;
+}

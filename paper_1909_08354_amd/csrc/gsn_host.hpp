@@ -1,0 +1,123 @@
+// gsn_host.hpp -- host-side helpers shared by the single-grid and batched
+// solvers: error reporting, the per-length kernel tables with their schedule
+// variants, and FP64 table generation.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "gsn.h"
+#include "gsn_kernels.hpp"
+
+using namespace gsn;
+
+// ------------------------------------------------------------------ errors
+// The last error message of this host thread (defined in gsn_api.hip).
+extern thread_local std::string g_last_error;
+
+static inline gsn_status fail(gsn_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(GSN_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+
+// ------------------------------------------------------------------ kernel tables per N
+struct NKernels {
+    int E, TPL, lm_lines, em_lines;
+    void (*em_fwd)(EmArgs);
+    void (*em_inv)(EmArgs);
+    void (*density)(EmArgs);
+    void (*density_store)(EmArgs);
+    void (*phase)(EmArgs);
+    void (*phase_real)(EmArgs);
+    void (*phase_energy)(EmArgs);
+    void (*lm_fwd)(LmArgs);
+    void (*lm_inv)(LmArgs);
+    void (*lm_kin)(LmArgs);
+    void (*lm_kern)(LmArgs);
+    void (*lm_kin_energy)(LmArgs);
+    int lm_threads() const { return lm_lines * TPL; }
+    int em_threads() const { return em_lines * TPL; }
+};
+
+// Schedule variants: E points per thread (16 or 8) for every pass kind.  The
+// EM tile holds 256/TPL rows (at most 64); the LM tile holds LINES columns
+// chosen so that a tile moves >= 64-byte contiguous segments per row.
+constexpr int kNumVariants = 2;
+static const char *kVariantNames[kNumVariants] = {"e16", "e8"};
+
+template <int N, int V> struct Cfg {
+    static constexpr int E0 = V == 0 ? 16 : 8;
+    static constexpr int E = N < E0 ? N : E0;
+    static constexpr int TPL = N / E;
+    static constexpr int LM_LINES = TPL <= 4 ? 64 : TPL <= 8 ? 32 : TPL <= 32 ? 16 : TPL <= 64 ? 8 : 4;
+    static constexpr int EM_LINES = (256 / TPL) > 64 ? 64 : (256 / TPL) < 1 ? 1 : 256 / TPL;
+};
+
+template <int N, int V> static NKernels make_kernels()
+{
+    using C = Cfg<N, V>;
+    constexpr int E = C::E, LL = C::LM_LINES, EL = C::EM_LINES;
+    NKernels k;
+    k.E = E;
+    k.TPL = C::TPL;
+    k.lm_lines = LL;
+    k.em_lines = EL;
+    k.em_fwd = k_em_fft<N, E, EL, -1>;
+    k.em_inv = k_em_fft<N, E, EL, 1>;
+    k.density = k_density<N, E, EL, false>;
+    k.density_store = k_density<N, E, EL, true>;
+    k.phase = k_phase<N, E, EL, false, false>;
+    k.phase_real = k_phase<N, E, EL, false, true>;
+    k.phase_energy = k_phase<N, E, EL, true, false>;
+    k.lm_fwd = k_lm<N, E, LL, LM_FWD>;
+    k.lm_inv = k_lm<N, E, LL, LM_INV>;
+    k.lm_kin = k_lm<N, E, LL, LM_KIN>;
+    k.lm_kern = k_lm<N, E, LL, LM_KERN>;
+    k.lm_kin_energy = k_lm<N, E, LL, LM_KIN_ENERGY>;
+    return k;
+}
+
+template <int N> static const NKernels *variant_table(int v)
+{
+    static const NKernels k[kNumVariants] = {make_kernels<N, 0>(), make_kernels<N, 1>()};
+    return &k[v];
+}
+
+static const NKernels *kernels_for(int N, int v = 0)
+{
+    if (v < 0 || v >= kNumVariants) v = 0;
+    switch (N) {
+    case 8: return variant_table<8>(v);
+    case 16: return variant_table<16>(v);
+    case 32: return variant_table<32>(v);
+    case 64: return variant_table<64>(v);
+    case 128: return variant_table<128>(v);
+    case 256: return variant_table<256>(v);
+    case 512: return variant_table<512>(v);
+    case 1024: return variant_table<1024>(v);
+    case 2048: return variant_table<2048>(v);
+    default: return nullptr;
+    }
+}
+
+
+// wavenumber of DFT index j on an axis with N points and length L
+static inline double wavenumber(int j, int N, double L)
+{
+    const int jj = j < N / 2 ? j : j - N;
+    return 2.0 * M_PI * (double)jj / L;
+}
+
+static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }

@@ -47,14 +47,24 @@ template <int N, int E> struct EmShape {
     static constexpr int TPL = N / E;
 };
 
+template <int N, int E, int LINES> struct EmTile {
+    static constexpr int TPL = N / E;
+    static constexpr int NT = LINES * TPL;
+    static constexpr int LDS = LINES * EmLayout<N, E>::PITCH;   // float2 slots
+};
+template <int N, int E, int LINES> struct LmTile {
+    static constexpr int TPL = N / E;
+    static constexpr int NT = LINES * TPL;
+    static constexpr int LDS = LINES * N;
+};
+
 // Plain row FFT (entry/exit of a run of steps, energy evaluation).
 template <int N, int E, int LINES, int S>
-__global__ __launch_bounds__(LINES *(N / E)) void k_em_fft(EmArgs a)
+__device__ __forceinline__ void em_fft_tile(const EmArgs &a, int tile, float2 *lds)
 {
     constexpr int TPL = N / E;
-    __shared__ float2 lds[LINES * EmLayout<N, E>::PITCH];
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
-    const int row = blockIdx.x * LINES + l;
+    const int row = tile * LINES + l;
     const bool act = row < a.nlines;
     const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     dc v[E];
@@ -75,13 +85,11 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_em_fft(EmArgs a)
 // STORE_PSI: also write psi (real space) back over the two psi_x rows, so the
 // phase pass can skip its two inverse x transforms (+8 bytes per point).
 template <int N, int E, int LINES, bool STORE_PSI>
-__global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
+__device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *lds, double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
-    __shared__ float2 lds[LINES * EmLayout<N, E>::PITCH];
-    __shared__ double sh[NT / 64 + 1];
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
-    const int pair = blockIdx.x * LINES + l;
+    const int pair = tile * LINES + l;
     const bool act = pair < a.nlines;
     const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     const long long r0 = 2LL * pair, r1 = r0 + 1;
@@ -139,7 +147,7 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
         }
     }
     const double bs = block_sum<NT>(msum, sh);
-    if (tid == 0) a.partials[blockIdx.x] = bs;
+    if (tid == 0) a.partials[tile] = bs;
 }
 
 // Phase pass.  Rebuild the full x-spectrum of two phi rows from their half
@@ -196,13 +204,11 @@ __host__ __device__ __forceinline__ void sincos_fp64(double th, double *s, doubl
 // REAL_IN: the psi rows already hold psi in real space (written by the density
 // pass with STORE_PSI), so the inverse x transform is skipped.
 template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
-__global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
+__device__ __forceinline__ void phase_tile(const EmArgs &a, int tile, float2 *lds, double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
-    __shared__ float2 lds[LINES * EmLayout<N, E>::PITCH];
-    __shared__ double sh[NT / 64 + 1];
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
-    const int pair = blockIdx.x * LINES + l;
+    const int pair = tile * LINES + l;
     const bool act = pair < a.nlines;
     const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     const long long r0 = 2LL * pair, r1 = r0 + 1;
@@ -273,8 +279,8 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
         const double b0 = block_sum<NT>(acc0, sh);
         const double b1 = block_sum<NT>(acc1, sh);
         if (tid == 0) {
-            a.partials[2 * blockIdx.x] = b0;
-            a.partials[2 * blockIdx.x + 1] = b1;
+            a.partials[2 * tile] = b0;
+            a.partials[2 * tile + 1] = b1;
         }
     }
 }
@@ -310,13 +316,11 @@ struct LmArgs {
 };
 
 template <int N, int E, int LINES, int MODE>
-__global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
+__device__ __forceinline__ void lm_tile(const LmArgs &a, int tile_in, float2 *lds, double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
-    __shared__ float2 lds[LINES * N];
-    __shared__ double sh[NT / 64 + 1];
     const int tid = threadIdx.x, l = tid % LINES, t = tid / LINES;
-    int tile = blockIdx.x;
+    int tile = tile_in;
     const bool second = tile >= a.s0.ntiles;
     const Seg sg = second ? a.s1 : a.s0;
     if (second) tile -= a.s0.ntiles;
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
                 for (int e = 0; e < E; ++e) acc += (q12 + a.k2_p[t + TPL * e]) * norm2(v[e]);
             }
             const double bs = block_sum<NT>(acc, sh);
-            if (tid == 0) a.partials[blockIdx.x] = bs;
+            if (tid == 0) a.partials[tile_in] = bs;
         }
         if constexpr (MODE != LM_KIN_ENERGY) fft<N, E, 1>(v, t, lay, lds, a.tw);
     }
@@ -378,7 +382,7 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
             for (int e = 0; e < E; ++e) base[(long long)(t + TPL * e) * sg.es] = to_f2(v[e]);
         }
     }
-    if (a.reduce && blockIdx.x == 0) {
+    if (a.reduce && tile_in == 0) {
         double s = 0.0;
         for (int i = tid; i < a.nmass; i += NT) s += a.mass_parts[i];
         s = block_sum<NT>(s, sh);
@@ -389,6 +393,70 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
             if (!isfinite(s)) a.st->nonfinite = 1;
         }
     }
+}
+
+// ---------------------------------------------------------------- kernels
+// One grid: block b is tile b.  Grouped: several instances of one shape in
+// one launch; block b is tile (b mod tpi) of instance (b / tpi), whose
+// arguments are read from a device array.
+template <int N, int E, int LINES, int S>
+__global__ __launch_bounds__(LINES *(N / E)) void k_em_fft(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    em_fft_tile<N, E, LINES, S>(a, blockIdx.x, lds);
+}
+template <int N, int E, int LINES, bool STORE_PSI>
+__global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
+    density_tile<N, E, LINES, STORE_PSI>(a, blockIdx.x, lds, sh);
+}
+template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
+__global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
+    phase_tile<N, E, LINES, ENERGY, REAL_IN>(a, blockIdx.x, lds, sh);
+}
+template <int N, int E, int LINES, int MODE>
+__global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
+{
+    __shared__ float2 lds[LmTile<N, E, LINES>::LDS];
+    __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
+    lm_tile<N, E, LINES, MODE>(a, blockIdx.x, lds, sh);
+}
+
+template <int N, int E, int LINES, int S>
+__global__ __launch_bounds__(LINES *(N / E)) void k_em_fft_g(const EmArgs *__restrict__ args, int tpi)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    const EmArgs a = args[blockIdx.x / tpi];
+    em_fft_tile<N, E, LINES, S>(a, blockIdx.x % tpi, lds);
+}
+template <int N, int E, int LINES, bool STORE_PSI>
+__global__ __launch_bounds__(LINES *(N / E)) void k_density_g(const EmArgs *__restrict__ args, int tpi)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
+    const EmArgs a = args[blockIdx.x / tpi];
+    density_tile<N, E, LINES, STORE_PSI>(a, blockIdx.x % tpi, lds, sh);
+}
+template <int N, int E, int LINES, bool REAL_IN>
+__global__ __launch_bounds__(LINES *(N / E)) void k_phase_g(const EmArgs *__restrict__ args, int tpi)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
+    const EmArgs a = args[blockIdx.x / tpi];
+    phase_tile<N, E, LINES, false, REAL_IN>(a, blockIdx.x % tpi, lds, sh);
+}
+template <int N, int E, int LINES, int MODE>
+__global__ __launch_bounds__(LINES *(N / E)) void k_lm_g(const LmArgs *__restrict__ args, int tpi)
+{
+    __shared__ float2 lds[LmTile<N, E, LINES>::LDS];
+    __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
+    const LmArgs a = args[blockIdx.x / tpi];
+    lm_tile<N, E, LINES, MODE>(a, blockIdx.x % tpi, lds, sh);
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -420,7 +488,7 @@ __global__ void k_readout(const float2 *__restrict__ src, void *dst, long long P
     }
 }
 
-__global__ void k_from_c128(const double2 *__restrict__ src, float2 *dst, long long P)
+static __global__ void k_from_c128(const double2 *__restrict__ src, float2 *dst, long long P)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < P;
          i += (long long)gridDim.x * blockDim.x) {
@@ -429,7 +497,7 @@ __global__ void k_from_c128(const double2 *__restrict__ src, float2 *dst, long l
     }
 }
 
-__global__ void k_reset_state(DevState *st)
+static __global__ void k_reset_state(DevState *st)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->theta = 0.0;

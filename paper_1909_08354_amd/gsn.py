@@ -55,6 +55,18 @@ _SIGNATURES = {
     "gsn_get_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
     "gsn_set_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
     "gsn_set_nonlinear_mode": [vp, ctypes.c_int],
+    "gsn_batch_workspace_bytes": [ctypes.c_int, ctypes.c_int, i32p, ctypes.POINTER(ctypes.c_size_t)],
+    "gsn_batch_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, i32p, dp, vp, ctypes.c_size_t, vp],
+    "gsn_batch_destroy": [vp],
+    "gsn_batch_set": [vp, ctypes.c_int, ctypes.POINTER(gsn_kernel), ctypes.c_double, ctypes.c_double,
+                      ctypes.c_double, vp, ctypes.c_int, ctypes.c_int],
+    "gsn_batch_step": [vp, ctypes.c_int64],
+    "gsn_batch_sync": [vp],
+    "gsn_batch_get": [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int],
+    "gsn_batch_mass": [vp, dp],
+    "gsn_batch_phase": [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)],
+    "gsn_batch_set_mode": [vp, ctypes.c_int],
+    "gsn_batch_set_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int],
     "gsn_get_nonlinear_mode": [vp, ctypes.POINTER(ctypes.c_int)],
 }
 
@@ -266,3 +278,79 @@ class Grid:
         ms = (ctypes.c_double * npass)()
         check(lib.gsn_profile_passes(self.h, int(nsteps), ms, npass))
         return dict(zip(self.pass_names(), list(ms)))
+
+
+BATCH_FAMILIES = ("kinetic", "x_density", "kernel", "x_phase", "x_fft")
+
+
+class Batch:
+    """Many independent 2-D instances advanced together (gsn_batch_create)."""
+
+    def __init__(self, shapes, boxes, stream=None):
+        torch = _torch()
+        lib = load()
+        self.shapes = [tuple(int(v) for v in n) for n in shapes]
+        self.boxes = [tuple(float(v) for v in L) for L in boxes]
+        self.count = len(self.shapes)
+        flat_n = [v for n in self.shapes for v in n]
+        flat_L = [v for L in self.boxes for v in L]
+        nb = ctypes.c_size_t(0)
+        check(lib.gsn_batch_workspace_bytes(self.count, 2, _i32(flat_n), ctypes.byref(nb)))
+        self._ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self._ws.data_ptr() + 255) & ~255
+        stream = torch.cuda.current_stream() if stream is None else stream
+        self.stream = stream
+        h = vp()
+        check(lib.gsn_batch_create(ctypes.byref(h), self.count, 2, _i32(flat_n), _f64(flat_L),
+                                   vp(aligned), nb.value, vp(stream.cuda_stream)))
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            check(load().gsn_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, i, kern, a, g, dz, psi):
+        k = gsn_kernel(*kern)
+        ptr, dev, code, keep = _ptr_and_flag(psi)
+        if tuple(keep.shape) != self.shapes[i]:
+            raise ValueError("psi shape does not match instance %d" % i)
+        check(load().gsn_batch_set(self.h, int(i), ctypes.byref(k), a, g, dz, vp(ptr), dev, code))
+        self._keep[i] = keep
+
+    def step(self, nsteps):
+        check(load().gsn_batch_step(self.h, int(nsteps)))
+
+    def sync(self):
+        check(load().gsn_batch_sync(self.h))
+
+    def get(self, i, dtype=np.complex128):
+        out = np.empty(self.shapes[i], dtype=dtype)
+        check(load().gsn_batch_get(self.h, int(i), vp(out.ctypes.data), 0,
+                                   GSN_C128 if dtype == np.complex128 else GSN_C64))
+        return out
+
+    def masses(self):
+        m = (ctypes.c_double * self.count)()
+        check(load().gsn_batch_mass(self.h, m))
+        return np.array(list(m))
+
+    def phase(self, i):
+        th = ctypes.c_double(0)
+        st = ctypes.c_int64(0)
+        check(load().gsn_batch_phase(self.h, int(i), ctypes.byref(th), ctypes.byref(st)))
+        return th.value, st.value
+
+    def set_mode(self, mode):
+        check(load().gsn_batch_set_mode(self.h, int(mode)))
+
+    def set_schedule(self, variants, nonlinear_mode=0):
+        v = (ctypes.c_int * len(variants))(*variants)
+        check(load().gsn_batch_set_schedule(self.h, v, len(variants), int(nonlinear_mode)))
