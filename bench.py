@@ -74,6 +74,53 @@ def cpu_baseline(w, psi0_c128, budget_s=30.0):
             "kind": "oracle", "sample": sample}
 
 
+def batch_bench(steps):
+    """The 64-instance sweep (256^2/512^2/1024^2, per-instance Yukawa couplings):
+    one gsn_batch_step graph launch vs the same instances run one after another
+    through gsn_step with the same schedule (bit-identical results)."""
+    import torch
+    from paper_1909_08354_amd import gsn, inputs
+    w = inputs.WORKLOADS["gsn2d_batch64_sweep"]
+    inst = inputs.batch_sweep(w["count"], w["seed"], w["sizes"])
+    total_pts = sum(int(np.prod(d["n"])) for d in inst)
+    b = gsn.Batch([d["n"] for d in inst], [d["L"] for d in inst])
+    for i, d in enumerate(inst):
+        b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+    m0 = b.masses()
+    b.step(steps)            # captures and instantiates the graph
+    b.sync()
+    for i, d in enumerate(inst):
+        b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    drift = float(np.max(np.abs(b.masses() / m0 - 1)))
+    grids = []
+    fam = {"kinetic": 0, "x_density": 0, "kernel": 0, "x_phase": 1}
+    for d in inst:
+        g = gsn.Grid(d["n"], d["L"])
+        g.set_kernel(*d["kern"])
+        g.set_coefficients(d["a"], d["g"], d["dz"])
+        g.set_schedule([fam.get(nm, 0) for nm in g.pass_names()])
+        g.set_psi(inputs.to_c64(d["psi"]))
+        grids.append(g)
+    grids[0].step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in grids:
+        g.step(steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    return {"workload": "gsn2d_batch64_sweep", "instances": len(inst), "steps": steps,
+            "grid_points": total_pts, "value": total_pts * steps / t_batch,
+            "unit": "grid-pt updates/s", "ms_batch_graph": 1e3 * t_batch,
+            "ms_sequential_gsn_step": 1e3 * t_seq, "speedup": t_seq / t_batch,
+            "max_norm_drift": drift,
+            "accuracy": "bit-identical to the sequential runs (same kernels and schedule)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +129,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--autotune-iters", type=int, default=10)
+    ap.add_argument("--batch-steps", type=int, default=500,
+                    help="steps of the 64-instance batched sweep (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -166,8 +215,14 @@ def main():
         "norm_drift": abs(m1 / m0 - 1),
         "energy_drift": abs(e1["total"] - e0["total"]) / scale,
         "batched_speedup": None,
+        "batched": None,
         "corrected_speedup": None,
     }
+    if args.batch_steps > 0:
+        grid.close()
+        del grid
+        line["batched"] = batch_bench(args.batch_steps)
+        line["batched_speedup"] = line["batched"]["speedup"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, inputs.as_oracle_input(psi0))
     print(json.dumps(line), flush=True)
