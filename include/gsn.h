@@ -187,6 +187,58 @@ gsn_status gsn_batch_set_mode(gsn_batch batch, int mode);
    gsn_set_nonlinear_mode). */
 gsn_status gsn_batch_set_schedule(gsn_batch batch, const int *variants, int nfam, int nonlinear_mode);
 
+/* ---------------------------------------------------------------- learned corrector
+   A 4-layer 3x3 convolutional network with circular padding (3 -> 32 -> 32 ->
+   32 -> 2 channels, ReLU after the first three; 19970 parameters) that maps
+   (Re psi_c, Im psi_c, phi_c) of a coarse split step (ratio * dz) to the
+   residual psi_fine - psi_c of the equivalent ratio fine steps.  bfloat16
+   weights and activations, FP32 accumulation on the matrix cores, FP32
+   master weights and Adam moments.  This is not part of the paper's method:
+   the plain fine-step solver stays the judge of its error and its fallback.
+   Flat FP32 parameter vector, per layer: w[tap][cout][cin] (tap = 3 dy + dx,
+   input offset (dy-1, dx-1)) then bias[cout].  Images are H x W with H*W a
+   multiple of 64; device buffers are psi complex64 H*W and phi float H*W. */
+typedef struct gsn_corrector_ *gsn_corrector;
+gsn_status gsn_corrector_workspace_bytes(int H, int W, int max_batch, size_t *bytes);
+gsn_status gsn_corrector_create(gsn_corrector *out, int H, int W, int max_batch, void *d_workspace,
+                                size_t bytes, void *hip_stream);
+gsn_status gsn_corrector_destroy(gsn_corrector c);
+/* Load FP32 master weights (n == 19970, host) and reset the Adam state. */
+gsn_status gsn_corrector_set_weights(gsn_corrector c, const float *w, size_t n);
+gsn_status gsn_corrector_get_weights(gsn_corrector c, float *w, size_t n);
+/* Input feature scales (Re, Im, phi) and the residual scale s_out: the net
+   sees scaled inputs and predicts residual / s_out. */
+gsn_status gsn_corrector_set_scales(gsn_corrector c, const float in_scale[3], float out_scale);
+/* Pack image slot b from device psi (complex64) and phi (float). */
+gsn_status gsn_corrector_pack(gsn_corrector c, int b, const void *psi, const float *phi);
+/* Training target of slot b: (psi_fine - psi_coarse) / s_out (device buffers). */
+gsn_status gsn_corrector_pack_target(gsn_corrector c, int b, const void *psi_fine, const void *psi_coarse);
+/* Forward pass over slots 0..B-1; optional copy of the output (B*H*W*2 FP32). */
+gsn_status gsn_corrector_forward(gsn_corrector c, int B, float *out_dev);
+/* Forward + MSE + backward over slots 0..B-1 without updating: gradient of
+   the loss w.r.t. the flat parameters to grad_host (19970 floats) and the
+   loss.  Synchronising. */
+gsn_status gsn_corrector_gradients(gsn_corrector c, int B, float *grad_host, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on slots 0..B-1. */
+gsn_status gsn_corrector_train_step(gsn_corrector c, int B, float lr, float *loss);
+/* psi_out = psi_c + s_out * (r0 + i r1) with the last forward output of slot b. */
+gsn_status gsn_corrector_apply(gsn_corrector c, int b, const void *psi_c, void *psi_out);
+
+/* Coarse steps: coarse_ratio * dz per step, same schedule (0 disables). */
+gsn_status gsn_set_coarse_ratio(gsn_grid grid, int ratio);
+gsn_status gsn_step_coarse(gsn_grid grid, int64_t nsteps);
+/* phi of the current psi (without its uniform k = 0 part) into a device
+   float buffer of P values.  Asynchronous. */
+gsn_status gsn_potential(gsn_grid grid, float *phi_dev);
+/* ncoarse corrected coarse steps on a 2-D grid: coarse step, potential, net,
+   psi += s_out * residual.  Every audit_every-th step (0 = never) the same
+   step is redone with coarse_ratio fine steps; if the relative L2 distance
+   between the corrected and fine states exceeds tol the fine state is kept
+   (a fallback).  Reports the fallbacks and the worst audited error.
+   Synchronising when audits run. */
+gsn_status gsn_step_corrected(gsn_grid grid, gsn_corrector c, int64_t ncoarse, int audit_every, double tol,
+                              int64_t *n_fallbacks, double *max_audit_err);
+
 /* Human-readable message for the last failure on this thread. */
 const char *gsn_last_error(void);
 

@@ -16,10 +16,60 @@
 #include <vector>
 
 #include "gsn_host.hpp"
+#include "gsn_corrector_internal.hpp"
 
 thread_local std::string g_last_error;
 
 extern "C" const char *gsn_last_error(void) { return g_last_error.c_str(); }
+
+template <int N, int V> static NKernels make_kernels()
+{
+    using C = Cfg<N, V>;
+    constexpr int E = C::E, LL = C::LM_LINES, EL = C::EM_LINES;
+    NKernels k;
+    k.E = E;
+    k.TPL = C::TPL;
+    k.lm_lines = LL;
+    k.em_lines = EL;
+    k.em_fwd = k_em_fft<N, E, EL, -1>;
+    k.em_inv = k_em_fft<N, E, EL, 1>;
+    k.density = k_density<N, E, EL, false>;
+    k.density_store = k_density<N, E, EL, true>;
+    k.phase = k_phase<N, E, EL, false, false>;
+    k.phase_real = k_phase<N, E, EL, false, true>;
+    k.phase_energy = k_phase<N, E, EL, true, false>;
+    k.potential = k_potential<N, E, EL>;
+    k.lm_fwd = k_lm<N, E, LL, LM_FWD>;
+    k.lm_inv = k_lm<N, E, LL, LM_INV>;
+    k.lm_kin = k_lm<N, E, LL, LM_KIN>;
+    k.lm_kern = k_lm<N, E, LL, LM_KERN>;
+    k.lm_kin_energy = k_lm<N, E, LL, LM_KIN_ENERGY>;
+    return k;
+}
+
+template <int N> static const NKernels *variant_table(int v)
+{
+    static const NKernels k[kNumVariants] = {make_kernels<N, 0>(), make_kernels<N, 1>()};
+    return &k[v];
+}
+
+const NKernels *kernels_for(int N, int v)
+{
+    if (v < 0 || v >= kNumVariants) v = 0;
+    switch (N) {
+    case 8: return variant_table<8>(v);
+    case 16: return variant_table<16>(v);
+    case 32: return variant_table<32>(v);
+    case 64: return variant_table<64>(v);
+    case 128: return variant_table<128>(v);
+    case 256: return variant_table<256>(v);
+    case 512: return variant_table<512>(v);
+    case 1024: return variant_table<1024>(v);
+    case 2048: return variant_table<2048>(v);
+    default: return nullptr;
+    }
+}
+
 
 // ------------------------------------------------------------------ passes
 enum PassId {
@@ -37,6 +87,10 @@ struct Launch {
     EmArgs ea;
     LmArgs la;
     int pass;
+};
+
+struct StepLists {
+    std::vector<Launch> entry, kin_half, kin_full, nonlin, exit_;
 };
 
 struct gsn_grid_ {
@@ -65,6 +119,11 @@ struct gsn_grid_ {
     bool have_dz, have_psi;
     // launch schedules
     std::vector<Launch> entry, kin_half, kin_full, nonlin, exit_, energy_rho, energy_kin;
+    std::vector<Launch> pot;      // potential readout (phi pointer set per call)
+    StepLists coarse;             // one coarse step of coarse_ratio * dz
+    int coarse_ratio;             // 0 = no coarse schedule
+    double2 *kinFc[3], *kinHc[3]; // kinetic tables of the coarse step
+    DevState *st_save[2];         // device copies of the state for audits
     int density_blocks;
 };
 
@@ -120,8 +179,8 @@ static Layout compute_layout(int ndim, const int32_t n[])
     L.st = off; off = align256(off + sizeof(DevState));
     L.tables = off;
     size_t tb = 0;
-    for (int d = 0; d < ndim; ++d) tb += align256(16ull * n[d]) * 3 + align256(8ull * n[d]);
-    tb += 512;
+    for (int d = 0; d < ndim; ++d) tb += align256(16ull * n[d]) * 5 + align256(8ull * n[d]);
+    tb += 512 + 512;
     off = align256(off + tb);
     L.total = off;
     return L;
@@ -216,7 +275,7 @@ static double kernel_k0(const gsn_kernel &k)
 }
 
 // Build every launch list from the current parameters (pointers never move).
-static void build_schedule(gsn_grid g)
+static void build_core(gsn_grid g)
 {
     const int nd = g->ndim, Nx = g->Nx, Ny = g->Ny, Nz = g->Nz;
     const int X = nd - 1, Y = nd - 2, Z = 0;   // table indices by axis
@@ -370,6 +429,50 @@ static void build_schedule(gsn_grid g)
     }
 }
 
+// Every launch list: the fine step lists, the energy lists, the potential
+// readout and (when a coarse ratio is set) the step lists of one coarse step,
+// built by the same code with dz and the kinetic tables swapped.
+static void build_schedule(gsn_grid g)
+{
+    build_core(g);
+    if (g->coarse_ratio > 0) {
+        StepLists fine{std::move(g->entry), std::move(g->kin_half), std::move(g->kin_full), std::move(g->nonlin),
+                       std::move(g->exit_)};
+        std::vector<Launch> er = std::move(g->energy_rho), ek = std::move(g->energy_kin);
+        const double dz = g->dz;
+        double2 *kf[3], *kh[3];
+        for (int d = 0; d < 3; ++d) { kf[d] = g->kinF[d]; kh[d] = g->kinH[d]; }
+        g->dz = dz * g->coarse_ratio;
+        for (int d = 0; d < g->ndim; ++d) { g->kinF[d] = g->kinFc[d]; g->kinH[d] = g->kinHc[d]; }
+        build_core(g);
+        g->coarse = StepLists{std::move(g->entry), std::move(g->kin_half), std::move(g->kin_full),
+                              std::move(g->nonlin), std::move(g->exit_)};
+        g->dz = dz;
+        for (int d = 0; d < 3; ++d) { g->kinF[d] = kf[d]; g->kinH[d] = kh[d]; }
+        g->entry = std::move(fine.entry);
+        g->kin_half = std::move(fine.kin_half);
+        g->kin_full = std::move(fine.kin_full);
+        g->nonlin = std::move(fine.nonlin);
+        g->exit_ = std::move(fine.exit_);
+        g->energy_rho = std::move(er);
+        g->energy_kin = std::move(ek);
+    }
+    // potential readout: x-FFT of a copy of psi, density, potential passes, C2R
+    g->pot.clear();
+    for (const Launch &L : g->entry) {
+        Launch c = L;
+        c.ea.psi = g->scratch;
+        g->pot.push_back(c);
+    }
+    for (size_t i = 0; i + 1 < g->energy_rho.size(); ++i) g->pot.push_back(g->energy_rho[i]);
+    {
+        const NKernels *kx = kernels_for(g->Nx, g->var[P_PHASE]);
+        EmArgs a = em_base(g, g->scratch);
+        a.nlines = (int)(g->P / g->Nx / 2);
+        g->pot.push_back(em_launch(kx->potential, kx, a, P_PHASE));
+    }
+}
+
 static hipError_t launch(const Launch &L, hipStream_t s)
 {
     void *args[1];
@@ -394,23 +497,30 @@ static gsn_status upload(gsn_grid g, void *dst, const void *src, size_t bytes)
     return GSN_OK;
 }
 
-static gsn_status upload_kinetic(gsn_grid g)
+static gsn_status upload_kinetic_tables(gsn_grid g, double dz, double2 *const *kf, double2 *const *kh)
 {
     for (int d = 0; d < g->ndim; ++d) {
         const int N = g->n[d];
         std::vector<double2> f(N), h(N);
         for (int j = 0; j < N; ++j) {
             const double k = wavenumber(j, N, g->L[d]);
-            const double thf = -g->a * k * k * g->dz, thh = 0.5 * thf;
+            const double thf = -g->a * k * k * dz, thh = 0.5 * thf;
             f[j] = make_double2(std::cos(thf), std::sin(thf));
             h[j] = make_double2(std::cos(thh), std::sin(thh));
         }
-        gsn_status s = upload(g, g->kinF[d], f.data(), 16ull * N);
+        gsn_status s = upload(g, kf[d], f.data(), 16ull * N);
         if (s) return s;
-        s = upload(g, g->kinH[d], h.data(), 16ull * N);
+        s = upload(g, kh[d], h.data(), 16ull * N);
         if (s) return s;
     }
     return GSN_OK;
+}
+
+static gsn_status upload_kinetic(gsn_grid g)
+{
+    gsn_status s = upload_kinetic_tables(g, g->dz, g->kinF, g->kinH);
+    if (s || g->coarse_ratio <= 0) return s;
+    return upload_kinetic_tables(g, g->dz * g->coarse_ratio, g->kinFc, g->kinHc);
 }
 
 static gsn_status upload_static_tables(gsn_grid g)
@@ -488,9 +598,14 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
         g->kinF[d] = (double2 *)(ws + off); off += align256(16ull * n[d]);
         g->kinH[d] = (double2 *)(ws + off); off += align256(16ull * n[d]);
         g->k2[d] = (double *)(ws + off); off += align256(8ull * n[d]);
+        g->kinFc[d] = (double2 *)(ws + off); off += align256(16ull * n[d]);
+        g->kinHc[d] = (double2 *)(ws + off); off += align256(16ull * n[d]);
     }
     g->k2_unit = (double *)(ws + off); off += 256;
     g->kin_unit = (double2 *)(ws + off); off += 256;
+    g->st_save[0] = (DevState *)(ws + off); off += 256;
+    g->st_save[1] = (DevState *)(ws + off); off += 256;
+    g->coarse_ratio = 0;
     if ((s = upload_static_tables(g)) || (s = upload_kinetic(g))) {
         delete g;
         return s;
@@ -1001,5 +1116,118 @@ extern "C" gsn_status gsn_get_nonlinear_mode(gsn_grid g, int *mode)
 {
     if (!g || !mode) return fail(GSN_EINVAL, "NULL argument");
     *mode = g->store_psi;
+    return GSN_OK;
+}
+
+// ------------------------------------------------------------------ coarse steps and the learned corrector
+extern "C" gsn_status gsn_set_coarse_ratio(gsn_grid g, int ratio)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (ratio < 0 || ratio > 4096) return fail(GSN_EINVAL, "ratio must be in [0, 4096]");
+    if (ratio > 0 && !g->have_dz) return fail(GSN_ESTATE, "set the coefficients (dz) first");
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->coarse_ratio = ratio;
+    gsn_status s = upload_kinetic(g);
+    if (s) return s;
+    build_schedule(g);
+    return GSN_OK;
+}
+
+static gsn_status run_potential(gsn_grid g, float *dst)
+{
+    HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, 8ull * g->P, hipMemcpyDeviceToDevice, g->stream));
+    for (Launch L : g->pot) {
+        if (L.em) L.ea.phi = dst;
+        HIP_TRY(launch(L, g->stream));
+    }
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_potential(gsn_grid g, float *phi_dev)
+{
+    if (!g || !phi_dev) return fail(GSN_EINVAL, "NULL argument");
+    if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
+    HIP_TRY(hipSetDevice(g->device));
+    return run_potential(g, phi_dev);
+}
+
+static gsn_status run_lists(gsn_grid g, const StepLists &L, int64_t nsteps)
+{
+    gsn_status s;
+    if ((s = run_list(g, L.entry)) || (s = run_list(g, L.kin_half))) return s;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        if ((s = run_list(g, L.nonlin))) return s;
+        if ((s = run_list(g, i + 1 < nsteps ? L.kin_full : L.kin_half))) return s;
+    }
+    return run_list(g, L.exit_);
+}
+
+extern "C" gsn_status gsn_step_coarse(gsn_grid g, int64_t nsteps)
+{
+    gsn_status s = ready(g);
+    if (s) return s;
+    if (g->coarse_ratio <= 0) return fail(GSN_ESTATE, "no coarse ratio set");
+    if (nsteps < 0) return fail(GSN_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return GSN_OK;
+    HIP_TRY(hipSetDevice(g->device));
+    return run_lists(g, g->coarse, nsteps);
+}
+
+extern "C" gsn_status gsn_step_corrected(gsn_grid g, gsn_corrector c, int64_t ncoarse, int audit_every, double tol,
+                                         int64_t *n_fallbacks, double *max_audit_err)
+{
+    gsn_status s = ready(g);
+    if (s) return s;
+    if (!c) return fail(GSN_EINVAL, "corrector is NULL");
+    if (g->ndim != 2) return fail(GSN_EUNSUPPORTED, "the corrector works on 2-D grids");
+    if (corrector_height(c) != g->n[0] || corrector_width(c) != g->n[1])
+        return fail(GSN_EINVAL, "corrector image size differs from the grid");
+    if (g->coarse_ratio <= 0) return fail(GSN_ESTATE, "no coarse ratio set");
+    if (ncoarse < 0 || audit_every < 0 || !(tol >= 0.0)) return fail(GSN_EINVAL, "bad stepping arguments");
+    HIP_TRY(hipSetDevice(g->device));
+    int64_t nfb = 0;
+    double worst = 0.0;
+    float *phi = corrector_phi_buffer(c);
+    float2 *saved = corrector_psi_buffer(c, 0), *corrected = corrector_psi_buffer(c, 1);
+    const size_t bytes = 8ull * g->P;
+    for (int64_t i = 0; i < ncoarse; ++i) {
+        const bool audit = audit_every > 0 && ((i + 1) % audit_every == 0);
+        if (audit) {
+            HIP_TRY(hipMemcpyAsync(saved, g->psi, bytes, hipMemcpyDeviceToDevice, g->stream));
+            HIP_TRY(hipMemcpyAsync(g->st_save[0], g->st, sizeof(DevState), hipMemcpyDeviceToDevice, g->stream));
+        }
+        if ((s = run_lists(g, g->coarse, 1))) return s;
+        if ((s = run_potential(g, phi))) return s;
+        if ((s = corrector_correct_inplace(c, g->psi, phi, g->stream))) return s;
+        if (audit) {
+            // the fine solver from the same state is the judge of the corrected step
+            HIP_TRY(hipMemcpyAsync(corrected, g->psi, bytes, hipMemcpyDeviceToDevice, g->stream));
+            HIP_TRY(hipMemcpyAsync(g->st_save[1], g->st, sizeof(DevState), hipMemcpyDeviceToDevice, g->stream));
+            HIP_TRY(hipMemcpyAsync(g->psi, saved, bytes, hipMemcpyDeviceToDevice, g->stream));
+            HIP_TRY(hipMemcpyAsync(g->st, g->st_save[0], sizeof(DevState), hipMemcpyDeviceToDevice, g->stream));
+            StepLists fine{g->entry, g->kin_half, g->kin_full, g->nonlin, g->exit_};
+            if ((s = run_lists(g, fine, g->coarse_ratio))) return s;
+            const int nb = 256;
+            hipLaunchKernelGGL(k_state_diff, dim3(nb), dim3(256), 0, g->stream, corrected, g->st_save[1], g->psi,
+                               g->st, g->P, g->epart);
+            HIP_TRY(hipGetLastError());
+            std::vector<double> h(2 * nb);
+            HIP_TRY(hipMemcpyAsync(h.data(), g->epart, 16ull * nb, hipMemcpyDeviceToHost, g->stream));
+            HIP_TRY(hipStreamSynchronize(g->stream));
+            double d = 0.0, n = 0.0;
+            for (int b = 0; b < nb; ++b) { d += h[2 * b]; n += h[2 * b + 1]; }
+            const double err = n > 0.0 ? std::sqrt(d / n) : 0.0;
+            if (!(err <= worst)) worst = err;
+            if (!(err <= tol)) {
+                ++nfb;   // keep the fine result already in psi
+            } else {
+                HIP_TRY(hipMemcpyAsync(g->psi, corrected, bytes, hipMemcpyDeviceToDevice, g->stream));
+                HIP_TRY(hipMemcpyAsync(g->st, g->st_save[1], sizeof(DevState), hipMemcpyDeviceToDevice, g->stream));
+            }
+        }
+    }
+    if (n_fallbacks) *n_fallbacks = nfb;
+    if (max_audit_err) *max_audit_err = worst;
     return GSN_OK;
 }

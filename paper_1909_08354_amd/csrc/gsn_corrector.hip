@@ -1,0 +1,675 @@
+// gsn_corrector.hip -- learned corrector for coarse split steps on gfx950.
+//
+// A 4-layer 3x3 convolutional network (3 -> 32 -> 32 -> 32 -> 2 channels,
+// ReLU after the first three, circular padding) reads (Re psi_c, Im psi_c,
+// phi_c) of a coarse step and predicts the residual to the fine result.
+// Activations and weights are bfloat16, every product accumulates in FP32 on
+// the matrix cores (v_mfma_f32_16x16x16_bf16), the master weights and Adam
+// moments are FP32.  Convolutions are implicit GEMMs over NHWC images:
+//   forward        M = pixels, N = Cout, K = 9 * Cin   (A: input, B: weights)
+//   backward data  M = pixels, N = Cin,  K = 9 * Cout  (A: dZ,    B: weights^T)
+//   backward wts   M = Cout,   N = Cin,  K = pixels    (A: dZ^T,  B: input^T)
+// MFMA 16x16x16 operand layout (64 lanes, l = lane): A[i = l%16][k = 4(l/16)+0..3],
+// B[k = 4(l/16)+0..3][j = l%16], D[i = 4(l/16)+0..3][j = l%16].
+// Weight gradients are reduced from per-block partials in a fixed order, so
+// training is bitwise deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "gsn_host.hpp"
+#include "gsn_corrector_internal.hpp"
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+constexpr int kNParams = 19970;
+constexpr int kLayers = 4;
+// per layer: real and padded channel counts
+constexpr int kCin[kLayers] = {3, 32, 32, 32};
+constexpr int kCout[kLayers] = {32, 32, 32, 2};
+constexpr int kCinP[kLayers] = {4, 32, 32, 32};
+constexpr int kCoutP[kLayers] = {32, 32, 32, 16};
+
+__device__ inline u16 f2bf(float f)
+{
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (u16)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ inline float bf2f(u16 h) { return __uint_as_float(((unsigned)h) << 16); }
+
+__device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// ---------------------------------------------------------------- forward conv
+template <int CIN_P, int COUT_P, int COUT, bool RELU, bool OUT_F32>
+__global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X, const u16 *__restrict__ Wf,
+                                                  const float *__restrict__ bias, void *__restrict__ Y,
+                                                  int H, int W, long long npix)
+{
+    constexpr int KTOT = 9 * CIN_P, KCH = (KTOT + 15) / 16, NB = COUT_P / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long pix0 = ((long long)blockIdx.x * 4 + wave) * 16;
+    if (pix0 >= npix) return;
+    const long long HW = (long long)H * W;
+    const long long pa = pix0 + (lane & 15);
+    const long long img = pa / HW;
+    const int rem = (int)(pa - img * HW), y = rem / W, x = rem - (rem / W) * W;
+    const int kq = 4 * (lane >> 4);
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kc = 0; kc < KCH; ++kc) {
+        const int k = kc * 16 + kq;
+        const int tap = k / CIN_P, c0 = k - tap * CIN_P;
+        bf16x4 av = {0, 0, 0, 0};
+        if (tap < 9) {
+            const int ys = wrap(y + tap / 3 - 1, H), xs = wrap(x + tap % 3 - 1, W);
+            av = *(const bf16x4 *)(X + ((img * H + ys) * W + xs) * CIN_P + c0);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            bf16x4 bv = {0, 0, 0, 0};
+            if (tap < 9) bv = *(const bf16x4 *)(Wf + ((long long)tap * COUT_P + nb * 16 + (lane & 15)) * CIN_P + c0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int ch = nb * 16 + (lane & 15);
+        const float bch = bias[ch];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long long p = pix0 + 4 * (lane >> 4) + r;
+            float v = acc[nb][r] + bch;
+            if (RELU) v = v > 0.f ? v : 0.f;
+            if constexpr (OUT_F32) {
+                if (ch < COUT) ((float *)Y)[p * COUT + ch] = v;
+            } else {
+                ((u16 *)Y)[p * COUT_P + ch] = f2bf(v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- backward data
+// dX[q][ci] = sum_tap sum_co dZ[q - off(tap)][co] W[tap][co][ci], masked by the
+// ReLU of the layer below (Aprev > 0), written as bf16.
+template <int CIN_P, int COUT_P>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const u16 *__restrict__ dZ, const u16 *__restrict__ Wb,
+                                                       const u16 *__restrict__ Aprev, u16 *__restrict__ dX,
+                                                       int H, int W, long long npix)
+{
+    constexpr int KTOT = 9 * COUT_P, KCH = KTOT / 16, NB = CIN_P / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long pix0 = ((long long)blockIdx.x * 4 + wave) * 16;
+    if (pix0 >= npix) return;
+    const long long HW = (long long)H * W;
+    const long long pa = pix0 + (lane & 15);
+    const long long img = pa / HW;
+    const int rem = (int)(pa - img * HW), y = rem / W, x = rem - (rem / W) * W;
+    const int kq = 4 * (lane >> 4);
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kc = 0; kc < KCH; ++kc) {
+        const int k = kc * 16 + kq;
+        const int tap = k / COUT_P, c0 = k - tap * COUT_P;
+        const int ys = wrap(y - (tap / 3 - 1), H), xs = wrap(x - (tap % 3 - 1), W);
+        const bf16x4 av = *(const bf16x4 *)(dZ + ((img * H + ys) * W + xs) * COUT_P + c0);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const bf16x4 bv = *(const bf16x4 *)(Wb + ((long long)tap * CIN_P + nb * 16 + (lane & 15)) * COUT_P + c0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int ch = nb * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long long p = pix0 + 4 * (lane >> 4) + r;
+            const float v = bf2f(Aprev[p * CIN_P + ch]) > 0.f ? acc[nb][r] : 0.f;
+            dX[p * CIN_P + ch] = f2bf(v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- backward weights
+// Per block, over its chunks of 64 flat pixels: dW[tap][co][ci] += dZ^T Xs and
+// db[co] += sum dZ, staged through LDS transposed (channel-major) so every
+// MFMA operand is one 8-byte read.  Partials go to part[block][...].
+template <int CIN_P, int COUT_P>
+__global__ __launch_bounds__(256) void k_conv_bwd_w(const u16 *__restrict__ X, const u16 *__restrict__ dZ,
+                                                    float *__restrict__ part, int H, int W, long long npix)
+{
+    constexpr int CINN = CIN_P < 16 ? 16 : CIN_P;
+    constexpr int MB = COUT_P / 16, NB = CINN / 16, NBLK = 9 * MB * NB;
+    constexpr int PER_WAVE = (NBLK + 3) / 4;
+    constexpr int PSTRIDE = 9 * COUT_P * CINN + COUT_P;
+    __shared__ __align__(16) u16 xs[9 * CINN * 64];
+    __shared__ __align__(16) u16 dz[COUT_P * 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long HW = (long long)H * W;
+    const long long nchunks = npix / 64;
+    f32x4 acc[PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < PER_WAVE; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dbias = 0.f;
+    for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const long long p0 = c * 64;
+        for (int e = tid; e < 9 * CINN * 64; e += 256) {
+            const int px = e & 63, ci = (e >> 6) % CINN, tap = (e >> 6) / CINN;
+            u16 v = 0;
+            if (ci < CIN_P) {
+                const long long p = p0 + px, img = p / HW;
+                const int rem = (int)(p - img * HW), y = rem / W, x = rem - (rem / W) * W;
+                const int ys = wrap(y + tap / 3 - 1, H), xx = wrap(x + tap % 3 - 1, W);
+                v = X[((img * H + ys) * W + xx) * CIN_P + ci];
+            }
+            xs[e] = v;
+        }
+        for (int e = tid; e < COUT_P * 64; e += 256) {
+            const int px = e & 63, co = e >> 6;
+            dz[e] = dZ[(p0 + px) * COUT_P + co];
+        }
+        __syncthreads();
+        if (tid < COUT_P) {
+            float s = 0.f;
+            for (int px = 0; px < 64; ++px) s += bf2f(dz[tid * 64 + px]);
+            dbias += s;
+        }
+#pragma unroll
+        for (int i = 0; i < PER_WAVE; ++i) {
+            const int blk = wave + 4 * i;
+            if (blk < NBLK) {
+                const int tap = blk / (MB * NB), mb = (blk / NB) % MB, nb = blk % NB;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int pk = kk * 16 + 4 * (lane >> 4);
+                    const bf16x4 av = *(const bf16x4 *)(dz + (mb * 16 + (lane & 15)) * 64 + pk);
+                    const bf16x4 bv = *(const bf16x4 *)(xs + (tap * CINN + nb * 16 + (lane & 15)) * 64 + pk);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[i], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *out = part + (long long)blockIdx.x * PSTRIDE;
+#pragma unroll
+    for (int i = 0; i < PER_WAVE; ++i) {
+        const int blk = wave + 4 * i;
+        if (blk < NBLK) {
+            const int tap = blk / (MB * NB), mb = (blk / NB) % MB, nb = blk % NB;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = mb * 16 + 4 * (lane >> 4) + r, ci = nb * 16 + (lane & 15);
+                out[(tap * COUT_P + co) * CINN + ci] = acc[i][r];
+            }
+        }
+    }
+    if (tid < COUT_P) out[9 * COUT_P * CINN + tid] = dbias;
+}
+
+// Sum the per-block partials of one layer into the flat gradient (fixed order).
+__global__ void k_reduce_grad(const float *__restrict__ part, int nparts, int pstride, int cin, int cout,
+                              int cinn, int coutp, float *__restrict__ gflat)
+{
+    const int nw = 9 * cout * cin;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw + cout) return;
+    int src;
+    if (i < nw) {
+        const int tap = i / (cout * cin), co = (i / cin) % cout, ci = i % cin;
+        src = (tap * coutp + co) * cinn + ci;
+    } else {
+        src = 9 * coutp * cinn + (i - nw);
+    }
+    float s = 0.f;
+    for (int b = 0; b < nparts; ++b) s += part[(long long)b * pstride + src];
+    gflat[i] = s;
+}
+
+// ---------------------------------------------------------------- loss, Adam, packing
+// MSE over the two output channels; dZ4 = 2 (out - target) / count as bf16
+// (16 padded channels), per-block FP32 partial of the squared error.
+__global__ __launch_bounds__(256) void k_mse(const float *__restrict__ out, const float *__restrict__ tgt,
+                                             u16 *__restrict__ dz4, float inv_count, long long npix,
+                                             double *__restrict__ part)
+{
+    __shared__ double sh[5];
+    double s = 0.0;
+    for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < npix; p += (long long)gridDim.x * 256) {
+        const float d0 = out[2 * p] - tgt[2 * p], d1 = out[2 * p + 1] - tgt[2 * p + 1];
+        s += (double)d0 * d0 + (double)d1 * d1;
+        u16 *o = dz4 + p * 16;
+        o[0] = f2bf(2.f * d0 * inv_count);
+        o[1] = f2bf(2.f * d1 * inv_count);
+#pragma unroll
+        for (int c = 2; c < 16; ++c) o[c] = 0;
+    }
+    s = block_sum<256>(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
+                       float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Master FP32 flat weights -> bf16 forward [tap][coutp][cinp] and backward
+// [tap][cinp][coutp] layouts (zero padded) and FP32 padded biases.
+__global__ void k_refresh(const float *__restrict__ flat, int off, int cin, int cout, int cinp, int coutp,
+                          u16 *__restrict__ wf, u16 *__restrict__ wb, float *__restrict__ bias)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = 9 * coutp * cinp;
+    if (i < n) {
+        const int tap = i / (coutp * cinp), co = (i / cinp) % coutp, ci = i % cinp;
+        const float v = (co < cout && ci < cin) ? flat[off + (tap * cout + co) * cin + ci] : 0.f;
+        const u16 h = f2bf(v);
+        wf[(tap * coutp + co) * cinp + ci] = h;
+        wb[(tap * cinp + ci) * coutp + co] = h;
+    }
+    if (i < coutp) bias[i] = i < cout ? flat[off + 9 * cout * cin + i] : 0.f;
+}
+
+// Input features of image b: (Re psi, Im psi, phi) times the input scales, bf16.
+__global__ void k_pack(const float2 *__restrict__ psi, const float *__restrict__ phi, u16 *__restrict__ x,
+                       long long n, float s0, float s1, float s2)
+{
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const float2 v = psi[p];
+        u16 *o = x + p * 4;
+        o[0] = f2bf(v.x * s0);
+        o[1] = f2bf(v.y * s1);
+        o[2] = f2bf(phi[p] * s2);
+        o[3] = 0;
+    }
+}
+
+// Target of image b: (psi_fine - psi_coarse) / s_out, FP32, two channels.
+__global__ void k_pack_target(const float2 *__restrict__ fine, const float2 *__restrict__ coarse,
+                              float *__restrict__ t, long long n, float inv_s)
+{
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const float2 f = fine[p], c = coarse[p];
+        t[2 * p] = (f.x - c.x) * inv_s;
+        t[2 * p + 1] = (f.y - c.y) * inv_s;
+    }
+}
+
+// psi_out = psi_c + s_out (r0 + i r1)
+__global__ void k_apply(const float2 *__restrict__ psi_c, const float *__restrict__ out, float2 *__restrict__ psi_o,
+                        long long n, float s)
+{
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const float2 c = psi_c[p];
+        psi_o[p] = make_float2(c.x + s * out[2 * p], c.y + s * out[2 * p + 1]);
+    }
+}
+
+constexpr int kBwBlocks = 256;   // blocks of the weight-gradient kernels
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+struct gsn_corrector_ {
+    int H, W, maxB;
+    long long P;   // pixels per image
+    hipStream_t stream;
+    int device;
+    // device buffers
+    u16 *x0, *a[3], *dz4, *dza, *dzb;
+    float *out, *tgt;
+    float *wflat, *mom1, *mom2, *grad;
+    u16 *wf[kLayers], *wb[kLayers];
+    float *bias[kLayers];
+    float *part;
+    double *lpart;
+    float *phi1;
+    float2 *psic[2];
+    int step;
+    float in_scale[3], out_scale;
+};
+
+static size_t corrector_layout(int H, int W, int maxB, size_t *offs /* 16 entries or null */)
+{
+    const long long N = (long long)H * W * maxB;
+    size_t o = 0, k = 0;
+    auto take = [&](size_t bytes) {
+        if (offs) offs[k] = o;
+        ++k;
+        o = align256(o + bytes);
+    };
+    take(8ull * N);        // x0: 4 bf16 channels
+    take(64ull * N);       // a1
+    take(64ull * N);       // a2
+    take(64ull * N);       // a3
+    take(32ull * N);       // dz4: 16 bf16 channels
+    take(64ull * N);       // dza
+    take(64ull * N);       // dzb
+    take(8ull * N);        // out: 2 fp32
+    take(8ull * N);        // target
+    take(4ull * kNParams * 4);   // wflat, m, v, grad
+    size_t wsz = 0;
+    for (int l = 0; l < kLayers; ++l) wsz += 2 * align256(2ull * 9 * kCinP[l] * kCoutP[l]) + align256(4ull * kCoutP[l]);
+    take(wsz);
+    take(4ull * kBwBlocks * (9 * 32 * 32 + 32));   // weight-gradient partials
+    take(8ull * 4096);                             // loss partials
+    take(4ull * H * W);                            // phi of one image (corrected stepping)
+    take(8ull * H * W);                            // psi copy 0
+    take(8ull * H * W);                            // psi copy 1
+    return o;
+}
+
+extern "C" gsn_status gsn_corrector_workspace_bytes(int H, int W, int max_batch, size_t *bytes)
+{
+    if (!bytes) return fail(GSN_EINVAL, "bytes is NULL");
+    if (H < 8 || W < 8 || H > 4096 || W > 4096 || max_batch < 1 || max_batch > 256)
+        return fail(GSN_EINVAL, "H, W must be in [8, 4096] and max_batch in [1, 256]");
+    if (((long long)H * W) % 64 != 0) return fail(GSN_EUNSUPPORTED, "H * W must be a multiple of 64");
+    *bytes = corrector_layout(H, W, max_batch, nullptr);
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_create(gsn_corrector *out, int H, int W, int max_batch, void *d_ws,
+                                           size_t bytes, void *stream)
+{
+    if (!out) return fail(GSN_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    gsn_status s = gsn_corrector_workspace_bytes(H, W, max_batch, &need);
+    if (s) return s;
+    if (!d_ws) return fail(GSN_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(GSN_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < need) return fail(GSN_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    gsn_corrector c = new (std::nothrow) gsn_corrector_();
+    if (!c) return fail(GSN_EINVAL, "out of host memory");
+    c->H = H;
+    c->W = W;
+    c->maxB = max_batch;
+    c->P = (long long)H * W;
+    c->stream = (hipStream_t)stream;
+    c->step = 0;
+    c->in_scale[0] = c->in_scale[1] = c->in_scale[2] = 1.f;
+    c->out_scale = 1.f;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(GSN_EHIP, "hipGetDevice failed");
+    }
+    size_t off[16];
+    corrector_layout(H, W, max_batch, off);
+    char *ws = (char *)d_ws;
+    c->x0 = (u16 *)(ws + off[0]);
+    for (int i = 0; i < 3; ++i) c->a[i] = (u16 *)(ws + off[1 + i]);
+    c->dz4 = (u16 *)(ws + off[4]);
+    c->dza = (u16 *)(ws + off[5]);
+    c->dzb = (u16 *)(ws + off[6]);
+    c->out = (float *)(ws + off[7]);
+    c->tgt = (float *)(ws + off[8]);
+    c->wflat = (float *)(ws + off[9]);
+    c->mom1 = c->wflat + kNParams;
+    c->mom2 = c->mom1 + kNParams;
+    c->grad = c->mom2 + kNParams;
+    char *wp = ws + off[10];
+    for (int l = 0; l < kLayers; ++l) {
+        const size_t wsz = align256(2ull * 9 * kCinP[l] * kCoutP[l]);
+        c->wf[l] = (u16 *)wp; wp += wsz;
+        c->wb[l] = (u16 *)wp; wp += wsz;
+        c->bias[l] = (float *)wp; wp += align256(4ull * kCoutP[l]);
+    }
+    c->part = (float *)(ws + off[11]);
+    c->lpart = (double *)(ws + off[12]);
+    c->phi1 = (float *)(ws + off[13]);
+    c->psic[0] = (float2 *)(ws + off[14]);
+    c->psic[1] = (float2 *)(ws + off[15]);
+    // weights start at zero until set
+    if (hipMemsetAsync(c->wflat, 0, 16ull * kNParams, c->stream) != hipSuccess) {
+        delete c;
+        return fail(GSN_EHIP, "hipMemsetAsync failed");
+    }
+    *out = c;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_destroy(gsn_corrector c)
+{
+    if (!c) return fail(GSN_EINVAL, "corrector is NULL");
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+    return GSN_OK;
+}
+
+static gsn_status refresh(gsn_corrector c)
+{
+    int off = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const int n = 9 * kCinP[l] * kCoutP[l];
+        hipLaunchKernelGGL(k_refresh, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->wflat, off, kCin[l],
+                           kCout[l], kCinP[l], kCoutP[l], c->wf[l], c->wb[l], c->bias[l]);
+        HIP_TRY(hipGetLastError());
+        off += 9 * kCin[l] * kCout[l] + kCout[l];
+    }
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_set_weights(gsn_corrector c, const float *w, size_t n)
+{
+    if (!c || !w) return fail(GSN_EINVAL, "NULL argument");
+    if (n != (size_t)kNParams) return fail(GSN_EINVAL, "expected 19970 weights");
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(w[i])) return fail(GSN_EINVAL, "weights must be finite");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipMemcpyAsync(c->wflat, w, 4ull * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemsetAsync(c->mom1, 0, 8ull * n, c->stream));   // Adam moments m and v
+    c->step = 0;
+    gsn_status s = refresh(c);
+    if (s) return s;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_get_weights(gsn_corrector c, float *w, size_t n)
+{
+    if (!c || !w) return fail(GSN_EINVAL, "NULL argument");
+    if (n != (size_t)kNParams) return fail(GSN_EINVAL, "expected 19970 weights");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipMemcpyAsync(w, c->wflat, 4ull * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_set_scales(gsn_corrector c, const float in_scale[3], float out_scale)
+{
+    if (!c || !in_scale) return fail(GSN_EINVAL, "NULL argument");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(in_scale[i])) return fail(GSN_EINVAL, "scales must be finite");
+    if (!(std::isfinite(out_scale) && out_scale != 0.f)) return fail(GSN_EINVAL, "out_scale must be finite and != 0");
+    for (int i = 0; i < 3; ++i) c->in_scale[i] = in_scale[i];
+    c->out_scale = out_scale;
+    return GSN_OK;
+}
+
+static gsn_status check_slot(gsn_corrector c, int b)
+{
+    if (!c) return fail(GSN_EINVAL, "corrector is NULL");
+    if (b < 0 || b >= c->maxB) return fail(GSN_EINVAL, "image slot out of range");
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_pack(gsn_corrector c, int b, const void *psi, const float *phi)
+{
+    gsn_status s = check_slot(c, b);
+    if (s) return s;
+    if (!psi || !phi) return fail(GSN_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_pack, dim3(512), dim3(256), 0, c->stream, (const float2 *)psi, phi, c->x0 + 4 * c->P * b,
+                       c->P, c->in_scale[0], c->in_scale[1], c->in_scale[2]);
+    HIP_TRY(hipGetLastError());
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_pack_target(gsn_corrector c, int b, const void *psi_fine, const void *psi_coarse)
+{
+    gsn_status s = check_slot(c, b);
+    if (s) return s;
+    if (!psi_fine || !psi_coarse) return fail(GSN_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_pack_target, dim3(512), dim3(256), 0, c->stream, (const float2 *)psi_fine,
+                       (const float2 *)psi_coarse, c->tgt + 2 * c->P * b, c->P, 1.f / c->out_scale);
+    HIP_TRY(hipGetLastError());
+    return GSN_OK;
+}
+
+// forward over B packed images: a1..a3 stashed, out (FP32, 2 channels)
+static gsn_status forward(gsn_corrector c, int B)
+{
+    const long long np = c->P * B;
+    const dim3 grid((unsigned)(np / 64)), block(256);
+    const int H = c->H, W = c->W;
+    hipLaunchKernelGGL((k_conv_fwd<4, 32, 32, true, false>), grid, block, 0, c->stream, c->x0, c->wf[0], c->bias[0],
+                       (void *)c->a[0], H, W, np);
+    hipLaunchKernelGGL((k_conv_fwd<32, 32, 32, true, false>), grid, block, 0, c->stream, c->a[0], c->wf[1],
+                       c->bias[1], (void *)c->a[1], H, W, np);
+    hipLaunchKernelGGL((k_conv_fwd<32, 32, 32, true, false>), grid, block, 0, c->stream, c->a[1], c->wf[2],
+                       c->bias[2], (void *)c->a[2], H, W, np);
+    hipLaunchKernelGGL((k_conv_fwd<32, 16, 2, false, true>), grid, block, 0, c->stream, c->a[2], c->wf[3],
+                       c->bias[3], (void *)c->out, H, W, np);
+    HIP_TRY(hipGetLastError());
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_forward(gsn_corrector c, int B, float *out_dev)
+{
+    if (!c) return fail(GSN_EINVAL, "corrector is NULL");
+    if (B < 1 || B > c->maxB) return fail(GSN_EINVAL, "batch size out of range");
+    HIP_TRY(hipSetDevice(c->device));
+    gsn_status s = forward(c, B);
+    if (s) return s;
+    if (out_dev)
+        HIP_TRY(hipMemcpyAsync(out_dev, c->out, 8ull * c->P * B, hipMemcpyDeviceToDevice, c->stream));
+    return GSN_OK;
+}
+
+// forward + loss + backward into c->grad (flat FP32); loss returned (synchronising)
+static gsn_status gradients(gsn_corrector c, int B, float *loss)
+{
+    const long long np = c->P * B;
+    const dim3 grid((unsigned)(np / 64)), block(256);
+    const int H = c->H, W = c->W;
+    gsn_status s = forward(c, B);
+    if (s) return s;
+    const int nlb = 1024;
+    hipLaunchKernelGGL(k_mse, dim3(nlb), block, 0, c->stream, c->out, c->tgt, c->dz4, 1.f / (float)(2 * np), np,
+                       c->lpart);
+    // layer 4 (32 -> 2, padded 16): weight grads, then data grads into dza
+    const int pstride_h = 9 * 32 * 32 + 32;
+    int offs[kLayers], o = 0;
+    for (int l = 0; l < kLayers; ++l) { offs[l] = o; o += 9 * kCin[l] * kCout[l] + kCout[l]; }
+    hipLaunchKernelGGL((k_conv_bwd_w<32, 16>), dim3(kBwBlocks), block, 0, c->stream, c->a[2], c->dz4, c->part, H, W, np);
+    hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 2 + 2 + 255) / 256), dim3(256), 0, c->stream, c->part,
+                       kBwBlocks, 9 * 16 * 32 + 16, 32, 2, 32, 16, c->grad + offs[3]);
+    hipLaunchKernelGGL((k_conv_bwd_data<32, 16>), grid, block, 0, c->stream, c->dz4, c->wb[3], c->a[2], c->dza, H, W, np);
+    // layer 3
+    hipLaunchKernelGGL((k_conv_bwd_w<32, 32>), dim3(kBwBlocks), block, 0, c->stream, c->a[1], c->dza, c->part, H, W, np);
+    hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
+                       kBwBlocks, pstride_h, 32, 32, 32, 32, c->grad + offs[2]);
+    hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dza, c->wb[2], c->a[1], c->dzb, H, W, np);
+    // layer 2
+    hipLaunchKernelGGL((k_conv_bwd_w<32, 32>), dim3(kBwBlocks), block, 0, c->stream, c->a[0], c->dzb, c->part, H, W, np);
+    hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
+                       kBwBlocks, pstride_h, 32, 32, 32, 32, c->grad + offs[1]);
+    hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dzb, c->wb[1], c->a[0], c->dza, H, W, np);
+    // layer 1 (3 -> 32, input padded to 4 channels; no data gradient needed)
+    hipLaunchKernelGGL((k_conv_bwd_w<4, 32>), dim3(kBwBlocks), block, 0, c->stream, c->x0, c->dza, c->part, H, W, np);
+    hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 3 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
+                       kBwBlocks, 9 * 32 * 16 + 32, 3, 32, 16, 32, c->grad + offs[0]);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> h(nlb);
+    HIP_TRY(hipMemcpyAsync(h.data(), c->lpart, 8ull * nlb, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    for (double v : h) sum += v;
+    if (loss) *loss = (float)(sum / (double)(2 * np));
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_gradients(gsn_corrector c, int B, float *grad_host, float *loss)
+{
+    if (!c) return fail(GSN_EINVAL, "corrector is NULL");
+    if (B < 1 || B > c->maxB) return fail(GSN_EINVAL, "batch size out of range");
+    HIP_TRY(hipSetDevice(c->device));
+    gsn_status s = gradients(c, B, loss);
+    if (s) return s;
+    if (grad_host) {
+        HIP_TRY(hipMemcpyAsync(grad_host, c->grad, 4ull * kNParams, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_corrector_train_step(gsn_corrector c, int B, float lr, float *loss)
+{
+    if (!c) return fail(GSN_EINVAL, "corrector is NULL");
+    if (B < 1 || B > c->maxB) return fail(GSN_EINVAL, "batch size out of range");
+    if (!(std::isfinite(lr) && lr > 0.f)) return fail(GSN_EINVAL, "lr must be finite and > 0");
+    HIP_TRY(hipSetDevice(c->device));
+    gsn_status s = gradients(c, B, loss);
+    if (s) return s;
+    if (loss && !std::isfinite(*loss)) return fail(GSN_ENONFINITE, "training loss is not finite");
+    c->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)c->step), c2 = 1.f - std::pow(b2, (float)c->step);
+    hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, c->stream, c->wflat, c->mom1, c->mom2,
+                       c->grad, kNParams, lr, b1, b2, 1e-8f, c1, c2);
+    HIP_TRY(hipGetLastError());
+    return refresh(c);
+}
+
+extern "C" gsn_status gsn_corrector_apply(gsn_corrector c, int b, const void *psi_c, void *psi_out)
+{
+    gsn_status s = check_slot(c, b);
+    if (s) return s;
+    if (!psi_c || !psi_out) return fail(GSN_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_apply, dim3(512), dim3(256), 0, c->stream, (const float2 *)psi_c, c->out + 2 * c->P * b,
+                       (float2 *)psi_out, c->P, c->out_scale);
+    HIP_TRY(hipGetLastError());
+    return GSN_OK;
+}
+
+// ------------------------------------------------------------------ internal hooks for corrected stepping
+gsn_status corrector_correct_inplace(gsn_corrector c, float2 *psi, const float *phi, hipStream_t s)
+{
+    hipStream_t keep = c->stream;
+    c->stream = s;
+    gsn_status st = gsn_corrector_pack(c, 0, psi, phi);
+    if (!st) st = forward(c, 1);
+    if (!st) st = gsn_corrector_apply(c, 0, psi, psi);
+    c->stream = keep;
+    return st;
+}
+
+int corrector_height(gsn_corrector c) { return c->H; }
+float *corrector_phi_buffer(gsn_corrector c) { return c->phi1; }
+float2 *corrector_psi_buffer(gsn_corrector c, int which) { return c->psic[which & 1]; }
+int corrector_width(gsn_corrector c) { return c->W; }

@@ -40,6 +40,7 @@ struct NKernels {
     void (*phase)(EmArgs);
     void (*phase_real)(EmArgs);
     void (*phase_energy)(EmArgs);
+    void (*potential)(EmArgs);
     void (*lm_fwd)(LmArgs);
     void (*lm_inv)(LmArgs);
     void (*lm_kin)(LmArgs);
@@ -63,53 +64,9 @@ template <int N, int V> struct Cfg {
     static constexpr int EM_LINES = (256 / TPL) > 64 ? 64 : (256 / TPL) < 1 ? 1 : 256 / TPL;
 };
 
-template <int N, int V> static NKernels make_kernels()
-{
-    using C = Cfg<N, V>;
-    constexpr int E = C::E, LL = C::LM_LINES, EL = C::EM_LINES;
-    NKernels k;
-    k.E = E;
-    k.TPL = C::TPL;
-    k.lm_lines = LL;
-    k.em_lines = EL;
-    k.em_fwd = k_em_fft<N, E, EL, -1>;
-    k.em_inv = k_em_fft<N, E, EL, 1>;
-    k.density = k_density<N, E, EL, false>;
-    k.density_store = k_density<N, E, EL, true>;
-    k.phase = k_phase<N, E, EL, false, false>;
-    k.phase_real = k_phase<N, E, EL, false, true>;
-    k.phase_energy = k_phase<N, E, EL, true, false>;
-    k.lm_fwd = k_lm<N, E, LL, LM_FWD>;
-    k.lm_inv = k_lm<N, E, LL, LM_INV>;
-    k.lm_kin = k_lm<N, E, LL, LM_KIN>;
-    k.lm_kern = k_lm<N, E, LL, LM_KERN>;
-    k.lm_kin_energy = k_lm<N, E, LL, LM_KIN_ENERGY>;
-    return k;
-}
-
-template <int N> static const NKernels *variant_table(int v)
-{
-    static const NKernels k[kNumVariants] = {make_kernels<N, 0>(), make_kernels<N, 1>()};
-    return &k[v];
-}
-
-static const NKernels *kernels_for(int N, int v = 0)
-{
-    if (v < 0 || v >= kNumVariants) v = 0;
-    switch (N) {
-    case 8: return variant_table<8>(v);
-    case 16: return variant_table<16>(v);
-    case 32: return variant_table<32>(v);
-    case 64: return variant_table<64>(v);
-    case 128: return variant_table<128>(v);
-    case 256: return variant_table<256>(v);
-    case 512: return variant_table<512>(v);
-    case 1024: return variant_table<1024>(v);
-    case 2048: return variant_table<2048>(v);
-    default: return nullptr;
-    }
-}
-
+// Kernel table of length N, schedule variant v (defined in gsn_api.hip, the
+// only translation unit that instantiates the single-grid kernels).
+const NKernels *kernels_for(int N, int v = 0);
 
 // wavenumber of DFT index j on an axis with N points and length L
 static inline double wavenumber(int j, int N, double L)

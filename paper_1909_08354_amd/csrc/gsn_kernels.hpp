@@ -41,6 +41,7 @@ struct EmArgs {
     double scale;         // plain FFT output scale
     double g, dz;         // phase stage
     double *partials;     // per-block FP64 partials
+    float *phi;           // potential readout destination (real rows of N)
 };
 
 template <int N, int E> struct EmShape {
@@ -150,6 +151,58 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *
     if (tid == 0) a.partials[tile] = bs;
 }
 
+// Full x-spectrum Z = X_0 + i X_1 of two real rows r0, r1 from their half
+// spectra (X[N-k] = conj X[k]; the DC and Nyquist bins are real).
+template <int N, int E>
+__device__ __forceinline__ void load_phi_pair(const EmArgs &a, bool act, int t, long long r0, long long r1,
+                                              dc (&z)[E])
+{
+    constexpr int TPL = N / E;
+    const float2 *h0 = a.half + r0 * (N / 2), *h1 = a.half + r1 * (N / 2);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        dc x0 = mk(0.0, 0.0), x1 = mk(0.0, 0.0);
+        if (act) {
+            if (e < E / 2) {
+                const int k = t + TPL * e;
+                x0 = from_f2(h0[k]);
+                x1 = from_f2(h1[k]);
+                if (k == 0) { x0.y = 0.0; x1.y = 0.0; }
+            } else if (e == E / 2 && t == 0) {
+                x0 = mk((double)a.nyq[r0].x, 0.0);
+                x1 = mk((double)a.nyq[r1].x, 0.0);
+            } else {
+                const int kk = N - (t + TPL * e);
+                x0 = conj(from_f2(h0[kk]));
+                x1 = conj(from_f2(h1[kk]));
+            }
+        }
+        z[e] = mk(x0.x - x1.y, x0.y + x1.x);
+    }
+}
+
+// Potential readout: phi rows (without the uniform k = 0 part) as float.
+template <int N, int E, int LINES>
+__device__ __forceinline__ void potential_tile(const EmArgs &a, int tile, float2 *lds)
+{
+    constexpr int TPL = N / E;
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    const int pair = tile * LINES + l;
+    const bool act = pair < a.nlines;
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
+    const long long r0 = 2LL * pair, r1 = r0 + 1;
+    dc z[E];
+    load_phi_pair<N, E>(a, act, t, r0, r1, z);
+    fft<N, E, 1>(z, t, lay, lds, a.tw);
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            a.phi[r0 * N + t + TPL * e] = (float)(z[e].x / N);
+            a.phi[r1 * N + t + TPL * e] = (float)(z[e].y / N);
+        }
+    }
+}
+
 // Phase pass.  Rebuild the full x-spectrum of two phi rows from their half
 // spectra (X[N-k] = conj X[k]; DC and Nyquist real), one inverse FFT gives
 // phi_0 + i phi_1.  Then per row: psi = G_x psi_x / N, multiply by
@@ -214,29 +267,7 @@ __device__ __forceinline__ void phase_tile(const EmArgs &a, int tile, float2 *ld
     const long long r0 = 2LL * pair, r1 = r0 + 1;
     const double inv_n = 1.0 / N;
     dc z[E];
-    {
-        const float2 *h0 = a.half + r0 * (N / 2), *h1 = a.half + r1 * (N / 2);
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            dc x0 = mk(0.0, 0.0), x1 = mk(0.0, 0.0);
-            if (act) {
-                if (e < E / 2) {
-                    const int k = t + TPL * e;
-                    x0 = from_f2(h0[k]);
-                    x1 = from_f2(h1[k]);
-                    if (k == 0) { x0.y = 0.0; x1.y = 0.0; }
-                } else if (e == E / 2 && t == 0) {
-                    x0 = mk((double)a.nyq[r0].x, 0.0);
-                    x1 = mk((double)a.nyq[r1].x, 0.0);
-                } else {
-                    const int kk = N - (t + TPL * e);
-                    x0 = conj(from_f2(h0[kk]));
-                    x1 = conj(from_f2(h1[kk]));
-                }
-            }
-            z[e] = mk(x0.x - x1.y, x0.y + x1.x);
-        }
-    }
+    load_phi_pair<N, E>(a, act, t, r0, r1, z);
     fft<N, E, 1>(z, t, lay, lds, a.tw);
     // phi of both rows, kept as float (it is complex64-stored data already)
     float phi0[E], phi1[E];
@@ -419,6 +450,12 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
     phase_tile<N, E, LINES, ENERGY, REAL_IN>(a, blockIdx.x, lds, sh);
 }
+template <int N, int E, int LINES>
+__global__ __launch_bounds__(LINES *(N / E)) void k_potential(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    potential_tile<N, E, LINES>(a, blockIdx.x, lds);
+}
 template <int N, int E, int LINES, int MODE>
 __global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
 {
@@ -494,6 +531,31 @@ static __global__ void k_from_c128(const double2 *__restrict__ src, float2 *dst,
          i += (long long)gridDim.x * blockDim.x) {
         const double2 v = src[i];
         dst[i] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+// Relative difference of two states including their global phases:
+// part[2b] = sum |a e^{i th_a} - b e^{i th_b}|^2, part[2b+1] = sum |b|^2.
+static __global__ void k_state_diff(const float2 *__restrict__ a, const DevState *sa, const float2 *__restrict__ b,
+                                    const DevState *sb, long long P, double *part)
+{
+    __shared__ double sh[5];
+    double ca, sa_, cb, sb_;
+    sincos(sa->theta, &sa_, &ca);
+    sincos(sb->theta, &sb_, &cb);
+    double d = 0.0, n = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < P; i += (long long)gridDim.x * 256) {
+        const float2 u = a[i], v = b[i];
+        const double ur = ca * u.x - sa_ * u.y, ui = sa_ * u.x + ca * u.y;
+        const double vr = cb * v.x - sb_ * v.y, vi = sb_ * v.x + cb * v.y;
+        d += (ur - vr) * (ur - vr) + (ui - vi) * (ui - vi);
+        n += vr * vr + vi * vi;
+    }
+    d = block_sum<256>(d, sh);
+    n = block_sum<256>(n, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = d;
+        part[2 * blockIdx.x + 1] = n;
     }
 }
 

@@ -55,6 +55,23 @@ _SIGNATURES = {
     "gsn_get_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
     "gsn_set_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
     "gsn_set_nonlinear_mode": [vp, ctypes.c_int],
+    "gsn_set_coarse_ratio": [vp, ctypes.c_int],
+    "gsn_step_coarse": [vp, ctypes.c_int64],
+    "gsn_potential": [vp, vp],
+    "gsn_step_corrected": [vp, vp, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                           ctypes.POINTER(ctypes.c_int64), dp],
+    "gsn_corrector_workspace_bytes": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "gsn_corrector_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp],
+    "gsn_corrector_destroy": [vp],
+    "gsn_corrector_set_weights": [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
+    "gsn_corrector_get_weights": [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
+    "gsn_corrector_set_scales": [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_float],
+    "gsn_corrector_pack": [vp, ctypes.c_int, vp, vp],
+    "gsn_corrector_pack_target": [vp, ctypes.c_int, vp, vp],
+    "gsn_corrector_forward": [vp, ctypes.c_int, vp],
+    "gsn_corrector_gradients": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+    "gsn_corrector_train_step": [vp, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_float)],
+    "gsn_corrector_apply": [vp, ctypes.c_int, vp, vp],
     "gsn_batch_workspace_bytes": [ctypes.c_int, ctypes.c_int, i32p, ctypes.POINTER(ctypes.c_size_t)],
     "gsn_batch_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, i32p, dp, vp, ctypes.c_size_t, vp],
     "gsn_batch_destroy": [vp],
@@ -272,6 +289,27 @@ class Grid:
         v = (ctypes.c_int * npass)(*variants)
         check(lib.gsn_set_schedule(self.h, v, npass))
 
+    def set_coarse_ratio(self, ratio):
+        check(load().gsn_set_coarse_ratio(self.h, int(ratio)))
+
+    def step_coarse(self, nsteps):
+        check(load().gsn_step_coarse(self.h, int(nsteps)))
+
+    def potential(self, out=None):
+        """phi of the current psi (float32 device tensor, no uniform k=0 part)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        check(load().gsn_potential(self.h, vp(out.data_ptr())))
+        return out
+
+    def step_corrected(self, corrector, ncoarse, audit_every=0, tol=0.0):
+        nfb = ctypes.c_int64(0)
+        worst = ctypes.c_double(0)
+        check(load().gsn_step_corrected(self.h, corrector.h, int(ncoarse), int(audit_every), float(tol),
+                                        ctypes.byref(nfb), ctypes.byref(worst)))
+        return nfb.value, worst.value
+
     def profile_passes(self, nsteps):
         lib = load()
         npass = lib.gsn_pass_count(self.h)
@@ -354,3 +392,76 @@ class Batch:
     def set_schedule(self, variants, nonlinear_mode=0):
         v = (ctypes.c_int * len(variants))(*variants)
         check(load().gsn_batch_set_schedule(self.h, v, len(variants), int(nonlinear_mode)))
+
+
+CORRECTOR_NPARAMS = 19970
+
+
+class Corrector:
+    """The learned coarse-step corrector (gsn_corrector_create)."""
+
+    def __init__(self, H, W, max_batch=1, stream=None):
+        torch = _torch()
+        lib = load()
+        self.H, self.W, self.max_batch = int(H), int(W), int(max_batch)
+        nb = ctypes.c_size_t(0)
+        check(lib.gsn_corrector_workspace_bytes(self.H, self.W, self.max_batch, ctypes.byref(nb)))
+        self._ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self._ws.data_ptr() + 255) & ~255
+        stream = torch.cuda.current_stream() if stream is None else stream
+        h = vp()
+        check(lib.gsn_corrector_create(ctypes.byref(h), self.H, self.W, self.max_batch, vp(aligned),
+                                       nb.value, vp(stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            check(load().gsn_corrector_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        check(load().gsn_corrector_set_weights(self.h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size))
+
+    def get_weights(self):
+        w = np.empty(CORRECTOR_NPARAMS, dtype=np.float32)
+        check(load().gsn_corrector_get_weights(self.h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size))
+        return w
+
+    def set_scales(self, in_scale, out_scale):
+        a = (ctypes.c_float * 3)(*[float(v) for v in in_scale])
+        check(load().gsn_corrector_set_scales(self.h, a, float(out_scale)))
+
+    def pack(self, b, psi, phi):
+        check(load().gsn_corrector_pack(self.h, int(b), vp(psi.data_ptr()), vp(phi.data_ptr())))
+
+    def pack_target(self, b, psi_fine, psi_coarse):
+        check(load().gsn_corrector_pack_target(self.h, int(b), vp(psi_fine.data_ptr()),
+                                               vp(psi_coarse.data_ptr())))
+
+    def forward(self, B):
+        torch = _torch()
+        out = torch.empty((B, self.H, self.W, 2), dtype=torch.float32, device="cuda")
+        check(load().gsn_corrector_forward(self.h, int(B), vp(out.data_ptr())))
+        return out
+
+    def gradients(self, B):
+        g = np.empty(CORRECTOR_NPARAMS, dtype=np.float32)
+        loss = ctypes.c_float(0)
+        check(load().gsn_corrector_gradients(self.h, int(B), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                             ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, B, lr):
+        loss = ctypes.c_float(0)
+        check(load().gsn_corrector_train_step(self.h, int(B), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def apply(self, b, psi_c, psi_out):
+        check(load().gsn_corrector_apply(self.h, int(b), vp(psi_c.data_ptr()), vp(psi_out.data_ptr())))

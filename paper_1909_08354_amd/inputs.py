@@ -155,10 +155,33 @@ def batch_sweep(count=64, seed=3, sizes=(256, 512, 1024)):
     return out
 
 
-def corrector_state(seed, n=(512, 512)):
-    """One seeded 2-D lump state for the learned-corrector workload."""
+def corrector_lumps(seed, n=(512, 512)):
+    """Lump parameters (centres, waists, velocities) of one seeded corrector
+    state: 1-4 lumps, waist U[2,6], velocity U[-0.5,0.5]^2, dx = 1."""
     rng = np.random.default_rng(seed)
     L = tuple(float(v) for v in n)
     nl = int(rng.integers(1, 5))
-    cs, ws, vs = random_lumps(rng, n, L, nl, (2.0, 6.0))
+    return random_lumps(rng, n, L, nl, (2.0, 6.0))
+
+
+def corrector_state(seed, n=(512, 512)):
+    """One seeded 2-D lump state for the learned-corrector workload."""
+    L = tuple(float(v) for v in n)
+    cs, ws, vs = corrector_lumps(seed, n)
     return lumps(n, L, cs, ws, vs)
+
+
+def corrector_state_device(seed, n=(512, 512), device="cuda"):
+    """The same state built on a torch device (complex64) from the separable
+    1-D factors, for generating many training states quickly."""
+    import torch
+    L = tuple(float(v) for v in n)
+    cs, ws, vs = corrector_lumps(seed, n)
+    psi = torch.zeros(tuple(n), dtype=torch.complex128, device=device)
+    for c, w, v in zip(cs, ws, vs):
+        f = []
+        for ax in range(2):
+            d = _min_image(axis_coords(n[ax], L[ax]) - c[ax], L[ax])
+            f.append(torch.from_numpy(np.exp(-(d * d) / (w * w)) * np.exp(1j * v[ax] * d)).to(device))
+        psi += torch.outer(f[0], f[1])
+    return psi.to(torch.complex64)

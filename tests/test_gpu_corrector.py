@@ -1,0 +1,204 @@
+"""GPU tests of the learned corrector and the coarse / corrected stepping.
+
+The HIP network computes in bfloat16 (inputs, weights, hidden activations)
+with FP32 accumulation.  The oracle is FP64; to compare the forward pass it is
+fed the same bf16-rounded inputs and weights and its hidden activations are
+rounded to bf16 where the kernels store them, so the remaining difference is
+FP32 vs FP64 accumulation (plus rare one-ulp bf16 flips).  Gradients are
+compared as whole vectors: the HIP backward also rounds dZ to bf16 at every
+layer, a relative 2^-8 per value, so the bar is a few percent in relative L2
+with a cosine similarity close to one.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import corrector_oracle as co
+from oracle import oracle as orc
+from paper_1909_08354_amd import gsn, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def random_fields(B, H, W, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    psi = (rng.standard_normal((B, H, W)) + 1j * rng.standard_normal((B, H, W))).astype(np.complex64)
+    phi = rng.standard_normal((B, H, W)).astype(np.float32) * 3
+    return psi, phi, torch.from_numpy(psi).cuda(), torch.from_numpy(phi).cuda()
+
+
+def packed_input(psi, phi, scales):
+    x = np.stack([psi.real * scales[0], psi.imag * scales[1], phi * scales[2]], axis=-1)
+    return co.bf16_round(x.astype(np.float32))
+
+
+def quantised_params(theta):
+    params = co.unflatten(theta)
+    return co.flatten([(co.bf16_round(w), b.astype(np.float32).astype(np.float64)) for w, b in params])
+
+
+def forward_like_kernels(x, theta):
+    """Oracle forward with bf16 storage of the hidden activations."""
+    h = x
+    for li, ((w, b), (_, _, relu)) in enumerate(zip(co.unflatten(theta), co.LAYERS)):
+        h = co.conv(h, w, b)
+        if relu:
+            h = co.bf16_round(np.maximum(h, 0.0))
+    return h
+
+
+def make(B, H, W, seed, scales=(0.7, 0.7, 0.2)):
+    c = gsn.Corrector(H, W, max_batch=B)
+    theta = co.init_params(seed).astype(np.float32)
+    c.set_weights(theta)
+    c.set_scales(scales, 1.0)
+    return c, theta.astype(np.float64)
+
+
+def test_corrector_forward_matches_oracle():
+    B, H, W, scales = 2, 16, 32, (0.7, 0.7, 0.2)
+    c, theta = make(B, H, W, 1, scales)
+    psi, phi, tpsi, tphi = random_fields(B, H, W, 2)
+    for b in range(B):
+        c.pack(b, tpsi[b], tphi[b])
+    out = c.forward(B).cpu().numpy().astype(np.float64)
+    ref = forward_like_kernels(packed_input(psi, phi, scales), quantised_params(theta))
+    rel = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    say(f"forward rel_l2 {rel:.2e}")
+    assert rel < 2e-3
+
+
+def test_corrector_gradients_match_oracle():
+    import torch
+    B, H, W, scales = 2, 16, 32, (0.7, 0.7, 0.2)
+    c, theta = make(B, H, W, 3, scales)
+    psi, phi, tpsi, tphi = random_fields(B, H, W, 4)
+    rng = np.random.default_rng(5)
+    fine = (psi + 0.1 * (rng.standard_normal(psi.shape) + 1j * rng.standard_normal(psi.shape))).astype(np.complex64)
+    tfine = torch.from_numpy(fine).cuda()
+    for b in range(B):
+        c.pack(b, tpsi[b], tphi[b])
+        c.pack_target(b, tfine[b], tpsi[b])
+    loss, g = c.gradients(B)
+    x = packed_input(psi, phi, scales)
+    target = np.stack([(fine - psi).real, (fine - psi).imag], axis=-1).astype(np.float32).astype(np.float64)
+    lref, gref = co.backward(x, quantised_params(theta), target)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    cos = float(np.dot(g, gref) / np.linalg.norm(g) / np.linalg.norm(gref))
+    say(f"loss {loss:.6e} vs {lref:.6e}; grad rel_l2 {rel:.2e} cos {cos:.6f}")
+    assert abs(loss - lref) < 1e-2 * lref
+    assert rel < 5e-2 and cos > 0.998
+    # every layer's bias gradient separately (sums of dZ)
+    off = 0
+    for ci, cout, _ in co.LAYERS:
+        off += 9 * ci * cout
+        gb, rb = g[off:off + cout], gref[off:off + cout]
+        assert np.linalg.norm(gb - rb) <= 5e-2 * np.linalg.norm(rb) + 1e-9
+        off += cout
+
+
+def test_corrector_adam_step_and_determinism():
+    import torch
+    B, H, W = 2, 16, 32
+    runs = []
+    for _ in range(2):
+        c, theta = make(B, H, W, 6)
+        psi, phi, tpsi, tphi = random_fields(B, H, W, 7)
+        tfine = tpsi * 1.01
+        for b in range(B):
+            c.pack(b, tpsi[b], tphi[b])
+            c.pack_target(b, tfine[b], tpsi[b])
+        _, g = c.gradients(B)
+        c.train_step(B, 1e-3)
+        w1 = c.get_weights().astype(np.float64)
+        ref, _, _ = co.adam(theta, g.astype(np.float64), np.zeros_like(theta), np.zeros_like(theta), 1, 1e-3)
+        assert np.max(np.abs(w1 - ref)) < 1e-6
+        losses = [c.train_step(B, 1e-3) for _ in range(20)]
+        assert losses[-1] < 0.7 * losses[0]
+        runs.append((c.get_weights(), losses))
+    assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
+
+
+@pytest.mark.parametrize("n", [(64, 128), (16, 32, 64)])
+def test_potential_matches_oracle(n):
+    rng = np.random.default_rng(8)
+    L = tuple(float(v) for v in n)
+    cs, ws, vs = inputs.random_lumps(rng, n, L, 2, (min(n) / 6, min(n) / 4))
+    psi = inputs.to_c64(inputs.lumps(n, L, cs, ws, vs))
+    kern = (1.0, 0.3, 0.2, 0.1)
+    g = gsn.Grid(n, L)
+    g.set_kernel(*kern)
+    g.set_coefficients(0.5, -0.5, 1e-3)
+    g.set_psi(psi)
+    phi = g.potential().cpu().numpy().astype(np.float64)
+    rho = np.abs(psi.astype(np.complex128)) ** 2
+    ref = orc.potential(rho, L, kern)
+    K0 = kern[1] / kern[2] ** 2 + kern[3]
+    ref -= K0 * rho.mean()                      # the uniform k = 0 part is left out
+    assert np.max(np.abs(phi - ref)) < 1e-5 * np.max(np.abs(ref))
+
+
+def test_coarse_step_matches_oracle():
+    n, L = (64, 64), (64.0, 64.0)
+    rng = np.random.default_rng(9)
+    cs, ws, vs = inputs.random_lumps(rng, n, L, 2, (4.0, 6.0))
+    psi0 = inputs.lumps(n, L, cs, ws, vs)
+    kern, a, gl, dz, r = (1.0, 0.2, 0.3, 0.0), 0.5, -0.5, 2e-3, 8
+    g = gsn.Grid(n, L)
+    g.set_kernel(*kern)
+    g.set_coefficients(a, gl, dz)
+    g.set_coarse_ratio(r)
+    g.set_psi(inputs.to_c64(psi0))
+    g.step_coarse(3)
+    ref = orc.evolve(inputs.as_oracle_input(psi0), L, kern, a, gl, dz * r, 3)
+    assert orc.rel_l2(g.get_psi(), ref) < 1e-5
+    # fine steps are untouched by the coarse schedule
+    g.set_psi(inputs.to_c64(psi0))
+    g.step(5)
+    ref = orc.evolve(inputs.as_oracle_input(psi0), L, kern, a, gl, dz, 5)
+    assert orc.rel_l2(g.get_psi(), ref) < 1e-5
+
+
+def test_corrected_stepping_semantics():
+    """Zero weights: a corrected step is the plain coarse step.  With audits on
+    every step and tol = 0 every audit falls back, so the result is the fine
+    solver's, bit for bit."""
+    n, L = (64, 64), (64.0, 64.0)
+    rng = np.random.default_rng(10)
+    cs, ws, vs = inputs.random_lumps(rng, n, L, 2, (4.0, 6.0))
+    psi0 = inputs.to_c64(inputs.lumps(n, L, cs, ws, vs))
+    kern, r = (1.0, 0.0, 0.0, 0.0), 8
+    corr = gsn.Corrector(*n, max_batch=1)
+    corr.set_weights(np.zeros(gsn.CORRECTOR_NPARAMS, dtype=np.float32))
+    corr.set_scales((1.0, 1.0, 0.1), 1e-4)
+
+    def grid():
+        g = gsn.Grid(n, L)
+        g.set_kernel(*kern)
+        g.set_coefficients(0.5, -0.5, 5e-3)
+        g.set_coarse_ratio(r)
+        g.set_psi(psi0)
+        return g
+
+    g1, g2, g3, g4 = grid(), grid(), grid(), grid()
+    g1.step_coarse(1)
+    g1.step_coarse(1)
+    g1.step_coarse(1)
+    nfb, _ = g2.step_corrected(corr, 3, 0, 0.0)
+    assert nfb == 0
+    assert np.array_equal(g1.get_psi(np.complex64), g2.get_psi(np.complex64))
+    for _ in range(3):
+        g3.step(r)
+    nfb, worst = g4.step_corrected(corr, 3, 1, 0.0)
+    assert nfb == 3 and worst > 0
+    assert np.array_equal(g3.get_psi(np.complex64), g4.get_psi(np.complex64))
+    # a loose tolerance accepts the corrected (here: plain coarse) steps
+    g5 = grid()
+    nfb, worst = g5.step_corrected(corr, 3, 1, 1.0)
+    assert nfb == 0 and np.array_equal(g5.get_psi(np.complex64), g1.get_psi(np.complex64))
