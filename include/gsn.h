@@ -179,9 +179,19 @@ gsn_status gsn_batch_get(gsn_batch batch, int i, void *dst, int dst_on_device, i
 /* FP64 mass of every instance into masses[count].  Synchronising. */
 gsn_status gsn_batch_mass(gsn_batch batch, double *masses);
 gsn_status gsn_batch_phase(gsn_batch batch, int i, double *theta, int64_t *steps);
-/* Execution mode: 0 = one captured hipGraph per step count (default),
-   2 = the same grouped launches issued directly. */
+/* Execution mode: 0 = one captured hipGraph per step count (default);
+   1 = one persistent kernel: 512-thread blocks pull (phase, instance, tile)
+   work items from a device queue in order and wait (bounded) on per-instance
+   completion counters, so instances overlap across passes; extents 128..1024
+   only (GSN_EUNSUPPORTED otherwise), and a wait that exceeds its spin limit is
+   reported as GSN_EHIP by the next synchronising call;
+   2 = the grouped launches of mode 0 issued directly. */
 gsn_status gsn_batch_set_mode(gsn_batch batch, int mode);
+/* Persistent-mode wait bound (iterations of ~50 ns, default 2^22) and a test
+   hook: fail_item >= 0 makes the block that pulls that work item raise the
+   queue error instead of running it (every block then leaves its loop), so the
+   failure path can be exercised without a real stall; -1 disables it. */
+gsn_status gsn_batch_set_queue_limits(gsn_batch batch, unsigned spin_limit, long long fail_item);
 /* Variant (0 "e16" / 1 "e8") per pass family {kinetic, density, kernel,
    phase, x entry/exit} (nfam >= 5) and the nonlinear mode (as
    gsn_set_nonlinear_mode). */

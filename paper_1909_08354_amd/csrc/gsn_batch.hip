@@ -20,8 +20,137 @@
 #include <vector>
 
 #include "gsn_host.hpp"
+#include "gsn_queue.hpp"
 
 namespace {
+
+// ------------------------------------------------------------------ persistent kernel
+// One 512-thread block shape serves every tile: x passes with 8 points per
+// thread (EM), y passes with 16 (LM), so LINES = 512 * E / N.
+constexpr int kPThreads = 512;
+template <int N> struct PCfg {
+    static constexpr int EE = 8, EL = kPThreads * EE / N;
+    static constexpr int LE = 16, LL = kPThreads * LE / N;
+};
+constexpr int kPLds = 64 * 1024 / 8;   // float2 slots: max over the supported sizes
+
+struct PInst {
+    EmArgs em[Q_NKIND];
+    LmArgs lm[Q_NKIND];
+    int nx, ny;
+};
+
+struct PArgs {
+    const PInst *inst;
+    QTables T;
+    unsigned long long total;
+    unsigned long long *head;
+    unsigned long long *done;
+    unsigned *err;
+    unsigned spin_limit;
+    int store_psi;
+    unsigned long long fail_item;   // test hook: raise the error when this item is pulled (~0 = never)
+};
+
+template <int N> __device__ __noinline__ void p_em(int kind, const EmArgs &a, int tile, float2 *lds, double *sh,
+                                                      int store)
+{
+    using C = PCfg<N>;
+    if (kind == Q_ENTRY) em_fft_tile<N, C::EE, C::EL, -1>(a, tile, lds);
+    else if (kind == Q_EXIT) em_fft_tile<N, C::EE, C::EL, 1>(a, tile, lds);
+    else if (kind == Q_DENSITY) {
+        if (store) density_tile<N, C::EE, C::EL, true>(a, tile, lds, sh);
+        else density_tile<N, C::EE, C::EL, false>(a, tile, lds, sh);
+    } else {
+        if (store) phase_tile<N, C::EE, C::EL, false, true>(a, tile, lds, sh);
+        else phase_tile<N, C::EE, C::EL, false, false>(a, tile, lds, sh);
+    }
+}
+
+template <int N> __device__ __noinline__ void p_lm(int kind, const LmArgs &a, int tile, float2 *lds, double *sh)
+{
+    using C = PCfg<N>;
+    if (kind == Q_KERNEL) lm_tile<N, C::LE, C::LL, LM_KERN>(a, tile, lds, sh);
+    else lm_tile<N, C::LE, C::LL, LM_KIN>(a, tile, lds, sh);
+}
+
+__global__ void k_queue_reset(unsigned long long *head, unsigned long long *done, unsigned *err, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *head = 0;
+        *err = 0;
+    }
+    if (i < count) done[i] = 0;
+}
+
+// Blocks pull items in increasing order; an item waits (bounded) until its
+// instance has completed every tile of the earlier phases.  Exit: the queue is
+// exhausted, or a wait exceeded spin_limit (then err is set and every block
+// leaves at its next wait).
+__global__ __launch_bounds__(kPThreads) void k_batch_persistent(PArgs a)
+{
+    __shared__ float2 lds[kPLds];
+    __shared__ double sh[kPThreads / 64 + 1];
+    __shared__ unsigned long long s_item;
+    __shared__ int s_stop;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int stop = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            unsigned long long x = 0;
+            if (!stop) {
+                x = atomicAdd(a.head, 1ull);
+                stop = x >= a.total;
+                if (x == a.fail_item) {
+                    atomicOr(a.err, 1u);
+                    stop = 1;
+                }
+            }
+            if (!stop) {
+                const QItem it = qdecode(a.T, x);
+                unsigned n = 0;
+                while (__hip_atomic_load(&a.done[it.inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it.need) {
+                    if (++n > a.spin_limit || __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        atomicOr(a.err, 1u);
+                        stop = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            s_item = x;
+            s_stop = stop;
+        }
+        __syncthreads();
+        if (s_stop) break;
+        __threadfence();   // acquire: see the tiles the counter covers
+        const QItem it = qdecode(a.T, s_item);
+        const PInst &I = a.inst[it.inst];
+        const bool lm = it.kind == Q_KIN_HALF || it.kind == Q_KIN_FULL || it.kind == Q_KERNEL;
+        if (lm) {
+            switch (I.ny) {
+            case 128: p_lm<128>(it.kind, I.lm[it.kind], it.tile, lds, sh); break;
+            case 256: p_lm<256>(it.kind, I.lm[it.kind], it.tile, lds, sh); break;
+            case 512: p_lm<512>(it.kind, I.lm[it.kind], it.tile, lds, sh); break;
+            default: p_lm<1024>(it.kind, I.lm[it.kind], it.tile, lds, sh); break;
+            }
+        } else {
+            switch (I.nx) {
+            case 128: p_em<128>(it.kind, I.em[it.kind], it.tile, lds, sh, a.store_psi); break;
+            case 256: p_em<256>(it.kind, I.em[it.kind], it.tile, lds, sh, a.store_psi); break;
+            case 512: p_em<512>(it.kind, I.em[it.kind], it.tile, lds, sh, a.store_psi); break;
+            default: p_em<1024>(it.kind, I.em[it.kind], it.tile, lds, sh, a.store_psi); break;
+            }
+        }
+        __threadfence();   // release: this tile's stores before the count
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&a.done[it.inst], 1ull);
+        __syncthreads();   // s_item / s_stop are rewritten next iteration
+    }
+}
+
+bool persistent_size(int n) { return n == 128 || n == 256 || n == 512 || n == 1024; }
+
 
 // ------------------------------------------------------------------ grouped kernel tables
 struct GKernels {
@@ -138,8 +267,15 @@ struct gsn_batch_ {
     hipGraphExec_t exec;
     int64_t exec_steps;
     bool dirty;
-    // persistent mode state
-    void *pq;   // device work-queue block
+    // persistent mode state (inside the workspace)
+    void *pq;
+    unsigned long long *q_head, *q_done;
+    unsigned *q_err, *q_prefix;
+    PInst *q_inst;
+    std::vector<unsigned> h_prefix;
+    bool q_built;
+    unsigned spin_limit;
+    long long fail_item;
 };
 
 namespace {
@@ -188,7 +324,8 @@ gsn_status compute_blayout(int count, const int32_t *n, BLayout *L)
     L->unit_off = off;
     off += 512;
     L->queue_off = off;
-    off += align256(4096 + 8ull * count + 64ull * count);
+    off += align256(256) + align256(8ull * count) + align256(4ull * Q_NKIND * (count + 1)) +
+           align256(sizeof(PInst) * (size_t)count);
     L->total = off;
     return GSN_OK;
 }
@@ -351,6 +488,7 @@ gsn_status build_batch(gsn_batch b)
         }
     }
     b->dirty = true;
+    b->q_built = false;
     return GSN_OK;
 }
 
@@ -419,6 +557,91 @@ gsn_status capture_graph(gsn_batch b, int64_t nsteps)
     return GSN_OK;
 }
 
+const int kQtoB[Q_NKIND] = {B_ENTRY, B_KIN_HALF, B_DENSITY, B_KERNEL, B_PHASE, B_KIN_FULL, B_EXIT};
+
+template <int N> void ptiles(int nlines_em, int *el, int *ll)
+{
+    (void)nlines_em;
+    *el = PCfg<N>::EL;
+    *ll = PCfg<N>::LL;
+}
+
+void pcfg_lines(int n, int *el, int *ll)
+{
+    switch (n) {
+    case 128: ptiles<128>(0, el, ll); break;
+    case 256: ptiles<256>(0, el, ll); break;
+    case 512: ptiles<512>(0, el, ll); break;
+    default: ptiles<1024>(0, el, ll); break;
+    }
+}
+
+// Per-instance tile arguments and per-kind tile prefixes for the persistent kernel.
+gsn_status build_persistent(gsn_batch b)
+{
+    const int count = b->count;
+    std::vector<PInst> pin(count);
+    std::vector<std::vector<unsigned>> tiles(Q_NKIND, std::vector<unsigned>(count, 0));
+    for (int i = 0; i < count; ++i) {
+        const Instance &I = b->inst[i];
+        if (!persistent_size(I.nx) || !persistent_size(I.ny))
+            return fail(GSN_EUNSUPPORTED, "persistent mode supports extents 128..1024");
+        int el_x, ll_x, el_y, ll_y;
+        pcfg_lines(I.nx, &el_x, &ll_x);
+        pcfg_lines(I.ny, &el_y, &ll_y);
+        PInst &P = pin[i];
+        std::memset(&P, 0, sizeof(P));
+        P.nx = I.nx;
+        P.ny = I.ny;
+        const int dens_tiles = (I.ny / 2 + el_x - 1) / el_x;
+        for (int q = 0; q < Q_NKIND; ++q) {
+            const int kind = kQtoB[q];
+            const bool is_lm = (kind == B_KIN_HALF || kind == B_KIN_FULL || kind == B_KERNEL);
+            if (is_lm) {
+                P.lm[q] = lm_args(b, I, kind, ll_y);
+                if (kind == B_KERNEL) P.lm[q].nmass = dens_tiles;
+                tiles[q][i] = P.lm[q].s0.ntiles + P.lm[q].s1.ntiles;
+            } else {
+                P.em[q] = em_args(b, I, kind);
+                tiles[q][i] = (P.em[q].nlines + el_x - 1) / el_x;
+            }
+        }
+    }
+    b->h_prefix.assign(Q_NKIND * (count + 1), 0);
+    for (int q = 0; q < Q_NKIND; ++q)
+        for (int i = 0; i < count; ++i)
+            b->h_prefix[q * (count + 1) + i + 1] = b->h_prefix[q * (count + 1) + i] + tiles[q][i];
+    gsn_status s = upload_sync(b->stream, b->q_inst, pin.data(), sizeof(PInst) * count);
+    if (s) return s;
+    s = upload_sync(b->stream, b->q_prefix, b->h_prefix.data(), 4ull * b->h_prefix.size());
+    if (s) return s;
+    b->q_built = true;
+    return GSN_OK;
+}
+
+gsn_status enqueue_persistent(gsn_batch b, int64_t nsteps, hipStream_t st)
+{
+    QTables T{b->count, (long long)nsteps, b->q_prefix};
+    QTables Th{b->count, (long long)nsteps, b->h_prefix.data()};
+    PArgs a;
+    a.inst = b->q_inst;
+    a.T = T;
+    a.total = qtotal_items(Th);
+    a.head = b->q_head;
+    a.done = b->q_done;
+    a.err = b->q_err;
+    a.spin_limit = b->spin_limit;
+    a.store_psi = b->store_psi;
+    a.fail_item = b->fail_item < 0 ? ~0ull : (unsigned long long)b->fail_item;
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    hipLaunchKernelGGL(k_queue_reset, dim3((b->count + 255) / 256), dim3(256), 0, st, b->q_head, b->q_done,
+                       b->q_err, b->count);
+    hipLaunchKernelGGL(k_batch_persistent, dim3(2 * cus), dim3(kPThreads), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    return GSN_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -467,6 +690,20 @@ extern "C" gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, cons
     b->mode = 0;
     b->store_psi = 0;
     b->pq = b->ws + lay.queue_off;
+    {
+        char *q = (char *)b->pq;
+        b->q_head = (unsigned long long *)q;
+        b->q_err = (unsigned *)(q + 64);
+        q += align256(256);
+        b->q_done = (unsigned long long *)q;
+        q += align256(8ull * count);
+        b->q_prefix = (unsigned *)q;
+        q += align256(4ull * Q_NKIND * (count + 1));
+        b->q_inst = (PInst *)q;
+        b->q_built = false;
+        b->spin_limit = 1u << 22;
+        b->fail_item = -1;
+    }
     // default schedule: the variants the single-grid autotuner favours on gfx950
     b->var[F_KIN] = 0;
     b->var[F_DENSITY] = 0;
@@ -634,6 +871,13 @@ extern "C" gsn_status gsn_batch_step(gsn_batch b, int64_t nsteps)
             if (s) return s;
         }
         HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    } else if (b->mode == 1) {
+        if (!b->q_built) {
+            gsn_status s = build_persistent(b);
+            if (s) return s;
+        }
+        gsn_status s = enqueue_persistent(b, nsteps, b->stream);
+        if (s) return s;
     } else {
         // mode 2: the same grouped launches issued directly (no graph)
         for (size_t gi = 0; gi < b->groups.size(); ++gi) {
@@ -652,6 +896,11 @@ extern "C" gsn_status gsn_batch_sync(gsn_batch b)
     HIP_TRY(hipSetDevice(b->device));
     HIP_TRY(hipStreamSynchronize(b->stream));
     HIP_TRY(hipStreamSynchronize(b->user));
+    if (b->mode == 1) {
+        unsigned err = 0;
+        HIP_TRY(hipMemcpy(&err, b->q_err, 4, hipMemcpyDeviceToHost));
+        if (err) return fail(GSN_EHIP, "persistent batch queue: a wait exceeded its spin limit");
+    }
     for (const Instance &I : b->inst) {
         DevState st;
         HIP_TRY(hipMemcpy(&st, I.st, sizeof(st), hipMemcpyDeviceToHost));
@@ -701,7 +950,13 @@ extern "C" gsn_status gsn_batch_mass(gsn_batch b, double *masses)
 extern "C" gsn_status gsn_batch_set_mode(gsn_batch b, int mode)
 {
     if (!b) return fail(GSN_EINVAL, "batch is NULL");
-    if (mode != 0 && mode != 2) return fail(GSN_EINVAL, "mode must be 0 (graph) or 2 (direct launches)");
+    if (mode != 0 && mode != 1 && mode != 2)
+        return fail(GSN_EINVAL, "mode must be 0 (graph), 1 (persistent) or 2 (direct launches)");
+    if (mode == 1) {
+        HIP_TRY(hipSetDevice(b->device));
+        gsn_status s = build_persistent(b);
+        if (s) return s;
+    }
     b->mode = mode;
     return GSN_OK;
 }
@@ -729,5 +984,14 @@ extern "C" gsn_status gsn_batch_phase(gsn_batch b, int i, double *theta, int64_t
     HIP_TRY(hipMemcpy(&st, b->inst[i].st, sizeof(st), hipMemcpyDeviceToHost));
     if (theta) *theta = st.theta;
     if (steps) *steps = st.steps;
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_batch_set_queue_limits(gsn_batch b, unsigned spin_limit, long long fail_item)
+{
+    if (!b) return fail(GSN_EINVAL, "batch is NULL");
+    if (spin_limit < 1) return fail(GSN_EINVAL, "spin_limit must be >= 1");
+    b->spin_limit = spin_limit;
+    b->fail_item = fail_item;
     return GSN_OK;
 }

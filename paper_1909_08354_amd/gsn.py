@@ -83,6 +83,7 @@ _SIGNATURES = {
     "gsn_batch_mass": [vp, dp],
     "gsn_batch_phase": [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)],
     "gsn_batch_set_mode": [vp, ctypes.c_int],
+    "gsn_batch_set_queue_limits": [vp, ctypes.c_uint, ctypes.c_longlong],
     "gsn_batch_set_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int],
     "gsn_get_nonlinear_mode": [vp, ctypes.POINTER(ctypes.c_int)],
 }
@@ -388,6 +389,9 @@ class Batch:
 
     def set_mode(self, mode):
         check(load().gsn_batch_set_mode(self.h, int(mode)))
+
+    def set_queue_limits(self, spin_limit=1 << 22, fail_item=-1):
+        check(load().gsn_batch_set_queue_limits(self.h, int(spin_limit), int(fail_item)))
 
     def set_schedule(self, variants, nonlinear_mode=0):
         v = (ctypes.c_int * len(variants))(*variants)

@@ -131,3 +131,47 @@ def test_batch_sweep_64_full_size():
         g.step(20)
         ref = orc.evolve(inputs.as_oracle_input(d["psi"]), d["L"], d["kern"], d["a"], d["g"], d["dz"], 20)
         assert orc.rel_l2(g.get_psi(), ref) < 1e-5
+
+
+PSHAPES = [(128, 128), (256, 128), (128, 256), (256, 256), (128, 128), (512, 256)]
+
+
+@pytest.mark.parametrize("nlmode", [0, 1])
+def test_persistent_mode_matches_graph_mode(nlmode):
+    """The persistent work-queue kernel runs the same per-line arithmetic as the
+    grouped launches with x passes at 8 and y passes at 16 points per thread."""
+    inst = make_instances(PSHAPES, 21)
+    outs = []
+    for mode in (0, 1):
+        b = gsn.Batch([d["n"] for d in inst], [d["L"] for d in inst])
+        b.set_schedule([0, 1, 0, 1, 1], nlmode)
+        for i, d in enumerate(inst):
+            b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+        b.set_mode(mode)
+        b.step(13)
+        b.step(4)
+        outs.append([b.get(i) for i in range(len(inst))])
+    for i, (x, y) in enumerate(zip(*outs)):
+        assert orc.rel_l2(y, x) < 1e-12, i
+    d = inst[1]
+    ref = orc.evolve(inputs.as_oracle_input(d["psi"]), d["L"], d["kern"], d["a"], d["g"], d["dz"], 17)
+    assert orc.rel_l2(outs[1][1], ref) < 1e-5
+
+
+def test_persistent_queue_error_is_reported():
+    inst = make_instances(PSHAPES[:3], 22)
+    b = gsn.Batch([d["n"] for d in inst], [d["L"] for d in inst])
+    for i, d in enumerate(inst):
+        b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+    b.set_mode(1)
+    b.set_queue_limits(fail_item=40)
+    b.step(3)
+    with pytest.raises(gsn.GsnError) as ei:
+        b.sync()
+    assert ei.value.status == gsn.GSN_EHIP
+    # the next run without the hook completes normally
+    b.set_queue_limits(fail_item=-1)
+    for i, d in enumerate(inst):
+        b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+    b.step(3)
+    b.sync()
