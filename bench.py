@@ -97,6 +97,20 @@ def batch_bench(steps):
     b.sync()
     t_batch = time.perf_counter() - t0
     drift = float(np.max(np.abs(b.masses() / m0 - 1)))
+    t_pers = None
+    if all(256 <= n[0] <= 1024 and 256 <= n[1] <= 1024 for n in (d["n"] for d in inst)):
+        b.set_mode(1)
+        for i, d in enumerate(inst):
+            b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+        b.step(2)
+        b.sync()
+        for i, d in enumerate(inst):
+            b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        b.sync()
+        t_pers = time.perf_counter() - t0
     grids = []
     fam = {"kinetic": 0, "x_density": 0, "kernel": 0, "x_phase": 1}
     for d in inst:
@@ -117,8 +131,47 @@ def batch_bench(steps):
             "grid_points": total_pts, "value": total_pts * steps / t_batch,
             "unit": "grid-pt updates/s", "ms_batch_graph": 1e3 * t_batch,
             "ms_sequential_gsn_step": 1e3 * t_seq, "speedup": t_seq / t_batch,
+            "ms_batch_persistent": None if t_pers is None else 1e3 * t_pers,
+            "speedup_persistent": None if t_pers is None else t_seq / t_pers,
             "max_norm_drift": drift,
             "accuracy": "bit-identical to the sequential runs (same kernels and schedule)"}
+
+
+def corrector_bench(ntrain, epochs, neval, ncoarse, tol):
+    """Learned corrector on 512^2 lump states: train on solver-generated pairs
+    (seeds 10000..), then on held-out seeds (20000..) compare, after ncoarse
+    coarse steps (ratio 8), the plain coarse solver and the corrected one with
+    the fine solver (the judge): relative L2 errors, share of seeds within tol,
+    and device time of the fine and corrected runs."""
+    from paper_1909_08354_amd import corrector_train as ct
+    from paper_1909_08354_amd import gsn, inputs
+    w = inputs.WORKLOADS["gsn2d_512_corrector"]
+    t0 = time.perf_counter()
+    data = ct.generate_pairs(list(range(w["train_seeds"][0], w["train_seeds"][0] + ntrain)))
+    t_gen = time.perf_counter() - t0
+    insc, outsc = ct.fit_scales(*data)
+    corr = gsn.Corrector(*w["n"], max_batch=8)
+    rng = np.random.default_rng(1)
+    theta = []
+    for ci, co in ((3, 32), (32, 32), (32, 32), (32, 2)):
+        theta.append(rng.standard_normal(9 * co * ci) * 0.5 * np.sqrt(2.0 / (9 * ci)))
+        theta.append(np.zeros(co))
+    corr.set_weights(np.concatenate(theta).astype(np.float32))
+    corr.set_scales(insc, outsc)
+    tr = ct.train(corr, data, epochs=epochs, batch=8, lr=2e-3, lr_final=1e-4)
+    del data
+    ev = ct.evaluate(corr, list(range(w["heldout_seeds"][0], w["heldout_seeds"][0] + neval)), ncoarse=ncoarse)
+    within_c = float(np.mean(np.array(ev["err_corrected"]) <= tol))
+    within_k = float(np.mean(np.array(ev["err_coarse"]) <= tol))
+    return {"workload": "gsn2d_512_corrector", "train_pairs": 2 * ntrain, "train_trajectories": ntrain,
+            "epochs": epochs, "train_s": tr["seconds"], "gen_s": t_gen, "loss_first": tr["first_loss"],
+            "loss_final": tr["final_loss"], "heldout_seeds": neval, "coarse_steps": ncoarse,
+            "ratio": w["ratio"], "tol_rel_l2": tol,
+            "err_coarse_mean": ev["err_coarse_mean"], "err_coarse_max": ev["err_coarse_max"],
+            "err_corrected_mean": ev["err_corrected_mean"], "err_corrected_max": ev["err_corrected_max"],
+            "share_within_tol_coarse": within_k, "share_within_tol_corrected": within_c,
+            "ms_fine": 1e3 * ev["t_fine"] / neval, "ms_corrected": 1e3 * ev["t_corrected"] / neval,
+            "ms_coarse": 1e3 * ev["t_coarse"] / neval, "speedup": ev["t_fine"] / ev["t_corrected"]}
 
 
 def main():
@@ -131,6 +184,10 @@ def main():
     ap.add_argument("--autotune-iters", type=int, default=10)
     ap.add_argument("--batch-steps", type=int, default=500,
                     help="steps of the 64-instance batched sweep (0 skips it)")
+    ap.add_argument("--corrector-train", type=int, default=2000,
+                    help="training trajectories of the corrector leg (0 skips it)")
+    ap.add_argument("--corrector-epochs", type=int, default=4)
+    ap.add_argument("--corrector-eval", type=int, default=100)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -217,12 +274,18 @@ def main():
         "batched_speedup": None,
         "batched": None,
         "corrected_speedup": None,
+        "corrected": None,
     }
-    if args.batch_steps > 0:
+    if args.batch_steps > 0 or args.corrector_train > 0:
         grid.close()
         del grid
+    if args.batch_steps > 0:
         line["batched"] = batch_bench(args.batch_steps)
         line["batched_speedup"] = line["batched"]["speedup"]
+    if args.corrector_train > 0:
+        line["corrected"] = corrector_bench(args.corrector_train, args.corrector_epochs,
+                                            args.corrector_eval, 10, 1e-4)
+        line["corrected_speedup"] = line["corrected"]["speedup"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, inputs.as_oracle_input(psi0))
     print(json.dumps(line), flush=True)
