@@ -11,6 +11,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -44,12 +45,25 @@ template <int N, int V> static NKernels make_kernels()
     k.lm_kin = k_lm<N, E, LL, LM_KIN>;
     k.lm_kern = k_lm<N, E, LL, LM_KERN>;
     k.lm_kin_energy = k_lm<N, E, LL, LM_KIN_ENERGY>;
+    for (int m = 0; m < 4; ++m) k.lmp[m] = nullptr;
+    k.em_pipe = C::PIPE;
+    if constexpr (C::PIPE) {
+        k.density = k_densityp<N, E, EL, false>;
+        k.density_store = k_densityp<N, E, EL, true>;
+        k.phase = k_phasep<N, E, EL, false>;
+        k.phase_real = k_phasep<N, E, EL, true>;
+        k.lmp[LM_FWD] = k_lmp<N, E, LL, LM_FWD, float2>;
+        k.lmp[LM_INV] = k_lmp<N, E, LL, LM_INV, float2>;
+        k.lmp[LM_KIN] = k_lmp<N, E, LL, LM_KIN, float2>;
+        k.lmp[LM_KERN] = k_lmp<N, E, LL, LM_KERN, float2>;
+    }
     return k;
 }
 
 template <int N> static const NKernels *variant_table(int v)
 {
-    static const NKernels k[kNumVariants] = {make_kernels<N, 0>(), make_kernels<N, 1>()};
+    static const NKernels k[kNumVariants] = {make_kernels<N, 0>(), make_kernels<N, 1>(), make_kernels<N, 2>(),
+                                             make_kernels<N, 3>()};
     return &k[v];
 }
 
@@ -229,12 +243,56 @@ static LmArgs lm_base(gsn_grid g, const double2 *tw, double scale)
     return a;
 }
 
+// The pipelined LM form addresses a tile with 32-bit offsets: every offset
+// inside a tile, ((LINES - 1) ls + (N - 1) es) * 8 bytes, must stay below 2^31.
+static bool lm_fits(const Seg &s, int N, int lines)
+{
+    if (s.ntiles == 0) return true;
+    const long long span = ((long long)(lines - 1) * s.ls + (long long)(N - 1) * s.es) * 8 + 8;
+    return span > 0 && span < (1LL << 31);
+}
+
+// Resident blocks per CU times CUs (persistent grid size); 0 if unknown.
+static int persistent_blocks(const void *fn, int threads)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(fn, dev);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int n = per_cu > 0 && cus > 0 ? per_cu * cus : 0;
+    cache[key] = n;
+    return n;
+}
+
 static Launch lm_launch(void (*fn)(LmArgs), const NKernels *k, const LmArgs &a, int pass)
 {
     Launch L;
     std::memset(&L, 0, sizeof(L));
+    const int ntiles = a.s0.ntiles + a.s1.ntiles;
+    int mode = -1;
+    if (fn == k->lm_fwd) mode = LM_FWD;
+    else if (fn == k->lm_inv) mode = LM_INV;
+    else if (fn == k->lm_kin) mode = LM_KIN;
+    else if (fn == k->lm_kern) mode = LM_KERN;
+    const int N = k->E * k->TPL;
+    int grid = ntiles;
+    if (mode >= 0 && k->lmp[mode] && lm_fits(a.s0, N, k->lm_lines) && lm_fits(a.s1, N, k->lm_lines)) {
+        fn = k->lmp[mode];
+        const int pb = persistent_blocks((const void *)fn, k->lm_threads());
+        if (pb > 0 && pb < grid) grid = pb;
+    }
     L.fn = (const void *)fn;
-    L.grid = dim3(a.s0.ntiles + a.s1.ntiles);
+    L.grid = dim3(grid);
     L.block = dim3(k->lm_threads());
     L.em = false;
     L.la = a;
@@ -246,8 +304,13 @@ static Launch em_launch(void (*fn)(EmArgs), const NKernels *k, const EmArgs &a, 
 {
     Launch L;
     std::memset(&L, 0, sizeof(L));
+    int grid = (a.nlines + k->em_lines - 1) / k->em_lines;
+    if (k->em_pipe && (fn == k->density || fn == k->density_store || fn == k->phase || fn == k->phase_real)) {
+        const int pb = persistent_blocks((const void *)fn, k->em_threads());
+        if (pb > 0 && pb < grid) grid = pb;
+    }
     L.fn = (const void *)fn;
-    L.grid = dim3((a.nlines + k->em_lines - 1) / k->em_lines);
+    L.grid = dim3(grid);
     L.block = dim3(k->em_threads());
     L.em = true;
     L.ea = a;

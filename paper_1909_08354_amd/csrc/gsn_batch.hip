@@ -189,13 +189,13 @@ template <int N, int V> GKernels make_gkernels()
 
 template <int N> const GKernels *gvariant(int v)
 {
-    static const GKernels k[kNumVariants] = {make_gkernels<N, 0>(), make_gkernels<N, 1>()};
+    static const GKernels k[kNumBatchVariants] = {make_gkernels<N, 0>(), make_gkernels<N, 1>()};
     return &k[v];
 }
 
 const GKernels *gkernels_for(int N, int v)
 {
-    if (v < 0 || v >= kNumVariants) v = 0;
+    if (v < 0 || v >= kNumBatchVariants) v = 0;
     switch (N) {
     case 8: return gvariant<8>(v);
     case 16: return gvariant<16>(v);
@@ -965,7 +965,7 @@ extern "C" gsn_status gsn_batch_set_schedule(gsn_batch b, const int *variants, i
 {
     if (!b || !variants || nfam < F_NFAM) return fail(GSN_EINVAL, "bad schedule arguments");
     for (int i = 0; i < F_NFAM; ++i)
-        if (variants[i] < 0 || variants[i] >= kNumVariants) return fail(GSN_EINVAL, "unknown schedule variant");
+        if (variants[i] < 0 || variants[i] >= kNumBatchVariants) return fail(GSN_EINVAL, "unknown schedule variant");
     if (nonlinear_mode != 0 && nonlinear_mode != 1) return fail(GSN_EINVAL, "nonlinear mode must be 0 or 1");
     HIP_TRY(hipSetDevice(b->device));
     HIP_TRY(hipStreamSynchronize(b->stream));

@@ -7,7 +7,7 @@
 // twiddles exp(+-2 pi i (j mod Ns) r / (Ns R)), does a length-R DFT in
 // registers and sends the outputs to positions expand(j) + r*Ns, with
 // expand(j) = (j / Ns) Ns R + (j mod Ns).  Between stages the data goes
-// through LDS as complex64; the last stage's outputs land in the same
+// through LDS (complex64 or complex128 slots); the last stage's outputs land in the same
 // registers in natural order (position t + TPL*e holds bin t + TPL*e), so a
 // pointwise multiplier and an inverse transform can follow without another
 // exchange.  Transforms are unnormalised in both directions.
@@ -31,6 +31,13 @@ __device__ __forceinline__ double norm2(dc a) { return fma(a.x, a.x, a.y * a.y);
 __device__ __forceinline__ dc from_f2(float2 v) { return mk((double)v.x, (double)v.y); }
 __device__ __forceinline__ float2 to_f2(dc v) { return make_float2((float)v.x, (float)v.y); }
 __device__ __forceinline__ dc from_d2(double2 v) { return mk(v.x, v.y); }
+
+// LDS exchange slots: complex64 (half the LDS footprint) or complex128 (no
+// conversions, no intermediate rounding)
+__device__ __forceinline__ void lds_put(float2 *p, int i, dc v) { p[i] = to_f2(v); }
+__device__ __forceinline__ void lds_put(double2 *p, int i, dc v) { p[i] = make_double2(v.x, v.y); }
+__device__ __forceinline__ dc lds_get(const float2 *p, int i) { return from_f2(p[i]); }
+__device__ __forceinline__ dc lds_get(const double2 *p, int i) { return from_d2(p[i]); }
 
 // multiply by S*i (S = -1 forward, +1 inverse)
 template <int S> __device__ __forceinline__ dc mul_si(dc a)
@@ -200,8 +207,8 @@ template <int LINES> struct LmLayout {
 };
 
 // One Stockham stage and the recursion over the remaining stages.
-template <int N, int E, int S, int ST, class Lay>
-__device__ __forceinline__ void fft_stages(dc (&v)[E], int t, const Lay &lay, float2 *lds,
+template <int N, int E, int S, int ST, class Lay, class LT>
+__device__ __forceinline__ void fft_stages(dc (&v)[E], int t, const Lay &lay, LT *lds,
                                            const double2 *__restrict__ tw)
 {
     using P = Plan<N, E>;
@@ -234,13 +241,13 @@ __device__ __forceinline__ void fft_stages(dc (&v)[E], int t, const Lay &lay, fl
             } else {
                 const int base = (j / NS) * NS * R + (j & (NS - 1));
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[lay(base + r * NS)] = to_f2(a[r]);
+                for (int r = 0; r < R; ++r) lds_put(lds, lay(base + r * NS), a[r]);
             }
         }
         if constexpr (!LAST) {
             exchange_sync<Lay::WAVE_LOCAL>();
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = from_f2(lds[lay(t + TPL * e)]);
+            for (int e = 0; e < E; ++e) v[e] = lds_get(lds, lay(t + TPL * e));
             exchange_sync<Lay::WAVE_LOCAL>();
             fft_stages<N, E, S, ST + 1>(v, t, lay, lds, tw);
         }
@@ -248,10 +255,10 @@ __device__ __forceinline__ void fft_stages(dc (&v)[E], int t, const Lay &lay, fl
 }
 
 // Unnormalised DFT of the line held in v (S = -1 forward, +1 inverse).
-// tw[q] = exp(-2 pi i q / N), q < N, FP64.  Every thread of the block must
+// tw[q] = exp(-2 pi i q / N), q < N, FP64 (global or LDS).  Every thread of the block must
 // call this (it contains barriers when the plan has more than one stage).
-template <int N, int E, int S, class Lay>
-__device__ __forceinline__ void fft(dc (&v)[E], int t, const Lay &lay, float2 *lds,
+template <int N, int E, int S, class Lay, class LT>
+__device__ __forceinline__ void fft(dc (&v)[E], int t, const Lay &lay, LT *lds,
                                     const double2 *__restrict__ tw)
 {
     fft_stages<N, E, S, 0>(v, t, lay, lds, tw);

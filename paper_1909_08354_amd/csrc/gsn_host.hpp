@@ -46,18 +46,27 @@ struct NKernels {
     void (*lm_kin)(LmArgs);
     void (*lm_kern)(LmArgs);
     void (*lm_kin_energy)(LmArgs);
+    // pipelined persistent forms of LM_FWD .. LM_KERN (null: not in this variant)
+    void (*lmp[4])(LmArgs);
+    // density / phase entries are the pipelined persistent kernels
+    bool em_pipe;
     int lm_threads() const { return lm_lines * TPL; }
     int em_threads() const { return em_lines * TPL; }
 };
 
-// Schedule variants: E points per thread (16 or 8) for every pass kind.  The
-// EM tile holds 256/TPL rows (at most 64); the LM tile holds LINES columns
-// chosen so that a tile moves >= 64-byte contiguous segments per row.
-constexpr int kNumVariants = 2;
-static const char *kVariantNames[kNumVariants] = {"e16", "e8"};
+// Schedule variants: E points per thread (16 or 8) for every pass kind, and
+// for the strided-axis (LM), density and phase passes either one tile per
+// block or persistent blocks that prefetch their next tile ("p16", "p8").  The EM tile holds
+// 256/TPL rows (at most 64); the LM tile holds LINES columns chosen so that a
+// tile moves >= 64-byte contiguous segments per row.  The batched solver
+// uses the first kNumBatchVariants.
+constexpr int kNumVariants = 4;
+constexpr int kNumBatchVariants = 2;
+static const char *kVariantNames[kNumVariants] = {"e16", "e8", "p16", "p8"};
 
 template <int N, int V> struct Cfg {
-    static constexpr int E0 = V == 0 ? 16 : 8;
+    static constexpr int E0 = (V & 1) ? 8 : 16;
+    static constexpr bool PIPE = V >= 2;
     static constexpr int E = N < E0 ? N : E0;
     static constexpr int TPL = N / E;
     static constexpr int LM_LINES = TPL <= 4 ? 64 : TPL <= 8 ? 32 : TPL <= 32 ? 16 : TPL <= 64 ? 8 : 4;

@@ -19,6 +19,9 @@
 // Powers of two make every scale exact.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <utility>
+
 #include "gsn_fft.hpp"
 
 namespace gsn {
@@ -426,6 +429,425 @@ __device__ __forceinline__ void lm_tile(const LmArgs &a, int tile_in, float2 *ld
     }
 }
 
+// ---------------------------------------------------------------- pipelined LM passes
+// Persistent blocks walk the tiles tile = blockIdx.x + k gridDim.x.  Before
+// the transforms of one tile run, the points of the next tile (and its
+// per-line multiplier factors) are already requested into registers, so
+// their HBM latency hides behind the arithmetic.  Twiddles and per-position
+// tables are copied to LDS once per block: no vector-memory load is issued
+// between a prefetch and its use, so waiting for one never waits for another.
+// Points move through buffer loads and stores whose per-point offsets are
+// scalar (wave-uniform), so addressing costs no vector instructions.  The
+// host uses this form only when a tile spans less than 2^31 bytes.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p)
+{
+    // raw buffer: stride 0, range 2^31 - 1 bytes, gfx9 data-format word
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_st2(float2 v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+// Where the lanes of a block find tile `tile` of an LM pass.  A lane whose
+// line lies past the end of its segment takes the segment's last line: it
+// loads, transforms and stores exactly what that line's own lane does (the
+// same values to the same addresses), so no load or store is predicated and
+// every iteration issues the same vector-memory operations.
+struct LmWhere {
+    __amdgpu_buffer_rsrc_t r;   // tile base (uniform)
+    unsigned voff;              // this lane's line start, bytes
+    unsigned step;              // bytes between positions t + TPL e and t + TPL (e + 1)
+    int c1, c2;                 // multiplier table indices of this lane's line
+};
+
+template <int N, int E, int LINES>
+__device__ __forceinline__ LmWhere lm_where(const LmArgs &a, int tile, int l, int t)
+{
+    constexpr int TPL = N / E;
+    const bool second = tile >= a.s0.ntiles;
+    const Seg &sg = second ? a.s1 : a.s0;
+    if (second) tile -= a.s0.ntiles;
+    const int o = tile / sg.ngroups, grp = tile - o * sg.ngroups;
+    const int lg0 = grp * LINES;
+    const int lg = min(lg0 + l, sg.nlines - 1);
+    LmWhere w;
+    w.r = buf_rsrc(sg.ptr + (long long)o * sg.os + (long long)lg0 * sg.ls);
+    w.voff = (unsigned)(((long long)(lg - lg0) * sg.ls + (long long)t * sg.es) * 8);
+    w.step = (unsigned)(sg.es * TPL * 8);
+    w.c1 = sg.c1f + lg * sg.c1l + o * sg.c1o;
+    w.c2 = sg.c2f + lg * sg.c2l + o * sg.c2o;
+    return w;
+}
+
+// An empty asm that takes x as input and output: code that computes x stays
+// before this point.
+__device__ __forceinline__ void pin(dc &x) { asm volatile("" : "+v"(x.x), "+v"(x.y)); }
+
+template <int E, int... I>
+__device__ __forceinline__ void convert_pinned(dc (&v)[E], const float2 (&p)[E], std::integer_sequence<int, I...>)
+{
+    ((v[I] = from_f2(p[I]), pin(v[I])), ...);
+}
+
+template <int E> struct LmPrefetch {
+    float2 p[E];
+    double2 f1, f2;   // kinetic factors kin1[c1], kin2[c2]
+    double q1, q2;    // |k|^2 parts k2_1[c1], k2_2[c2]
+};
+
+// Issue the loads of one tile.  live = false (no tile left): every lane loads
+// the tile base point E times instead, so the count of vector-memory
+// operations per iteration stays fixed and costs one cache line.
+template <int N, int E, int LINES, int MODE>
+__device__ __forceinline__ void lm_fetch(const LmArgs &a, const LmWhere &w, bool live, LmPrefetch<E> &f)
+{
+    const unsigned vo = live ? w.voff : 0u, st = live ? w.step : 0u;
+#pragma unroll
+    for (int e = 0; e < E; ++e) f.p[e] = buf_ld2(w.r, vo, e * st);
+    if constexpr (MODE == LM_KIN) {
+        f.f1 = a.kin1[live ? w.c1 : 0];
+        f.f2 = a.kin2[live ? w.c2 : 0];
+    } else if constexpr (MODE == LM_KERN) {
+        f.q1 = a.k2_1[live ? w.c1 : 0];
+        f.q2 = a.k2_2[live ? w.c2 : 0];
+    }
+}
+
+template <int N, int E, int LINES, int MODE, class LT>
+__device__ __forceinline__ void lmp_body(const LmArgs &a, LT *lds, double2 *twl, double2 *kpl, double *k2l,
+                                         double *sh)
+{
+    constexpr int TPL = N / E, NT = LINES * TPL;
+    static_assert(MODE == LM_FWD || MODE == LM_INV || MODE == LM_KIN || MODE == LM_KERN, "mode");
+    const int tid = threadIdx.x, l = tid % LINES, t = tid / LINES;
+    for (int i = tid; i < N; i += NT) {
+        twl[i] = a.tw[i];
+        if constexpr (MODE == LM_KIN) kpl[i] = a.kinp[i];
+        if constexpr (MODE == LM_KERN) k2l[i] = a.k2_p[i];
+    }
+    if (a.reduce && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = tid; i < a.nmass; i += NT) s += a.mass_parts[i];
+        s = block_sum<NT>(s, sh);
+        if (tid == 0) {
+            a.st->mass_sum = s;
+            a.st->theta += a.k0_dz_over_P * s;
+            a.st->steps += 1;
+            if (!isfinite(s)) a.st->nonfinite = 1;
+        }
+    }
+    __syncthreads();
+    const int ntiles = a.s0.ntiles + a.s1.ntiles;
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const LmLayout<LINES> lay{l};
+    LmPrefetch<E> f;
+    lm_fetch<N, E, LINES, MODE>(a, lm_where<N, E, LINES>(a, tile, l, t), true, f);
+    dc v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = from_f2(f.p[e]);
+    // this tile's line factors, taken before the prefetch reuses f
+    dc m12 = mk(0.0, 0.0);
+    double q12 = 0.0;
+    if constexpr (MODE == LM_KIN) m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), a.scale);
+    if constexpr (MODE == LM_KERN) q12 = f.q1 + f.q2;
+    for (;;) {
+        const int nxt = tile + gridDim.x;
+        const bool more = nxt < ntiles;
+        lm_fetch<N, E, LINES, MODE>(a, lm_where<N, E, LINES>(a, more ? nxt : tile, l, t), more, f);
+        if constexpr (MODE == LM_FWD || MODE == LM_INV) {
+            fft<N, E, MODE == LM_FWD ? -1 : 1>(v, t, lay, lds, twl);
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = scl(v[e], a.scale);
+        } else {
+            fft<N, E, -1>(v, t, lay, lds, twl);
+            if constexpr (MODE == LM_KIN) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = cmul(v[e], cmul(m12, from_d2(kpl[t + TPL * e])));
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const double k2 = q12 + k2l[t + TPL * e];
+                    const double km = k2 + a.mY2;
+                    const double num = fma(a.cN, km, a.cY * k2);
+                    const double den = k2 * km;
+                    double r = __builtin_amdgcn_rcp(den);
+                    r = fma(r, fma(-den, r, 1.0), r);
+                    r = fma(r, fma(-den, r, 1.0), r);
+                    const double K = k2 > 0.0 ? fma(num, r, a.c0) : 0.0;
+                    v[e] = scl(v[e], K * a.scale);
+                }
+            }
+            fft<N, E, 1>(v, t, lay, lds, twl);
+        }
+        const LmWhere w = lm_where<N, E, LINES>(a, tile, l, t);
+#pragma unroll
+        for (int e = 0; e < E; ++e) buf_st2(to_f2(v[e]), w.r, w.voff, e * w.step);
+        if (!more) break;
+        // convert here, where the only outstanding operations are this
+        // iteration's loads and stores (the empty asm keeps the compiler from
+        // sinking the conversion into the loop header, whose wait would then
+        // also have to cover the path from the first fetch: vmcnt(0))
+        convert_pinned(v, f.p, std::make_integer_sequence<int, E>{});
+        if constexpr (MODE == LM_KIN) {
+            m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), a.scale);
+            pin(m12);
+        }
+        if constexpr (MODE == LM_KERN) {
+            q12 = f.q1 + f.q2;
+            asm volatile("" : "+v"(q12));
+        }
+        tile = nxt;
+    }
+}
+
+// ---------------------------------------------------------------- pipelined EM passes
+// The density and phase passes in the same persistent, prefetching form: a
+// block walks tiles of LINES row pairs; each row's loads for the next tile are
+// issued as soon as that row's registers of the current tile have been
+// converted, twiddles come from LDS, and rows past the end of the grid take
+// the last row pair (identical loads, arithmetic and stores; they add nothing
+// to the mass partial).  Loads with live = false read the tile's first point.
+template <int N, int E, int LINES>
+__device__ __forceinline__ int em_pair(const EmArgs &a, int tile, int l)
+{
+    return min(tile * LINES + l, a.nlines - 1);
+}
+
+// psi row r (0 or 1) of the pair `pair`: E float2 at positions t + TPL e
+template <int N, int E>
+__device__ __forceinline__ void em_fetch_row(const EmArgs &a, int pair, int r, int t, bool live, float2 (&p)[E])
+{
+    constexpr int TPL = N / E;
+    const int pair0 = __builtin_amdgcn_readfirstlane(pair);
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.psi + (long long)pair0 * 2 * N);
+    const unsigned vo = live ? (unsigned)(((pair - pair0) * 2 * N + r * N + t) * 8) : 0u;
+#pragma unroll
+    for (int e = 0; e < E; ++e) p[e] = buf_ld2(rs, vo, live ? e * TPL * 8 : 0);
+}
+
+template <int N, int E>
+__device__ __forceinline__ void em_store_row(const EmArgs &a, int pair, int r, int t, const dc (&v)[E], double s)
+{
+    constexpr int TPL = N / E;
+    const int pair0 = __builtin_amdgcn_readfirstlane(pair);
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.psi + (long long)pair0 * 2 * N);
+    const unsigned vo = (unsigned)(((pair - pair0) * 2 * N + r * N + t) * 8);
+#pragma unroll
+    for (int e = 0; e < E; ++e) buf_st2(to_f2(scl(v[e], s)), rs, vo, e * TPL * 8);
+}
+
+// Half spectra of the two phi rows of a pair, as load_phi_pair reads them
+// (bin k for e < E/2, bin N - k for e >= E/2; the Nyquist bin separately).
+template <int N, int E> struct PhiRaw {
+    float2 h0[E], h1[E];
+    float2 n0, n1;
+};
+
+template <int N, int E>
+__device__ __forceinline__ void em_fetch_phi(const EmArgs &a, int pair, int t, bool live, PhiRaw<N, E> &f)
+{
+    constexpr int TPL = N / E, H = N / 2;
+    const int pair0 = __builtin_amdgcn_readfirstlane(pair);
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.half + (long long)pair0 * 2 * H);
+    const int row = live ? (pair - pair0) * 2 * H : 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        int idx;
+        if (e < E / 2) idx = t + TPL * e;
+        else if (e == E / 2) idx = t == 0 ? 0 : N - (t + TPL * e);
+        else idx = N - (t + TPL * e);
+        if (!live) idx = 0;
+        const unsigned vo = (unsigned)((row + idx) * 8);
+        f.h0[e] = buf_ld2(rs, vo, 0);
+        f.h1[e] = buf_ld2(rs, vo, H * 8);
+    }
+    const long long r0 = live ? 2LL * pair : 2LL * pair0;
+    f.n0 = a.nyq[r0];
+    f.n1 = a.nyq[r0 + 1];
+}
+
+// The full spectrum Z = X_0 + i X_1 of the pair (conjugate symmetry; DC and
+// Nyquist real), the same operations as load_phi_pair.
+template <int N, int E>
+__device__ __forceinline__ void em_build_z(const PhiRaw<N, E> &f, int t, dc (&z)[E])
+{
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        dc x0 = from_f2(f.h0[e]), x1 = from_f2(f.h1[e]);
+        if (e < E / 2) {
+            if (e == 0 && t == 0) { x0.y = 0.0; x1.y = 0.0; }
+        } else if (e == E / 2 && t == 0) {
+            x0 = mk((double)f.n0.x, 0.0);
+            x1 = mk((double)f.n1.x, 0.0);
+        } else {
+            x0 = conj(x0);
+            x1 = conj(x1);
+        }
+        z[e] = mk(x0.x - x1.y, x0.y + x1.x);
+    }
+}
+
+template <int E, int... I>
+__device__ __forceinline__ void pin_all(dc (&v)[E], std::integer_sequence<int, I...>)
+{
+    (pin(v[I]), ...);
+}
+
+template <int N, int E, int LINES>
+__device__ __forceinline__ void copy_twiddles(const double2 *__restrict__ tw, double2 *twl)
+{
+    constexpr int NT = LINES * (N / E);
+    for (int i = threadIdx.x; i < N; i += NT) twl[i] = tw[i];
+    __syncthreads();
+}
+
+// Phase pass (as phase_tile without ENERGY).
+template <int N, int E, int LINES, bool REAL_IN>
+__device__ __forceinline__ void phasep_body(const EmArgs &a, float2 *lds, double2 *twl)
+{
+    constexpr int TPL = N / E;
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    copy_twiddles<N, E, LINES>(a.tw, twl);
+    const int ntiles = (a.nlines + LINES - 1) / LINES;
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
+    const double inv_n = 1.0 / N;
+    PhiRaw<N, E> fp;
+    float2 p0[E], p1[E];
+    int pair = em_pair<N, E, LINES>(a, tile, l);
+    em_fetch_phi<N, E>(a, pair, t, true, fp);
+    em_fetch_row<N, E>(a, pair, 0, t, true, p0);
+    em_fetch_row<N, E>(a, pair, 1, t, true, p1);
+    // nothing outstanding on entry to the loop: its waits then only count
+    // the loop's own operations
+    __builtin_amdgcn_s_waitcnt(0);
+    dc z[E];
+    em_build_z<N, E>(fp, t, z);
+    for (;;) {
+        const int nxt = tile + gridDim.x;
+        const bool more = nxt < ntiles;
+        const int npair = more ? em_pair<N, E, LINES>(a, nxt, l) : pair;
+        fft<N, E, 1>(z, t, lay, lds, twl);
+        float phi0[E], phi1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            phi0[e] = (float)(z[e].x * inv_n);
+            phi1[e] = (float)(z[e].y * inv_n);
+        }
+        em_fetch_phi<N, E>(a, npair, t, more, fp);
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            dc v[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = from_f2(half ? p1[e] : p0[e]);
+            em_fetch_row<N, E>(a, npair, half, t, more, half ? p1 : p0);
+            if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, twl);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const dc ps = REAL_IN ? v[e] : scl(v[e], inv_n);
+                const double rho = norm2(ps);
+                const double phi = (double)(half ? phi1[e] : phi0[e]);
+                double sn, cs;
+                sincos_fp64(fma(a.g, rho, phi) * a.dz, &sn, &cs);
+                v[e] = cmul(ps, mk(cs, sn));
+            }
+            fft<N, E, -1>(v, t, lay, lds, twl);
+            em_store_row<N, E>(a, pair, half, t, v, 1.0);
+        }
+        if (!more) break;
+        em_build_z<N, E>(fp, t, z);
+        pin_all(z, std::make_integer_sequence<int, E>{});
+        tile = nxt;
+        pair = npair;
+    }
+}
+
+// Density pass (as density_tile).
+template <int N, int E, int LINES, bool STORE_PSI>
+__device__ __forceinline__ void densityp_body(const EmArgs &a, float2 *lds, double2 *twl, double *sh)
+{
+    constexpr int TPL = N / E, NT = LINES * TPL, H = N / 2;
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    copy_twiddles<N, E, LINES>(a.tw, twl);
+    const int ntiles = (a.nlines + LINES - 1) / LINES;
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
+    const double inv_n = 1.0 / N;
+    float2 p0[E], p1[E];
+    int pair = em_pair<N, E, LINES>(a, tile, l);
+    em_fetch_row<N, E>(a, pair, 0, t, true, p0);
+    em_fetch_row<N, E>(a, pair, 1, t, true, p1);
+    __builtin_amdgcn_s_waitcnt(0);
+    dc v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = from_f2(p0[e]);
+    for (;;) {
+        const int nxt = tile + gridDim.x;
+        const bool more = nxt < ntiles;
+        const int npair = more ? em_pair<N, E, LINES>(a, nxt, l) : pair;
+        const bool real = tile * LINES + l < a.nlines;
+        double rho0[E];
+        em_fetch_row<N, E>(a, npair, 0, t, more, p0);
+        fft<N, E, 1>(v, t, lay, lds, twl);
+#pragma unroll
+        for (int e = 0; e < E; ++e) rho0[e] = norm2(v[e]) * (inv_n * inv_n);
+        if constexpr (STORE_PSI) em_store_row<N, E>(a, pair, 0, t, v, inv_n);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = from_f2(p1[e]);
+        em_fetch_row<N, E>(a, npair, 1, t, more, p1);
+        fft<N, E, 1>(v, t, lay, lds, twl);
+        if constexpr (STORE_PSI) em_store_row<N, E>(a, pair, 1, t, v, inv_n);
+        double msum = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const double rho1 = norm2(v[e]) * (inv_n * inv_n);
+            msum += rho0[e] + rho1;
+            v[e] = mk(rho0[e], rho1);
+        }
+        fft<N, E, -1>(v, t, lay, lds, twl);
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds[lay(t + TPL * e)] = to_f2(v[e]);
+        exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
+        {
+            const int pair0 = __builtin_amdgcn_readfirstlane(pair);
+            const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.half + (long long)pair0 * 2 * H);
+            const unsigned vo = (unsigned)(((pair - pair0) * 2 * H + t) * 8);
+#pragma unroll
+            for (int e = 0; e < E / 2; ++e) {
+                const int k = t + TPL * e;
+                const dc zz = v[e];
+                const dc zc = conj(from_f2(lds[lay((N - k) & (N - 1))]));
+                const dc sm = add(zz, zc), df = sub(zz, zc);
+                buf_st2(to_f2(scl(sm, 0.5)), rs, vo, e * TPL * 8);
+                buf_st2(to_f2(mk(0.5 * df.y, -0.5 * df.x)), rs, vo, H * 8 + e * TPL * 8);
+            }
+        }
+        if (t == 0) {
+            const dc zn = v[E / 2];   // bin N/2: both halves are real
+            a.nyq[2LL * pair] = make_float2((float)zn.x, 0.0f);
+            a.nyq[2LL * pair + 1] = make_float2((float)zn.y, 0.0f);
+        }
+        // the LDS slots are rewritten by the next tile's first transform
+        exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
+        const double bs = block_sum<NT>(real ? msum : 0.0, sh);
+        if (tid == 0) a.partials[tile] = bs;
+        if (!more) break;
+        convert_pinned(v, p0, std::make_integer_sequence<int, E>{});
+        tile = nxt;
+        pair = npair;
+    }
+}
+
 // ---------------------------------------------------------------- kernels
 // One grid: block b is tile b.  Grouped: several instances of one shape in
 // one launch; block b is tile (b mod tpi) of instance (b / tpi), whose
@@ -462,6 +884,34 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
     __shared__ float2 lds[LmTile<N, E, LINES>::LDS];
     __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
     lm_tile<N, E, LINES, MODE>(a, blockIdx.x, lds, sh);
+}
+
+// Pipelined EM passes (persistent grid).
+template <int N, int E, int LINES, bool REAL_IN>
+__global__ __launch_bounds__(LINES *(N / E)) void k_phasep(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double2 twl[N];
+    phasep_body<N, E, LINES, REAL_IN>(a, lds, twl);
+}
+template <int N, int E, int LINES, bool STORE_PSI>
+__global__ __launch_bounds__(LINES *(N / E)) void k_densityp(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double2 twl[N];
+    __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
+    densityp_body<N, E, LINES, STORE_PSI>(a, lds, twl, sh);
+}
+// Pipelined LM pass (persistent grid); LT: complex64 or complex128 LDS slots.
+template <int N, int E, int LINES, int MODE, class LT>
+__global__ __launch_bounds__(LINES *(N / E)) void k_lmp(LmArgs a)
+{
+    __shared__ LT lds[LmTile<N, E, LINES>::LDS];
+    __shared__ double2 twl[N];
+    __shared__ double2 kpl[MODE == LM_KIN ? N : 1];
+    __shared__ double k2l[MODE == LM_KERN ? N : 1];
+    __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
+    lmp_body<N, E, LINES, MODE, LT>(a, lds, twl, kpl, k2l, sh);
 }
 
 template <int N, int E, int LINES, int S>

@@ -59,6 +59,31 @@ def test_gsn3d_256_matches_oracle_after_1000_steps():
     assert abs(e["nonlocal"] - eo["nonlocal"]) < 1e-5 * scale
 
 
+@pytest.mark.parametrize("plain,piped", [(0, 2), (1, 3)])
+def test_gsn3d_256_pipelined_passes_match_plain(plain, piped):
+    """The persistent prefetching LM passes (p16 / p8: several tiles per
+    block at this size) against the one-tile-per-block passes of the same
+    radix plan, 20 steps from the same state."""
+    import torch
+    w = inputs.WORKLOADS["gsn3d_256_newton_yukawa"]
+    dev0 = torch.from_numpy(inputs.to_c64(inputs.gaussian_3d_256())).cuda()
+    outs = []
+    for v in (plain, piped):
+        grid = gsn.Grid(w["n"], w["L"])
+        grid.set_kernel(*w["kern"])
+        grid.set_coefficients(w["a"], w["g"], w["dz"])
+        grid.set_schedule(v)
+        grid.set_nonlinear_mode(1)
+        grid.set_psi(dev0)
+        grid.step(20)
+        outs.append(grid.get_psi(np.complex64, device=True))
+        grid.close()
+    diff = torch.max(torch.abs(outs[0] - outs[1])).item()
+    top = torch.max(torch.abs(outs[0])).item()
+    say(f"256^3 variant {plain} vs {piped}: max |diff| {diff:.3e} of max |psi| {top:.3e}")
+    assert diff <= 1e-6 * top
+
+
 def test_gsn3d_512_lumps_invariants():
     import torch
     w = inputs.WORKLOADS["gsn3d_512_lumps"]
