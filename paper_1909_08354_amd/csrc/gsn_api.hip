@@ -124,6 +124,7 @@ struct gsn_grid_ {
     double2 *kinF[3], *kinH[3];
     double *k2_unit;
     double2 *kin_unit;
+    double2 *sct;              // sin / cos table of the pipelined phase pass
     int var[P_COUNT];          // schedule variant per pass
     int store_psi;             // 1: density pass stores real-space psi for the phase pass
     int max_density_blocks;    // over all variants (sizes the partial arrays)
@@ -194,7 +195,7 @@ static Layout compute_layout(int ndim, const int32_t n[])
     L.tables = off;
     size_t tb = 0;
     for (int d = 0; d < ndim; ++d) tb += align256(16ull * n[d]) * 5 + align256(8ull * n[d]);
-    tb += 512 + 512;
+    tb += 512 + 512 + 16 * kSinCosTable;
     off = align256(off + tb);
     L.total = off;
     return L;
@@ -326,6 +327,7 @@ static EmArgs em_base(gsn_grid g, float2 *psi)
     a.half = g->half;
     a.nyq = g->nyq;
     a.tw = g->tw[g->ndim - 1];
+    a.sct = g->sct;
     a.scale = 1.0;
     return a;
 }
@@ -603,9 +605,13 @@ static gsn_status upload_static_tables(gsn_grid g)
         s = upload(g, g->k2[d], k2.data(), 8ull * N);
         if (s) return s;
     }
+    std::vector<double2> sct(kSinCosTable);
+    fill_sincos_table(sct.data());
+    gsn_status s = upload(g, g->sct, sct.data(), 16ull * kSinCosTable);
+    if (s) return s;
     const double zero = 0.0;
     const double2 one = make_double2(1.0, 0.0);
-    gsn_status s = upload(g, g->k2_unit, &zero, 8);
+    s = upload(g, g->k2_unit, &zero, 8);
     if (s) return s;
     return upload(g, g->kin_unit, &one, 16);
 }
@@ -668,6 +674,7 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
     g->kin_unit = (double2 *)(ws + off); off += 256;
     g->st_save[0] = (DevState *)(ws + off); off += 256;
     g->st_save[1] = (DevState *)(ws + off); off += 256;
+    g->sct = (double2 *)(ws + off); off += 16 * kSinCosTable;
     g->coarse_ratio = 0;
     if ((s = upload_static_tables(g)) || (s = upload_kinetic(g))) {
         delete g;

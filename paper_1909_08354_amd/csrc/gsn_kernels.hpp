@@ -20,6 +20,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <utility>
 
 #include "gsn_fft.hpp"
@@ -45,6 +46,7 @@ struct EmArgs {
     double g, dz;         // phase stage
     double *partials;     // per-block FP64 partials
     float *phi;           // potential readout destination (real rows of N)
+    const double2 *sct;   // (cos, sin) of j pi/128, j < 256 (pipelined phase pass)
 };
 
 template <int N, int E> struct EmShape {
@@ -254,6 +256,41 @@ __host__ __device__ __forceinline__ void sincos_fp64(double th, double *s, doubl
     const double ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
     *s = (q & 2) ? -ss : ss;
     *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// sin and cos in FP64 from a table: th = j pi/128 + r with |r| <= pi/256 (the
+// three parts of pi/2 above scaled by 1/64; each step is one FMA, whose exact
+// product keeps the reduced argument accurate to its own rounding while j fits
+// the table index, |th| < 5e7); tab[j mod 256] = (cos, sin)(j pi/128), and
+// sin r, cos r from their Taylor series to r^5 and r^6 (truncation below 1e-17
+// on |r| <= pi/256), combined by the angle-addition formulas.
+constexpr int kSinCosTable = 256;
+
+__host__ __device__ __forceinline__ void sincos_tab(double th, const double2 *tab, double *s, double *c)
+{
+    constexpr double k128OverPi = 40.743665431525205957;
+    constexpr double kQ1 = 1.5707963267341256e+00 / 64.0;
+    constexpr double kQ2 = 6.077100506303966e-11 / 64.0;
+    constexpr double kQ3 = 2.0222662487959506e-21 / 64.0;
+    const double jf = rint(th * k128OverPi);
+    double r = fma(-jf, kQ1, th);
+    r = fma(-jf, kQ2, r);
+    r = fma(-jf, kQ3, r);
+    const double2 cs = tab[(int)jf & (kSinCosTable - 1)];
+    const double r2 = r * r;
+    const double sr = fma(r * r2, fma(r2, 1.0 / 120.0, -1.0 / 6.0), r);
+    const double cr = fma(r2, fma(r2, fma(r2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    *s = fma(cs.y, cr, cs.x * sr);
+    *c = fma(cs.x, cr, -(cs.y * sr));
+}
+
+// The table sincos_tab reads, computed in extended precision and rounded.
+inline void fill_sincos_table(double2 *tab)
+{
+    for (int j = 0; j < kSinCosTable; ++j) {
+        const long double ang = (long double)j * 3.14159265358979323846264338327950288L / 128.0L;
+        tab[j] = make_double2((double)cosl(ang), (double)sinl(ang));
+    }
 }
 
 //
@@ -711,10 +748,11 @@ __device__ __forceinline__ void copy_twiddles(const double2 *__restrict__ tw, do
 
 // Phase pass (as phase_tile without ENERGY).
 template <int N, int E, int LINES, bool REAL_IN>
-__device__ __forceinline__ void phasep_body(const EmArgs &a, float2 *lds, double2 *twl)
+__device__ __forceinline__ void phasep_body(const EmArgs &a, float2 *lds, double2 *twl, double2 *scl_tab)
 {
-    constexpr int TPL = N / E;
+    constexpr int TPL = N / E, NT = LINES * TPL;
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    for (int i = tid; i < kSinCosTable; i += NT) scl_tab[i] = a.sct[i];
     copy_twiddles<N, E, LINES>(a.tw, twl);
     const int ntiles = (a.nlines + LINES - 1) / LINES;
     int tile = blockIdx.x;
@@ -757,7 +795,7 @@ __device__ __forceinline__ void phasep_body(const EmArgs &a, float2 *lds, double
                 const double rho = norm2(ps);
                 const double phi = (double)(half ? phi1[e] : phi0[e]);
                 double sn, cs;
-                sincos_fp64(fma(a.g, rho, phi) * a.dz, &sn, &cs);
+                sincos_tab(fma(a.g, rho, phi) * a.dz, scl_tab, &sn, &cs);
                 v[e] = cmul(ps, mk(cs, sn));
             }
             fft<N, E, -1>(v, t, lay, lds, twl);
@@ -892,7 +930,8 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phasep(EmArgs a)
 {
     __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
     __shared__ double2 twl[N];
-    phasep_body<N, E, LINES, REAL_IN>(a, lds, twl);
+    __shared__ double2 sct[kSinCosTable];
+    phasep_body<N, E, LINES, REAL_IN>(a, lds, twl, sct);
 }
 template <int N, int E, int LINES, bool STORE_PSI>
 __global__ __launch_bounds__(LINES *(N / E)) void k_densityp(EmArgs a)

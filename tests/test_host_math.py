@@ -1,5 +1,6 @@
-"""Host-side checks of device math helpers: the phase pass's FP64 sincos is an
-inline __host__ __device__ function, compiled here for the CPU from the same
+"""Host-side checks of device math helpers: the phase passes' FP64 sincos
+routines (series after a pi/2 reduction, and the 256-entry table form) are
+inline __host__ __device__ functions, compiled here for the CPU from the same
 header and compared with libm over every quadrant and large arguments."""
 import math
 import os
@@ -29,11 +30,12 @@ def test_sincos_fp64_matches_libm(tmp_path):
     out = subprocess.run([str(exe)], input="\n".join(repr(float(t)) for t in th),
                          capture_output=True, text=True, check=True).stdout.split("\n")
     sc = np.array([[float(v) for v in line.split()] for line in out if line.strip()])
-    assert sc.shape == (th.size, 2)
-    assert np.max(np.abs(sc[:, 0] - np.sin(th))) < 4e-16 * np.maximum(1, np.abs(th) / 1e5).max()
-    assert np.max(np.abs(sc[:, 1] - np.cos(th))) < 4e-16 * np.maximum(1, np.abs(th) / 1e5).max()
-    # the nonlinear step must be unitary to FP64 accuracy (no systematic norm drift)
-    assert np.max(np.abs(sc[:, 0] ** 2 + sc[:, 1] ** 2 - 1)) < 5e-16
+    assert sc.shape == (th.size, 4)
+    for s_col, c_col in ((0, 1), (2, 3)):   # sincos_fp64, then sincos_tab
+        assert np.max(np.abs(sc[:, s_col] - np.sin(th))) < 4e-16 * np.maximum(1, np.abs(th) / 1e5).max()
+        assert np.max(np.abs(sc[:, c_col] - np.cos(th))) < 4e-16 * np.maximum(1, np.abs(th) / 1e5).max()
+        # the nonlinear step must be unitary to FP64 accuracy (no systematic norm drift)
+        assert np.max(np.abs(sc[:, s_col] ** 2 + sc[:, c_col] ** 2 - 1)) < 5e-16
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
