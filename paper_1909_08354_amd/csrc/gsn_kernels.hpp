@@ -747,8 +747,8 @@ __device__ __forceinline__ void copy_twiddles(const double2 *__restrict__ tw, do
 }
 
 // Phase pass (as phase_tile without ENERGY).
-template <int N, int E, int LINES, bool REAL_IN>
-__device__ __forceinline__ void phasep_body(const EmArgs &a, float2 *lds, double2 *twl, double2 *scl_tab)
+template <int N, int E, int LINES, bool REAL_IN, class LT>
+__device__ __forceinline__ void phasep_body(const EmArgs &a, LT *lds, double2 *twl, double2 *scl_tab)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
@@ -810,8 +810,8 @@ __device__ __forceinline__ void phasep_body(const EmArgs &a, float2 *lds, double
 }
 
 // Density pass (as density_tile).
-template <int N, int E, int LINES, bool STORE_PSI>
-__device__ __forceinline__ void densityp_body(const EmArgs &a, float2 *lds, double2 *twl, double *sh)
+template <int N, int E, int LINES, bool STORE_PSI, class LT>
+__device__ __forceinline__ void densityp_body(const EmArgs &a, LT *lds, double2 *twl, double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL, H = N / 2;
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
@@ -854,7 +854,7 @@ __device__ __forceinline__ void densityp_body(const EmArgs &a, float2 *lds, doub
         }
         fft<N, E, -1>(v, t, lay, lds, twl);
 #pragma unroll
-        for (int e = 0; e < E; ++e) lds[lay(t + TPL * e)] = to_f2(v[e]);
+        for (int e = 0; e < E; ++e) lds_put(lds, lay(t + TPL * e), v[e]);
         exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
         {
             const int pair0 = __builtin_amdgcn_readfirstlane(pair);
@@ -864,7 +864,7 @@ __device__ __forceinline__ void densityp_body(const EmArgs &a, float2 *lds, doub
             for (int e = 0; e < E / 2; ++e) {
                 const int k = t + TPL * e;
                 const dc zz = v[e];
-                const dc zc = conj(from_f2(lds[lay((N - k) & (N - 1))]));
+                const dc zc = conj(lds_get(lds, lay((N - k) & (N - 1))));
                 const dc sm = add(zz, zc), df = sub(zz, zc);
                 buf_st2(to_f2(scl(sm, 0.5)), rs, vo, e * TPL * 8);
                 buf_st2(to_f2(mk(0.5 * df.y, -0.5 * df.x)), rs, vo, H * 8 + e * TPL * 8);
@@ -924,22 +924,22 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
     lm_tile<N, E, LINES, MODE>(a, blockIdx.x, lds, sh);
 }
 
-// Pipelined EM passes (persistent grid).
-template <int N, int E, int LINES, bool REAL_IN>
+// Pipelined EM passes (persistent grid); LT: complex64 or complex128 LDS slots.
+template <int N, int E, int LINES, bool REAL_IN, class LT = float2>
 __global__ __launch_bounds__(LINES *(N / E)) void k_phasep(EmArgs a)
 {
-    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ LT lds[EmTile<N, E, LINES>::LDS];
     __shared__ double2 twl[N];
     __shared__ double2 sct[kSinCosTable];
-    phasep_body<N, E, LINES, REAL_IN>(a, lds, twl, sct);
+    phasep_body<N, E, LINES, REAL_IN, LT>(a, lds, twl, sct);
 }
-template <int N, int E, int LINES, bool STORE_PSI>
+template <int N, int E, int LINES, bool STORE_PSI, class LT = float2>
 __global__ __launch_bounds__(LINES *(N / E)) void k_densityp(EmArgs a)
 {
-    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ LT lds[EmTile<N, E, LINES>::LDS];
     __shared__ double2 twl[N];
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
-    densityp_body<N, E, LINES, STORE_PSI>(a, lds, twl, sh);
+    densityp_body<N, E, LINES, STORE_PSI, LT>(a, lds, twl, sh);
 }
 // Pipelined LM pass (persistent grid); LT: complex64 or complex128 LDS slots.
 template <int N, int E, int LINES, int MODE, class LT>
