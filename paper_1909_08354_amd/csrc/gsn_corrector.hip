@@ -15,6 +15,7 @@
 // training is bitwise deterministic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -97,6 +98,104 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X, con
                 ((u16 *)Y)[p * COUT_P + ch] = f2bf(v);
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------- forward conv, LDS-tiled
+// Layers with 32 input channels on images whose width is a multiple of 64
+// and height a multiple of 4 (the 512^2 workload).  A block owns 4 rows x 64
+// pixels; the 6 x 66 input halo (circular) is staged once in LDS, each wave
+// computes one row (4 M-tiles of 16 pixels) against all output channels with
+// v_mfma_f32_16x16x32_bf16 (one K chunk = the 32 channels of one tap), the
+// weights live in registers for the block's lifetime (persistent blocks walk
+// the tiles), and outputs go back through LDS so each lane stores 16 bytes.
+// 16x16x32 operands (l = lane): A[i = l%16][k = 8(l/16)+0..7],
+// B[k = 8(l/16)+0..7][j = l%16], D[i = 4(l/16)+0..3][j = l%16].
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
+
+constexpr int kTH = 4, kTW = 64;              // output tile
+constexpr int kHP = kTH + 2, kWP = kTW + 2;   // staged input tile (halo 1)
+
+template <int COUT_P, int COUT, bool RELU, bool OUT_F32>
+__global__ __launch_bounds__(256) void k_conv_fwd_t(const u16 *__restrict__ X, const u16 *__restrict__ Wf,
+                                                    const float *__restrict__ bias, void *__restrict__ Y,
+                                                    int H, int W, int ntiles)
+{
+    constexpr int NB = COUT_P / 16;
+    constexpr int OUT_B = OUT_F32 ? 4 * COUT : 2 * COUT_P;   // output bytes per pixel
+    __shared__ u32x4v xin[kHP * kWP * 4];                      // 16-byte quarters of 64-byte pixels
+    __shared__ u32x4v yst[4][kTW * OUT_B / 16];                // per-wave output staging
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i16 = lane & 15, q = lane >> 4;
+    // weights: B fragments of all 9 taps and NB column blocks
+    bf16x8 wb[9][NB];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            wb[t][nb] = *(const bf16x8 *)(Wf + ((long long)(t * COUT_P + nb * 16 + i16)) * 32 + 8 * q);
+    float bch[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) bch[nb] = bias[nb * 16 + i16];
+    const int tx = W / kTW, ty = H / kTH;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int img = tile / (tx * ty), r0 = tile - img * tx * ty;
+        const int y0 = (r0 / tx) * kTH, x0 = (r0 % tx) * kTW;
+        const u16 *Xi = X + (long long)img * H * W * 32;
+        __syncthreads();   // the previous tile's readers are done with xin
+        for (int c = tid; c < kHP * kWP * 4; c += 256) {
+            const int pq = c & 3, pix = c >> 2, rr = pix / kWP, cc = pix - rr * kWP;
+            int ys = y0 + rr - 1, xs = x0 + cc - 1;
+            ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+            xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+            xin[c] = *(const u32x4v *)(Xi + ((long long)ys * W + xs) * 32 + pq * 8);
+        }
+        __syncthreads();
+        f32x4 acc[4][NB];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t % 3;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const u32x4v raw = xin[((wave + dy) * kWP + m * 16 + i16 + dx) * 4 + q];
+                const bf16x8 av = __builtin_bit_cast(bf16x8, raw);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, wb[t][nb], acc[m][nb], 0, 0, 0);
+            }
+        }
+        // bias, ReLU, convert, stage this wave's row in LDS
+        u16 *ys16 = (u16 *)yst[wave];
+        float *ysf = (float *)yst[wave];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int px = m * 16 + 4 * q + r, ch = nb * 16 + i16;
+                    float v = acc[m][nb][r] + bch[nb];
+                    if (RELU) v = v > 0.f ? v : 0.f;
+                    if constexpr (OUT_F32) {
+                        if (ch < COUT) ysf[px * COUT + ch] = v;
+                    } else {
+                        ys16[px * COUT_P + ch] = f2bf(v);
+                    }
+                }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // row (y0 + wave), pixels x0 .. x0 + 63: contiguous OUT_B * 64 bytes
+        char *yrow = (char *)Y + (((long long)img * H + y0 + wave) * W + x0) * OUT_B;
+#pragma unroll
+        for (int c = lane; c < kTW * OUT_B / 16; c += 64) ((u32x4v *)yrow)[c] = yst[wave][c];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -548,12 +647,27 @@ static gsn_status forward(gsn_corrector c, int B)
     const int H = c->H, W = c->W;
     hipLaunchKernelGGL((k_conv_fwd<4, 32, 32, true, false>), grid, block, 0, c->stream, c->x0, c->wf[0], c->bias[0],
                        (void *)c->a[0], H, W, np);
-    hipLaunchKernelGGL((k_conv_fwd<32, 32, 32, true, false>), grid, block, 0, c->stream, c->a[0], c->wf[1],
-                       c->bias[1], (void *)c->a[1], H, W, np);
-    hipLaunchKernelGGL((k_conv_fwd<32, 32, 32, true, false>), grid, block, 0, c->stream, c->a[1], c->wf[2],
-                       c->bias[2], (void *)c->a[2], H, W, np);
-    hipLaunchKernelGGL((k_conv_fwd<32, 16, 2, false, true>), grid, block, 0, c->stream, c->a[2], c->wf[3],
-                       c->bias[3], (void *)c->out, H, W, np);
+    if (W % kTW == 0 && H % kTH == 0) {
+        // LDS-tiled layers: persistent grid of at most 3 blocks per CU
+        const int ntiles = (int)(np / (kTW * kTH));
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
+            cus = 256;
+        const dim3 tg((unsigned)std::min(ntiles, 3 * cus));
+        hipLaunchKernelGGL((k_conv_fwd_t<32, 32, true, false>), tg, block, 0, c->stream, c->a[0], c->wf[1],
+                           c->bias[1], (void *)c->a[1], H, W, ntiles);
+        hipLaunchKernelGGL((k_conv_fwd_t<32, 32, true, false>), tg, block, 0, c->stream, c->a[1], c->wf[2],
+                           c->bias[2], (void *)c->a[2], H, W, ntiles);
+        hipLaunchKernelGGL((k_conv_fwd_t<16, 2, false, true>), tg, block, 0, c->stream, c->a[2], c->wf[3],
+                           c->bias[3], (void *)c->out, H, W, ntiles);
+    } else {
+        hipLaunchKernelGGL((k_conv_fwd<32, 32, 32, true, false>), grid, block, 0, c->stream, c->a[0], c->wf[1],
+                           c->bias[1], (void *)c->a[1], H, W, np);
+        hipLaunchKernelGGL((k_conv_fwd<32, 32, 32, true, false>), grid, block, 0, c->stream, c->a[1], c->wf[2],
+                           c->bias[2], (void *)c->a[2], H, W, np);
+        hipLaunchKernelGGL((k_conv_fwd<32, 16, 2, false, true>), grid, block, 0, c->stream, c->a[2], c->wf[3],
+                           c->bias[3], (void *)c->out, H, W, np);
+    }
     HIP_TRY(hipGetLastError());
     return GSN_OK;
 }

@@ -61,8 +61,12 @@ def make(B, H, W, seed, scales=(0.7, 0.7, 0.2)):
     return c, theta.astype(np.float64)
 
 
-def test_corrector_forward_matches_oracle():
-    B, H, W, scales = 2, 16, 32, (0.7, 0.7, 0.2)
+@pytest.mark.parametrize("B,H,W", [(2, 16, 32), (2, 8, 64), (1, 512, 512)])
+def test_corrector_forward_matches_oracle(B, H, W):
+    """16 x 32: one-wave implicit GEMM for every layer; 8 x 64 and 512 x 512:
+    the LDS-tiled 16x16x32 MFMA kernels for the 32-channel layers (the 512^2
+    image has more tiles than resident blocks, so blocks loop)."""
+    scales = (0.7, 0.7, 0.2)
     c, theta = make(B, H, W, 1, scales)
     psi, phi, tpsi, tphi = random_fields(B, H, W, 2)
     for b in range(B):
@@ -74,9 +78,10 @@ def test_corrector_forward_matches_oracle():
     assert rel < 2e-3
 
 
-def test_corrector_gradients_match_oracle():
+@pytest.mark.parametrize("B,H,W", [(2, 16, 32), (2, 8, 64)])
+def test_corrector_gradients_match_oracle(B, H, W):
     import torch
-    B, H, W, scales = 2, 16, 32, (0.7, 0.7, 0.2)
+    scales = (0.7, 0.7, 0.2)
     c, theta = make(B, H, W, 3, scales)
     psi, phi, tpsi, tphi = random_fields(B, H, W, 4)
     rng = np.random.default_rng(5)
