@@ -133,7 +133,9 @@ double gsn_pass_bytes_per_point(gsn_grid grid, int i);
    (variant 0 "e16", variant 1 "e8"); variants 2 "p16" and 3 "p8" run the
    strided-axis, density and phase passes with persistent blocks that
    prefetch their next tile while transforming the current one (the
-   operations of e16 / e8).  A variant changes the Stockham radix plan, the
+   operations of e16 / e8); variant 4 "s8" uses 8 points per thread with the
+   smallest tiles that fill a wavefront, for grids too small to give every
+   compute unit a tile.  A variant changes the Stockham radix plan, the
    tile shape and the LDS footprint, never the result beyond rounding.
    gsn_autotune times every variant of every pass of this grid (iters launches
    each, on a scratch copy of psi: the state is not modified) and keeps the

@@ -63,7 +63,7 @@ template <int N, int V> static NKernels make_kernels()
 template <int N> static const NKernels *variant_table(int v)
 {
     static const NKernels k[kNumVariants] = {make_kernels<N, 0>(), make_kernels<N, 1>(), make_kernels<N, 2>(),
-                                             make_kernels<N, 3>()};
+                                             make_kernels<N, 3>(), make_kernels<N, 4>()};
     return &k[v];
 }
 

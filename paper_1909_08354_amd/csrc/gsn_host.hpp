@@ -56,21 +56,28 @@ struct NKernels {
 
 // Schedule variants: E points per thread (16 or 8) for every pass kind, and
 // for the strided-axis (LM), density and phase passes either one tile per
-// block or persistent blocks that prefetch their next tile ("p16", "p8").  The EM tile holds
+// block or persistent blocks that prefetch their next tile ("p16", "p8");
+// "s8" is the small-tile form for small grids.  The EM tile holds
 // 256/TPL rows (at most 64); the LM tile holds LINES columns chosen so that a
 // tile moves >= 64-byte contiguous segments per row.  The batched solver
 // uses the first kNumBatchVariants.
-constexpr int kNumVariants = 4;
+constexpr int kNumVariants = 5;
 constexpr int kNumBatchVariants = 2;
-static const char *kVariantNames[kNumVariants] = {"e16", "e8", "p16", "p8"};
+static const char *kVariantNames[kNumVariants] = {"e16", "e8", "p16", "p8", "s8"};
 
+// "s8": 8 points per thread with the smallest tiles that still fill a
+// wavefront (one row pair per block where a row takes 64 threads, four
+// strided lines per block), for grids too small to give every CU a tile.
 template <int N, int V> struct Cfg {
-    static constexpr int E0 = (V & 1) ? 8 : 16;
-    static constexpr bool PIPE = V >= 2;
+    static constexpr bool SMALL = V == 4;
+    static constexpr int E0 = (V & 1) || SMALL ? 8 : 16;
+    static constexpr bool PIPE = V == 2 || V == 3;
     static constexpr int E = N < E0 ? N : E0;
     static constexpr int TPL = N / E;
-    static constexpr int LM_LINES = TPL <= 4 ? 64 : TPL <= 8 ? 32 : TPL <= 32 ? 16 : TPL <= 64 ? 8 : 4;
-    static constexpr int EM_LINES = (256 / TPL) > 64 ? 64 : (256 / TPL) < 1 ? 1 : 256 / TPL;
+    static constexpr int LM_LINES = SMALL ? (TPL >= 16 ? 4 : 64 / TPL)
+                                          : TPL <= 4 ? 64 : TPL <= 8 ? 32 : TPL <= 32 ? 16 : TPL <= 64 ? 8 : 4;
+    static constexpr int EM_LINES = SMALL ? (TPL >= 64 ? 1 : 64 / TPL)
+                                          : (256 / TPL) > 64 ? 64 : (256 / TPL) < 1 ? 1 : 256 / TPL;
 };
 
 // Kernel table of length N, schedule variant v (defined in gsn_api.hip, the
