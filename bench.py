@@ -77,7 +77,8 @@ def cpu_baseline(w, psi0_c128, budget_s=30.0):
 def batch_bench(steps):
     """The 64-instance sweep (256^2/512^2/1024^2, per-instance Yukawa couplings):
     one gsn_batch_step graph launch vs the same instances run one after another
-    through gsn_step with the same schedule (bit-identical results)."""
+    through gsn_step, with the batch's schedule (bit-identical results) and with
+    each shape's autotuned schedule."""
     import torch
     from paper_1909_08354_amd import gsn, inputs
     w = inputs.WORKLOADS["gsn2d_batch64_sweep"]
@@ -111,26 +112,54 @@ def batch_bench(steps):
         b.step(steps)
         b.sync()
         t_pers = time.perf_counter() - t0
-    grids = []
-    fam = {"kinetic": 0, "x_density": 0, "kernel": 0, "x_phase": 1}
-    for d in inst:
-        g = gsn.Grid(d["n"], d["L"])
-        g.set_kernel(*d["kern"])
-        g.set_coefficients(d["a"], d["g"], d["dz"])
-        g.set_schedule([fam.get(nm, 0) for nm in g.pass_names()])
-        g.set_psi(inputs.to_c64(d["psi"]))
-        grids.append(g)
-    grids[0].step(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for g in grids:
-        g.step(steps)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
+    # the plain form: every instance through gsn_step, (a) with the batch's own
+    # schedule (the batch default: persistent kinetic/kernel p16, density/phase
+    # p8, x entry/exit e16, stored real-space psi), bit-identical results;
+    # (b) with each shape's own autotuned schedule
+    fam = {"kinetic": 2, "x_density": 3, "kernel": 2, "x_phase": 3}
+
+    def make_grids(tuned):
+        out, sched = [], {}
+        for d in inst:
+            g = gsn.Grid(d["n"], d["L"])
+            g.set_kernel(*d["kern"])
+            g.set_coefficients(d["a"], d["g"], d["dz"])
+            g.set_psi(inputs.to_c64(d["psi"]))
+            if not tuned:
+                g.set_schedule([fam.get(nm, 0) for nm in g.pass_names()])
+                g.set_nonlinear_mode(1)
+            elif d["n"] not in sched:
+                g.autotune(5)
+                sched[d["n"]] = (g.schedule(), g.nonlinear_mode())
+            else:
+                names = g.pass_names()
+                vn = {nm: v for v, nm in enumerate(gsn.variant_names())}
+                s0, m = sched[d["n"]]
+                g.set_schedule([vn[s0[nm]] for nm in names])
+                g.set_nonlinear_mode(m)
+            out.append(g)
+        return out
+
+    def time_seq(grids):
+        grids[0].step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g in grids:
+            g.step(steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    grids = make_grids(False)
+    t_seq = time_seq(grids)
+    del grids
+    grids = make_grids(True)
+    t_tuned = time_seq(grids)
+    del grids
     return {"workload": "gsn2d_batch64_sweep", "instances": len(inst), "steps": steps,
             "grid_points": total_pts, "value": total_pts * steps / t_batch,
             "unit": "grid-pt updates/s", "ms_batch_graph": 1e3 * t_batch,
             "ms_sequential_gsn_step": 1e3 * t_seq, "speedup": t_seq / t_batch,
+            "ms_sequential_autotuned": 1e3 * t_tuned, "speedup_vs_autotuned": t_tuned / t_batch,
             "ms_batch_persistent": None if t_pers is None else 1e3 * t_pers,
             "speedup_persistent": None if t_pers is None else t_seq / t_pers,
             "max_norm_drift": drift,

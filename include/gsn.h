@@ -197,8 +197,12 @@ gsn_status gsn_batch_set_mode(gsn_batch batch, int mode);
    queue error instead of running it (every block then leaves its loop), so the
    failure path can be exercised without a real stall; -1 disables it. */
 gsn_status gsn_batch_set_queue_limits(gsn_batch batch, unsigned spin_limit, long long fail_item);
-/* Variant (0 "e16" / 1 "e8") per pass family {kinetic, density, kernel,
-   phase, x entry/exit} (nfam >= 5) and the nonlinear mode (as
+/* Variant per pass family {kinetic, density, kernel, phase, x entry/exit}
+   (nfam >= 5): 0 "e16" / 1 "e8" (one tile per block), 2 "p16" / 3 "p8"
+   (persistent blocks walking the tiles of every instance of a shape group,
+   prefetching the next tile; used for a group only when all its instances
+   share box lengths, a and dz, else that group runs variant - 2; x entry/exit
+   always one tile per block), and the nonlinear mode (as
    gsn_set_nonlinear_mode). */
 gsn_status gsn_batch_set_schedule(gsn_batch batch, const int *variants, int nfam, int nonlinear_mode);
 

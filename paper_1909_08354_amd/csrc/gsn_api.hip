@@ -254,7 +254,7 @@ static bool lm_fits(const Seg &s, int N, int lines)
 }
 
 // Resident blocks per CU times CUs (persistent grid size); 0 if unknown.
-static int persistent_blocks(const void *fn, int threads)
+int persistent_blocks(const void *fn, int threads)
 {
     static std::mutex mu;
     static std::map<std::pair<const void *, int>, int> cache;

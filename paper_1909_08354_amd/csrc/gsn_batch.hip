@@ -153,16 +153,14 @@ bool persistent_size(int n) { return n == 128 || n == 256 || n == 512 || n == 10
 
 
 // ------------------------------------------------------------------ grouped kernel tables
+// pipe: the density, phase, kinetic and kernel entries are the persistent
+// prefetching kernels (arguments: array, tiles per instance, instances).
 struct GKernels {
     int E, TPL, lm_lines, em_lines;
-    void (*em_fwd)(const EmArgs *, int);
-    void (*em_inv)(const EmArgs *, int);
-    void (*density)(const EmArgs *, int);
-    void (*density_store)(const EmArgs *, int);
-    void (*phase)(const EmArgs *, int);
-    void (*phase_real)(const EmArgs *, int);
-    void (*lm_kin)(const LmArgs *, int);
-    void (*lm_kern)(const LmArgs *, int);
+    bool pipe;
+    const void *em_fwd, *em_inv;
+    const void *density, *density_store, *phase, *phase_real;
+    const void *lm_kin, *lm_kern;
     int lm_threads() const { return lm_lines * TPL; }
     int em_threads() const { return em_lines * TPL; }
 };
@@ -176,20 +174,31 @@ template <int N, int V> GKernels make_gkernels()
     k.TPL = C::TPL;
     k.lm_lines = LL;
     k.em_lines = EL;
-    k.em_fwd = k_em_fft_g<N, E, EL, -1>;
-    k.em_inv = k_em_fft_g<N, E, EL, 1>;
-    k.density = k_density_g<N, E, EL, false>;
-    k.density_store = k_density_g<N, E, EL, true>;
-    k.phase = k_phase_g<N, E, EL, false>;
-    k.phase_real = k_phase_g<N, E, EL, true>;
-    k.lm_kin = k_lm_g<N, E, LL, LM_KIN>;
-    k.lm_kern = k_lm_g<N, E, LL, LM_KERN>;
+    k.pipe = C::PIPE;
+    k.em_fwd = (const void *)k_em_fft_g<N, E, EL, -1>;
+    k.em_inv = (const void *)k_em_fft_g<N, E, EL, 1>;
+    if constexpr (C::PIPE) {
+        k.density = (const void *)k_densityp_g<N, E, EL, false>;
+        k.density_store = (const void *)k_densityp_g<N, E, EL, true>;
+        k.phase = (const void *)k_phasep_g<N, E, EL, false>;
+        k.phase_real = (const void *)k_phasep_g<N, E, EL, true>;
+        k.lm_kin = (const void *)k_lmp_g<N, E, LL, LM_KIN>;
+        k.lm_kern = (const void *)k_lmp_g<N, E, LL, LM_KERN>;
+    } else {
+        k.density = (const void *)k_density_g<N, E, EL, false>;
+        k.density_store = (const void *)k_density_g<N, E, EL, true>;
+        k.phase = (const void *)k_phase_g<N, E, EL, false>;
+        k.phase_real = (const void *)k_phase_g<N, E, EL, true>;
+        k.lm_kin = (const void *)k_lm_g<N, E, LL, LM_KIN>;
+        k.lm_kern = (const void *)k_lm_g<N, E, LL, LM_KERN>;
+    }
     return k;
 }
 
 template <int N> const GKernels *gvariant(int v)
 {
-    static const GKernels k[kNumBatchVariants] = {make_gkernels<N, 0>(), make_gkernels<N, 1>()};
+    static const GKernels k[kNumBatchVariants] = {make_gkernels<N, 0>(), make_gkernels<N, 1>(), make_gkernels<N, 2>(),
+                                                  make_gkernels<N, 3>()};
     return &k[v];
 }
 
@@ -235,6 +244,8 @@ struct GLaunch {
     dim3 grid, block;
     const void *args;   // device array of EmArgs or LmArgs
     int tpi;
+    int count;          // instances (persistent kernels walk count * tpi tiles)
+    bool pipe;
 };
 
 struct Group {
@@ -263,6 +274,7 @@ struct gsn_batch_ {
     float2 *scratch;   // readout staging, 16 * max P bytes
     double *k2_unit;
     double2 *kin_unit;
+    double2 *sct;      // sin / cos table of the persistent phase pass
     // graph cache
     hipGraphExec_t exec;
     int64_t exec_steps;
@@ -322,7 +334,7 @@ gsn_status compute_blayout(int count, const int32_t *n, BLayout *L)
     L->scratch_off = off;
     off += align256(16ull * maxP);
     L->unit_off = off;
-    off += 512;
+    off += 512 + 16 * kSinCosTable;
     L->queue_off = off;
     off += align256(256) + align256(8ull * count) + align256(4ull * Q_NKIND * (count + 1)) +
            align256(sizeof(PInst) * (size_t)count);
@@ -392,12 +404,12 @@ EmArgs em_args(gsn_batch b, const Instance &I, int kind)
     a.half = I.half;
     a.nyq = I.nyq;
     a.tw = I.tw_x;
+    a.sct = b->sct;
     a.scale = kind == B_EXIT ? 1.0 / I.nx : 1.0;
     a.g = I.g;
     a.dz = I.dz;
     a.partials = I.mass_parts;
     a.nlines = (kind == B_ENTRY || kind == B_EXIT) ? I.ny : I.ny / 2;
-    (void)b;
     return a;
 }
 
@@ -451,24 +463,42 @@ LmArgs lm_args(gsn_batch b, const Instance &I, int kind, int lpt)
     return a;
 }
 
+// The persistent grouped kernels keep the first instance's tables (twiddles,
+// kinetic factors, |k|^2) in LDS for every instance of the group: only valid
+// when every member would have built identical tables.
+bool same_tables(gsn_batch b, const Group &G)
+{
+    const Instance &I0 = b->inst[G.members[0]];
+    for (int m : G.members) {
+        const Instance &I = b->inst[m];
+        if (I.Lx != I0.Lx || I.Ly != I0.Ly || I.a != I0.a || I.dz != I0.dz) return false;
+    }
+    return true;
+}
+
 // Rebuild every group's launch descriptors and upload the argument arrays.
 gsn_status build_batch(gsn_batch b)
 {
     for (Group &G : b->groups) {
         const int cnt = (int)G.members.size();
+        const bool uniform = same_tables(b, G);
         for (int kind = 0; kind < B_NKIND; ++kind) {
             const int fam = kFamOf[kind];
             const bool is_lm = (kind == B_KIN_HALF || kind == B_KIN_FULL || kind == B_KERNEL);
             const int N = is_lm ? G.ny : G.nx;
-            const GKernels *k = gkernels_for(N, b->var[fam]);
+            int var = b->var[fam];
+            if (var >= 2 && !uniform) var -= 2;   // same radix plan, one tile per block
+            const GKernels *k = gkernels_for(N, var);
             GLaunch &L = G.launch[kind];
+            L.pipe = k->pipe && kind != B_ENTRY && kind != B_EXIT;
+            L.count = cnt;
             if (is_lm) {
                 std::vector<LmArgs> v(cnt);
                 for (int m = 0; m < cnt; ++m) v[m] = lm_args(b, b->inst[G.members[m]], kind, k->lm_lines);
                 gsn_status s = upload_sync(b->stream, G.args_dev[kind], v.data(), sizeof(LmArgs) * cnt);
                 if (s) return s;
                 L.tpi = v[0].s0.ntiles + v[0].s1.ntiles;
-                L.fn = (const void *)(kind == B_KERNEL ? k->lm_kern : k->lm_kin);
+                L.fn = kind == B_KERNEL ? k->lm_kern : k->lm_kin;
                 L.block = dim3(k->lm_threads());
             } else {
                 std::vector<EmArgs> v(cnt);
@@ -477,13 +507,18 @@ gsn_status build_batch(gsn_batch b)
                 if (s) return s;
                 L.tpi = (v[0].nlines + k->em_lines - 1) / k->em_lines;
                 const bool st = b->store_psi != 0;
-                L.fn = kind == B_ENTRY ? (const void *)k->em_fwd
-                     : kind == B_EXIT ? (const void *)k->em_inv
-                     : kind == B_DENSITY ? (const void *)(st ? k->density_store : k->density)
-                                         : (const void *)(st ? k->phase_real : k->phase);
+                L.fn = kind == B_ENTRY ? k->em_fwd
+                     : kind == B_EXIT ? k->em_inv
+                     : kind == B_DENSITY ? (st ? k->density_store : k->density)
+                                         : (st ? k->phase_real : k->phase);
                 L.block = dim3(k->em_threads());
             }
-            L.grid = dim3(L.tpi * cnt);
+            int grid = L.tpi * cnt;
+            if (L.pipe) {
+                const int pb = persistent_blocks(L.fn, (int)L.block.x);
+                if (pb > 0 && pb < grid) grid = pb;
+            }
+            L.grid = dim3(grid);
             L.args = G.args_dev[kind];
         }
     }
@@ -495,8 +530,8 @@ gsn_status build_batch(gsn_batch b)
 hipError_t glaunch(const GLaunch &L, hipStream_t s)
 {
     const void *args_ptr = L.args;
-    int tpi = L.tpi;
-    void *args[2] = {(void *)&args_ptr, (void *)&tpi};
+    int tpi = L.tpi, count = L.count;
+    void *args[3] = {(void *)&args_ptr, (void *)&tpi, (void *)&count};
     return hipLaunchKernel(L.fn, L.grid, L.block, args, 0, s);
 }
 
@@ -688,7 +723,7 @@ extern "C" gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, cons
     b->exec_steps = -1;
     b->dirty = true;
     b->mode = 0;
-    b->store_psi = 0;
+    b->store_psi = 1;
     b->pq = b->ws + lay.queue_off;
     {
         char *q = (char *)b->pq;
@@ -704,11 +739,13 @@ extern "C" gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, cons
         b->spin_limit = 1u << 22;
         b->fail_item = -1;
     }
-    // default schedule: the variants the single-grid autotuner favours on gfx950
-    b->var[F_KIN] = 0;
-    b->var[F_DENSITY] = 0;
-    b->var[F_KERNEL] = 0;
-    b->var[F_PHASE] = 1;
+    // default schedule: the fastest measured on gfx950 for the 64-instance
+    // sweep of 256^2 / 512^2 / 1024^2 grids (persistent passes, real-space
+    // psi stored by the density pass)
+    b->var[F_KIN] = 2;
+    b->var[F_DENSITY] = 3;
+    b->var[F_KERNEL] = 2;
+    b->var[F_PHASE] = 3;
     b->var[F_XFFT] = 0;
     if (hipGetDevice(&b->device) != hipSuccess) {
         delete b;
@@ -717,6 +754,7 @@ extern "C" gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, cons
     b->scratch = (float2 *)(b->ws + lay.scratch_off);
     b->k2_unit = (double *)(b->ws + lay.unit_off);
     b->kin_unit = (double2 *)(b->ws + lay.unit_off + 256);
+    b->sct = (double2 *)(b->ws + lay.unit_off + 512);
     b->inst.resize(count);
     std::map<std::pair<int, int>, int> gidx;
     for (int i = 0; i < count; ++i) {
@@ -770,7 +808,10 @@ extern "C" gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, cons
     }
     const double zero = 0.0;
     const double2 one = make_double2(1.0, 0.0);
-    if ((s = upload_sync(b->stream, b->k2_unit, &zero, 8)) || (s = upload_sync(b->stream, b->kin_unit, &one, 16))) {
+    std::vector<double2> sct(kSinCosTable);
+    fill_sincos_table(sct.data());
+    if ((s = upload_sync(b->stream, b->k2_unit, &zero, 8)) || (s = upload_sync(b->stream, b->kin_unit, &one, 16)) ||
+        (s = upload_sync(b->stream, b->sct, sct.data(), 16ull * kSinCosTable))) {
         delete b;
         return s;
     }

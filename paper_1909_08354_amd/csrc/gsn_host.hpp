@@ -60,9 +60,9 @@ struct NKernels {
 // "s8" is the small-tile form for small grids.  The EM tile holds
 // 256/TPL rows (at most 64); the LM tile holds LINES columns chosen so that a
 // tile moves >= 64-byte contiguous segments per row.  The batched solver
-// uses the first kNumBatchVariants.
+// offers the first kNumBatchVariants.
 constexpr int kNumVariants = 5;
-constexpr int kNumBatchVariants = 2;
+constexpr int kNumBatchVariants = 4;
 static const char *kVariantNames[kNumVariants] = {"e16", "e8", "p16", "p8", "s8"};
 
 // "s8": 8 points per thread with the smallest tiles that still fill a
@@ -83,6 +83,11 @@ template <int N, int V> struct Cfg {
 // Kernel table of length N, schedule variant v (defined in gsn_api.hip, the
 // only translation unit that instantiates the single-grid kernels).
 const NKernels *kernels_for(int N, int v = 0);
+
+// Blocks of kernel fn (threads per block) resident on the whole device at
+// once (occupancy x compute units): the grid of a persistent kernel; 0 if
+// the runtime cannot say.  Cached per kernel and device.
+int persistent_blocks(const void *fn, int threads);
 
 // wavenumber of DFT index j on an axis with N points and length L
 static inline double wavenumber(int j, int N, double L)

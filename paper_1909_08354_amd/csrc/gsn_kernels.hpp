@@ -492,6 +492,33 @@ __device__ __forceinline__ void buf_st2(float2 v, __amdgpu_buffer_rsrc_t r, unsi
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
+// A pointer read from memory (a grouped pass's argument array) is generic;
+// generic accesses count on both the vector-memory and the scalar/LDS
+// counters, so a wait for them would also wait for every prefetch in flight.
+// The arrays live in global memory: say so.
+template <class T> __device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+// element i of a global double2 / float2 array (the vector types' operators
+// take generic references, so go through the scalar components)
+__device__ __forceinline__ double2 gld(const double2 *p, long long i)
+{
+    const auto q = gmem((const double *)p) + 2 * i;
+    return make_double2(q[0], q[1]);
+}
+__device__ __forceinline__ float2 gld(const float2 *p, long long i)
+{
+    const auto q = gmem((const float *)p) + 2 * i;
+    return make_float2(q[0], q[1]);
+}
+__device__ __forceinline__ void gst(float2 *p, long long i, float2 v)
+{
+    const auto q = gmem((float *)p) + 2 * i;
+    q[0] = v.x;
+    q[1] = v.y;
+}
+
 // Where the lanes of a block find tile `tile` of an LM pass.  A lane whose
 // line lies past the end of its segment takes the segment's last line: it
 // loads, transforms and stores exactly what that line's own lane does (the
@@ -549,56 +576,99 @@ __device__ __forceinline__ void lm_fetch(const LmArgs &a, const LmWhere &w, bool
 #pragma unroll
     for (int e = 0; e < E; ++e) f.p[e] = buf_ld2(w.r, vo, e * st);
     if constexpr (MODE == LM_KIN) {
-        f.f1 = a.kin1[live ? w.c1 : 0];
-        f.f2 = a.kin2[live ? w.c2 : 0];
+        f.f1 = gld(a.kin1, live ? w.c1 : 0);
+        f.f2 = gld(a.kin2, live ? w.c2 : 0);
     } else if constexpr (MODE == LM_KERN) {
-        f.q1 = a.k2_1[live ? w.c1 : 0];
-        f.q2 = a.k2_2[live ? w.c2 : 0];
+        f.q1 = gmem(a.k2_1)[live ? w.c1 : 0];
+        f.q2 = gmem(a.k2_2)[live ? w.c2 : 0];
     }
 }
 
-template <int N, int E, int LINES, int MODE, class LT>
-__device__ __forceinline__ void lmp_body(const LmArgs &a, LT *lds, double2 *twl, double2 *kpl, double *k2l,
+// Where the tiles of a pipelined pass come from: one grid (tile t of its
+// argument struct) or the instances of a batch group (tile t is tile t mod tpi
+// of instance t / tpi; the structs sit in a device array and are read with
+// scalar loads, since t is uniform across the block).
+template <class A> struct Src1 {
+    static constexpr bool GROUPED = false;
+    A a;   // by value: the fields then stay scalar values after inlining
+    int n;
+    __device__ __forceinline__ int ntiles() const { return n; }
+    __device__ __forceinline__ const A &args(int) const { return a; }
+    __device__ __forceinline__ int local(int tile) const { return tile; }
+};
+template <class A> struct SrcG {
+    static constexpr bool GROUPED = true;
+    const A *__restrict__ arr;
+    int tpi, count;
+    __device__ __forceinline__ int ntiles() const { return tpi * count; }
+    __device__ __forceinline__ const A &args(int tile) const { return arr[tile / tpi]; }
+    __device__ __forceinline__ int local(int tile) const { return tile - (tile / tpi) * tpi; }
+};
+
+// FP64 sum of the density pass's mass partials, folded into the state
+// (global phase, step count, non-finite flag); every thread of the block calls it.
+template <int NT>
+__device__ __forceinline__ void reduce_mass(const LmArgs &a, double *sh)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < a.nmass; i += NT) s += gmem(a.mass_parts)[i];
+    s = block_sum<NT>(s, sh);
+    if (threadIdx.x == 0) {
+        auto st = gmem(a.st);
+        st->mass_sum = s;
+        st->theta += a.k0_dz_over_P * s;
+        st->steps += 1;
+        if (!isfinite(s)) st->nonfinite = 1;
+    }
+}
+
+// Tables shared by every tile (and, in a group, by every instance: the host
+// only groups instances whose tables are identical) go to LDS once.
+template <int N, int E, int LINES, int MODE, class LT, class Src>
+__device__ __forceinline__ void lmp_body(const Src &src, LT *lds, double2 *twl, double2 *kpl, double *k2l,
                                          double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
     static_assert(MODE == LM_FWD || MODE == LM_INV || MODE == LM_KIN || MODE == LM_KERN, "mode");
     const int tid = threadIdx.x, l = tid % LINES, t = tid / LINES;
-    for (int i = tid; i < N; i += NT) {
-        twl[i] = a.tw[i];
-        if constexpr (MODE == LM_KIN) kpl[i] = a.kinp[i];
-        if constexpr (MODE == LM_KERN) k2l[i] = a.k2_p[i];
-    }
-    if (a.reduce && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = tid; i < a.nmass; i += NT) s += a.mass_parts[i];
-        s = block_sum<NT>(s, sh);
-        if (tid == 0) {
-            a.st->mass_sum = s;
-            a.st->theta += a.k0_dz_over_P * s;
-            a.st->steps += 1;
-            if (!isfinite(s)) a.st->nonfinite = 1;
+    {
+        const LmArgs &a0 = src.args(0);
+        for (int i = tid; i < N; i += NT) {
+            twl[i] = gld(a0.tw, i);
+            if constexpr (MODE == LM_KIN) kpl[i] = gld(a0.kinp, i);
+            if constexpr (MODE == LM_KERN) k2l[i] = gmem(a0.k2_p)[i];
+        }
+        if constexpr (!Src::GROUPED) {
+            if (a0.reduce && blockIdx.x == 0) reduce_mass<NT>(a0, sh);
         }
     }
     __syncthreads();
-    const int ntiles = a.s0.ntiles + a.s1.ntiles;
+    const int ntiles = src.ntiles();
     int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const LmLayout<LINES> lay{l};
     LmPrefetch<E> f;
-    lm_fetch<N, E, LINES, MODE>(a, lm_where<N, E, LINES>(a, tile, l, t), true, f);
+    lm_fetch<N, E, LINES, MODE>(src.args(tile), lm_where<N, E, LINES>(src.args(tile), src.local(tile), l, t), true, f);
     dc v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = from_f2(f.p[e]);
     // this tile's line factors, taken before the prefetch reuses f
     dc m12 = mk(0.0, 0.0);
     double q12 = 0.0;
-    if constexpr (MODE == LM_KIN) m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), a.scale);
+    if constexpr (MODE == LM_KIN) m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), src.args(tile).scale);
     if constexpr (MODE == LM_KERN) q12 = f.q1 + f.q2;
     for (;;) {
+        const LmArgs &a = src.args(tile);
         const int nxt = tile + gridDim.x;
         const bool more = nxt < ntiles;
-        lm_fetch<N, E, LINES, MODE>(a, lm_where<N, E, LINES>(a, more ? nxt : tile, l, t), more, f);
+        {
+            const int pf = more ? nxt : tile;
+            const LmArgs &an = src.args(pf);
+            lm_fetch<N, E, LINES, MODE>(an, lm_where<N, E, LINES>(an, src.local(pf), l, t), more, f);
+        }
+        if constexpr (Src::GROUPED) {
+            if (a.reduce && src.local(tile) == 0) reduce_mass<NT>(a, sh);
+        }
         if constexpr (MODE == LM_FWD || MODE == LM_INV) {
             fft<N, E, MODE == LM_FWD ? -1 : 1>(v, t, lay, lds, twl);
 #pragma unroll
@@ -611,20 +681,22 @@ __device__ __forceinline__ void lmp_body(const LmArgs &a, LT *lds, double2 *twl,
             } else {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
+                    // branch-free: k = 0 divides by 1 and is then zeroed
                     const double k2 = q12 + k2l[t + TPL * e];
+                    const bool pos = k2 > 0.0;
                     const double km = k2 + a.mY2;
                     const double num = fma(a.cN, km, a.cY * k2);
-                    const double den = k2 * km;
+                    const double den = pos ? k2 * km : 1.0;
                     double r = __builtin_amdgcn_rcp(den);
                     r = fma(r, fma(-den, r, 1.0), r);
                     r = fma(r, fma(-den, r, 1.0), r);
-                    const double K = k2 > 0.0 ? fma(num, r, a.c0) : 0.0;
+                    const double K = pos ? fma(num, r, a.c0) : 0.0;
                     v[e] = scl(v[e], K * a.scale);
                 }
             }
             fft<N, E, 1>(v, t, lay, lds, twl);
         }
-        const LmWhere w = lm_where<N, E, LINES>(a, tile, l, t);
+        const LmWhere w = lm_where<N, E, LINES>(a, src.local(tile), l, t);
 #pragma unroll
         for (int e = 0; e < E; ++e) buf_st2(to_f2(v[e]), w.r, w.voff, e * w.step);
         if (!more) break;
@@ -634,7 +706,7 @@ __device__ __forceinline__ void lmp_body(const LmArgs &a, LT *lds, double2 *twl,
         // also have to cover the path from the first fetch: vmcnt(0))
         convert_pinned(v, f.p, std::make_integer_sequence<int, E>{});
         if constexpr (MODE == LM_KIN) {
-            m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), a.scale);
+            m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), src.args(nxt).scale);
             pin(m12);
         }
         if constexpr (MODE == LM_KERN) {
@@ -707,8 +779,8 @@ __device__ __forceinline__ void em_fetch_phi(const EmArgs &a, int pair, int t, b
         f.h1[e] = buf_ld2(rs, vo, H * 8);
     }
     const long long r0 = live ? 2LL * pair : 2LL * pair0;
-    f.n0 = a.nyq[r0];
-    f.n1 = a.nyq[r0 + 1];
+    f.n0 = gld(a.nyq, r0);
+    f.n1 = gld(a.nyq, r0 + 1);
 }
 
 // The full spectrum Z = X_0 + i X_1 of the pair (conjugate symmetry; DC and
@@ -742,38 +814,40 @@ template <int N, int E, int LINES>
 __device__ __forceinline__ void copy_twiddles(const double2 *__restrict__ tw, double2 *twl)
 {
     constexpr int NT = LINES * (N / E);
-    for (int i = threadIdx.x; i < N; i += NT) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < N; i += NT) twl[i] = gld(tw, i);
     __syncthreads();
 }
 
 // Phase pass (as phase_tile without ENERGY).
-template <int N, int E, int LINES, bool REAL_IN, class LT>
-__device__ __forceinline__ void phasep_body(const EmArgs &a, LT *lds, double2 *twl, double2 *scl_tab)
+template <int N, int E, int LINES, bool REAL_IN, class LT, class Src>
+__device__ __forceinline__ void phasep_body(const Src &src, LT *lds, double2 *twl, double2 *scl_tab)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
-    for (int i = tid; i < kSinCosTable; i += NT) scl_tab[i] = a.sct[i];
-    copy_twiddles<N, E, LINES>(a.tw, twl);
-    const int ntiles = (a.nlines + LINES - 1) / LINES;
+    for (int i = tid; i < kSinCosTable; i += NT) scl_tab[i] = gld(src.args(0).sct, i);
+    copy_twiddles<N, E, LINES>(src.args(0).tw, twl);
+    const int ntiles = src.ntiles();
     int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     const double inv_n = 1.0 / N;
     PhiRaw<N, E> fp;
     float2 p0[E], p1[E];
-    int pair = em_pair<N, E, LINES>(a, tile, l);
-    em_fetch_phi<N, E>(a, pair, t, true, fp);
-    em_fetch_row<N, E>(a, pair, 0, t, true, p0);
-    em_fetch_row<N, E>(a, pair, 1, t, true, p1);
+    int pair = em_pair<N, E, LINES>(src.args(tile), src.local(tile), l);
+    em_fetch_phi<N, E>(src.args(tile), pair, t, true, fp);
+    em_fetch_row<N, E>(src.args(tile), pair, 0, t, true, p0);
+    em_fetch_row<N, E>(src.args(tile), pair, 1, t, true, p1);
     // nothing outstanding on entry to the loop: its waits then only count
     // the loop's own operations
     __builtin_amdgcn_s_waitcnt(0);
     dc z[E];
     em_build_z<N, E>(fp, t, z);
     for (;;) {
+        const EmArgs &a = src.args(tile);
         const int nxt = tile + gridDim.x;
         const bool more = nxt < ntiles;
-        const int npair = more ? em_pair<N, E, LINES>(a, nxt, l) : pair;
+        const EmArgs &an = src.args(more ? nxt : tile);
+        const int npair = more ? em_pair<N, E, LINES>(an, src.local(nxt), l) : pair;
         fft<N, E, 1>(z, t, lay, lds, twl);
         float phi0[E], phi1[E];
 #pragma unroll
@@ -781,13 +855,13 @@ __device__ __forceinline__ void phasep_body(const EmArgs &a, LT *lds, double2 *t
             phi0[e] = (float)(z[e].x * inv_n);
             phi1[e] = (float)(z[e].y * inv_n);
         }
-        em_fetch_phi<N, E>(a, npair, t, more, fp);
+        em_fetch_phi<N, E>(an, npair, t, more, fp);
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             dc v[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = from_f2(half ? p1[e] : p0[e]);
-            em_fetch_row<N, E>(a, npair, half, t, more, half ? p1 : p0);
+            em_fetch_row<N, E>(an, npair, half, t, more, half ? p1 : p0);
             if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, twl);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -810,39 +884,42 @@ __device__ __forceinline__ void phasep_body(const EmArgs &a, LT *lds, double2 *t
 }
 
 // Density pass (as density_tile).
-template <int N, int E, int LINES, bool STORE_PSI, class LT>
-__device__ __forceinline__ void densityp_body(const EmArgs &a, LT *lds, double2 *twl, double *sh)
+template <int N, int E, int LINES, bool STORE_PSI, class LT, class Src>
+__device__ __forceinline__ void densityp_body(const Src &src, LT *lds, double2 *twl, double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL, H = N / 2;
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
-    copy_twiddles<N, E, LINES>(a.tw, twl);
-    const int ntiles = (a.nlines + LINES - 1) / LINES;
+    copy_twiddles<N, E, LINES>(src.args(0).tw, twl);
+    const int ntiles = src.ntiles();
     int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     const double inv_n = 1.0 / N;
     float2 p0[E], p1[E];
-    int pair = em_pair<N, E, LINES>(a, tile, l);
-    em_fetch_row<N, E>(a, pair, 0, t, true, p0);
-    em_fetch_row<N, E>(a, pair, 1, t, true, p1);
+    int pair = em_pair<N, E, LINES>(src.args(tile), src.local(tile), l);
+    em_fetch_row<N, E>(src.args(tile), pair, 0, t, true, p0);
+    em_fetch_row<N, E>(src.args(tile), pair, 1, t, true, p1);
     __builtin_amdgcn_s_waitcnt(0);
     dc v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = from_f2(p0[e]);
     for (;;) {
+        const EmArgs &a = src.args(tile);
+        const int loc = src.local(tile);
         const int nxt = tile + gridDim.x;
         const bool more = nxt < ntiles;
-        const int npair = more ? em_pair<N, E, LINES>(a, nxt, l) : pair;
-        const bool real = tile * LINES + l < a.nlines;
+        const EmArgs &an = src.args(more ? nxt : tile);
+        const int npair = more ? em_pair<N, E, LINES>(an, src.local(nxt), l) : pair;
+        const bool real = loc * LINES + l < a.nlines;
         double rho0[E];
-        em_fetch_row<N, E>(a, npair, 0, t, more, p0);
+        em_fetch_row<N, E>(an, npair, 0, t, more, p0);
         fft<N, E, 1>(v, t, lay, lds, twl);
 #pragma unroll
         for (int e = 0; e < E; ++e) rho0[e] = norm2(v[e]) * (inv_n * inv_n);
         if constexpr (STORE_PSI) em_store_row<N, E>(a, pair, 0, t, v, inv_n);
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = from_f2(p1[e]);
-        em_fetch_row<N, E>(a, npair, 1, t, more, p1);
+        em_fetch_row<N, E>(an, npair, 1, t, more, p1);
         fft<N, E, 1>(v, t, lay, lds, twl);
         if constexpr (STORE_PSI) em_store_row<N, E>(a, pair, 1, t, v, inv_n);
         double msum = 0.0;
@@ -872,13 +949,13 @@ __device__ __forceinline__ void densityp_body(const EmArgs &a, LT *lds, double2 
         }
         if (t == 0) {
             const dc zn = v[E / 2];   // bin N/2: both halves are real
-            a.nyq[2LL * pair] = make_float2((float)zn.x, 0.0f);
-            a.nyq[2LL * pair + 1] = make_float2((float)zn.y, 0.0f);
+            gst(a.nyq, 2LL * pair, make_float2((float)zn.x, 0.0f));
+            gst(a.nyq, 2LL * pair + 1, make_float2((float)zn.y, 0.0f));
         }
         // the LDS slots are rewritten by the next tile's first transform
         exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
         const double bs = block_sum<NT>(real ? msum : 0.0, sh);
-        if (tid == 0) a.partials[tile] = bs;
+        if (tid == 0) gmem(a.partials)[loc] = bs;
         if (!more) break;
         convert_pinned(v, p0, std::make_integer_sequence<int, E>{});
         tile = nxt;
@@ -931,7 +1008,8 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phasep(EmArgs a)
     __shared__ LT lds[EmTile<N, E, LINES>::LDS];
     __shared__ double2 twl[N];
     __shared__ double2 sct[kSinCosTable];
-    phasep_body<N, E, LINES, REAL_IN, LT>(a, lds, twl, sct);
+    const Src1<EmArgs> src{a, (a.nlines + LINES - 1) / LINES};
+    phasep_body<N, E, LINES, REAL_IN, LT>(src, lds, twl, sct);
 }
 template <int N, int E, int LINES, bool STORE_PSI, class LT = float2>
 __global__ __launch_bounds__(LINES *(N / E)) void k_densityp(EmArgs a)
@@ -939,7 +1017,8 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_densityp(EmArgs a)
     __shared__ LT lds[EmTile<N, E, LINES>::LDS];
     __shared__ double2 twl[N];
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
-    densityp_body<N, E, LINES, STORE_PSI, LT>(a, lds, twl, sh);
+    const Src1<EmArgs> src{a, (a.nlines + LINES - 1) / LINES};
+    densityp_body<N, E, LINES, STORE_PSI, LT>(src, lds, twl, sh);
 }
 // Pipelined LM pass (persistent grid); LT: complex64 or complex128 LDS slots.
 template <int N, int E, int LINES, int MODE, class LT>
@@ -950,7 +1029,8 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lmp(LmArgs a)
     __shared__ double2 kpl[MODE == LM_KIN ? N : 1];
     __shared__ double k2l[MODE == LM_KERN ? N : 1];
     __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
-    lmp_body<N, E, LINES, MODE, LT>(a, lds, twl, kpl, k2l, sh);
+    const Src1<LmArgs> src{a, a.s0.ntiles + a.s1.ntiles};
+    lmp_body<N, E, LINES, MODE, LT>(src, lds, twl, kpl, k2l, sh);
 }
 
 template <int N, int E, int LINES, int S>
@@ -983,6 +1063,38 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lm_g(const LmArgs *__restric
     __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
     const LmArgs a = args[blockIdx.x / tpi];
     lm_tile<N, E, LINES, MODE>(a, blockIdx.x % tpi, lds, sh);
+}
+
+// Grouped persistent prefetching passes: blocks walk the tiles of every
+// instance of the group (instance-major numbering, tpi tiles per instance).
+template <int N, int E, int LINES, int MODE>
+__global__ __launch_bounds__(LINES *(N / E)) void k_lmp_g(const LmArgs *__restrict__ args, int tpi, int count)
+{
+    __shared__ float2 lds[LmTile<N, E, LINES>::LDS];
+    __shared__ double2 twl[N];
+    __shared__ double2 kpl[MODE == LM_KIN ? N : 1];
+    __shared__ double k2l[MODE == LM_KERN ? N : 1];
+    __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
+    const SrcG<LmArgs> src{args, tpi, count};
+    lmp_body<N, E, LINES, MODE, float2>(src, lds, twl, kpl, k2l, sh);
+}
+template <int N, int E, int LINES, bool STORE_PSI>
+__global__ __launch_bounds__(LINES *(N / E)) void k_densityp_g(const EmArgs *__restrict__ args, int tpi, int count)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double2 twl[N];
+    __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
+    const SrcG<EmArgs> src{args, tpi, count};
+    densityp_body<N, E, LINES, STORE_PSI, float2>(src, lds, twl, sh);
+}
+template <int N, int E, int LINES, bool REAL_IN>
+__global__ __launch_bounds__(LINES *(N / E)) void k_phasep_g(const EmArgs *__restrict__ args, int tpi, int count)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double2 twl[N];
+    __shared__ double2 sct[kSinCosTable];
+    const SrcG<EmArgs> src{args, tpi, count};
+    phasep_body<N, E, LINES, REAL_IN, float2>(src, lds, twl, sct);
 }
 
 // ---------------------------------------------------------------- small kernels

@@ -322,6 +322,12 @@ class Grid:
 BATCH_FAMILIES = ("kinetic", "x_density", "kernel", "x_phase", "x_fft")
 
 
+def variant_names():
+    """Names of the FFT schedule variants by index (gsn_variant_name)."""
+    lib = load()
+    return [lib.gsn_variant_name(i).decode() for i in range(lib.gsn_variant_count())]
+
+
 class Batch:
     """Many independent 2-D instances advanced together (gsn_batch_create)."""
 

@@ -33,7 +33,9 @@ def grid_schedule(grid, variants):
     return v
 
 
-def make_instances(shapes, seed):
+def make_instances(shapes, seed, dz=None):
+    """dz=None: a different dz per instance (so members of one shape group
+    have different kinetic tables); else that dz for all."""
     rng = np.random.default_rng(seed)
     out = []
     for n in shapes:
@@ -41,7 +43,8 @@ def make_instances(shapes, seed):
         w = max(1.5, min(n) / 6)
         cs, ws, vs = inputs.random_lumps(rng, n, L, int(rng.integers(1, 4)), (w, 1.5 * w))
         kern = (1.0, float(rng.uniform(0, 1)), float(rng.uniform(0.05, 0.5)), 0.0)
-        out.append(dict(n=n, L=L, kern=kern, a=0.5, g=-0.5, dz=float(rng.uniform(1e-3, 3e-3)),
+        ddz = float(rng.uniform(1e-3, 3e-3))
+        out.append(dict(n=n, L=L, kern=kern, a=0.5, g=-0.5, dz=ddz if dz is None else dz,
                         psi=inputs.lumps(n, L, cs, ws, vs)))
     return out
 
@@ -49,9 +52,15 @@ def make_instances(shapes, seed):
 SHAPES = [(32, 32), (64, 32), (32, 32), (16, 64), (64, 32), (128, 128), (32, 32)]
 
 
-@pytest.mark.parametrize("variants,nlmode", [((0, 0, 0, 1, 0), 0), ((1, 1, 1, 0, 1), 1)])
-def test_batch_equals_independent_grids(variants, nlmode):
-    inst = make_instances(SHAPES, 5)
+@pytest.mark.parametrize("variants,nlmode,dz,grid_variants", [
+    ((0, 0, 0, 1, 0), 0, None, None), ((1, 1, 1, 0, 1), 1, None, None),
+    # persistent grouped passes (one table set per shape group)
+    ((2, 2, 2, 3, 0), 1, 2e-3, None), ((3, 3, 3, 2, 1), 0, 1.5e-3, None),
+    # persistent variants asked for, but the members' tables differ: the
+    # group runs the one-tile-per-block passes of the same radix plan
+    ((2, 3, 2, 3, 0), 1, None, (0, 1, 0, 1, 0))])
+def test_batch_equals_independent_grids(variants, nlmode, dz, grid_variants):
+    inst = make_instances(SHAPES, 5, dz)
     b = gsn.Batch([d["n"] for d in inst], [d["L"] for d in inst])
     b.set_schedule(list(variants), nlmode)
     for i, d in enumerate(inst):
@@ -64,7 +73,7 @@ def test_batch_equals_independent_grids(variants, nlmode):
         g = gsn.Grid(d["n"], d["L"])
         g.set_kernel(*d["kern"])
         g.set_coefficients(d["a"], d["g"], d["dz"])
-        g.set_schedule(grid_schedule(g, variants))
+        g.set_schedule(grid_schedule(g, grid_variants or variants))
         g.set_nonlinear_mode(nlmode)
         g.set_psi(inputs.to_c64(d["psi"]))
         g.step(steps)
@@ -106,6 +115,8 @@ def test_batch_sweep_64_full_size():
     w = inputs.WORKLOADS["gsn2d_batch64_sweep"]
     inst = inputs.batch_sweep(w["count"], w["seed"], w["sizes"])
     b = gsn.Batch([d["n"] for d in inst], [d["L"] for d in inst])
+    sched = (2, 3, 2, 3, 0)   # the default: persistent passes, stored real-space psi
+    b.set_schedule(list(sched), 1)
     for i, d in enumerate(inst):
         b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
     m0 = b.masses()
@@ -123,7 +134,8 @@ def test_batch_sweep_64_full_size():
         g = gsn.Grid(d["n"], d["L"])
         g.set_kernel(*d["kern"])
         g.set_coefficients(d["a"], d["g"], d["dz"])
-        g.set_schedule(grid_schedule(g, (0, 0, 0, 1, 0)))
+        g.set_schedule(grid_schedule(g, sched))
+        g.set_nonlinear_mode(1)
         g.set_psi(inputs.to_c64(d["psi"]))
         g.step(w["steps"])
         assert np.array_equal(b.get(i, np.complex64), g.get_psi(np.complex64))
