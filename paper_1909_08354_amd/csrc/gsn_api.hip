@@ -36,6 +36,7 @@ template <int N, int V> static NKernels make_kernels()
     k.em_inv = k_em_fft<N, E, EL, 1>;
     k.density = k_density<N, E, EL, false>;
     k.density_store = k_density<N, E, EL, true>;
+    k.density_real = k_density_real<N, E, EL>;
     k.phase = k_phase<N, E, EL, false, false>;
     k.phase_real = k_phase<N, E, EL, false, true>;
     k.phase_energy = k_phase<N, E, EL, true, false>;
@@ -522,14 +523,18 @@ static void build_schedule(gsn_grid g)
         g->energy_rho = std::move(er);
         g->energy_kin = std::move(ek);
     }
-    // potential readout: x-FFT of a copy of psi, density, potential passes, C2R
+    // potential readout of the real-space psi between calls: density straight
+    // from real space (psi is only read), the potential passes, the C2R
+    // readout kernel
     g->pot.clear();
-    for (const Launch &L : g->entry) {
-        Launch c = L;
-        c.ea.psi = g->scratch;
-        g->pot.push_back(c);
+    {
+        const NKernels *kx = kernels_for(g->Nx, g->var[P_DENSITY]);
+        EmArgs d = em_base(g, g->psi);
+        d.nlines = (int)(g->P / g->Nx / 2);
+        d.partials = g->mass_parts;
+        g->pot.push_back(em_launch(kx->density_real, kx, d, P_DENSITY));
     }
-    for (size_t i = 0; i + 1 < g->energy_rho.size(); ++i) g->pot.push_back(g->energy_rho[i]);
+    for (size_t i = 1; i + 1 < g->energy_rho.size(); ++i) g->pot.push_back(g->energy_rho[i]);
     {
         const NKernels *kx = kernels_for(g->Nx, g->var[P_PHASE]);
         EmArgs a = em_base(g, g->scratch);
@@ -1206,7 +1211,6 @@ extern "C" gsn_status gsn_set_coarse_ratio(gsn_grid g, int ratio)
 
 static gsn_status run_potential(gsn_grid g, float *dst)
 {
-    HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, 8ull * g->P, hipMemcpyDeviceToDevice, g->stream));
     for (Launch L : g->pot) {
         if (L.em) L.ea.phi = dst;
         HIP_TRY(launch(L, g->stream));
@@ -1269,7 +1273,7 @@ extern "C" gsn_status gsn_step_corrected(gsn_grid g, gsn_corrector c, int64_t nc
         }
         if ((s = run_lists(g, g->coarse, 1))) return s;
         if ((s = run_potential(g, phi))) return s;
-        if ((s = corrector_correct_inplace(c, g->psi, phi, g->stream))) return s;
+        if ((s = corrector_correct_inplace(c, g->psi, phi, &g->st->theta, g->stream))) return s;
         if (audit) {
             // the fine solver from the same state is the judge of the corrected step
             HIP_TRY(hipMemcpyAsync(corrected, g->psi, bytes, hipMemcpyDeviceToDevice, g->stream));

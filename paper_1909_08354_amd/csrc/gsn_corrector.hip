@@ -49,6 +49,17 @@ __device__ inline float bf2f(u16 h) { return __uint_as_float(((unsigned)h) << 16
 
 __device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// (cos theta, sin theta) of a device FP64 phase (null: no rotation)
+__device__ inline float2 phase_of(const double *theta)
+{
+    if (!theta) return make_float2(1.f, 0.f);
+    double s, c;
+    sincos_fp64(*theta, &s, &c);
+    return make_float2((float)c, (float)s);
+}
+__device__ inline float2 rot(float2 v, float2 e) { return make_float2(v.x * e.x - v.y * e.y, v.x * e.y + v.y * e.x); }
+
+
 // ---------------------------------------------------------------- forward conv
 template <int CIN_P, int COUT_P, int COUT, bool RELU, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ X, const u16 *__restrict__ Wf,
@@ -117,11 +128,15 @@ typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
 constexpr int kTH = 4, kTW = 64;              // output tile
 constexpr int kHP = kTH + 2, kWP = kTW + 2;   // staged input tile (halo 1)
 
-template <int COUT_P, int COUT, bool RELU, bool OUT_F32>
+// APPLY (last layer, inference): instead of storing the two FP32 outputs,
+// write psi_o = psi_c + s (out0 + i out1) for the tile's pixels.
+template <int COUT_P, int COUT, bool RELU, bool OUT_F32, bool APPLY = false>
 __global__ __launch_bounds__(256) void k_conv_fwd_t(const u16 *__restrict__ X, const u16 *__restrict__ Wf,
                                                     const float *__restrict__ bias, void *__restrict__ Y,
-                                                    int H, int W, int ntiles)
+                                                    int H, int W, int ntiles, const float2 *__restrict__ psi_c,
+                                                    float2 *__restrict__ psi_o, float s_out, const double *theta)
 {
+    static_assert(!APPLY || (OUT_F32 && COUT == 2), "apply needs the two-channel FP32 output");
     constexpr int NB = COUT_P / 16;
     constexpr int OUT_B = OUT_F32 ? 4 * COUT : 2 * COUT_P;   // output bytes per pixel
     __shared__ u32x4v xin[kHP * kWP * 4];                      // 16-byte quarters of 64-byte pixels
@@ -191,9 +206,110 @@ __global__ __launch_bounds__(256) void k_conv_fwd_t(const u16 *__restrict__ X, c
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // row (y0 + wave), pixels x0 .. x0 + 63: contiguous OUT_B * 64 bytes
-        char *yrow = (char *)Y + (((long long)img * H + y0 + wave) * W + x0) * OUT_B;
+        const long long p0 = ((long long)img * H + y0 + wave) * W + x0;
+        if constexpr (APPLY) {
+            const float2 e = phase_of(theta);
+            const long long p = p0 + lane;
+            const float2 c = psi_c[p];
+            const float2 r = rot(make_float2(ysf[2 * lane], ysf[2 * lane + 1]), make_float2(e.x, -e.y));
+            psi_o[p] = make_float2(c.x + s_out * r.x, c.y + s_out * r.y);
+        } else {
+            char *yrow = (char *)Y + p0 * OUT_B;
 #pragma unroll
-        for (int c = lane; c < kTW * OUT_B / 16; c += 64) ((u32x4v *)yrow)[c] = yst[wave][c];
+            for (int c = lane; c < kTW * OUT_B / 16; c += 64) ((u32x4v *)yrow)[c] = yst[wave][c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// First layer (3 input channels padded to 4) in the same tiling.  K = 9 taps
+// x 4 channels = 36 in two 16x16x32 chunks: taps 0-7, then tap 8 and zeros;
+// lane (i, q) of a chunk holds taps 2q and 2q + 1 (4 channels each, 8 bytes
+// apiece in LDS).  FROM_PSI (inference): the halo is built from
+// (Re u, Im u, phi) times the input scales, u = e^{i theta} psi, instead of
+// the packed image.
+template <bool FROM_PSI>
+__global__ __launch_bounds__(256) void k_conv1_t(const u16 *__restrict__ X, const float2 *__restrict__ psi,
+                                                 const float *__restrict__ phi, float s0, float s1, float s2,
+                                                 const u16 *__restrict__ Wf, const float *__restrict__ bias,
+                                                 u16 *__restrict__ Y, int H, int W, int ntiles, const double *theta)
+{
+    typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
+    __shared__ u32x2v xin[kHP * kWP];           // 4 bf16 per pixel
+    __shared__ u32x4v yst[4][kTW * 64 / 16];    // per-wave output staging, 64 bytes per pixel
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i16 = lane & 15, q = lane >> 4;
+    const u32x2v zero2 = {0u, 0u};
+    bf16x8 wb[2][2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const int co = nb * 16 + i16;
+        const u32x2v lo = *(const u32x2v *)(Wf + ((2 * q) * 32 + co) * 4);
+        const u32x2v hi = *(const u32x2v *)(Wf + ((2 * q + 1) * 32 + co) * 4);
+        wb[0][nb] = __builtin_bit_cast(bf16x8, u32x4v{lo.x, lo.y, hi.x, hi.y});
+        const u32x2v l8 = q == 0 ? *(const u32x2v *)(Wf + (8 * 32 + co) * 4) : zero2;
+        wb[1][nb] = __builtin_bit_cast(bf16x8, u32x4v{l8.x, l8.y, 0u, 0u});
+    }
+    const float bch[2] = {bias[i16], bias[16 + i16]};
+    const float2 e = FROM_PSI ? phase_of(theta) : make_float2(1.f, 0.f);
+    const int tx = W / kTW, ty = H / kTH;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int img = tile / (tx * ty), r0 = tile - img * tx * ty;
+        const int y0 = (r0 / tx) * kTH, x0 = (r0 % tx) * kTW;
+        const long long ib = (long long)img * H * W;
+        __syncthreads();   // the previous tile's readers are done with xin
+        for (int c = tid; c < kHP * kWP; c += 256) {
+            const int rr = c / kWP, cc = c - rr * kWP;
+            int ys = y0 + rr - 1, xs = x0 + cc - 1;
+            ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+            xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+            const long long pix = ib + (long long)ys * W + xs;
+            if constexpr (FROM_PSI) {
+                const float2 v = rot(psi[pix], e);
+                const float f = phi[pix];
+                xin[c] = u32x2v{(unsigned)f2bf(v.x * s0) | ((unsigned)f2bf(v.y * s1) << 16), (unsigned)f2bf(f * s2)};
+            } else {
+                xin[c] = *(const u32x2v *)(X + pix * 4);
+            }
+        }
+        __syncthreads();
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int t0 = 2 * q, t1 = 2 * q + 1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int col = m * 16 + i16;
+            const u32x2v a0 = xin[(wave + t0 / 3) * kWP + col + t0 % 3];
+            const u32x2v a1 = xin[(wave + t1 / 3) * kWP + col + t1 % 3];
+            const u32x2v a8 = q == 0 ? xin[(wave + 2) * kWP + col + 2] : zero2;
+            const bf16x8 av0 = __builtin_bit_cast(bf16x8, u32x4v{a0.x, a0.y, a1.x, a1.y});
+            const bf16x8 av1 = __builtin_bit_cast(bf16x8, u32x4v{a8.x, a8.y, 0u, 0u});
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, wb[0][nb], acc[m][nb], 0, 0, 0);
+                acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, wb[1][nb], acc[m][nb], 0, 0, 0);
+            }
+        }
+        u16 *ys16 = (u16 *)yst[wave];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float v = acc[m][nb][r] + bch[nb];
+                    ys16[(m * 16 + 4 * q + r) * 32 + nb * 16 + i16] = f2bf(v > 0.f ? v : 0.f);
+                }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        char *yrow = (char *)Y + ((ib + (long long)(y0 + wave) * W + x0) * 64);
+#pragma unroll
+        for (int c = lane; c < kTW * 64 / 16; c += 64) ((u32x4v *)yrow)[c] = yst[wave][c];
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
@@ -391,12 +507,14 @@ __global__ void k_refresh(const float *__restrict__ flat, int off, int cin, int 
     if (i < coutp) bias[i] = i < cout ? flat[off + 9 * cout * cin + i] : 0.f;
 }
 
-// Input features of image b: (Re psi, Im psi, phi) times the input scales, bf16.
+// Input features of image b: (Re u, Im u, phi) times the input scales, bf16,
+// with u = e^{i theta} psi.
 __global__ void k_pack(const float2 *__restrict__ psi, const float *__restrict__ phi, u16 *__restrict__ x,
-                       long long n, float s0, float s1, float s2)
+                       long long n, float s0, float s1, float s2, const double *theta)
 {
+    const float2 e = phase_of(theta);
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
-        const float2 v = psi[p];
+        const float2 v = rot(psi[p], e);
         u16 *o = x + p * 4;
         o[0] = f2bf(v.x * s0);
         o[1] = f2bf(v.y * s1);
@@ -416,13 +534,16 @@ __global__ void k_pack_target(const float2 *__restrict__ fine, const float2 *__r
     }
 }
 
-// psi_out = psi_c + s_out (r0 + i r1)
+// psi_out = psi_c + s_out e^{-i theta} (r0 + i r1)
 __global__ void k_apply(const float2 *__restrict__ psi_c, const float *__restrict__ out, float2 *__restrict__ psi_o,
-                        long long n, float s)
+                        long long n, float s, const double *theta)
 {
+    const float2 e = phase_of(theta);
+    const float2 eb = make_float2(e.x, -e.y);
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
         const float2 c = psi_c[p];
-        psi_o[p] = make_float2(c.x + s * out[2 * p], c.y + s * out[2 * p + 1]);
+        const float2 r = rot(make_float2(out[2 * p], out[2 * p + 1]), eb);
+        psi_o[p] = make_float2(c.x + s * r.x, c.y + s * r.y);
     }
 }
 
@@ -622,7 +743,7 @@ extern "C" gsn_status gsn_corrector_pack(gsn_corrector c, int b, const void *psi
     if (!psi || !phi) return fail(GSN_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(c->device));
     hipLaunchKernelGGL(k_pack, dim3(512), dim3(256), 0, c->stream, (const float2 *)psi, phi, c->x0 + 4 * c->P * b,
-                       c->P, c->in_scale[0], c->in_scale[1], c->in_scale[2]);
+                       c->P, c->in_scale[0], c->in_scale[1], c->in_scale[2], (const double *)nullptr);
     HIP_TRY(hipGetLastError());
     return GSN_OK;
 }
@@ -640,27 +761,47 @@ extern "C" gsn_status gsn_corrector_pack_target(gsn_corrector c, int b, const vo
 }
 
 // forward over B packed images: a1..a3 stashed, out (FP32, 2 channels)
+static bool tiled(gsn_corrector c) { return c->W % kTW == 0 && c->H % kTH == 0; }
+
+// persistent grid of the LDS-tiled layers: at most 3 blocks per CU
+static dim3 tiled_grid(gsn_corrector c, int ntiles)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
+        cus = 256;
+    return dim3((unsigned)std::min(ntiles, 3 * cus));
+}
+
+// the two hidden layers, tiled (a1 -> a2 -> a3)
+static void hidden_tiled(gsn_corrector c, dim3 tg, int ntiles)
+{
+    const int H = c->H, W = c->W;
+    hipLaunchKernelGGL((k_conv_fwd_t<32, 32, true, false>), tg, dim3(256), 0, c->stream, c->a[0], c->wf[1],
+                       c->bias[1], (void *)c->a[1], H, W, ntiles, (const float2 *)nullptr, (float2 *)nullptr, 0.f,
+                       (const double *)nullptr);
+    hipLaunchKernelGGL((k_conv_fwd_t<32, 32, true, false>), tg, dim3(256), 0, c->stream, c->a[1], c->wf[2],
+                       c->bias[2], (void *)c->a[2], H, W, ntiles, (const float2 *)nullptr, (float2 *)nullptr, 0.f,
+                       (const double *)nullptr);
+}
+
 static gsn_status forward(gsn_corrector c, int B)
 {
     const long long np = c->P * B;
     const dim3 grid((unsigned)(np / 64)), block(256);
     const int H = c->H, W = c->W;
-    hipLaunchKernelGGL((k_conv_fwd<4, 32, 32, true, false>), grid, block, 0, c->stream, c->x0, c->wf[0], c->bias[0],
-                       (void *)c->a[0], H, W, np);
-    if (W % kTW == 0 && H % kTH == 0) {
-        // LDS-tiled layers: persistent grid of at most 3 blocks per CU
+    if (tiled(c)) {
         const int ntiles = (int)(np / (kTW * kTH));
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
-            cus = 256;
-        const dim3 tg((unsigned)std::min(ntiles, 3 * cus));
-        hipLaunchKernelGGL((k_conv_fwd_t<32, 32, true, false>), tg, block, 0, c->stream, c->a[0], c->wf[1],
-                           c->bias[1], (void *)c->a[1], H, W, ntiles);
-        hipLaunchKernelGGL((k_conv_fwd_t<32, 32, true, false>), tg, block, 0, c->stream, c->a[1], c->wf[2],
-                           c->bias[2], (void *)c->a[2], H, W, ntiles);
+        const dim3 tg = tiled_grid(c, ntiles);
+        hipLaunchKernelGGL((k_conv1_t<false>), tg, block, 0, c->stream, c->x0, (const float2 *)nullptr,
+                           (const float *)nullptr, 0.f, 0.f, 0.f, c->wf[0], c->bias[0], c->a[0], H, W, ntiles,
+                           (const double *)nullptr);
+        hidden_tiled(c, tg, ntiles);
         hipLaunchKernelGGL((k_conv_fwd_t<16, 2, false, true>), tg, block, 0, c->stream, c->a[2], c->wf[3],
-                           c->bias[3], (void *)c->out, H, W, ntiles);
+                           c->bias[3], (void *)c->out, H, W, ntiles, (const float2 *)nullptr, (float2 *)nullptr, 0.f,
+                           (const double *)nullptr);
     } else {
+        hipLaunchKernelGGL((k_conv_fwd<4, 32, 32, true, false>), grid, block, 0, c->stream, c->x0, c->wf[0],
+                           c->bias[0], (void *)c->a[0], H, W, np);
         hipLaunchKernelGGL((k_conv_fwd<32, 32, 32, true, false>), grid, block, 0, c->stream, c->a[0], c->wf[1],
                            c->bias[1], (void *)c->a[1], H, W, np);
         hipLaunchKernelGGL((k_conv_fwd<32, 32, 32, true, false>), grid, block, 0, c->stream, c->a[1], c->wf[2],
@@ -766,19 +907,44 @@ extern "C" gsn_status gsn_corrector_apply(gsn_corrector c, int b, const void *ps
     if (!psi_c || !psi_out) return fail(GSN_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(c->device));
     hipLaunchKernelGGL(k_apply, dim3(512), dim3(256), 0, c->stream, (const float2 *)psi_c, c->out + 2 * c->P * b,
-                       (float2 *)psi_out, c->P, c->out_scale);
+                       (float2 *)psi_out, c->P, c->out_scale, (const double *)nullptr);
     HIP_TRY(hipGetLastError());
     return GSN_OK;
 }
 
 // ------------------------------------------------------------------ internal hooks for corrected stepping
-gsn_status corrector_correct_inplace(gsn_corrector c, float2 *psi, const float *phi, hipStream_t s)
+gsn_status corrector_correct_inplace(gsn_corrector c, float2 *psi, const float *phi, const double *theta,
+                                     hipStream_t s)
 {
     hipStream_t keep = c->stream;
     c->stream = s;
-    gsn_status st = gsn_corrector_pack(c, 0, psi, phi);
-    if (!st) st = forward(c, 1);
-    if (!st) st = gsn_corrector_apply(c, 0, psi, psi);
+    gsn_status st = GSN_OK;
+    if (tiled(c)) {
+        // features straight from (psi, phi) into the first layer; the last
+        // layer adds s_out * output to psi (it reads only the third layer's
+        // activations, so writing psi in place is safe)
+        HIP_TRY(hipSetDevice(c->device));
+        const int ntiles = (int)(c->P / (kTW * kTH));
+        const dim3 tg = tiled_grid(c, ntiles);
+        hipLaunchKernelGGL((k_conv1_t<true>), tg, dim3(256), 0, c->stream, (const u16 *)nullptr, (const float2 *)psi,
+                           phi, c->in_scale[0], c->in_scale[1], c->in_scale[2], c->wf[0], c->bias[0], c->a[0], c->H,
+                           c->W, ntiles, theta);
+        hidden_tiled(c, tg, ntiles);
+        hipLaunchKernelGGL((k_conv_fwd_t<16, 2, false, true, true>), tg, dim3(256), 0, c->stream, c->a[2], c->wf[3],
+                           c->bias[3], (void *)nullptr, c->H, c->W, ntiles, (const float2 *)psi, psi, c->out_scale,
+                           theta);
+        if (hipGetLastError() != hipSuccess) st = fail(GSN_EHIP, "corrector inference launch failed");
+    } else {
+        HIP_TRY(hipSetDevice(c->device));
+        hipLaunchKernelGGL(k_pack, dim3(512), dim3(256), 0, c->stream, (const float2 *)psi, phi, c->x0, c->P,
+                           c->in_scale[0], c->in_scale[1], c->in_scale[2], theta);
+        st = forward(c, 1);
+        if (!st) {
+            hipLaunchKernelGGL(k_apply, dim3(512), dim3(256), 0, c->stream, (const float2 *)psi, c->out, psi, c->P,
+                               c->out_scale, theta);
+            if (hipGetLastError() != hipSuccess) st = fail(GSN_EHIP, "corrector apply launch failed");
+        }
+    }
     c->stream = keep;
     return st;
 }

@@ -5,8 +5,11 @@
 
 #include "gsn.h"
 
-// psi <- psi + s_out * net(Re psi, Im psi, phi) for one image, queued on s.
-gsn_status corrector_correct_inplace(gsn_corrector c, float2 *psi, const float *phi, hipStream_t s);
+// One image, queued on s: with u = e^{i theta} psi the state as the caller
+// reads it (theta: the grid's FP64 global phase, a device scalar),
+// psi <- psi + s_out e^{-i theta} net(Re u, Im u, phi).
+gsn_status corrector_correct_inplace(gsn_corrector c, float2 *psi, const float *phi, const double *theta,
+                                     hipStream_t s);
 int corrector_height(gsn_corrector c);
 int corrector_width(gsn_corrector c);
 // device scratch of the corrector for one image: phi (float), two psi copies

@@ -37,6 +37,7 @@ struct NKernels {
     void (*em_inv)(EmArgs);
     void (*density)(EmArgs);
     void (*density_store)(EmArgs);
+    void (*density_real)(EmArgs);   // real-space psi rows in (potential readout)
     void (*phase)(EmArgs);
     void (*phase_real)(EmArgs);
     void (*phase_energy)(EmArgs);

@@ -90,9 +90,13 @@ __device__ __forceinline__ void em_fft_tile(const EmArgs &a, int tile, float2 *l
 //
 // STORE_PSI: also write psi (real space) back over the two psi_x rows, so the
 // phase pass can skip its two inverse x transforms (+8 bytes per point).
-template <int N, int E, int LINES, bool STORE_PSI>
+//
+// REAL_IN: the rows hold psi in real space (not x-spectral); the inverse x
+// transforms are skipped (the potential readout of a state between calls).
+template <int N, int E, int LINES, bool STORE_PSI, bool REAL_IN = false>
 __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *lds, double *sh)
 {
+    static_assert(!(STORE_PSI && REAL_IN), "real-space input is not stored back");
     constexpr int TPL = N / E, NT = LINES * TPL;
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
     const int pair = tile * LINES + l;
@@ -100,14 +104,15 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *
     const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     const long long r0 = 2LL * pair, r1 = r0 + 1;
     const double inv_n = 1.0 / N;
+    const double rs = REAL_IN ? 1.0 : inv_n * inv_n;   // |psi|^2 scale
     dc v[E];
     double rho0[E];
     float2 *p0 = a.psi + r0 * N, *p1 = a.psi + r1 * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p0[t + TPL * e]) : mk(0.0, 0.0);
-    fft<N, E, 1>(v, t, lay, lds, a.tw);
+    if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
 #pragma unroll
-    for (int e = 0; e < E; ++e) rho0[e] = norm2(v[e]) * (inv_n * inv_n);
+    for (int e = 0; e < E; ++e) rho0[e] = norm2(v[e]) * rs;
     if constexpr (STORE_PSI) {
         if (act) {
 #pragma unroll
@@ -116,7 +121,7 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p1[t + TPL * e]) : mk(0.0, 0.0);
-    fft<N, E, 1>(v, t, lay, lds, a.tw);
+    if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
     if constexpr (STORE_PSI) {
         if (act) {
 #pragma unroll
@@ -126,7 +131,7 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *
     double msum = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const double rho1 = norm2(v[e]) * (inv_n * inv_n);
+        const double rho1 = norm2(v[e]) * rs;
         msum += rho0[e] + rho1;
         v[e] = mk(rho0[e], rho1);
     }
@@ -979,6 +984,13 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
     __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
     density_tile<N, E, LINES, STORE_PSI>(a, blockIdx.x, lds, sh);
+}
+template <int N, int E, int LINES>
+__global__ __launch_bounds__(LINES *(N / E)) void k_density_real(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
+    density_tile<N, E, LINES, false, true>(a, blockIdx.x, lds, sh);
 }
 template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
 __global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)

@@ -207,3 +207,45 @@ def test_corrected_stepping_semantics():
     g5 = grid()
     nfb, worst = g5.step_corrected(corr, 3, 1, 1.0)
     assert nfb == 0 and np.array_equal(g5.get_psi(np.complex64), g1.get_psi(np.complex64))
+
+
+def test_fused_inference_equals_pack_forward_apply():
+    """On tiled shapes the corrected step runs the features, the four layers
+    and the residual update as four kernels (first layer reading psi and phi,
+    last layer updating psi in place); the result equals the step-by-step
+    path (pack, forward, apply) on the same coarse state as the caller reads
+    it (the Yukawa term gives a nonzero global phase, which the network sees
+    applied)."""
+    import torch
+    n, L = (64, 128), (64.0, 128.0)
+    rng = np.random.default_rng(12)
+    cs, ws, vs = inputs.random_lumps(rng, n, L, 2, (4.0, 6.0))
+    psi0 = inputs.to_c64(inputs.lumps(n, L, cs, ws, vs))
+    corr = gsn.Corrector(*n, max_batch=1)
+    corr.set_weights(co.init_params(13).astype(np.float32))
+    corr.set_scales((1.3, 1.3, 0.05), 2e-3)
+
+    def grid():
+        g = gsn.Grid(n, L)
+        g.set_kernel(1.0, 0.2, 0.3, 0.0)
+        g.set_coefficients(0.5, -0.5, 5e-3)
+        g.set_coarse_ratio(8)
+        g.set_psi(psi0)
+        return g
+
+    g1, g2 = grid(), grid()
+    nfb, _ = g1.step_corrected(corr, 1, 0, 0.0)
+    assert nfb == 0
+    fused = g1.get_psi(np.complex64)
+    g2.step_coarse(1)
+    psi_c = g2.get_psi(np.complex64, device=True)
+    phi = g2.potential()
+    corr.pack(0, psi_c, phi)
+    corr.forward(1)
+    out = torch.empty_like(psi_c)
+    corr.apply(0, psi_c, out)
+    ref = out.cpu().numpy()
+    assert np.abs(ref - psi_c.cpu().numpy()).max() > 1e-6   # the network changed the state
+    diff = np.abs(fused - ref).max()
+    say(f"fused vs stepwise max |diff| {diff:.3e}")
+    assert diff <= 1e-6 * np.abs(ref).max()
