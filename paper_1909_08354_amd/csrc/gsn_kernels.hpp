@@ -866,7 +866,12 @@ __device__ __forceinline__ void phasep_body(const Src &src, LT *lds, double2 *tw
             dc v[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = from_f2(half ? p1[e] : p0[e]);
-            em_fetch_row<N, E>(an, npair, half, t, more, half ? p1 : p0);
+            // both rows of the next tile once both of this tile's are in
+            // registers: fewer prefetch registers live at once
+            if (half) {
+                em_fetch_row<N, E>(an, npair, 0, t, more, p0);
+                em_fetch_row<N, E>(an, npair, 1, t, more, p1);
+            }
             if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, twl);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
