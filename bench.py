@@ -37,9 +37,10 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_pass):
-    """HBM bytes per launch from committed rocprofv3 counter runs, only when they
-    were taken on the current kernel sources."""
+def measured_traffic(kernel_pass, variant):
+    """HBM bytes per launch of a pass in a schedule variant, from committed
+    rocprofv3 counter runs, only when they were taken on the current kernel
+    sources."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -49,7 +50,7 @@ def measured_traffic(kernel_pass):
         return None
     if rec.get("csrc_hash") != csrc_hash():
         return None
-    return rec.get("passes", {}).get(kernel_pass)
+    return rec.get("passes", {}).get(kernel_pass, {}).get(variant)
 
 
 def cpu_baseline(w, psi0_c128, budget_s=30.0):
@@ -267,7 +268,7 @@ def main():
     steady = {k: v for k, v in prof.items() if k not in ("x_entry_fft", "x_exit_ifft")}
     dom = max(steady, key=steady.get)
     achieved = bpp[dom] * P / (steady[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, schedule.get(dom))
     step_bytes = sum(bpp[k] for k in steady) * P
     scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
 
