@@ -435,6 +435,107 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const u16 *__restrict__ X, c
     if (tid < COUT_P) out[9 * COUT_P * CINN + tid] = dbias;
 }
 
+// Weight gradients on tiled shapes: a block walks tiles of 4 rows x 64
+// pixels (fixed tiles per block, fixed order: deterministic partials).  Per
+// tile the 6 x 66 input halo is read once and stored channel-major in LDS in
+// three copies shifted by the tap column (so every 8-pixel run of a tap is an
+// aligned 16-byte read), dZ channel-major beside it, and
+// dW[tap][co][ci] += sum_px dZ[px][co] X[px + off(tap)][ci] runs on
+// v_mfma_f32_16x16x32_bf16 with K = 32 pixels per chunk.
+template <int CIN_P, int COUT_P>
+__global__ __launch_bounds__(512) void k_conv_bwd_w_t(const u16 *__restrict__ X, const u16 *__restrict__ dZ,
+                                                      float *__restrict__ part, int H, int W, int ntiles)
+{
+    constexpr int CINN = CIN_P < 16 ? 16 : CIN_P;
+    constexpr int MB = COUT_P / 16, NB = CINN / 16, NBLK = 9 * MB * NB;
+    constexpr int NWAVE = 8, PER_WAVE = (NBLK + NWAVE - 1) / NWAVE;
+    constexpr int PSTRIDE = 9 * COUT_P * CINN + COUT_P;
+    constexpr int TPX = kTH * kTW;
+    constexpr int XQ = CIN_P / 4;   // 8-byte pieces (4 channels) per input pixel
+    typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
+    __shared__ __align__(16) u16 xt[3][CIN_P][kHP][kTW];
+    __shared__ __align__(16) u16 dzt[COUT_P][TPX];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i16 = lane & 15, q = lane >> 4;
+    f32x4 acc[PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < PER_WAVE; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dbias = 0.f;
+    const int tx = W / kTW, ty = H / kTH;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int img = tile / (tx * ty), r0 = tile - img * tx * ty;
+        const int y0 = (r0 / tx) * kTH, x0 = (r0 % tx) * kTW;
+        const long long ib = (long long)img * H * W;
+        __syncthreads();   // the previous tile's readers are done
+        for (int it = tid; it < kHP * kWP * XQ; it += 512) {
+            const int piece = it % XQ, pix = it / XQ, rr = pix / kWP, cc = pix - rr * kWP;
+            int ys = y0 + rr - 1, xs = x0 + cc - 1;
+            ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+            xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+            const u32x2v v = *(const u32x2v *)(X + (ib + (long long)ys * W + xs) * CIN_P + 4 * piece);
+            const u16 h[4] = {(u16)(v.x & 0xffffu), (u16)(v.x >> 16), (u16)(v.y & 0xffffu), (u16)(v.y >> 16)};
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int c = cc - dx;
+                if (c >= 0 && c < kTW) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) xt[dx][4 * piece + k][rr][c] = h[k];
+                }
+            }
+        }
+        for (int it = tid; it < TPX * (COUT_P / 4); it += 512) {
+            const int piece = it % (COUT_P / 4), px = it / (COUT_P / 4);
+            const int r = px / kTW, c = px - r * kTW;
+            const u32x2v v = *(const u32x2v *)(dZ + (ib + (long long)(y0 + r) * W + x0 + c) * COUT_P + 4 * piece);
+            dzt[4 * piece + 0][px] = (u16)(v.x & 0xffffu);
+            dzt[4 * piece + 1][px] = (u16)(v.x >> 16);
+            dzt[4 * piece + 2][px] = (u16)(v.y & 0xffffu);
+            dzt[4 * piece + 3][px] = (u16)(v.y >> 16);
+        }
+        __syncthreads();
+        if (tid < COUT_P) {
+            float sb = 0.f;
+            for (int px = 0; px < TPX; px += 8) {
+                const u32x4v w = *(const u32x4v *)&dzt[tid][px];
+                const unsigned u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) sb += bf2f((u16)(u[k] & 0xffffu)) + bf2f((u16)(u[k] >> 16));
+            }
+            dbias += sb;
+        }
+#pragma unroll
+        for (int i = 0; i < PER_WAVE; ++i) {
+            const int blk = wave + NWAVE * i;
+            if (blk < NBLK) {
+                const int tap = blk / (MB * NB), mb = (blk / NB) % MB, nb = blk % NB;
+                const int dy = tap / 3, dx = tap % 3, ci = nb * 16 + i16;
+#pragma unroll
+                for (int kc = 0; kc < TPX / 32; ++kc) {
+                    const int px0 = kc * 32 + 8 * q, r = px0 / kTW, c = px0 - r * kTW;
+                    const bf16x8 av = *(const bf16x8 *)&dzt[mb * 16 + i16][px0];
+                    bf16x8 bv = __builtin_bit_cast(bf16x8, u32x4v{0u, 0u, 0u, 0u});
+                    if (ci < CIN_P) bv = *(const bf16x8 *)&xt[dx][ci][r + dy][c];
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *out = part + (long long)blockIdx.x * PSTRIDE;
+#pragma unroll
+    for (int i = 0; i < PER_WAVE; ++i) {
+        const int blk = wave + NWAVE * i;
+        if (blk < NBLK) {
+            const int tap = blk / (MB * NB), mb = (blk / NB) % MB, nb = blk % NB;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = mb * 16 + 4 * q + r, ci = nb * 16 + i16;
+                out[(tap * COUT_P + co) * CINN + ci] = acc[i][r];
+            }
+        }
+    }
+    if (tid < COUT_P) out[9 * COUT_P * CINN + tid] = dbias;
+}
+
 // Sum the per-block partials of one layer into the flat gradient (fixed order).
 __global__ void k_reduce_grad(const float *__restrict__ part, int nparts, int pstride, int cin, int cout,
                               int cinn, int coutp, float *__restrict__ gflat)
@@ -840,22 +941,43 @@ static gsn_status gradients(gsn_corrector c, int B, float *loss)
     const int pstride_h = 9 * 32 * 32 + 32;
     int offs[kLayers], o = 0;
     for (int l = 0; l < kLayers; ++l) { offs[l] = o; o += 9 * kCin[l] * kCout[l] + kCout[l]; }
-    hipLaunchKernelGGL((k_conv_bwd_w<32, 16>), dim3(kBwBlocks), block, 0, c->stream, c->a[2], c->dz4, c->part, H, W, np);
+    const bool tl = tiled(c);
+    const int ntl = (int)(np / (kTW * kTH));
+    if (tl)
+        hipLaunchKernelGGL((k_conv_bwd_w_t<32, 16>), dim3(kBwBlocks), dim3(512), 0, c->stream, c->a[2], c->dz4, c->part,
+                           H, W, ntl);
+    else
+        hipLaunchKernelGGL((k_conv_bwd_w<32, 16>), dim3(kBwBlocks), block, 0, c->stream, c->a[2], c->dz4, c->part, H, W,
+                           np);
     hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 2 + 2 + 255) / 256), dim3(256), 0, c->stream, c->part,
                        kBwBlocks, 9 * 16 * 32 + 16, 32, 2, 32, 16, c->grad + offs[3]);
     hipLaunchKernelGGL((k_conv_bwd_data<32, 16>), grid, block, 0, c->stream, c->dz4, c->wb[3], c->a[2], c->dza, H, W, np);
     // layer 3
-    hipLaunchKernelGGL((k_conv_bwd_w<32, 32>), dim3(kBwBlocks), block, 0, c->stream, c->a[1], c->dza, c->part, H, W, np);
+    if (tl)
+        hipLaunchKernelGGL((k_conv_bwd_w_t<32, 32>), dim3(kBwBlocks), dim3(512), 0, c->stream, c->a[1], c->dza, c->part,
+                           H, W, ntl);
+    else
+        hipLaunchKernelGGL((k_conv_bwd_w<32, 32>), dim3(kBwBlocks), block, 0, c->stream, c->a[1], c->dza, c->part, H, W,
+                           np);
     hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
                        kBwBlocks, pstride_h, 32, 32, 32, 32, c->grad + offs[2]);
     hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dza, c->wb[2], c->a[1], c->dzb, H, W, np);
     // layer 2
-    hipLaunchKernelGGL((k_conv_bwd_w<32, 32>), dim3(kBwBlocks), block, 0, c->stream, c->a[0], c->dzb, c->part, H, W, np);
+    if (tl)
+        hipLaunchKernelGGL((k_conv_bwd_w_t<32, 32>), dim3(kBwBlocks), dim3(512), 0, c->stream, c->a[0], c->dzb, c->part,
+                           H, W, ntl);
+    else
+        hipLaunchKernelGGL((k_conv_bwd_w<32, 32>), dim3(kBwBlocks), block, 0, c->stream, c->a[0], c->dzb, c->part, H, W,
+                           np);
     hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
                        kBwBlocks, pstride_h, 32, 32, 32, 32, c->grad + offs[1]);
     hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dzb, c->wb[1], c->a[0], c->dza, H, W, np);
     // layer 1 (3 -> 32, input padded to 4 channels; no data gradient needed)
-    hipLaunchKernelGGL((k_conv_bwd_w<4, 32>), dim3(kBwBlocks), block, 0, c->stream, c->x0, c->dza, c->part, H, W, np);
+    if (tl)
+        hipLaunchKernelGGL((k_conv_bwd_w_t<4, 32>), dim3(kBwBlocks), dim3(512), 0, c->stream, c->x0, c->dza, c->part, H,
+                           W, ntl);
+    else
+        hipLaunchKernelGGL((k_conv_bwd_w<4, 32>), dim3(kBwBlocks), block, 0, c->stream, c->x0, c->dza, c->part, H, W, np);
     hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 3 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
                        kBwBlocks, 9 * 32 * 16 + 32, 3, 32, 16, 32, c->grad + offs[0]);
     HIP_TRY(hipGetLastError());
