@@ -28,10 +28,15 @@ HBM_PEAK_GBPS = 8000.0
 WORKLOAD = "gsn3d_256_newton_yukawa"
 
 
+# the sources of the single-grid passes (the batched and corrector files do
+# not change them)
+PASS_SOURCES = ("gsn_api.hip", "gsn_fft.hpp", "gsn_host.hpp", "gsn_kernels.hpp")
+
+
 def csrc_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1909_08354_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in PASS_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
