@@ -35,6 +35,17 @@
  *   N(h): rho = |psi|^2; phi = Re IDFT[ K DFT rho ]; psi <- psi exp(i (g rho + phi) h)
  * The nonlinear sub-step is exact because rho is unchanged by a pointwise phase.
  *
+ * Local terms of Eq. (15) (Sec. II C), optional: the Kerr term g rho generalises
+ * to the local potential
+ *   U = g rho + c_p f_n(max(rho, rho_f)) + c_B lap(s) / (2 max(s, sqrt(rho_f))),
+ *   s = sqrt(rho),  f_1(rho) = ln rho,  f_n(rho) = n/(n-1) rho^(n-1) (n > 1 or n < 0),
+ * the polytropic pressure potential and the Bohm potential lap(sqrt rho)/(2 sqrt rho),
+ * with lap(s) = Re IDFT[-|k|^2 DFT s] and rho_f > 0 a floor that keeps ln rho,
+ * negative powers and the division finite where the density vanishes.  Then
+ *   N(h): psi <- psi exp(i (U + phi) h).
+ * Eq. (15) divided by nu is this form with a = nu/2, c_B = -nu, c_p = -w/nu and
+ * phi = -(phi_N + phi_C)/nu.
+ *
  * The FFT is an iterative radix-2 transform with twiddles from direct FP64
  * cos/sin of 2 pi m / n (never a recurrence).  Multi-dimensional transforms are
  * applied axis by axis.  OpenMP threads run independent 1-D lines in parallel;
@@ -236,6 +247,97 @@ int orc_dft_brute(const double *in, double *out, int ndim, const int *n, int sig
 }
 
 /* ------------------------------------------------------------------------ */
+/* local terms of Eq. (15)                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* lp = {c_p, n_p, c_B, rho_f}; lp == NULL: Kerr term only */
+typedef struct {
+    int on;
+    double cp, np, cb, floor;
+} local_t;
+
+static int local_init(local_t *lt, const double *lp)
+{
+    memset(lt, 0, sizeof(*lt));
+    if (!lp) return ORC_OK;
+    for (int i = 0; i < 4; i++)
+        if (!isfinite(lp[i])) return ORC_EINVAL;
+    lt->cp = lp[0];
+    lt->np = lp[1];
+    lt->cb = lp[2];
+    lt->floor = lp[3];
+    if (lt->floor < 0.0) return ORC_EINVAL;
+    /* the pressure law is given for n = 1, n > 1 and n < 0 */
+    if (lt->cp != 0.0 && lt->np >= 0.0 && lt->np < 1.0) return ORC_EINVAL;
+    /* ln rho, rho^(n-1) with n < 1 and 1/sqrt(rho) need a positive floor */
+    if (((lt->cp != 0.0 && lt->np <= 1.0) || lt->cb != 0.0) && !(lt->floor > 0.0)) return ORC_EINVAL;
+    lt->on = lt->cp != 0.0 || lt->cb != 0.0;
+    return ORC_OK;
+}
+
+/* polytropic pressure potential f_n of Eq. (15) */
+static double poly_f(double rho, double n)
+{
+    return n == 1.0 ? log(rho) : n / (n - 1.0) * pow(rho, n - 1.0);
+}
+
+/* its antiderivative F_n (F_n' = f_n): the pressure energy density */
+static double poly_F(double rho, double n)
+{
+    return n == 1.0 ? rho * log(rho) - rho : pow(rho, n) / (n - 1.0);
+}
+
+/* antiderivative of the floored potential f_n(max(rho, rho_f)) */
+static double poly_G(double rho, double n, double rho_f)
+{
+    if (rho >= rho_f) return poly_F(rho, n);
+    return poly_F(rho_f, n) + (rho - rho_f) * poly_f(rho_f, n);
+}
+
+/* lap(sqrt rho) = Re IDFT[-|k|^2 DFT sqrt(rho)] into lap (real), tmp scratch */
+static int laplacian_of_sqrt(double *lap, const double *rho, cx *tmp, const grid_t *g, int nt)
+{
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) tmp[q] = sqrt(rho[q]);
+    int e = fft_nd(tmp, g, -1, nt);
+    if (e) return e;
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) tmp[q] *= -k_squared(g, q);
+    e = fft_nd(tmp, g, +1, nt);
+    if (e) return e;
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) lap[q] = creal(tmp[q]);
+    return ORC_OK;
+}
+
+/* U = g rho + polytropic + Bohm terms (see the header); tmp scratch */
+static int local_potential_into(double *U, const double *rho, cx *tmp, double gloc,
+                                const local_t *lt, const grid_t *g, int nt)
+{
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) U[q] = gloc * rho[q];
+    if (!lt->on) return ORC_OK;
+    if (lt->cp != 0.0) {
+#pragma omp parallel for num_threads(nt) schedule(static)
+        for (long long q = 0; q < g->P; q++) U[q] += lt->cp * poly_f(fmax(rho[q], lt->floor), lt->np);
+    }
+    if (lt->cb != 0.0) {
+        double *lap = (double *)malloc(sizeof(double) * (size_t)g->P);
+        if (!lap) return ORC_ENOMEM;
+        int e = laplacian_of_sqrt(lap, rho, tmp, g, nt);
+        if (!e) {
+            const double sf = sqrt(lt->floor);
+#pragma omp parallel for num_threads(nt) schedule(static)
+            for (long long q = 0; q < g->P; q++)
+                U[q] += lt->cb * lap[q] / (2.0 * fmax(sqrt(rho[q]), sf));
+        }
+        free(lap);
+        return e;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* potential, sub-steps, evolution                                          */
 /* ------------------------------------------------------------------------ */
 
@@ -283,20 +385,22 @@ static int kinetic_step(cx *psi, const cx *prop, const grid_t *g, int nt)
     return fft_nd(psi, g, +1, nt);
 }
 
-/* nonlinear sub-step N(h): psi <- psi exp(i (g rho + phi) h) */
-static int nonlinear_step(cx *psi, cx *tmp, double *rho, const double *Kk,
-                          double gloc, double h, const grid_t *g, int nt)
+/* nonlinear sub-step N(h): psi <- psi exp(i (U + phi) h), U the local potential */
+static int nonlinear_step(cx *psi, cx *tmp, double *rho, double *U, const double *Kk,
+                          double gloc, const local_t *lt, double h, const grid_t *g, int nt)
 {
 #pragma omp parallel for num_threads(nt) schedule(static)
     for (long long q = 0; q < g->P; q++) {
         double re = creal(psi[q]), im = cimag(psi[q]);
         rho[q] = re * re + im * im;
     }
-    int e = potential_into(tmp, rho, Kk, g, nt);
+    int e = local_potential_into(U, rho, tmp, gloc, lt, g, nt);
+    if (e) return e;
+    e = potential_into(tmp, rho, Kk, g, nt);
     if (e) return e;
 #pragma omp parallel for num_threads(nt) schedule(static)
     for (long long q = 0; q < g->P; q++) {
-        double th = (gloc * rho[q] + creal(tmp[q])) * h;
+        double th = (U[q] + creal(tmp[q])) * h;
         psi[q] *= cos(th) + sin(th) * I;
     }
     return ORC_OK;
@@ -310,12 +414,14 @@ static int nonlinear_step(cx *psi, cx *tmp, double *rho, const double *Kk,
  *               same product of operators (L(h1) L(h2) = L(h1 + h2) exactly).
  * Returns 0 on success.
  */
-int orc_evolve(double *psi_io, int ndim, const int *n, const double *L,
-               const double *kp, double a, double gloc, double dz,
-               long long nsteps, int merged, int nthreads)
+int orc_evolve_local(double *psi_io, int ndim, const int *n, const double *L,
+                     const double *kp, double a, double gloc, const double *lp, double dz,
+                     long long nsteps, int merged, int nthreads)
 {
     grid_t g;
+    local_t lt;
     if (!psi_io || !kp || grid_init(&g, ndim, n, L) || nsteps < 0) return ORC_EINVAL;
+    if (local_init(&lt, lp)) return ORC_EINVAL;
     if (kp[1] != 0.0 && !(kp[2] > 0.0)) return ORC_EINVAL;
     if (!isfinite(dz) || !isfinite(a) || !isfinite(gloc)) return ORC_EINVAL;
     if (nsteps == 0) return ORC_OK;
@@ -327,8 +433,9 @@ int orc_evolve(double *psi_io, int ndim, const int *n, const double *L,
     cx *tmp = (cx *)malloc(sizeof(cx) * P);
     double *Kk = (double *)malloc(sizeof(double) * P);
     double *rho = (double *)malloc(sizeof(double) * P);
+    double *U = (double *)malloc(sizeof(double) * P);
     int e = ORC_ENOMEM;
-    if (!half || !full || !tmp || !Kk || !rho) goto done;
+    if (!half || !full || !tmp || !Kk || !rho || !U) goto done;
 #pragma omp parallel for num_threads(nt) schedule(static)
     for (long long q = 0; q < g.P; q++) {
         double k2 = k_squared(&g, q);
@@ -340,13 +447,13 @@ int orc_evolve(double *psi_io, int ndim, const int *n, const double *L,
     if (!merged) {
         for (long long s = 0; s < nsteps; s++) {
             if ((e = kinetic_step(psi, half, &g, nt))) goto done;
-            if ((e = nonlinear_step(psi, tmp, rho, Kk, gloc, dz, &g, nt))) goto done;
+            if ((e = nonlinear_step(psi, tmp, rho, U, Kk, gloc, &lt, dz, &g, nt))) goto done;
             if ((e = kinetic_step(psi, half, &g, nt))) goto done;
         }
     } else {
         if ((e = kinetic_step(psi, half, &g, nt))) goto done;
         for (long long s = 0; s < nsteps; s++) {
-            if ((e = nonlinear_step(psi, tmp, rho, Kk, gloc, dz, &g, nt))) goto done;
+            if ((e = nonlinear_step(psi, tmp, rho, U, Kk, gloc, &lt, dz, &g, nt))) goto done;
             if ((e = kinetic_step(psi, s + 1 < nsteps ? full : half, &g, nt))) goto done;
         }
     }
@@ -357,23 +464,63 @@ done:
     free(tmp);
     free(Kk);
     free(rho);
+    free(U);
+    return e;
+}
+
+/* orc_evolve_local with the Kerr term only */
+int orc_evolve(double *psi_io, int ndim, const int *n, const double *L,
+               const double *kp, double a, double gloc, double dz,
+               long long nsteps, int merged, int nthreads)
+{
+    return orc_evolve_local(psi_io, ndim, n, L, kp, a, gloc, NULL, dz, nsteps, merged, nthreads);
+}
+
+/* The local potential U of psi (see the header) into U_out (P doubles). */
+int orc_local_potential(const double *psi_in, int ndim, const int *n, const double *L,
+                        double gloc, const double *lp, double *U_out, int nthreads)
+{
+    grid_t g;
+    local_t lt;
+    if (!psi_in || !U_out || grid_init(&g, ndim, n, L) || local_init(&lt, lp)) return ORC_EINVAL;
+    int nt = nthreads_or_default(nthreads);
+    const cx *psi = (const cx *)psi_in;
+    cx *tmp = (cx *)malloc(sizeof(cx) * (size_t)g.P);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)g.P);
+    int e = ORC_ENOMEM;
+    if (tmp && rho) {
+        for (long long q = 0; q < g.P; q++) {
+            double re = creal(psi[q]), im = cimag(psi[q]);
+            rho[q] = re * re + im * im;
+        }
+        e = local_potential_into(U_out, rho, tmp, gloc, &lt, &g, nt);
+    }
+    free(tmp);
+    free(rho);
     return e;
 }
 
 /*
- * Observables of psi: out = {M, E_kin, E_loc, E_nl, E_total} with
+ * Observables of psi: out = {M, E_kin, E_loc, E_nl, E_total, E_p, E_B} with
  *   M     = dV sum |psi|^2
  *   E_kin = a dV / P sum_k |k|^2 |psi_hat_k|^2      (= a dV sum |grad psi|^2)
- *   E_loc = -(g/2) dV sum rho^2
+ *   E_loc = -(g/2) dV sum rho^2 + E_p + E_B
+ *   E_p   = -c_p dV sum G_n(rho),  G_n' = f_n(max(rho, rho_f))
+ *   E_B   = (c_B/2) dV sum |grad s|^2 = -(c_B/2) dV sum s lap(s),  s = sqrt(rho)
  *   E_nl  = -(1/2) dV sum rho phi
  * E_total is the Hamiltonian of the equation above: its variation with
- * respect to conj(psi) is -a lap(psi) - g rho psi - phi psi.
+ * respect to conj(psi) is -a lap(psi) - U psi - phi psi (for the Bohm part
+ * where rho >= rho_f, since the variation of sum |grad s|^2 with respect to rho
+ * is -lap(s)/s).  lp == NULL: E_p = E_B = 0.
  */
-int orc_observables(const double *psi_in, int ndim, const int *n, const double *L,
-                    const double *kp, double a, double gloc, double *out, int nthreads)
+int orc_observables_local(const double *psi_in, int ndim, const int *n, const double *L,
+                          const double *kp, double a, double gloc, const double *lp,
+                          double *out, int nthreads)
 {
     grid_t g;
+    local_t lt;
     if (!psi_in || !kp || !out || grid_init(&g, ndim, n, L)) return ORC_EINVAL;
+    if (local_init(&lt, lp)) return ORC_EINVAL;
     if (kp[1] != 0.0 && !(kp[2] > 0.0)) return ORC_EINVAL;
     int nt = nthreads_or_default(nthreads);
     const cx *psi = (const cx *)psi_in;
@@ -383,6 +530,7 @@ int orc_observables(const double *psi_in, int ndim, const int *n, const double *
     cx *tmp = (cx *)malloc(sizeof(cx) * P);
     double *Kk = (double *)malloc(sizeof(double) * P);
     double *rho = (double *)malloc(sizeof(double) * P);
+    double *lap = NULL;
     int e = ORC_ENOMEM;
     if (!tmp || !Kk || !rho) goto done;
     double mass = 0.0, ekin = 0.0, eloc = 0.0, enl = 0.0;
@@ -401,16 +549,43 @@ int orc_observables(const double *psi_in, int ndim, const int *n, const double *
     }
     if ((e = potential_into(tmp, rho, Kk, &g, nt))) goto done;
     for (long long q = 0; q < g.P; q++) enl += rho[q] * creal(tmp[q]);
+    double ep = 0.0, eb = 0.0;
+    if (lt.cp != 0.0) {
+        for (long long q = 0; q < g.P; q++) ep += poly_G(rho[q], lt.np, lt.floor);
+        ep *= -lt.cp * dV;
+    }
+    if (lt.cb != 0.0) {
+        lap = (double *)malloc(sizeof(double) * P);
+        e = ORC_ENOMEM;
+        if (!lap) goto done;
+        if ((e = laplacian_of_sqrt(lap, rho, tmp, &g, nt))) goto done;
+        for (long long q = 0; q < g.P; q++) eb += sqrt(rho[q]) * lap[q];
+        eb *= -0.5 * lt.cb * dV;
+    }
     out[0] = dV * mass;
     out[1] = a * dV / (double)g.P * ekin;
-    out[2] = -0.5 * gloc * dV * eloc;
+    out[2] = -0.5 * gloc * dV * eloc + ep + eb;
     out[3] = -0.5 * dV * enl;
     out[4] = out[1] + out[2] + out[3];
+    out[5] = ep;
+    out[6] = eb;
     e = ORC_OK;
 done:
     free(tmp);
     free(Kk);
     free(rho);
+    free(lap);
+    return e;
+}
+
+/* orc_observables_local with the Kerr term only; out has 5 entries */
+int orc_observables(const double *psi_in, int ndim, const int *n, const double *L,
+                    const double *kp, double a, double gloc, double *out, int nthreads)
+{
+    double o[7];
+    int e = orc_observables_local(psi_in, ndim, n, L, kp, a, gloc, NULL, o, nthreads);
+    if (!e)
+        for (int i = 0; i < 5; i++) out[i] = o[i];
     return e;
 }
 

@@ -9,7 +9,10 @@ Conventions (arXiv:1909.08354 Sec. II Eq. (1)-(3), Sec. III):
   * ``kern`` = (c_N, c_Y, m_Y, c_0): K(k) = c_N/|k|^2 [k != 0]
     + c_Y/(|k|^2 + m_Y^2) + c_0;
   * ``a`` kinetic coefficient (1/2 for Eq. (3) with k = k0 = 1),
-    ``g`` local (Kerr) coefficient, ``dz`` the step.
+    ``g`` local (Kerr) coefficient, ``dz`` the step;
+  * ``local`` = (c_p, n_p, c_B, rho_f) or None: the local terms of Eq. (15),
+    U = g rho + c_p f_n(max(rho, rho_f)) + c_B lap(sqrt rho) / (2 max(sqrt rho,
+    sqrt rho_f)) with f_1 = ln rho, f_n = n/(n-1) rho^(n-1) (Sec. II C).
 """
 import ctypes
 import os
@@ -39,9 +42,17 @@ def _load():
                                ctypes.c_int, ctypes.c_int]
     lib.orc_observables.argtypes = [dp, ctypes.c_int, ip, dp, dp, ctypes.c_double,
                                     ctypes.c_double, dp, ctypes.c_int]
+    lib.orc_evolve_local.argtypes = [dp, ctypes.c_int, ip, dp, dp, ctypes.c_double,
+                                     ctypes.c_double, dp, ctypes.c_double, ctypes.c_longlong,
+                                     ctypes.c_int, ctypes.c_int]
+    lib.orc_observables_local.argtypes = [dp, ctypes.c_int, ip, dp, dp, ctypes.c_double,
+                                          ctypes.c_double, dp, dp, ctypes.c_int]
+    lib.orc_local_potential.argtypes = [dp, ctypes.c_int, ip, dp, ctypes.c_double, dp, dp,
+                                        ctypes.c_int]
     lib.orc_max_threads.argtypes = []
     for f in ("orc_fft", "orc_dft_brute", "orc_potential", "orc_evolve",
-              "orc_observables", "orc_max_threads"):
+              "orc_observables", "orc_evolve_local", "orc_observables_local",
+              "orc_local_potential", "orc_max_threads"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -97,26 +108,59 @@ def potential(rho, L, kern, nthreads=0):
     return phi
 
 
-def evolve(psi, L, kern, a, g, dz, nsteps, merged=True, nthreads=0):
+def _local_arr(local):
+    if local is None:
+        return None
+    arr = np.ascontiguousarray(local, dtype=np.float64).reshape(4)
+    return arr
+
+
+def evolve(psi, L, kern, a, g, dz, nsteps, merged=True, nthreads=0, local=None):
     """nsteps symmetric split steps of the equation; returns a new array."""
     p = np.array(psi, dtype=np.complex128, order="C", copy=True)
     n, Larr = _shape_args(p.shape, L)
     k = np.ascontiguousarray(kern, dtype=np.float64)
-    _check(_load().orc_evolve(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a), float(g),
-                              float(dz), int(nsteps), 1 if merged else 0, nthreads), "evolve")
+    lp = _local_arr(local)
+    if lp is None:
+        rc = _load().orc_evolve(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a), float(g),
+                                float(dz), int(nsteps), 1 if merged else 0, nthreads)
+    else:
+        rc = _load().orc_evolve_local(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a),
+                                      float(g), _dptr(lp), float(dz), int(nsteps),
+                                      1 if merged else 0, nthreads)
+    _check(rc, "evolve")
     return p
 
 
-def observables(psi, L, kern, a, g, nthreads=0):
-    """dict(mass, kinetic, local, nonlocal, total) of psi."""
+def observables(psi, L, kern, a, g, nthreads=0, local=None):
+    """dict(mass, kinetic, local, nonlocal, total, pressure, bohm) of psi;
+    ``local`` (the total local energy) includes the pressure and Bohm parts."""
     p = np.ascontiguousarray(psi, dtype=np.complex128)
     n, Larr = _shape_args(p.shape, L)
     k = np.ascontiguousarray(kern, dtype=np.float64)
-    out = np.zeros(5)
-    _check(_load().orc_observables(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a),
-                                   float(g), _dptr(out), nthreads), "observables")
+    out = np.zeros(7)
+    lp = _local_arr(local)
+    if lp is None:
+        rc = _load().orc_observables(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a),
+                                     float(g), _dptr(out), nthreads)
+    else:
+        rc = _load().orc_observables_local(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a),
+                                           float(g), _dptr(lp), _dptr(out), nthreads)
+    _check(rc, "observables")
     return {"mass": out[0], "kinetic": out[1], "local": out[2], "nonlocal": out[3],
-            "total": out[4]}
+            "total": out[4], "pressure": out[5], "bohm": out[6]}
+
+
+def local_potential(psi, L, g, local, nthreads=0):
+    """The local potential U(x) of psi (Kerr + pressure + Bohm), real array."""
+    p = np.ascontiguousarray(psi, dtype=np.complex128)
+    n, Larr = _shape_args(p.shape, L)
+    U = np.empty(p.shape, dtype=np.float64)
+    lp = _local_arr(local)
+    _check(_load().orc_local_potential(_dptr(p), p.ndim, n, _dptr(Larr), float(g),
+                                       None if lp is None else _dptr(lp), _dptr(U), nthreads),
+           "local_potential")
+    return U
 
 
 def rel_l2(x, ref):

@@ -303,3 +303,179 @@ def test_oracle_rejects_bad_arguments():
         orc.evolve(np.zeros((12, 16), complex), (1.0, 1.0), (1, 0, 0, 0), 0.5, 0, 1e-3, 1)
     with pytest.raises(ValueError):
         orc.evolve(np.zeros((16, 16), complex), (1.0, 1.0), (0, 1.0, 0.0, 0), 0.5, 0, 1e-3, 1)
+
+
+# ---------------------------------------------------------------- Eq. (15) local terms
+# U = g rho + c_p f_n(max(rho, rho_f)) + c_B lap(s) / (2 max(s, sqrt rho_f)), s = sqrt rho,
+# f_1 = ln rho, f_n = n/(n-1) rho^(n-1): the polytropic pressure and Bohm potentials.
+
+def _pedestal(n, L, A, sig, phase=0.0):
+    """s = 1 + A exp(-r^2/(2 sig^2)) (positive everywhere), psi = s e^{i phase}."""
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    r2 = sum(x * x for x in xs)
+    s = 1.0 + A * np.exp(-r2 / (2 * sig * sig))
+    return s * np.exp(1j * phase), s, r2
+
+
+@pytest.mark.parametrize("n,L,sig", [((64, 64), (40.0, 40.0), 2.5), ((32, 32, 32), (32.0, 32.0, 32.0), 2.2)])
+def test_bohm_potential_closed_form(n, L, sig):
+    """lap s for s = 1 + A exp(-r^2/(2 sig^2)) in D dimensions is
+    A exp(-r^2/(2 sig^2)) (r^2/sig^4 - D/sig^2); a constant phase of psi and a
+    floor below min rho change nothing."""
+    A, cB = 0.5, 0.8
+    psi, s, r2 = _pedestal(n, L, A, sig, phase=0.7)
+    U = orc.local_potential(psi, L, 0.0, (0.0, 1.0, cB, 1e-6))
+    D = len(n)
+    lap = A * np.exp(-r2 / (2 * sig * sig)) * (r2 / sig ** 4 - D / sig ** 2)
+    exact = cB * lap / (2 * s)
+    assert np.max(np.abs(U - exact)) < 1e-9 * np.max(np.abs(exact))
+
+
+def test_bohm_floor_takes_over_where_density_vanishes():
+    """Where sqrt rho < sqrt rho_f the division uses sqrt rho_f: for a Gaussian
+    psi = exp(-r^2/(2 sig^2)) the regularised potential equals lap(s)/(2 sqrt rho_f)
+    in the far tail and the unregularised closed form (r^2/sig^4 - D/sig^2)/2 in
+    the core."""
+    n, L, sig, rf = (64, 64), (40.0, 40.0), 2.5, 1e-4
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    r2 = sum(x * x for x in xs)
+    s = np.exp(-r2 / (2 * sig * sig))
+    U = orc.local_potential(s.astype(complex), L, 0.0, (0.0, 1.0, 1.0, rf))
+    lap = s * (r2 / sig ** 4 - 2 / sig ** 2)
+    core = s > 10 * np.sqrt(rf)
+    assert np.max(np.abs(U[core] - lap[core] / (2 * s[core]))) < 1e-8
+    tail = s < 0.1 * np.sqrt(rf)
+    assert np.max(np.abs(U[tail] - lap[tail] / (2 * np.sqrt(rf)))) < 1e-9
+
+
+def test_bohm_term_cancels_quantum_pressure():
+    """Eq. (15) with its own Bohm coefficient (c_B = -nu, a = nu/2, so c_B = -2a)
+    turns a real positive psi with no other potential into an exactly stationary
+    state: one Strang step then changes psi by its local error O(dz^3), while
+    without the Bohm term the change is O(dz)."""
+    n, L, a = (64, 64), (40.0, 40.0), 0.5
+    psi, _, _ = _pedestal(n, L, 0.5, 2.5)
+    zero = (0, 0, 0, 0)
+    chg, chg_free = [], []
+    for dz in (0.04, 0.02):
+        out = orc.evolve(psi, L, zero, a, 0.0, dz, 1, local=(0.0, 1.0, -2 * a, 1e-6))
+        chg.append(orc.rel_l2(out, psi))
+        free = orc.evolve(psi, L, zero, a, 0.0, dz, 1)
+        chg_free.append(orc.rel_l2(free, psi))
+    assert 7.0 < chg[0] / chg[1] < 9.0, chg
+    assert 1.8 < chg_free[0] / chg_free[1] < 2.2, chg_free
+    assert chg[0] < 1e-3 * chg_free[0]
+    # the wrong sign doubles the quantum pressure instead of cancelling it
+    wrong = orc.evolve(psi, L, zero, a, 0.0, 0.04, 1, local=(0.0, 1.0, 2 * a, 1e-6))
+    assert orc.rel_l2(wrong, psi) > 1.5 * chg_free[0]
+
+
+@pytest.mark.parametrize("npoly", [1.0, 2.5, -1.0])
+def test_pressure_uniform_state_rotates_at_its_potential(npoly):
+    """A uniform state only picks up the phase of its local potential:
+    psi(z) = psi0 exp(i (g rho0 + c_p f_n(rho0)) z) (the kinetic factor is 1 at
+    k = 0, the Newtonian k = 0 term is dropped and lap sqrt rho0 = 0)."""
+    n, L, rho0, g, cp, dz, steps = (16, 32), (10.0, 20.0), 0.64, -0.3, 0.45, 0.01, 9
+    psi0 = np.full(n, np.sqrt(rho0) * np.exp(0.3j))
+    out = orc.evolve(psi0, L, (1.0, 0, 0, 0), 0.5, g, dz, steps, local=(cp, npoly, 0.7, 1e-6))
+    fn = np.log(rho0) if npoly == 1.0 else npoly / (npoly - 1) * rho0 ** (npoly - 1)
+    exact = psi0 * np.exp(1j * (g * rho0 + cp * fn) * dz * steps)
+    assert np.max(np.abs(out - exact)) < 1e-13
+
+
+def test_pressure_n2_is_kerr_and_n1_is_the_limit_of_the_power_law():
+    """f_2(rho) = 2 rho, so n = 2 with c_p equals the Kerr term with g = 2 c_p;
+    f_n(rho) = n/(n-1) + n ln rho + O(n-1), so n -> 1 reaches the logarithm up to
+    the uniform potential c_p n/(n-1), a global phase."""
+    w = inputs.WORKLOADS["gsn2d_128_kerr_newton"]
+    psi0 = inputs.as_oracle_input(inputs.gaussian_2d_128())
+    L, kern, a, dz, steps = w["L"], w["kern"], w["a"], w["dz"], 20
+    cp = 0.35
+    p2 = orc.evolve(psi0, L, kern, a, 0.0, dz, steps, local=(cp, 2.0, 0.0, 0.0))
+    kerr = orc.evolve(psi0, L, kern, a, 2 * cp, dz, steps)
+    assert orc.rel_l2(p2, kerr) < 1e-13
+    eps = 2.0 ** -23   # 1 + eps - 1 is exact, so the uniform part is known exactly
+    rf = 1e-8
+    plog = orc.evolve(psi0, L, kern, a, 0.0, dz, steps, local=(cp / (1 + eps), 1.0, 0.0, rf))
+    ppow = orc.evolve(psi0, L, kern, a, 0.0, dz, steps, local=(cp / (1 + eps), 1.0 + eps, 0.0, rf))
+    ppow = ppow * np.exp(-1j * cp / eps * dz * steps)
+    assert orc.rel_l2(ppow, plog) < 1e-5
+    assert orc.rel_l2(plog, kerr) > 1e-3
+
+
+def _grad_energy_pin(n, L, kern, a, g, local, seed):
+    """dE/de at e = 0 along psi + e eta equals 2 Re sum dV conj(eta) H psi with
+    H psi = -a lap psi - (U + phi) psi, the right-hand side the evolution uses:
+    the energy is the Hamiltonian of the stepped equation."""
+    rng = np.random.default_rng(seed)
+    psi, s, r2 = _pedestal(n, L, 0.6, 2.5)
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    psi = psi * np.exp(1j * 0.3 * xs[-1] / L[-1] * 2 * np.pi)
+    c = rng.uniform(-4, 4, len(n))
+    eta = np.exp(-sum((x - cc) ** 2 for x, cc in zip(xs, c)) / 8.0) * np.exp(1j * rng.uniform(0, 6.28))
+    dV = np.prod([Ld / N for N, Ld in zip(n, L)])
+    k2 = sum(k * k for k in np.meshgrid(*[2 * np.pi * np.fft.fftfreq(N, Ld / N) for N, Ld in zip(n, L)],
+                                         indexing="ij"))
+    lap = orc.fft(-k2 * orc.fft(psi), inverse=True)
+    U = orc.local_potential(psi, L, g, local)
+    phi = orc.potential(np.abs(psi) ** 2, L, kern)
+    Hpsi = -a * lap - (U + phi) * psi
+    expect = 2 * np.real(np.sum(np.conj(eta) * Hpsi)) * dV
+    e = 1e-4
+    Ep = orc.observables(psi + e * eta, L, kern, a, g, local=local)["total"]
+    Em = orc.observables(psi - e * eta, L, kern, a, g, local=local)["total"]
+    return (Ep - Em) / (2 * e), expect
+
+
+@pytest.mark.parametrize("local", [(0.4, 1.0, 0.0, 1e-6), (0.4, 2.5, 0.0, 0.0),
+                                   (-0.3, -1.0, 0.0, 1e-6), (0.0, 1.0, -0.7, 1e-6),
+                                   (0.3, 1.0, 0.9, 1e-6)])
+def test_energy_is_the_hamiltonian_of_the_local_terms(local):
+    got, expect = _grad_energy_pin((64, 64), (40.0, 40.0), (1.0, 0.3, 0.5, 0.0), 0.5, -0.4, local, 3)
+    assert abs(got - expect) < 1e-7 * max(1.0, abs(expect)), (got, expect)
+
+
+def test_energy_bohm_and_pressure_closed_forms():
+    """E_B = (c_B/2) integral |grad s|^2 = (c_B/2) pi A^2 in 2-D for
+    s = 1 + A exp(-r^2/(2 sig^2)); for a uniform state E_p = -c_p V F_n(rho0)
+    with F_1 = rho ln rho - rho (F_1' = ln rho) and F_n = rho^n/(n-1)."""
+    n, L, A, sig, cB = (128, 128), (48.0, 48.0), 0.5, 2.5, 0.8
+    psi, _, _ = _pedestal(n, L, A, sig)
+    ob = orc.observables(psi, L, (0, 0, 0, 0), 0.5, 0.0, local=(0.0, 1.0, cB, 1e-6))
+    assert abs(ob["bohm"] - 0.5 * cB * np.pi * A * A) < 1e-10
+    n2, L2, rho0, cp = (16, 16), (8.0, 4.0), 0.3, 0.7
+    psi = np.full(n2, np.sqrt(rho0), dtype=complex)
+    V = L2[0] * L2[1]
+    for npoly, F in ((1.0, rho0 * np.log(rho0) - rho0), (3.0, rho0 ** 3 / 2.0)):
+        ob = orc.observables(psi, L2, (0, 0, 0, 0), 0.5, 0.0, local=(cp, npoly, 0.0, 1e-6))
+        assert abs(ob["pressure"] + cp * V * F) < 1e-12
+        assert ob["bohm"] == 0.0
+
+
+def test_energy_drift_second_order_with_local_terms():
+    """The full Eq. (15) local model conserves mass exactly and energy to O(dz^2)."""
+    n, L, a = (64, 64), (40.0, 40.0), 0.5
+    psi0, _, _ = _pedestal(n, L, 0.6, 2.5)
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    psi0 = psi0 * np.exp(2j * np.pi * 2 * xs[1] / L[1])
+    kern, g, local = (1.0, 0.3, 0.5, 0.0), -0.2, (0.3, 1.0, -0.5, 1e-6)
+    E0 = orc.observables(psi0, L, kern, a, g, local=local)
+    drifts = []
+    for dz in (0.02, 0.01):
+        psi = orc.evolve(psi0, L, kern, a, g, dz, int(round(0.4 / dz)), local=local)
+        E = orc.observables(psi, L, kern, a, g, local=local)
+        assert abs(E["mass"] / E0["mass"] - 1) < 1e-13
+        drifts.append(abs(E["total"] - E0["total"]))
+    assert 3.0 < drifts[0] / drifts[1] < 5.0, drifts
+
+
+def test_local_terms_reject_bad_arguments():
+    psi = np.ones((16, 16), complex)
+    L, kern = (1.0, 1.0), (0, 0, 0, 0)
+    for local in [(0.5, 0.5, 0.0, 1e-6),    # 0 <= n < 1: outside the pressure law
+                  (0.5, 1.0, 0.0, 0.0),     # ln rho needs a floor
+                  (0.0, 1.0, 0.5, 0.0),     # so does 1/sqrt(rho)
+                  (0.5, 1.0, 0.0, -1.0),
+                  (np.nan, 1.0, 0.0, 1e-6)]:
+        with pytest.raises(ValueError):
+            orc.evolve(psi, L, kern, 0.5, 0.0, 1e-3, 1, local=local)
