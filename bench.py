@@ -209,6 +209,56 @@ def corrector_bench(ntrain, epochs, neval, ncoarse, tol):
             "ms_coarse": 1e3 * ev["t_coarse"] / neval, "speedup": ev["t_fine"] / ev["t_corrected"]}
 
 
+def eq15_bench(steps, autotune_iters, profile_steps):
+    """The 256^3 Eq. (15) fluid (pressure and Bohm terms on): step rate, the
+    per-pass times and the roofline of its dominant pass, and its invariants."""
+    import torch
+    from paper_1909_08354_amd import gsn, inputs
+    w = inputs.WORKLOADS["gsn3d_256_eq15"]
+    n, L = w["n"], w["L"]
+    P = int(np.prod(n))
+    psi0 = inputs.fluid_gaussian(n, L, w["mass"], w["waist"], seed=w["seed"])
+    grid = gsn.Grid(n, L)
+    grid.set_kernel(*w["kern"])
+    grid.set_coefficients(w["a"], w["g"], w["dz"])
+    grid.set_local_terms(*w["local"])
+    dev0 = torch.from_numpy(inputs.to_c64(psi0)).cuda()
+    grid.set_psi(dev0)
+    schedule = grid.autotune(autotune_iters) if autotune_iters > 0 else grid.schedule()
+    grid.set_psi(dev0)
+    m0 = grid.mass()
+    e0 = grid.energy()
+    grid.step(10)
+    grid.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    grid.sync()
+    m1 = grid.mass()
+    e1 = grid.energy()
+    prof = grid.profile_passes(profile_steps)
+    bpp = dict(zip(grid.pass_names(), grid.pass_bytes_per_point()))
+    steady = {k: v for k, v in prof.items() if k not in ("x_entry_fft", "x_exit_ifft") and bpp[k] > 0}
+    dom = max(steady, key=steady.get)
+    achieved = bpp[dom] * P / (steady[dom] * 1e-3) / 1e9
+    step_bytes = sum(bpp[k] for k in steady) * P
+    ms = 1e3 * elapsed / steps
+    scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
+    grid.close()
+    return {"workload": "gsn3d_256_eq15", "grid": list(n), "local": list(w["local"]),
+            "kernel": list(w["kern"]), "steps": steps, "value": P * steps / elapsed,
+            "unit": "grid-pt updates/s", "ms_per_step": ms,
+            "model_bytes_per_point": step_bytes / P,
+            "model_step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                         "algorithmic_bytes_per_launch": bpp[dom] * P, "avg_launch_ms": steady[dom]},
+            "pass_ms": {k: round(v, 5) for k, v in steady.items()}, "schedule": schedule,
+            "norm_drift": abs(m1 / m0 - 1), "energy_drift": abs(e1["total"] - e0["total"]) / scale}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +272,8 @@ def main():
     ap.add_argument("--corrector-train", type=int, default=2000,
                     help="training trajectories of the corrector leg (0 skips it)")
     ap.add_argument("--corrector-epochs", type=int, default=4)
+    ap.add_argument("--eq15-steps", type=int, default=200,
+                    help="steps of the 256^3 Eq. (15) fluid leg (0 skips it)")
     ap.add_argument("--corrector-eval", type=int, default=100)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
@@ -310,10 +362,13 @@ def main():
         "batched": None,
         "corrected_speedup": None,
         "corrected": None,
+        "eq15": None,
     }
-    if args.batch_steps > 0 or args.corrector_train > 0:
+    if args.batch_steps > 0 or args.corrector_train > 0 or args.eq15_steps > 0:
         grid.close()
         del grid
+    if args.eq15_steps > 0:
+        line["eq15"] = eq15_bench(args.eq15_steps, min(args.autotune_iters, 5), args.profile_steps)
     if args.batch_steps > 0:
         line["batched"] = batch_bench(args.batch_steps)
         line["batched_speedup"] = line["batched"]["speedup"]

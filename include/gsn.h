@@ -91,6 +91,25 @@ gsn_status gsn_set_kernel(gsn_grid grid, const gsn_kernel *kernel);
    (Kerr; Eq. (16) with n = 2 gives g = -2w) and the step dz (finite, != 0). */
 gsn_status gsn_set_coefficients(gsn_grid grid, double a_kin, double g_local, double dz);
 
+/* Local terms of Eq. (15) (Sec. II C): replace the Kerr term g rho of the
+   phase by the local potential
+     U = g rho + c_pressure f_n(max(rho, rho_floor))
+               + c_bohm lap(sqrt rho) / (2 max(sqrt rho, sqrt rho_floor)),
+     f_n(rho) = ln rho (n = 1),  n/(n-1) rho^(n-1) (n > 1 or n < 0),
+   the polytropic pressure potential and the Bohm potential, with lap the
+   spectral Laplacian.  Eq. (15) divided by nu maps to a = nu/2,
+   c_bohm = -nu, c_pressure = -w/nu and c_newton = gamma/nu (for
+   lap phi_N = gamma rho).  rho_floor >= 0 keeps ln rho, negative powers and the
+   division finite where the density vanishes; it must be > 0 when the pressure
+   term has n <= 1 or the Bohm term is on.  All zero (the default) is the Kerr
+   model.  The Bohm term adds one real-to-complex transform pair per step (the
+   passes "y_fwd_sqrt", "laplacian", "y_inv_lap"); the density and phase passes
+   with these terms run one tile per block in every schedule variant.
+   Validation failures return GSN_EINVAL and leave the grid unchanged.
+   Synchronising. */
+gsn_status gsn_set_local_terms(gsn_grid grid, double c_pressure, double n_pressure, double c_bohm,
+                               double rho_floor);
+
 /* Load psi (P complex values, C order) from host (src_on_device = 0) or
    device memory, as complex64 or complex128.  Resets the global phase and the
    step count.  Synchronising for host sources. */
@@ -113,7 +132,10 @@ gsn_status gsn_mass(gsn_grid grid, double *mass);
 
 /* FP64 energy of the current state (the Hamiltonian of the equation):
    e[0] total, e[1] kinetic a dV/P sum |k|^2 |psi_hat|^2, e[2] local
-   -(g/2) dV sum rho^2, e[3] nonlocal -(1/2) dV sum rho phi.  Synchronising. */
+   -(g/2) dV sum rho^2 - c_pressure dV sum G_n(rho) + (c_bohm/2) dV sum |grad sqrt rho|^2
+   (G_n' = f_n(max(rho, rho_floor)); the Bohm part is evaluated as
+   -(c_bohm/2) dV sum sqrt(rho) lap(sqrt rho)), e[3] nonlocal
+   -(1/2) dV sum rho phi.  Synchronising. */
 gsn_status gsn_energy(gsn_grid grid, double e[4]);
 
 /* Global phase accumulated since gsn_set_psi (FP64) and steps taken. */

@@ -87,13 +87,16 @@ const NKernels *kernels_for(int N, int v)
 
 
 // ------------------------------------------------------------------ passes
+// The last three carry sqrt(rho) to lap(sqrt rho) for the Bohm potential of
+// Eq. (15); they run only while that term is on (the 2-D grid uses only the
+// Laplacian column pass).
 enum PassId {
     P_ENTRY = 0, P_Y_FWD_PSI, P_KINETIC, P_Y_INV_PSI, P_DENSITY, P_Y_FWD_RHO, P_KERNEL,
-    P_Y_INV_PHI, P_PHASE, P_EXIT, P_COUNT
+    P_Y_INV_PHI, P_PHASE, P_EXIT, P_Y_FWD_SQRT, P_LAPLACIAN, P_Y_INV_LAP, P_COUNT
 };
 static const char *kPassNames[P_COUNT] = {
     "x_entry_fft", "y_fwd_psi", "kinetic", "y_inv_psi", "x_density", "y_fwd_rho",
-    "kernel", "y_inv_phi", "x_phase", "x_exit_ifft"};
+    "kernel", "y_inv_phi", "x_phase", "x_exit_ifft", "y_fwd_sqrt", "laplacian", "y_inv_lap"};
 
 struct Launch {
     const void *fn;
@@ -118,6 +121,7 @@ struct gsn_grid_ {
     int device;
     // workspace carve-up
     float2 *psi, *scratch, *half, *nyq;
+    float2 *half2, *nyq2;      // sqrt(rho) -> lap(sqrt rho) spectrum (Bohm term)
     double *mass_parts, *epart;
     DevState *st;
     double2 *tw[3];            // twiddles for x, y, z lengths
@@ -132,6 +136,8 @@ struct gsn_grid_ {
     // parameters
     double a, g, dz;
     gsn_kernel kern;
+    double lp_cp, lp_n, lp_cb, lp_floor;   // local terms of Eq. (15)
+    bool local_on, bohm_on;
     bool have_dz, have_psi;
     // launch schedules
     std::vector<Launch> entry, kin_half, kin_full, nonlin, exit_, energy_rho, energy_kin;
@@ -145,7 +151,7 @@ struct gsn_grid_ {
 
 
 struct Layout {
-    size_t psi, scratch, half, nyq, mass_parts, epart, st, tables, total;
+    size_t psi, scratch, half, nyq, half2, nyq2, mass_parts, epart, st, tables, total;
     int density_blocks, em_blocks, lm_blocks_max;
 };
 
@@ -189,8 +195,10 @@ static Layout compute_layout(int ndim, const int32_t n[])
     L.scratch = off; off = align256(off + 8ull * P);
     L.half = off; off = align256(off + 8ull * (P / 2));
     L.nyq = off; off = align256(off + 8ull * rows);
+    L.half2 = off; off = align256(off + 8ull * (P / 2));
+    L.nyq2 = off; off = align256(off + 8ull * rows);
     L.mass_parts = off; off = align256(off + 8ull * (size_t)(L.density_blocks > 1024 ? L.density_blocks : 1024));
-    size_t ep = 2ull * (size_t)L.density_blocks + (size_t)lmb + 1024;
+    size_t ep = 4ull * (size_t)L.density_blocks + (size_t)lmb + 1024;
     L.epart = off; off = align256(off + 8ull * ep);
     L.st = off; off = align256(off + sizeof(DevState));
     L.tables = off;
@@ -330,6 +338,26 @@ static EmArgs em_base(gsn_grid g, float2 *psi)
     a.tw = g->tw[g->ndim - 1];
     a.sct = g->sct;
     a.scale = 1.0;
+    a.half2 = g->half2;
+    a.nyq2 = g->nyq2;
+    if (g->local_on) {
+        const double n = g->lp_n, fl = g->lp_floor;
+        a.cp = g->lp_cp;
+        a.pmode = g->lp_cp == 0.0 ? 0 : (n == 1.0 ? 1 : 2);
+        a.pn1 = n - 1.0;
+        a.pfac = a.pmode == 2 ? n / (n - 1.0) : 0.0;
+        a.rfl = fl;
+        a.sfl = std::sqrt(fl);
+        a.cb2 = 0.5 * g->lp_cb;
+        a.bohm = g->bohm_on ? 1 : 0;
+        if (a.pmode == 1 && fl > 0.0) {
+            a.f_fl = std::log(fl);
+            a.F_fl = fl * (std::log(fl) - 1.0);
+        } else if (a.pmode == 2 && fl > 0.0) {
+            a.f_fl = a.pfac * std::pow(fl, n - 1.0);
+            a.F_fl = std::pow(fl, n) / (n - 1.0);
+        }
+    }
     return a;
 }
 
@@ -402,8 +430,13 @@ static void build_core(gsn_grid g)
         d.nlines = (int)(rows / 2);
         d.partials = g->mass_parts;
         const bool store = g->store_psi && !energy;
-        dst.push_back(em_launch(store ? KX(P_DENSITY)->density_store : KX(P_DENSITY)->density,
-                                KX(P_DENSITY), d, P_DENSITY));
+        if (g->bohm_on) {
+            const LKernels *lk = local_kernels_for(Nx, g->var[P_DENSITY]);
+            dst.push_back(em_launch(store ? lk->density_store : lk->density, KX(P_DENSITY), d, P_DENSITY));
+        } else {
+            dst.push_back(em_launch(store ? KX(P_DENSITY)->density_store : KX(P_DENSITY)->density,
+                                    KX(P_DENSITY), d, P_DENSITY));
+        }
         if (nd == 3) {
             const NKernels *ky = KY(P_Y_FWD_RHO), *kz = KZ(P_KERNEL), *ky2 = KY(P_Y_INV_PHI);
             LmArgs e = lm_base(g, g->tw[Y], 1.0);
@@ -456,18 +489,60 @@ static void build_core(gsn_grid g)
             }
             dst.push_back(lm_launch(ky->lm_kern, ky, f, P_KERNEL));
         }
+        if (g->bohm_on) {
+            // sqrt(rho) -> lap(sqrt rho): the same passes with -|k|^2 for K
+            if (nd == 3) {
+                const NKernels *ky = KY(P_Y_FWD_SQRT), *ky2 = KY(P_Y_INV_LAP);
+                const LKernels *lz = local_kernels_for(Nz, g->var[P_LAPLACIAN]);
+                LmArgs e = lm_base(g, g->tw[Y], 1.0);
+                e.s0 = make_seg(g->half2, H, 1, (long long)Ny * H, H, Nz, ky->lm_lines);
+                e.s1 = make_seg(g->nyq2, 1, Ny, 0, Nz, 1, ky->lm_lines);
+                dst.push_back(lm_launch(ky->lm_fwd, ky, e, P_Y_FWD_SQRT));
+                LmArgs f = lm_base(g, g->tw[Z], 1.0 / ((double)Ny * Nz));
+                f.s0 = make_seg(g->half2, (long long)Ny * H, 1, H, H, Ny, KZ(P_LAPLACIAN)->lm_lines);
+                f.s0.c1l = 1;
+                f.s0.c2o = 1;
+                f.s1 = make_seg(g->nyq2, Ny, 1, 0, Ny, 1, KZ(P_LAPLACIAN)->lm_lines);
+                f.s1.c1f = H;
+                f.s1.c2l = 1;
+                f.k2_1 = g->k2[X];
+                f.k2_2 = g->k2[Y];
+                f.k2_p = g->k2[Z];
+                dst.push_back(lm_launch(lz->lm_lap, KZ(P_LAPLACIAN), f, P_LAPLACIAN));
+                LmArgs gg = lm_base(g, g->tw[Y], 1.0);
+                gg.s0 = make_seg(g->half2, H, 1, (long long)Ny * H, H, Nz, ky2->lm_lines);
+                gg.s1 = make_seg(g->nyq2, 1, Ny, 0, Nz, 1, ky2->lm_lines);
+                dst.push_back(lm_launch(ky2->lm_inv, ky2, gg, P_Y_INV_LAP));
+            } else {
+                const LKernels *ly = local_kernels_for(Ny, g->var[P_LAPLACIAN]);
+                LmArgs f = lm_base(g, g->tw[Y], 1.0 / (double)Ny);
+                f.s0 = make_seg(g->half2, H, 1, 0, H, 1, KY(P_LAPLACIAN)->lm_lines);
+                f.s0.c1l = 1;
+                f.s1 = make_seg(g->nyq2, 1, 0, 0, 1, 1, KY(P_LAPLACIAN)->lm_lines);
+                f.s1.c1f = H;
+                f.k2_1 = g->k2[X];
+                f.k2_p = g->k2[Y];
+                dst.push_back(lm_launch(ly->lm_lap, KY(P_LAPLACIAN), f, P_LAPLACIAN));
+            }
+        }
         EmArgs h = em_base(g, src);
         h.nlines = (int)(rows / 2);
         h.g = g->g;
         h.dz = g->dz;
         h.partials = g->epart;
-        dst.push_back(em_launch(energy ? KX(P_PHASE)->phase_energy
-                                       : store ? KX(P_PHASE)->phase_real : KX(P_PHASE)->phase,
-                                KX(P_PHASE), h, P_PHASE));
+        if (g->local_on) {
+            const LKernels *lk = local_kernels_for(Nx, g->var[P_PHASE]);
+            dst.push_back(em_launch(energy ? lk->phase_energy : store ? lk->phase_real : lk->phase,
+                                    KX(P_PHASE), h, P_PHASE));
+        } else {
+            dst.push_back(em_launch(energy ? KX(P_PHASE)->phase_energy
+                                           : store ? KX(P_PHASE)->phase_real : KX(P_PHASE)->phase,
+                                    KX(P_PHASE), h, P_PHASE));
+        }
     }
     // kinetic energy: F_y (3-D) then the last-axis forward FFT with sum |k|^2 |psi_hat|^2
     {
-        const int ep_off = 2 * g->max_density_blocks;
+        const int ep_off = 4 * g->max_density_blocks;
         if (nd == 3) {
             const NKernels *ky = KY(P_Y_FWD_PSI), *kz = KZ(P_KINETIC);
             LmArgs a = lm_base(g, g->tw[Y], 1.0);
@@ -534,7 +609,10 @@ static void build_schedule(gsn_grid g)
         d.partials = g->mass_parts;
         g->pot.push_back(em_launch(kx->density_real, kx, d, P_DENSITY));
     }
-    for (size_t i = 1; i + 1 < g->energy_rho.size(); ++i) g->pot.push_back(g->energy_rho[i]);
+    for (size_t i = 1; i + 1 < g->energy_rho.size(); ++i) {
+        const int p = g->energy_rho[i].pass;
+        if (p == P_Y_FWD_RHO || p == P_KERNEL || p == P_Y_INV_PHI) g->pot.push_back(g->energy_rho[i]);
+    }
     {
         const NKernels *kx = kernels_for(g->Nx, g->var[P_PHASE]);
         EmArgs a = em_base(g, g->scratch);
@@ -654,6 +732,9 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
     g->g = 0.0;
     g->dz = 0.0;
     std::memset(&g->kern, 0, sizeof(g->kern));
+    g->lp_cp = g->lp_cb = g->lp_floor = 0.0;
+    g->lp_n = 1.0;
+    g->local_on = g->bohm_on = false;
     if (hipGetDevice(&g->device) != hipSuccess) {
         delete g;
         return fail(GSN_EHIP, "hipGetDevice failed");
@@ -663,6 +744,8 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
     g->scratch = (float2 *)(ws + lay.scratch);
     g->half = (float2 *)(ws + lay.half);
     g->nyq = (float2 *)(ws + lay.nyq);
+    g->half2 = (float2 *)(ws + lay.half2);
+    g->nyq2 = (float2 *)(ws + lay.nyq2);
     g->mass_parts = (double *)(ws + lay.mass_parts);
     g->epart = (double *)(ws + lay.epart);
     g->st = (DevState *)(ws + lay.st);
@@ -712,6 +795,30 @@ extern "C" gsn_status gsn_set_kernel(gsn_grid g, const gsn_kernel *k)
     if (k->c_yukawa != 0.0 && !(k->m_yukawa > 0.0))
         return fail(GSN_EINVAL, "m_yukawa must be > 0 when c_yukawa != 0");
     g->kern = *k;
+    build_schedule(g);
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_set_local_terms(gsn_grid g, double c_pressure, double n_pressure, double c_bohm,
+                                          double rho_floor)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (!std::isfinite(c_pressure) || !std::isfinite(n_pressure) || !std::isfinite(c_bohm) ||
+        !std::isfinite(rho_floor))
+        return fail(GSN_EINVAL, "local-term coefficients must be finite");
+    if (rho_floor < 0.0) return fail(GSN_EINVAL, "rho_floor must be >= 0");
+    if (c_pressure != 0.0 && n_pressure >= 0.0 && n_pressure < 1.0)
+        return fail(GSN_EINVAL, "the pressure law is defined for n = 1, n > 1 and n < 0");
+    if (((c_pressure != 0.0 && n_pressure <= 1.0) || c_bohm != 0.0) && !(rho_floor > 0.0))
+        return fail(GSN_EINVAL, "ln rho, negative powers of rho and the Bohm term need rho_floor > 0");
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->lp_cp = c_pressure;
+    g->lp_n = n_pressure;
+    g->lp_cb = c_bohm;
+    g->lp_floor = rho_floor;
+    g->local_on = c_pressure != 0.0 || c_bohm != 0.0;
+    g->bohm_on = c_bohm != 0.0;
     build_schedule(g);
     return GSN_OK;
 }
@@ -898,14 +1005,17 @@ extern "C" gsn_status gsn_energy(gsn_grid g, double e[4])
     if ((s = run_list(g, g->energy_kin))) return s;
     const int nphase = (int)g->energy_rho.back().grid.x;
     const int nkin = (int)g->energy_kin.back().grid.x;
-    double rho_sum = 0.0, rho_phi = 0.0, rho2 = 0.0, k2sum = 0.0;
+    double rho_sum = 0.0, rho_phi = 0.0, rho2 = 0.0, k2sum = 0.0, gsum = 0.0, slap = 0.0;
     if ((s = sum_device(g, g->mass_parts, g->density_blocks, 1, 0, &rho_sum))) return s;
-    if ((s = sum_device(g, g->epart, nphase, 2, 0, &rho_phi))) return s;
-    if ((s = sum_device(g, g->epart, nphase, 2, 1, &rho2))) return s;
-    if ((s = sum_device(g, g->epart + 2 * g->max_density_blocks, nkin, 1, 0, &k2sum))) return s;
+    if ((s = sum_device(g, g->epart, nphase, 4, 0, &rho_phi))) return s;
+    if ((s = sum_device(g, g->epart, nphase, 4, 1, &rho2))) return s;
+    if ((s = sum_device(g, g->epart, nphase, 4, 2, &gsum))) return s;
+    if ((s = sum_device(g, g->epart, nphase, 4, 3, &slap))) return s;
+    if ((s = sum_device(g, g->epart + 4 * g->max_density_blocks, nkin, 1, 0, &k2sum))) return s;
     const double dV = cell_volume(g), P = (double)g->P, K0 = kernel_k0(g->kern);
     const double ekin = g->a * dV / P * k2sum;
-    const double eloc = -0.5 * g->g * dV * rho2;
+    // Kerr, pressure (-c_p sum G) and Bohm (-(c_B/2) sum s lap s = (c_B/2) sum |grad s|^2)
+    const double eloc = -0.5 * g->g * dV * rho2 - g->lp_cp * dV * gsum - 0.5 * g->lp_cb * dV * slap;
     const double enl = -0.5 * dV * (rho_phi + K0 * rho_sum * rho_sum / P);
     e[0] = ekin + eloc + enl;
     e[1] = ekin;
@@ -928,9 +1038,11 @@ extern "C" double gsn_pass_bytes_per_point(gsn_grid g, int i)
     // reads + writes of complex64 psi (8 B), half spectrum (4 B per point)
     switch (i) {
     case P_ENTRY: case P_EXIT: case P_Y_FWD_PSI: case P_Y_INV_PSI: case P_KINETIC: return 16.0;
-    case P_DENSITY: return g->store_psi ? 20.0 : 12.0;
+    case P_DENSITY: return (g->store_psi ? 20.0 : 12.0) + (g->bohm_on ? 4.0 : 0.0);
     case P_Y_FWD_RHO: case P_KERNEL: case P_Y_INV_PHI: return 8.0;
-    case P_PHASE: return 20.0;
+    case P_PHASE: return 20.0 + (g->bohm_on ? 4.0 : 0.0);
+    case P_Y_FWD_SQRT: case P_Y_INV_LAP: return g->bohm_on && g->ndim == 3 ? 8.0 : 0.0;
+    case P_LAPLACIAN: return g->bohm_on ? 8.0 : 0.0;
     default: return 0.0;
     }
 }
@@ -1078,6 +1190,7 @@ static std::string cache_key(gsn_grid g, int p)
     k << arch << " " << g->ndim << "d";
     for (int d = 0; d < g->ndim; ++d) k << (d ? "x" : " ") << g->n[d];
     k << " " << (p < P_COUNT ? kPassNames[p] : "nonlinear_mode");
+    if (g->local_on) k << (g->bohm_on ? "+eq15b" : "+eq15");
     return k.str();
 }
 

@@ -82,8 +82,22 @@ template <int N, int V> struct Cfg {
 };
 
 // Kernel table of length N, schedule variant v (defined in gsn_api.hip, the
-// only translation unit that instantiates the single-grid kernels).
+// only translation unit that instantiates the single-grid kernels of the Kerr
+// model).
 const NKernels *kernels_for(int N, int v = 0);
+
+// Kernels of the local terms of Eq. (15) (pressure and Bohm potential) of
+// length N in the tile configuration of schedule variant v; one tile per block
+// (defined in gsn_local.hip).
+struct LKernels {
+    void (*density)(EmArgs);         // also the half spectrum of sqrt(rho)
+    void (*density_store)(EmArgs);   // ... and stores real-space psi
+    void (*phase)(EmArgs);
+    void (*phase_real)(EmArgs);
+    void (*phase_energy)(EmArgs);
+    void (*lm_lap)(LmArgs);          // FFT, -|k|^2, inverse FFT
+};
+const LKernels *local_kernels_for(int N, int v = 0);
 
 // Blocks of kernel fn (threads per block) resident on the whole device at
 // once (occupancy x compute units): the grid of a persistent kernel; 0 if

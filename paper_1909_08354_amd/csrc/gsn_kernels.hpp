@@ -47,6 +47,15 @@ struct EmArgs {
     double *partials;     // per-block FP64 partials
     float *phi;           // potential readout destination (real rows of N)
     const double2 *sct;   // (cos, sin) of j pi/128, j < 256 (pipelined phase pass)
+    // local terms of Eq. (15) (the general density and phase passes):
+    // U = g rho + cp f(max(rho, rfl)) + cb2 lap(s) / max(s, sfl), s = sqrt(rho),
+    // f = ln rho (pmode 1) or pfac rho^pn1 (pmode 2, pfac = n/(n-1), pn1 = n-1)
+    float2 *half2;        // half spectrum of s, then lap(s) (Bohm term)
+    float2 *nyq2;
+    double cp, pfac, pn1, cb2, rfl, sfl;
+    double f_fl, F_fl;    // f and its antiderivative F at the floor (pressure energy)
+    int pmode;            // 0: no pressure term, 1: ln rho, 2: power law
+    int bohm;             // 1: Bohm term
 };
 
 template <int N, int E> struct EmShape {
@@ -93,7 +102,40 @@ __device__ __forceinline__ void em_fft_tile(const EmArgs &a, int tile, float2 *l
 //
 // REAL_IN: the rows hold psi in real space (not x-spectral); the inverse x
 // transforms are skipped (the potential readout of a state between calls).
-template <int N, int E, int LINES, bool STORE_PSI, bool REAL_IN = false>
+// Split the spectrum Z = X_0 + i X_1 of two real rows held in v (one exchange
+// through LDS, so bin k can see bin N-k) into X_0[k] = (Z[k] + conj Z[N-k]) / 2,
+// X_1[k] = (Z[k] - conj Z[N-k]) / (2i); store bins 0..N/2-1 to the half rows
+// r0, r1 and the real bin N/2 to nyq.
+template <int N, int E>
+__device__ __forceinline__ void store_real_pair(const dc (&v)[E], bool act, int t, const EmLayout<N, E> &lay,
+                                                float2 *lds, float2 *half, float2 *nyq, long long r0, long long r1)
+{
+    constexpr int TPL = N / E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[lay(t + TPL * e)] = to_f2(v[e]);
+    exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
+    if (act) {
+        float2 *h0 = half + r0 * (N / 2), *h1 = half + r1 * (N / 2);
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            const int k = t + TPL * e;
+            const dc z = v[e];
+            const dc zc = conj(from_f2(lds[lay((N - k) & (N - 1))]));
+            const dc s = add(z, zc), d = sub(z, zc);
+            h0[k] = to_f2(scl(s, 0.5));
+            h1[k] = to_f2(mk(0.5 * d.y, -0.5 * d.x));
+        }
+        if (t == 0) {
+            const dc z = v[E / 2];   // bin N/2: both halves are real
+            nyq[r0] = make_float2((float)z.x, 0.0f);
+            nyq[r1] = make_float2((float)z.y, 0.0f);
+        }
+    }
+}
+
+// BOHM: also transform s = sqrt(rho) of both rows the same way into half2 /
+// nyq2 (the Bohm potential of Eq. (15) needs lap(s)).
+template <int N, int E, int LINES, bool STORE_PSI, bool REAL_IN = false, bool BOHM = false>
 __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *lds, double *sh)
 {
     static_assert(!(STORE_PSI && REAL_IN), "real-space input is not stored back");
@@ -129,33 +171,20 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *
         }
     }
     double msum = 0.0;
+    dc w[BOHM ? E : 1];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const double rho1 = norm2(v[e]) * rs;
         msum += rho0[e] + rho1;
+        if constexpr (BOHM) w[e] = mk(sqrt(rho0[e]), sqrt(rho1));
         v[e] = mk(rho0[e], rho1);
     }
     fft<N, E, -1>(v, t, lay, lds, a.tw);
-    // exchange Z so that bin k can see bin N-k
-#pragma unroll
-    for (int e = 0; e < E; ++e) lds[lay(t + TPL * e)] = to_f2(v[e]);
-    exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
-    if (act) {
-        float2 *h0 = a.half + r0 * (N / 2), *h1 = a.half + r1 * (N / 2);
-#pragma unroll
-        for (int e = 0; e < E / 2; ++e) {
-            const int k = t + TPL * e;
-            const dc z = v[e];
-            const dc zc = conj(from_f2(lds[lay((N - k) & (N - 1))]));
-            const dc s = add(z, zc), d = sub(z, zc);
-            h0[k] = to_f2(scl(s, 0.5));
-            h1[k] = to_f2(mk(0.5 * d.y, -0.5 * d.x));
-        }
-        if (t == 0) {
-            const dc z = v[E / 2];   // bin N/2: both halves are real
-            a.nyq[r0] = make_float2((float)z.x, 0.0f);
-            a.nyq[r1] = make_float2((float)z.y, 0.0f);
-        }
+    store_real_pair<N, E>(v, act, t, lay, lds, a.half, a.nyq, r0, r1);
+    if constexpr (BOHM) {
+        exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();   // the split above has read LDS
+        fft<N, E, -1>(w, t, lay, lds, a.tw);
+        store_real_pair<N, E>(w, act, t, lay, lds, a.half2, a.nyq2, r0, r1);
     }
     const double bs = block_sum<NT>(msum, sh);
     if (tid == 0) a.partials[tile] = bs;
@@ -164,11 +193,11 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *
 // Full x-spectrum Z = X_0 + i X_1 of two real rows r0, r1 from their half
 // spectra (X[N-k] = conj X[k]; the DC and Nyquist bins are real).
 template <int N, int E>
-__device__ __forceinline__ void load_phi_pair(const EmArgs &a, bool act, int t, long long r0, long long r1,
-                                              dc (&z)[E])
+__device__ __forceinline__ void load_real_pair(const float2 *half, const float2 *nyq, bool act, int t, long long r0,
+                                               long long r1, dc (&z)[E])
 {
     constexpr int TPL = N / E;
-    const float2 *h0 = a.half + r0 * (N / 2), *h1 = a.half + r1 * (N / 2);
+    const float2 *h0 = half + r0 * (N / 2), *h1 = half + r1 * (N / 2);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         dc x0 = mk(0.0, 0.0), x1 = mk(0.0, 0.0);
@@ -179,8 +208,8 @@ __device__ __forceinline__ void load_phi_pair(const EmArgs &a, bool act, int t, 
                 x1 = from_f2(h1[k]);
                 if (k == 0) { x0.y = 0.0; x1.y = 0.0; }
             } else if (e == E / 2 && t == 0) {
-                x0 = mk((double)a.nyq[r0].x, 0.0);
-                x1 = mk((double)a.nyq[r1].x, 0.0);
+                x0 = mk((double)nyq[r0].x, 0.0);
+                x1 = mk((double)nyq[r1].x, 0.0);
             } else {
                 const int kk = N - (t + TPL * e);
                 x0 = conj(from_f2(h0[kk]));
@@ -189,6 +218,13 @@ __device__ __forceinline__ void load_phi_pair(const EmArgs &a, bool act, int t, 
         }
         z[e] = mk(x0.x - x1.y, x0.y + x1.x);
     }
+}
+
+template <int N, int E>
+__device__ __forceinline__ void load_phi_pair(const EmArgs &a, bool act, int t, long long r0, long long r1,
+                                              dc (&z)[E])
+{
+    load_real_pair<N, E>(a.half, a.nyq, act, t, r0, r1, z);
 }
 
 // Potential readout: phi rows (without the uniform k = 0 part) as float.
@@ -355,8 +391,116 @@ __device__ __forceinline__ void phase_tile(const EmArgs &a, int tile, float2 *ld
         const double b0 = block_sum<NT>(acc0, sh);
         const double b1 = block_sum<NT>(acc1, sh);
         if (tid == 0) {
-            a.partials[2 * tile] = b0;
-            a.partials[2 * tile + 1] = b1;
+            a.partials[4 * tile] = b0;
+            a.partials[4 * tile + 1] = b1;
+            a.partials[4 * tile + 2] = 0.0;
+            a.partials[4 * tile + 3] = 0.0;
+        }
+    }
+}
+
+// Local terms of Eq. (15) at one point: U = g rho + pressure + Bohm (see EmArgs).
+__device__ __forceinline__ double local_potential(const EmArgs &a, double rho, double lap)
+{
+    double U = a.g * rho;
+    if (a.pmode) {
+        const double lr = log(fmax(rho, a.rfl));
+        U = fma(a.cp, a.pmode == 1 ? lr : a.pfac * exp(a.pn1 * lr), U);
+    }
+    if (a.bohm) U = fma(a.cb2, lap / fmax(sqrt(rho), a.sfl), U);
+    return U;
+}
+
+// Antiderivative G of the floored pressure potential f(max(rho, floor)):
+// F(rho) above the floor (F = rho ln rho - rho, or rho^n / (n-1)), and
+// F(floor) + (rho - floor) f(floor) below it.
+__device__ __forceinline__ double pressure_energy_density(const EmArgs &a, double rho)
+{
+    if (rho < a.rfl) return fma(rho - a.rfl, a.f_fl, a.F_fl);
+    const double lr = log(rho);
+    return a.pmode == 1 ? rho * (lr - 1.0) : a.pfac / (a.pn1 + 1.0) * rho * exp(a.pn1 * lr);
+}
+
+// (fft() ends with a barrier after its last LDS read, so transforms follow
+// each other without one; a split that reads LDS needs one before the next.)
+//
+// Phase pass with the local terms of Eq. (15): as phase_tile, plus (a.bohm)
+// lap(s) of both rows from the half2 spectrum, and the local potential U of
+// local_potential in place of g rho.  ENERGY: per tile the sums of rho phi,
+// rho^2, G(rho) (pressure) and s lap(s) (Bohm).
+template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
+__device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, float2 *lds, double *sh)
+{
+    constexpr int TPL = N / E, NT = LINES * TPL;
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    const int pair = tile * LINES + l;
+    const bool act = pair < a.nlines;
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
+    const long long r0 = 2LL * pair, r1 = r0 + 1;
+    const double inv_n = 1.0 / N;
+    dc z[E];
+    load_real_pair<N, E>(a.half, a.nyq, act, t, r0, r1, z);
+    fft<N, E, 1>(z, t, lay, lds, a.tw);
+    float phi0[E], phi1[E], lap0[E], lap1[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        phi0[e] = (float)(z[e].x * inv_n);
+        phi1[e] = (float)(z[e].y * inv_n);
+        lap0[e] = 0.0f;
+        lap1[e] = 0.0f;
+    }
+    if (a.bohm) {   // uniform over the grid
+        load_real_pair<N, E>(a.half2, a.nyq2, act, t, r0, r1, z);
+        fft<N, E, 1>(z, t, lay, lds, a.tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            lap0[e] = (float)(z[e].x * inv_n);
+            lap1[e] = (float)(z[e].y * inv_n);
+        }
+    }
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        float2 *p = a.psi + (half ? r1 : r0) * N;
+        dc v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+        if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const dc ps = REAL_IN ? v[e] : scl(v[e], inv_n);
+            const double rho = norm2(ps);
+            const double phi = (double)(half ? phi1[e] : phi0[e]);
+            const double lap = (double)(half ? lap1[e] : lap0[e]);
+            if constexpr (ENERGY) {
+                acc0 += rho * phi;
+                acc1 += rho * rho;
+                if (a.pmode) acc2 += pressure_energy_density(a, rho);
+                acc3 += sqrt(rho) * lap;
+            } else {
+                double sn, cs;
+                sincos_fp64((local_potential(a, rho, lap) + phi) * a.dz, &sn, &cs);
+                v[e] = cmul(ps, mk(cs, sn));
+            }
+        }
+        if constexpr (!ENERGY) {
+            fft<N, E, -1>(v, t, lay, lds, a.tw);
+            if (act) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) p[t + TPL * e] = to_f2(v[e]);
+            }
+        }
+    }
+    if constexpr (ENERGY) {
+        const double b0 = block_sum<NT>(acc0, sh);
+        const double b1 = block_sum<NT>(acc1, sh);
+        const double b2 = block_sum<NT>(acc2, sh);
+        const double b3 = block_sum<NT>(acc3, sh);
+        if (tid == 0) {
+            a.partials[4 * tile] = b0;
+            a.partials[4 * tile + 1] = b1;
+            a.partials[4 * tile + 2] = b2;
+            a.partials[4 * tile + 3] = b3;
         }
     }
 }
@@ -373,7 +517,7 @@ struct Seg {
     int c1f, c1l, c1o, c2f, c2l, c2o;
 };
 
-enum LmMode { LM_FWD = 0, LM_INV = 1, LM_KIN = 2, LM_KERN = 3, LM_KIN_ENERGY = 4 };
+enum LmMode { LM_FWD = 0, LM_INV = 1, LM_KIN = 2, LM_KERN = 3, LM_KIN_ENERGY = 4, LM_LAP = 5 };
 
 struct LmArgs {
     Seg s0, s1;              // s1 used for tiles >= s0.ntiles (ntiles 0 if absent)
@@ -440,6 +584,11 @@ __device__ __forceinline__ void lm_tile(const LmArgs &a, int tile_in, float2 *ld
                 const double K = k2 > 0.0 ? fma(num, r, a.c0) : 0.0;
                 v[e] = scl(v[e], K * a.scale);
             }
+        } else if constexpr (MODE == LM_LAP) {
+            // the Laplacian: -|k|^2 (Bohm potential)
+            const double q12 = a.k2_1[c1] + a.k2_2[c2];
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = scl(v[e], -(q12 + a.k2_p[t + TPL * e]) * a.scale);
         } else if constexpr (MODE == LM_KIN_ENERGY) {
             const double q12 = a.k2_1[c1] + a.k2_2[c2];
             double acc = 0.0;
@@ -983,12 +1132,19 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_em_fft(EmArgs a)
     __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
     em_fft_tile<N, E, LINES, S>(a, blockIdx.x, lds);
 }
-template <int N, int E, int LINES, bool STORE_PSI>
+template <int N, int E, int LINES, bool STORE_PSI, bool BOHM = false>
 __global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
 {
     __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
-    density_tile<N, E, LINES, STORE_PSI>(a, blockIdx.x, lds, sh);
+    density_tile<N, E, LINES, STORE_PSI, false, BOHM>(a, blockIdx.x, lds, sh);
+}
+template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
+__global__ __launch_bounds__(LINES *(N / E)) void k_phase_local(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
+    phase_local_tile<N, E, LINES, ENERGY, REAL_IN>(a, blockIdx.x, lds, sh);
 }
 template <int N, int E, int LINES>
 __global__ __launch_bounds__(LINES *(N / E)) void k_density_real(EmArgs a)

@@ -43,6 +43,7 @@ _SIGNATURES = {
     "gsn_destroy": [vp],
     "gsn_set_kernel": [vp, ctypes.POINTER(gsn_kernel)],
     "gsn_set_coefficients": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "gsn_set_local_terms": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "gsn_set_psi": [vp, vp, ctypes.c_int, ctypes.c_int],
     "gsn_step": [vp, ctypes.c_int64],
     "gsn_sync": [vp],
@@ -211,6 +212,10 @@ class Grid:
 
     def set_coefficients(self, a, g, dz):
         check(load().gsn_set_coefficients(self.h, a, g, dz))
+
+    def set_local_terms(self, c_pressure=0.0, n_pressure=1.0, c_bohm=0.0, rho_floor=0.0):
+        """Pressure and Bohm terms of Eq. (15) (all zero: the Kerr model)."""
+        check(load().gsn_set_local_terms(self.h, c_pressure, n_pressure, c_bohm, rho_floor))
 
     def set_psi(self, psi):
         ptr, dev, code, keep = _ptr_and_flag(psi)

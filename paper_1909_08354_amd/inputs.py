@@ -98,6 +98,13 @@ WORKLOADS = {
         n=(512, 512, 512), L=(512.0, 512.0, 512.0), kern=(1.0, 0.3, 0.1, 0.0), a=0.5,
         g=0.0, dz=2.5e-4, steps=2000, seed=4,
         ic="8 lumps, centres U[0,512)^3, w U[4,10], v U[-0.5,0.5]^3"),
+    # Eq. (15) fluid: a Gaussian number density of total mass M0 (Sec. IV:
+    # M0 = 25, nu = 1, w = 1.02, n = 1), so a = nu/2, c_bohm = -nu,
+    # c_pressure = -w/nu and c_newton = gamma/nu with gamma = 1/2 (GR)
+    "gsn3d_256_eq15": dict(
+        n=(256, 256, 256), L=(256.0, 256.0, 256.0), kern=(0.5, 0.0, 0.0, 0.0), a=0.5,
+        g=0.0, local=(-1.02, 1.0, -1.0, 1e-10), dz=5e-4, steps=200, seed=5, mass=25.0,
+        waist=6.0, ic="Gaussian number density, total mass 25, waist 6, phase noise 1e-3"),
     "gsn2d_512_corrector": dict(
         n=(512, 512), L=(512.0, 512.0), kern=(1.0, 0.0, 0.0, 0.0), a=0.5, g=-0.5,
         dz_fine=5e-3, ratio=8, train_seeds=(10000, 12000), heldout_seeds=(20000, 20100),
@@ -110,6 +117,15 @@ def gaussian_2d_128(seed=None):
     w = WORKLOADS["gsn2d_128_kerr_newton"]
     psi = gaussian(w["n"], w["L"], 3.0)
     return phase_noise(psi, 1e-3, w["seed"] if seed is None else seed)
+
+
+def fluid_gaussian(n, L, mass, waist, noise=1e-3, seed=5):
+    """psi = sqrt(rho) for a Gaussian number density rho = rho0 exp(-|x|^2/w^2)
+    of total mass ``mass`` (rho0 = mass / (pi w^2)^(D/2)), times a phase noise
+    of size ``noise``."""
+    rho0 = mass / (np.pi * waist * waist) ** (len(n) / 2)
+    psi = gaussian(n, L, np.sqrt(2.0) * waist, amplitude=np.sqrt(rho0))
+    return phase_noise(psi, noise, seed) if noise else psi
 
 
 def gaussian_3d_256(n=None):

@@ -1,0 +1,198 @@
+"""GPU parity of the local terms of Eq. (15) -- the polytropic pressure
+potential and the Bohm potential -- against the FP64 oracle, through the C ABI.
+
+The tolerance argument is the Kerr model's: psi, rho, phi and lap(sqrt rho) are
+stored as complex64/float, every operation runs in FP64, so each pass adds one
+FP32 rounding and the relative L2 error stays near 1e-7 * sqrt(passes).  The
+Bohm term divides lap(sqrt rho) by sqrt(rho); its storage error is amplified
+where the density is small, but it enters psi multiplied by |psi| = sqrt(rho),
+so the error it adds to psi stays of the order of the stored spectrum's own.
+Bar: relative L2 <= 1e-5 against the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1909_08354_amd import gsn, inputs
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+
+# (kern, g, local = (c_pressure, n_pressure, c_bohm, rho_floor))
+CASES = {
+    "pressure_log": ((0.5, 0.0, 0.0, 0.0), 0.0, (-1.02, 1.0, 0.0, 1e-10)),
+    "pressure_pow": ((0.5, 0.3, 0.2, 0.0), 0.0, (0.3, 2.5, 0.0, 0.0)),
+    "pressure_neg": ((0.5, 0.0, 0.0, 0.0), -0.2, (-0.02, -1.0, 0.0, 1e-2)),
+    "bohm": ((0.5, 0.0, 0.0, 0.0), 0.0, (0.0, 1.0, -1.0, 1e-10)),
+    "eq15": ((0.5, 0.3, 0.2, 0.0), -0.2, (-1.02, 1.0, -1.0, 1e-10)),
+}
+
+SHAPES = {
+    "2d": ((64, 128), (32.0, 64.0), 4.0),
+    "3d": ((32, 32, 64), (32.0, 32.0, 64.0), 4.0),
+}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fluid(shape_key, seed=5):
+    n, L, w = SHAPES[shape_key]
+    return inputs.fluid_gaussian(n, L, 25.0, w, noise=1e-3, seed=seed), n, L
+
+
+def make_grid(n, L, kern, g, local, dz, schedule=None, mode=0):
+    grid = gsn.Grid(n, L)
+    grid.set_kernel(*kern)
+    grid.set_coefficients(0.5, g, dz)
+    grid.set_local_terms(*local)
+    if schedule is not None:
+        grid.set_schedule(schedule)
+    grid.set_nonlinear_mode(mode)
+    return grid
+
+
+@pytest.mark.parametrize("shape", ["2d", "3d"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_local_terms_match_oracle(shape, case):
+    kern, g, local = CASES[case]
+    psi0, n, L = fluid(shape)
+    dz, steps = 1e-3, 20
+    say("eq15", case, shape, n)
+    ref = orc.evolve(inputs.as_oracle_input(psi0), L, kern, 0.5, g, dz, steps, local=local)
+    grid = make_grid(n, L, kern, g, local, dz)
+    grid.set_psi(inputs.to_c64(psi0))
+    grid.step(7)
+    grid.step(13)
+    err = orc.rel_l2(grid.get_psi(), ref)
+    say(f"  rel_l2 {err:.3e}")
+    assert err < REL_L2
+    # the state really moved under these terms
+    assert orc.rel_l2(ref, inputs.as_oracle_input(psi0)) > 1e-4
+
+
+@pytest.mark.parametrize("schedule,mode", [(1, 0), (4, 0), (2, 0), (3, 1), (0, 1), (4, 1)])
+@pytest.mark.parametrize("shape", ["2d", "3d"])
+def test_local_terms_all_schedules(shape, schedule, mode):
+    """Every schedule variant and both nonlinear modes (stored real-space psi
+    or not) with all terms on."""
+    kern, g, local = CASES["eq15"]
+    psi0, n, L = fluid(shape, seed=8)
+    dz, steps = 1e-3, 12
+    say("eq15 schedule", schedule, "mode", mode, shape)
+    ref = orc.evolve(inputs.as_oracle_input(psi0), L, kern, 0.5, g, dz, steps, local=local)
+    grid = make_grid(n, L, kern, g, local, dz, schedule, mode)
+    grid.set_psi(inputs.to_c64(psi0))
+    grid.step(steps)
+    assert orc.rel_l2(grid.get_psi(), ref) < REL_L2
+
+
+def test_zero_local_terms_are_the_kerr_kernels_bit_for_bit():
+    kern, g = (0.5, 0.3, 0.2, 0.0), -0.3
+    psi0, n, L = fluid("3d", seed=9)
+    outs = []
+    for local in (None, (0.0, 1.0, 0.0, 0.0)):
+        grid = gsn.Grid(n, L)
+        grid.set_kernel(*kern)
+        grid.set_coefficients(0.5, g, 1e-3)
+        if local is not None:
+            grid.set_local_terms(0.4, 1.0, -0.5, 1e-8)   # on, then back off
+            grid.set_local_terms(*local)
+        grid.set_psi(inputs.to_c64(psi0))
+        grid.step(9)
+        outs.append(grid.get_psi(np.complex64))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_pressure_n2_equals_kerr_on_gpu():
+    """f_2(rho) = 2 rho: the general phase pass with n = 2 reproduces the Kerr
+    pass with g = 2 c_p up to the rounding of exp(log rho)."""
+    kern = (0.5, 0.0, 0.0, 0.0)
+    psi0, n, L = fluid("2d", seed=10)
+    cp = -0.3
+    a = make_grid(n, L, kern, 0.0, (cp, 2.0, 0.0, 0.0), 1e-3)
+    b = make_grid(n, L, kern, 2 * cp, (0.0, 1.0, 0.0, 0.0), 1e-3)
+    for grid in (a, b):
+        grid.set_psi(inputs.to_c64(psi0))
+        grid.step(15)
+    assert orc.rel_l2(a.get_psi(), b.get_psi()) < 1e-9
+
+
+def test_bohm_term_keeps_a_fluid_at_rest_on_gpu():
+    """With c_bohm = -2a a real positive psi is a stationary state of Eq. (15)
+    with no other potential; the split-step drift is O(dz^2)."""
+    n, L, dz, steps = (64, 64), (40.0, 40.0), 0.02, 40
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    psi0 = 1.0 + 0.5 * np.exp(-(xs[0] ** 2 + xs[1] ** 2) / (2 * 2.5 ** 2))
+    local = (0.0, 1.0, -1.0, 1e-6)
+    grid = make_grid(n, L, (0, 0, 0, 0), 0.0, local, dz)
+    grid.set_psi(inputs.to_c64(psi0))
+    grid.step(steps)
+    out = grid.get_psi()
+    ref = orc.evolve(inputs.as_oracle_input(psi0), L, (0, 0, 0, 0), 0.5, 0.0, dz, steps, local=local)
+    free = orc.evolve(inputs.as_oracle_input(psi0), L, (0, 0, 0, 0), 0.5, 0.0, dz, steps)
+    moved = orc.rel_l2(out, psi0)
+    say(f"at rest: moved {moved:.3e}, without the Bohm term {orc.rel_l2(free, psi0):.3e}")
+    assert orc.rel_l2(out, ref) < REL_L2
+    assert moved < 1e-3 * orc.rel_l2(free, psi0)
+
+
+@pytest.mark.parametrize("shape", ["2d", "3d"])
+def test_energy_with_local_terms_matches_oracle(shape):
+    kern, g, local = CASES["eq15"]
+    psi0, n, L = fluid(shape, seed=11)
+    grid = make_grid(n, L, kern, g, local, 1e-3)
+    grid.set_psi(inputs.to_c64(psi0))
+    grid.step(10)
+    psi = grid.get_psi()
+    e = grid.energy()
+    eo = orc.observables(psi, L, kern, 0.5, g, local=local)
+    scale = abs(eo["kinetic"]) + abs(eo["local"]) + abs(eo["nonlocal"])
+    say(f"energy {shape}: gpu {e} oracle {eo}")
+    for k in ("total", "kinetic", "local", "nonlocal"):
+        assert abs(e[k] - eo[k]) < 1e-6 * scale, k
+    # the pressure and Bohm parts are a large share of the local energy here
+    assert abs(eo["pressure"]) + abs(eo["bohm"]) > 0.1 * abs(eo["local"])
+
+
+def test_set_local_terms_rejects_bad_arguments():
+    grid = gsn.Grid((16, 16), (8.0, 8.0))
+    for args in [(0.5, 0.5, 0.0, 1e-6), (0.5, 1.0, 0.0, 0.0), (0.0, 1.0, 0.5, 0.0),
+                 (0.5, 1.0, 0.0, -1.0), (float("nan"), 1.0, 0.0, 1e-6), (0.0, 1.0, float("inf"), 1e-6)]:
+        with pytest.raises(gsn.GsnError) as ei:
+            grid.set_local_terms(*args)
+        assert ei.value.status == gsn.GSN_EINVAL
+
+
+def test_eq15_256_full_size_matches_oracle():
+    """The 256^3 Eq. (15) fluid workload in the benchmark's launch
+    configuration (autotuned schedule with the local terms on): 4 steps against
+    the oracle on the whole grid, and mass conservation over 200 steps."""
+    import torch
+    w = inputs.WORKLOADS["gsn3d_256_eq15"]
+    psi0 = inputs.fluid_gaussian(w["n"], w["L"], w["mass"], w["waist"], seed=w["seed"])
+    dev0 = torch.from_numpy(inputs.to_c64(psi0)).cuda()
+    grid = gsn.Grid(w["n"], w["L"])
+    grid.set_kernel(*w["kern"])
+    grid.set_coefficients(w["a"], w["g"], w["dz"])
+    grid.set_local_terms(*w["local"])
+    grid.set_psi(dev0)
+    say("eq15 256^3 autotune:", grid.autotune(3))
+    grid.set_psi(dev0)
+    grid.step(4)
+    out = grid.get_psi(np.complex128)
+    say("eq15 256^3: oracle 4 steps")
+    ref = orc.evolve(inputs.as_oracle_input(psi0), w["L"], w["kern"], w["a"], w["g"], w["dz"], 4,
+                     local=w["local"])
+    err = orc.rel_l2(out, ref)
+    say(f"eq15 256^3: rel_l2 {err:.3e}")
+    assert err < REL_L2
+    m0 = grid.mass()
+    grid.step(w["steps"] - 4)
+    drift = abs(grid.mass() / m0 - 1)
+    say(f"eq15 256^3: norm drift over {w['steps']} steps {drift:.3e}")
+    assert drift < 1e-6
