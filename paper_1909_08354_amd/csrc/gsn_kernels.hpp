@@ -325,6 +325,70 @@ __host__ __device__ __forceinline__ void sincos_tab(double th, const double2 *ta
     *c = fma(cs.x, cr, -(cs.y * sr));
 }
 
+// Natural logarithm in FP64 for finite x > 0: x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), f = m - 1, u = f / (2 + f) (|u| <= 0.1716) and
+// ln m = 2 atanh(u) = 2 (u + u^3/3 + ... + u^21/21) (the remainder is below
+// 2e-18 relative), plus e ln 2 with ln 2 split into a 32-bit head (so e times
+// it is exact) and its tail.
+__host__ __device__ __forceinline__ double log_fp64(double x)
+{
+    constexpr double kLn2Hi = 0.6931471806019545;
+    constexpr double kLn2Lo = -4.2009150726810846e-11;
+    int e;
+    double m = frexp(x, &e);   // m in [1/2, 1)
+    if (m < 0.70710678118654752) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double f = m - 1.0;
+    const double u = f / (2.0 + f);
+    const double z = u * u;
+    double p = 1.0 / 21.0;
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double lm = fma(2.0 * u * z, p, 2.0 * u);
+    const double ed = (double)e;
+    return fma(ed, kLn2Hi, fma(ed, kLn2Lo, lm));
+}
+
+// e^y in FP64: y = k ln 2 + r with |r| <= ln(2)/2 (the same two-part ln 2),
+// e^r from its Taylor series to r^14 (remainder below 5e-18 relative), scaled
+// by 2^k.  Arguments are clamped to [-746, 709.7]: 0 below, finite above.
+__host__ __device__ __forceinline__ double exp_fp64(double y)
+{
+    constexpr double kLog2E = 1.4426950408889634;
+    constexpr double kLn2Hi = 0.6931471806019545;
+    constexpr double kLn2Lo = -4.2009150726810846e-11;
+    y = fmin(fmax(y, -746.0), 709.7);
+    const double k = rint(y * kLog2E);
+    double r = fma(-k, kLn2Hi, y);
+    r = fma(-k, kLn2Lo, r);
+    // sum r^j / j!, j = 0..14, by Horner
+    double p = 1.0 / 87178291200.0;         // 1/14!
+    p = fma(p, r, 1.0 / 6227020800.0);      // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);       // 1/12!
+    p = fma(p, r, 1.0 / 39916800.0);        // 1/11!
+    p = fma(p, r, 1.0 / 3628800.0);         // 1/10!
+    p = fma(p, r, 1.0 / 362880.0);          // 1/9!
+    p = fma(p, r, 1.0 / 40320.0);           // 1/8!
+    p = fma(p, r, 1.0 / 5040.0);            // 1/7!
+    p = fma(p, r, 1.0 / 720.0);             // 1/6!
+    p = fma(p, r, 1.0 / 120.0);             // 1/5!
+    p = fma(p, r, 1.0 / 24.0);              // 1/4!
+    p = fma(p, r, 1.0 / 6.0);               // 1/3!
+    p = fma(p, r, 0.5);                     // 1/2!
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)k);
+}
+
 // The table sincos_tab reads, computed in extended precision and rounded.
 inline void fill_sincos_table(double2 *tab)
 {
@@ -399,16 +463,38 @@ __device__ __forceinline__ void phase_tile(const EmArgs &a, int tile, float2 *ld
     }
 }
 
-// Local terms of Eq. (15) at one point: U = g rho + pressure + Bohm (see EmArgs).
-__device__ __forceinline__ double local_potential(const EmArgs &a, double rho, double lap)
+// 1/sqrt(x) in FP64 for x > 0: the hardware estimate refined by two Newton
+// steps y <- y + y (1 - x y^2) / 2.
+__device__ __forceinline__ double rsqrt_fp64(double x)
 {
-    double U = a.g * rho;
-    if (a.pmode) {
-        const double lr = log(fmax(rho, a.rfl));
-        U = fma(a.cp, a.pmode == 1 ? lr : a.pfac * exp(a.pn1 * lr), U);
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return y;
+}
+
+// Local terms of Eq. (15) for the E points of one row: U = g rho + pressure +
+// Bohm (see EmArgs); pmode and bohm are uniform, so each term is one branch
+// around its loop.  1 / max(sqrt rho, sqrt floor) = 1 / sqrt(max(rho, floor)).
+// The power law's floor is at least 1e-300 so that its logarithm is finite.
+template <int E>
+__device__ __forceinline__ void local_potential(const EmArgs &a, const double (&rho)[E], const float (&lap)[E],
+                                                double (&U)[E])
+{
+#pragma unroll
+    for (int e = 0; e < E; ++e) U[e] = a.g * rho[e];
+    if (a.pmode == 1) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) U[e] = fma(a.cp, log_fp64(fmax(rho[e], a.rfl)), U[e]);
+    } else if (a.pmode == 2) {
+        const double fl = fmax(a.rfl, 1e-300), cpf = a.cp * a.pfac;
+#pragma unroll
+        for (int e = 0; e < E; ++e) U[e] = fma(cpf, exp_fp64(a.pn1 * log_fp64(fmax(rho[e], fl))), U[e]);
     }
-    if (a.bohm) U = fma(a.cb2, lap / fmax(sqrt(rho), a.sfl), U);
-    return U;
+    if (a.bohm) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) U[e] = fma(a.cb2 * (double)lap[e], rsqrt_fp64(fmax(rho[e], a.rfl)), U[e]);
+    }
 }
 
 // Antiderivative G of the floored pressure potential f(max(rho, floor)):
@@ -416,9 +502,9 @@ __device__ __forceinline__ double local_potential(const EmArgs &a, double rho, d
 // F(floor) + (rho - floor) f(floor) below it.
 __device__ __forceinline__ double pressure_energy_density(const EmArgs &a, double rho)
 {
-    if (rho < a.rfl) return fma(rho - a.rfl, a.f_fl, a.F_fl);
-    const double lr = log(rho);
-    return a.pmode == 1 ? rho * (lr - 1.0) : a.pfac / (a.pn1 + 1.0) * rho * exp(a.pn1 * lr);
+    if (rho < a.rfl || rho <= 0.0) return fma(rho - a.rfl, a.f_fl, a.F_fl);
+    const double lr = log_fp64(rho);
+    return a.pmode == 1 ? rho * (lr - 1.0) : a.pfac / (a.pn1 + 1.0) * rho * exp_fp64(a.pn1 * lr);
 }
 
 // (fft() ends with a barrier after its last LDS read, so transforms follow
@@ -466,21 +552,31 @@ __device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, floa
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
         if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
+        double rho[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const dc ps = REAL_IN ? v[e] : scl(v[e], inv_n);
-            const double rho = norm2(ps);
-            const double phi = (double)(half ? phi1[e] : phi0[e]);
-            const double lap = (double)(half ? lap1[e] : lap0[e]);
-            if constexpr (ENERGY) {
-                acc0 += rho * phi;
-                acc1 += rho * rho;
-                if (a.pmode) acc2 += pressure_energy_density(a, rho);
-                acc3 += sqrt(rho) * lap;
-            } else {
+            if constexpr (!REAL_IN) v[e] = scl(v[e], inv_n);
+            rho[e] = norm2(v[e]);
+        }
+        if constexpr (ENERGY) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                acc0 += rho[e] * (double)(half ? phi1[e] : phi0[e]);
+                acc1 += rho[e] * rho[e];
+                if (a.pmode) acc2 += pressure_energy_density(a, rho[e]);
+                acc3 += sqrt(rho[e]) * (double)(half ? lap1[e] : lap0[e]);
+            }
+        } else {
+            double U[E];
+            float lap[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) lap[e] = half ? lap1[e] : lap0[e];
+            local_potential<E>(a, rho, lap, U);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
                 double sn, cs;
-                sincos_fp64((local_potential(a, rho, lap) + phi) * a.dz, &sn, &cs);
-                v[e] = cmul(ps, mk(cs, sn));
+                sincos_tab((U[e] + (double)(half ? phi1[e] : phi0[e])) * a.dz, a.sct, &sn, &cs);
+                v[e] = cmul(v[e], mk(cs, sn));
             }
         }
         if constexpr (!ENERGY) {

@@ -51,3 +51,33 @@ def test_persistent_queue_decode_and_progress(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout[-2000:]
     assert "failures 0" in r.stdout
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
+def test_log_and_exp_fp64_match_libm(tmp_path):
+    """The phase pass's own FP64 ln and exp (series after a 2^e / ln 2
+    reduction) against libm, over the dynamic range the pressure term meets."""
+    exe = tmp_path / "host_logexp"
+    subprocess.run([HIPCC, "-O2", "-std=c++17", "--offload-arch=gfx950",
+                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                    "-I" + os.path.join(ROOT, "paper_1909_08354_amd", "csrc"),
+                    "-o", str(exe), os.path.join(HERE, "host_logexp.hip")],
+                   check=True, capture_output=True)
+    rng = np.random.default_rng(4)
+    xl = np.concatenate([10.0 ** rng.uniform(-300, 300, 3000), rng.uniform(0.5, 2.0, 3000),
+                         [1.0, 2.0, 0.5, math.sqrt(0.5), math.sqrt(2.0), 1e-300, 5e-324, 1.7e308]])
+    out = subprocess.run([str(exe)], input="\n".join(repr(float(t)) for t in xl),
+                         capture_output=True, text=True, check=True).stdout.split("\n")
+    le = np.array([[float(v) for v in line.split()] for line in out if line.strip()])
+    ref = np.log(xl)
+    assert np.max(np.abs(le[:, 0] - ref) / np.maximum(1.0, np.abs(ref))) < 4e-16
+    assert le[list(xl).index(1.0), 0] == 0.0
+    xe = np.concatenate([rng.uniform(-700, 700, 3000), rng.uniform(-1, 1, 3000), [0.0, 1.0, -1.0, 709.0, -745.0]])
+    out = subprocess.run([str(exe)], input="\n".join(repr(float(t)) for t in xe),
+                         capture_output=True, text=True, check=True).stdout.split("\n")
+    ee = np.array([[float(v) for v in line.split()] for line in out if line.strip()])[:, 1]
+    refe = np.exp(xe)
+    ok = refe > 1e-300
+    assert np.max(np.abs(ee[ok] - refe[ok]) / refe[ok]) < 6e-16
+    assert ee[list(xe).index(0.0)] == 1.0
+    assert np.all(ee[~ok] < 1e-300)
