@@ -125,6 +125,51 @@ static double kernel_value(double k2, const double *kp)
     return K;
 }
 
+/*
+ * The multiplier K(k) of phi_hat = K rho_hat, from either the kernel family
+ * (kp) or Eq. (1)-(2) with their own constants: lap phi + C phi = D rho gives
+ * phi_hat = D rho_hat / (C - |k|^2), and Eq. (1)'s term B phi enters the phase
+ * with the opposite sign of this file's phi, so K = B D / (|k|^2 - C).  With
+ * C = 0 the k = 0 mode of the Poisson problem is dropped; with C > 0 (a
+ * Helmholtz operator) a grid wavenumber with |k|^2 = C has no solution and is
+ * rejected.
+ */
+typedef struct {
+    int eq;              /* 0: kp; 1: (B, C, D) */
+    const double *kp;
+    double B, C, D;
+} kspec_t;
+
+static int kspec_check(const kspec_t *ks)
+{
+    if (!ks->eq) return ks->kp && !(ks->kp[1] != 0.0 && !(ks->kp[2] > 0.0)) ? ORC_OK : ORC_EINVAL;
+    return isfinite(ks->B) && isfinite(ks->C) && isfinite(ks->D) ? ORC_OK : ORC_EINVAL;
+}
+
+static int kspec_value(const kspec_t *ks, double k2, double *K)
+{
+    if (!ks->eq) {
+        *K = kernel_value(k2, ks->kp);
+        return ORC_OK;
+    }
+    if (ks->C == 0.0 && k2 == 0.0) {
+        *K = 0.0;
+        return ORC_OK;
+    }
+    double den = k2 - ks->C;
+    if (fabs(den) <= 1e-12 * fmax(1.0, fabs(ks->C))) return ORC_EINVAL;
+    *K = ks->B * ks->D / den;
+    return ORC_OK;
+}
+
+static int kspec_table(double *Kk, const kspec_t *ks, const grid_t *g)
+{
+    int bad = 0;
+    for (long long q = 0; q < g->P; q++)
+        if (kspec_value(ks, k_squared(g, q), &Kk[q])) bad = 1;
+    return bad ? ORC_EINVAL : ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* 1-D radix-2 FFT                                                          */
 /* ------------------------------------------------------------------------ */
@@ -354,18 +399,16 @@ static int potential_into(cx *tmp, const double *rho, const double *Kk,
     return fft_nd(tmp, g, +1, nt);
 }
 
-int orc_potential(const double *rho, double *phi, int ndim, const int *n,
-                  const double *L, const double *kp, int nthreads)
+static int potential_spec(const double *rho, double *phi, int ndim, const int *n,
+                          const double *L, const kspec_t *ks, int nthreads)
 {
     grid_t g;
-    if (!rho || !phi || !kp || grid_init(&g, ndim, n, L)) return ORC_EINVAL;
-    if (kp[1] != 0.0 && !(kp[2] > 0.0)) return ORC_EINVAL;
+    if (!rho || !phi || grid_init(&g, ndim, n, L) || kspec_check(ks)) return ORC_EINVAL;
     int nt = nthreads_or_default(nthreads);
     cx *tmp = (cx *)malloc(sizeof(cx) * (size_t)g.P);
     double *Kk = (double *)malloc(sizeof(double) * (size_t)g.P);
     int e = ORC_ENOMEM;
-    if (tmp && Kk) {
-        for (long long q = 0; q < g.P; q++) Kk[q] = kernel_value(k_squared(&g, q), kp);
+    if (tmp && Kk && !(e = kspec_table(Kk, ks, &g))) {
         e = potential_into(tmp, rho, Kk, &g, nt);
         if (!e)
             for (long long q = 0; q < g.P; q++) phi[q] = creal(tmp[q]);
@@ -373,6 +416,21 @@ int orc_potential(const double *rho, double *phi, int ndim, const int *n,
     free(tmp);
     free(Kk);
     return e;
+}
+
+int orc_potential(const double *rho, double *phi, int ndim, const int *n,
+                  const double *L, const double *kp, int nthreads)
+{
+    kspec_t ks = {0, kp, 0.0, 0.0, 0.0};
+    return potential_spec(rho, phi, ndim, n, L, &ks, nthreads);
+}
+
+/* phi of Eq. (2) with Eq. (1)'s coupling: Re IDFT[B D / (|k|^2 - C) DFT rho] */
+int orc_potential_equation(const double *rho, double *phi, int ndim, const int *n,
+                           const double *L, double B, double C, double D, int nthreads)
+{
+    kspec_t ks = {1, NULL, B, C, D};
+    return potential_spec(rho, phi, ndim, n, L, &ks, nthreads);
 }
 
 /* kinetic sub-step L(h) with a precomputed propagator table prop[q] */
@@ -414,15 +472,14 @@ static int nonlinear_step(cx *psi, cx *tmp, double *rho, double *U, const double
  *               same product of operators (L(h1) L(h2) = L(h1 + h2) exactly).
  * Returns 0 on success.
  */
-int orc_evolve_local(double *psi_io, int ndim, const int *n, const double *L,
-                     const double *kp, double a, double gloc, const double *lp, double dz,
-                     long long nsteps, int merged, int nthreads)
+static int evolve_spec(double *psi_io, int ndim, const int *n, const double *L,
+                       const kspec_t *ks, double a, double gloc, const double *lp, double dz,
+                       long long nsteps, int merged, int nthreads)
 {
     grid_t g;
     local_t lt;
-    if (!psi_io || !kp || grid_init(&g, ndim, n, L) || nsteps < 0) return ORC_EINVAL;
-    if (local_init(&lt, lp)) return ORC_EINVAL;
-    if (kp[1] != 0.0 && !(kp[2] > 0.0)) return ORC_EINVAL;
+    if (!psi_io || grid_init(&g, ndim, n, L) || nsteps < 0) return ORC_EINVAL;
+    if (local_init(&lt, lp) || kspec_check(ks)) return ORC_EINVAL;
     if (!isfinite(dz) || !isfinite(a) || !isfinite(gloc)) return ORC_EINVAL;
     if (nsteps == 0) return ORC_OK;
     int nt = nthreads_or_default(nthreads);
@@ -436,13 +493,13 @@ int orc_evolve_local(double *psi_io, int ndim, const int *n, const double *L,
     double *U = (double *)malloc(sizeof(double) * P);
     int e = ORC_ENOMEM;
     if (!half || !full || !tmp || !Kk || !rho || !U) goto done;
+    if ((e = kspec_table(Kk, ks, &g))) goto done;
 #pragma omp parallel for num_threads(nt) schedule(static)
     for (long long q = 0; q < g.P; q++) {
         double k2 = k_squared(&g, q);
         double th_h = -a * k2 * dz * 0.5, th_f = -a * k2 * dz;
         half[q] = cos(th_h) + sin(th_h) * I;
         full[q] = cos(th_f) + sin(th_f) * I;
-        Kk[q] = kernel_value(k2, kp);
     }
     if (!merged) {
         for (long long s = 0; s < nsteps; s++) {
@@ -466,6 +523,27 @@ done:
     free(rho);
     free(U);
     return e;
+}
+
+int orc_evolve_local(double *psi_io, int ndim, const int *n, const double *L,
+                     const double *kp, double a, double gloc, const double *lp, double dz,
+                     long long nsteps, int merged, int nthreads)
+{
+    kspec_t ks = {0, kp, 0.0, 0.0, 0.0};
+    return evolve_spec(psi_io, ndim, n, L, &ks, a, gloc, lp, dz, nsteps, merged, nthreads);
+}
+
+/*
+ * Eq. (1)-(2) with their own constants: i psi_t = A lap psi + B phi psi
+ * + G psi, lap phi + C phi = D rho, with G = -(g rho + local terms), i.e.
+ * a = -A and K = B D / (|k|^2 - C) in this file's form.
+ */
+int orc_evolve_equation(double *psi_io, int ndim, const int *n, const double *L,
+                        double A, double B, double C, double D, double gloc, const double *lp,
+                        double dz, long long nsteps, int merged, int nthreads)
+{
+    kspec_t ks = {1, NULL, B, C, D};
+    return evolve_spec(psi_io, ndim, n, L, &ks, -A, gloc, lp, dz, nsteps, merged, nthreads);
 }
 
 /* orc_evolve_local with the Kerr term only */
@@ -513,15 +591,14 @@ int orc_local_potential(const double *psi_in, int ndim, const int *n, const doub
  * where rho >= rho_f, since the variation of sum |grad s|^2 with respect to rho
  * is -lap(s)/s).  lp == NULL: E_p = E_B = 0.
  */
-int orc_observables_local(const double *psi_in, int ndim, const int *n, const double *L,
-                          const double *kp, double a, double gloc, const double *lp,
-                          double *out, int nthreads)
+static int observables_spec(const double *psi_in, int ndim, const int *n, const double *L,
+                            const kspec_t *ks, double a, double gloc, const double *lp,
+                            double *out, int nthreads)
 {
     grid_t g;
     local_t lt;
-    if (!psi_in || !kp || !out || grid_init(&g, ndim, n, L)) return ORC_EINVAL;
-    if (local_init(&lt, lp)) return ORC_EINVAL;
-    if (kp[1] != 0.0 && !(kp[2] > 0.0)) return ORC_EINVAL;
+    if (!psi_in || !out || grid_init(&g, ndim, n, L)) return ORC_EINVAL;
+    if (local_init(&lt, lp) || kspec_check(ks)) return ORC_EINVAL;
     int nt = nthreads_or_default(nthreads);
     const cx *psi = (const cx *)psi_in;
     size_t P = (size_t)g.P;
@@ -534,13 +611,13 @@ int orc_observables_local(const double *psi_in, int ndim, const int *n, const do
     int e = ORC_ENOMEM;
     if (!tmp || !Kk || !rho) goto done;
     double mass = 0.0, ekin = 0.0, eloc = 0.0, enl = 0.0;
+    if ((e = kspec_table(Kk, ks, &g))) goto done;
     for (long long q = 0; q < g.P; q++) {
         double re = creal(psi[q]), im = cimag(psi[q]);
         rho[q] = re * re + im * im;
         mass += rho[q];
         eloc += rho[q] * rho[q];
         tmp[q] = psi[q];
-        Kk[q] = kernel_value(k_squared(&g, q), kp);
     }
     if ((e = fft_nd(tmp, &g, -1, nt))) goto done;
     for (long long q = 0; q < g.P; q++) {
@@ -576,6 +653,23 @@ done:
     free(rho);
     free(lap);
     return e;
+}
+
+int orc_observables_local(const double *psi_in, int ndim, const int *n, const double *L,
+                          const double *kp, double a, double gloc, const double *lp,
+                          double *out, int nthreads)
+{
+    kspec_t ks = {0, kp, 0.0, 0.0, 0.0};
+    return observables_spec(psi_in, ndim, n, L, &ks, a, gloc, lp, out, nthreads);
+}
+
+/* observables of Eq. (1)-(2) with their own constants (a = -A) */
+int orc_observables_equation(const double *psi_in, int ndim, const int *n, const double *L,
+                             double A, double B, double C, double D, double gloc, const double *lp,
+                             double *out, int nthreads)
+{
+    kspec_t ks = {1, NULL, B, C, D};
+    return observables_spec(psi_in, ndim, n, L, &ks, -A, gloc, lp, out, nthreads);
 }
 
 /* orc_observables_local with the Kerr term only; out has 5 entries */

@@ -10,6 +10,9 @@ Conventions (arXiv:1909.08354 Sec. II Eq. (1)-(3), Sec. III):
     + c_Y/(|k|^2 + m_Y^2) + c_0;
   * ``a`` kinetic coefficient (1/2 for Eq. (3) with k = k0 = 1),
     ``g`` local (Kerr) coefficient, ``dz`` the step;
+  * ``eq`` = (A, B, C, D): Eq. (1)-(2) with their own constants,
+    i psi_t = A lap psi + B phi psi + G psi, lap phi + C phi = D rho, so that
+    a = -A and K = B D / (|k|^2 - C) (C > 0: Helmholtz, resonances rejected);
   * ``local`` = (c_p, n_p, c_B, rho_f) or None: the local terms of Eq. (15),
     U = g rho + c_p f_n(max(rho, rho_f)) + c_B lap(sqrt rho) / (2 max(sqrt rho,
     sqrt rho_f)) with f_1 = ln rho, f_n = n/(n-1) rho^(n-1) (Sec. II C).
@@ -49,10 +52,17 @@ def _load():
                                           ctypes.c_double, dp, dp, ctypes.c_int]
     lib.orc_local_potential.argtypes = [dp, ctypes.c_int, ip, dp, ctypes.c_double, dp, dp,
                                         ctypes.c_int]
+    d = ctypes.c_double
+    lib.orc_evolve_equation.argtypes = [dp, ctypes.c_int, ip, dp, d, d, d, d, d, dp, d,
+                                        ctypes.c_longlong, ctypes.c_int, ctypes.c_int]
+    lib.orc_potential_equation.argtypes = [dp, dp, ctypes.c_int, ip, dp, d, d, d, ctypes.c_int]
+    lib.orc_observables_equation.argtypes = [dp, ctypes.c_int, ip, dp, d, d, d, d, d, dp, dp,
+                                             ctypes.c_int]
     lib.orc_max_threads.argtypes = []
     for f in ("orc_fft", "orc_dft_brute", "orc_potential", "orc_evolve",
               "orc_observables", "orc_evolve_local", "orc_observables_local",
-              "orc_local_potential", "orc_max_threads"):
+              "orc_local_potential", "orc_evolve_equation", "orc_potential_equation",
+              "orc_observables_equation", "orc_max_threads"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -168,3 +178,40 @@ def rel_l2(x, ref):
     x = np.asarray(x, dtype=np.complex128)
     ref = np.asarray(ref, dtype=np.complex128)
     return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def evolve_equation(psi, L, eq, g, dz, nsteps, merged=True, nthreads=0, local=None):
+    """nsteps symmetric split steps of Eq. (1)-(2) with constants eq = (A, B, C, D)."""
+    p = np.array(psi, dtype=np.complex128, order="C", copy=True)
+    n, Larr = _shape_args(p.shape, L)
+    lp = _local_arr(local)
+    A, B, C, D = (float(v) for v in eq)
+    _check(_load().orc_evolve_equation(_dptr(p), p.ndim, n, _dptr(Larr), A, B, C, D, float(g),
+                                       None if lp is None else _dptr(lp), float(dz), int(nsteps),
+                                       1 if merged else 0, nthreads), "evolve_equation")
+    return p
+
+
+def potential_equation(rho, L, eq, nthreads=0):
+    """This file's phi (= -B phi of Eq. (2)) for a real density: Re IDFT[B D/(|k|^2 - C) DFT rho]."""
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    phi = np.empty_like(r)
+    n, Larr = _shape_args(r.shape, L)
+    _, B, C, D = (float(v) for v in eq)
+    _check(_load().orc_potential_equation(_dptr(r), _dptr(phi), r.ndim, n, _dptr(Larr), B, C, D,
+                                          nthreads), "potential_equation")
+    return phi
+
+
+def observables_equation(psi, L, eq, g, nthreads=0, local=None):
+    """observables() for Eq. (1)-(2) with constants eq = (A, B, C, D)."""
+    p = np.ascontiguousarray(psi, dtype=np.complex128)
+    n, Larr = _shape_args(p.shape, L)
+    out = np.zeros(7)
+    lp = _local_arr(local)
+    A, B, C, D = (float(v) for v in eq)
+    _check(_load().orc_observables_equation(_dptr(p), p.ndim, n, _dptr(Larr), A, B, C, D, float(g),
+                                            None if lp is None else _dptr(lp), _dptr(out), nthreads),
+           "observables_equation")
+    return {"mass": out[0], "kinetic": out[1], "local": out[2], "nonlocal": out[3],
+            "total": out[4], "pressure": out[5], "bohm": out[6]}

@@ -479,3 +479,90 @@ def test_local_terms_reject_bad_arguments():
                   (np.nan, 1.0, 0.0, 1e-6)]:
         with pytest.raises(ValueError):
             orc.evolve(psi, L, kern, 0.5, 0.0, 1e-3, 1, local=local)
+
+
+# ---------------------------------------------------------------- Eq. (1)-(2) constants
+# i psi_t = A lap psi + B phi psi + G psi,  lap phi + C phi = D rho  (G = -g rho):
+# a = -A and this file's potential is -B phi, K = B D / (|k|^2 - C).
+
+@pytest.mark.parametrize("C", [0.37, -0.8, 0.0])
+def test_equation_potential_of_a_cosine_source(C):
+    """lap phi + C phi = D (rho0 + r cos(q.x)) has phi = D rho0 / C + D r cos(q.x)/(C - q^2)
+    (the uniform part is dropped when C = 0); the phase sees -B phi."""
+    n, L = (32, 64), (2 * np.pi * 3, 2 * np.pi * 5)
+    B, D, rho0, r = -0.7, 1.3, 0.6, 0.25
+    y = inputs.axis_coords(n[0], L[0])[:, None]
+    x = inputs.axis_coords(n[1], L[1])[None, :]
+    q = (2 * np.pi * 2 / L[0], 2 * np.pi * 3 / L[1])
+    c = np.cos(q[0] * y + q[1] * x)
+    phi = orc.potential_equation(rho0 + r * c + 0 * x, L, (0.0, B, C, D))
+    q2 = q[0] ** 2 + q[1] ** 2
+    exact = D * r * c / (C - q2) + (D * rho0 / C if C != 0 else 0.0)
+    assert np.max(np.abs(phi - (-B) * exact)) < 1e-12
+
+
+def test_equation_rejects_resonant_grids():
+    """C > 0 equal to some grid |k|^2 (here 1 + 4 with L = 2 pi) has no solution."""
+    n, L = (16, 16), (2 * np.pi, 2 * np.pi)
+    psi = np.ones(n, complex)
+    with pytest.raises(ValueError):
+        orc.evolve_equation(psi, L, (-0.5, -1.0, 5.0, 1.0), 0.0, 1e-3, 1)
+    with pytest.raises(ValueError):
+        orc.potential_equation(np.ones(n), L, (-0.5, -1.0, 2.0, 1.0))
+    orc.evolve_equation(psi, L, (-0.5, -1.0, 3.0, 1.0), 0.0, 1e-3, 1)   # 3 is no sum of two squares
+
+
+def test_equation_plane_wave_closed_form():
+    """A plane wave A0 exp(i q.x) has uniform rho, so phi = D A0^2 / C and
+    psi(t) = psi0 exp(-i (-A q^2 + B D A0^2 / C - g A0^2) t), for C > 0 and C < 0."""
+    n, L = (16, 32), (10.0, 20.0)
+    y = inputs.axis_coords(n[0], L[0])[:, None]
+    x = inputs.axis_coords(n[1], L[1])[None, :]
+    q = (2 * np.pi * 1 / L[0], 2 * np.pi * 3 / L[1])
+    A0, g, dz, steps = 0.8, 0.4, 0.01, 13
+    psi0 = A0 * np.exp(1j * (q[0] * y + q[1] * x))
+    q2 = q[0] ** 2 + q[1] ** 2
+    for eq in [(-0.5, -1.0, 0.3, 2.0), (0.7, 0.5, -1.1, -0.6)]:
+        A, B, C, D = eq
+        out = orc.evolve_equation(psi0, L, eq, g, dz, steps)
+        w = -A * q2 + B * D * A0 ** 2 / C - g * A0 ** 2
+        assert np.max(np.abs(out - psi0 * np.exp(-1j * w * dz * steps))) < 1e-12
+
+
+def test_equation_with_negative_C_is_the_yukawa_kernel():
+    """C = -m^2 < 0: K = B D / (|k|^2 + m^2), the Yukawa member of the kernel
+    family with c_Y = B D; C = 0: the Newtonian member with c_N = B D."""
+    w = inputs.WORKLOADS["gsn2d_128_kerr_newton"]
+    psi0 = inputs.as_oracle_input(inputs.gaussian_2d_128())
+    L, g, dz = w["L"], w["g"], w["dz"]
+    A, B, D, m = -0.5, -1.0, -0.9, 0.4
+    a = orc.evolve_equation(psi0, L, (A, B, -m * m, D), g, dz, 30)
+    b = orc.evolve(psi0, L, (0.0, B * D, m, 0.0), -A, g, dz, 30)
+    assert orc.rel_l2(a, b) < 1e-13
+    a = orc.evolve_equation(psi0, L, (A, B, 0.0, D), g, dz, 30)
+    b = orc.evolve(psi0, L, (B * D, 0.0, 0.0, 0.0), -A, g, dz, 30)
+    assert orc.rel_l2(a, b) < 1e-13
+
+
+def test_equation_energy_is_the_hamiltonian_with_helmholtz_kernel():
+    """dE/de along psi + e eta equals 2 Re sum dV conj(eta) H psi with
+    H psi = A lap psi + B phi psi - g rho psi (Eq. (1)'s right-hand side)."""
+    n, L = (64, 64), (40.0, 40.0)
+    A, B, C, D, g = -0.5, -1.0, 0.05, 0.7, -0.3
+    rng = np.random.default_rng(7)
+    psi, _, _ = _pedestal(n, L, 0.6, 2.5)
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    psi = psi * np.exp(2j * np.pi * 2 * xs[1] / L[1])
+    c = rng.uniform(-4, 4, 2)
+    eta = np.exp(-sum((xx - cc) ** 2 for xx, cc in zip(xs, c)) / 8.0) * np.exp(0.4j)
+    dV = (L[0] / n[0]) * (L[1] / n[1])
+    k2 = sum(k * k for k in np.meshgrid(*[2 * np.pi * np.fft.fftfreq(N, Ld / N) for N, Ld in zip(n, L)],
+                                         indexing="ij"))
+    lap = orc.fft(-k2 * orc.fft(psi), inverse=True)
+    phi_eq2 = -orc.potential_equation(np.abs(psi) ** 2, L, (A, B, C, D)) / B   # phi of Eq. (2)
+    Hpsi = A * lap + B * phi_eq2 * psi - g * np.abs(psi) ** 2 * psi
+    expect = 2 * np.real(np.sum(np.conj(eta) * Hpsi)) * dV
+    e = 1e-4
+    Ep = orc.observables_equation(psi + e * eta, L, (A, B, C, D), g)["total"]
+    Em = orc.observables_equation(psi - e * eta, L, (A, B, C, D), g)["total"]
+    assert abs((Ep - Em) / (2 * e) - expect) < 1e-7 * max(1.0, abs(expect))
