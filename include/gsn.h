@@ -91,6 +91,19 @@ gsn_status gsn_set_kernel(gsn_grid grid, const gsn_kernel *kernel);
    (Kerr; Eq. (16) with n = 2 gives g = -2w) and the step dz (finite, != 0). */
 gsn_status gsn_set_coefficients(gsn_grid grid, double a_kin, double g_local, double dz);
 
+/* Eq. (1)-(2) with their own constants:
+     i psi_t = A lap psi + B phi psi + G psi,   lap phi + C phi = D |psi|^2,
+   G = -g |psi|^2 (- the local terms below).  Sets the kinetic coefficient
+   a = -A (a later gsn_set_coefficients sets a again) and the kernel
+   K = B D / (|k|^2 - C): the Newtonian member c_newton = B D for C = 0, else
+   the screened member c_yukawa = B D with squared mass -C, which for C > 0 is
+   the resonant Helmholtz kernel.  C > 0 equal to |k|^2 of a grid wavenumber
+   (relative tolerance 1e-12) has no periodic solution: GSN_EINVAL.  The
+   optics forms: Eq. (3) with k = k0 = 1 is A = -1/2, B = -1 (phi = Delta n);
+   the thermo-optic Eq. (4) is C = -1/sigma^2, D = -zeta mu / kappa; the
+   nematic Eq. (5) divided by nu is C = -2q/nu, D = -2/nu.  Synchronising. */
+gsn_status gsn_set_equation(gsn_grid grid, double A, double B, double C, double D);
+
 /* Local terms of Eq. (15) (Sec. II C): replace the Kerr term g rho of the
    phase by the local potential
      U = g rho + c_pressure f_n(max(rho, rho_floor))

@@ -5,6 +5,7 @@
 // host with double cos/sin), the per-step pass schedule and its launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -136,6 +137,7 @@ struct gsn_grid_ {
     // parameters
     double a, g, dz;
     gsn_kernel kern;
+    double mY2;                // squared screening mass of K; -C of Eq. (2) (may be < 0)
     double lp_cp, lp_n, lp_cb, lp_floor;   // local terms of Eq. (15)
     bool local_on, bohm_on;
     bool have_dz, have_psi;
@@ -361,10 +363,12 @@ static EmArgs em_base(gsn_grid g, float2 *psi)
     return a;
 }
 
-static double kernel_k0(const gsn_kernel &k)
+// K(0) of the grid's kernel: the contact and screened parts (the Newtonian
+// k = 0 term is dropped); mY2 may be negative (Helmholtz, C > 0).
+static double kernel_k0(gsn_grid g)
 {
-    double v = k.c_contact;
-    if (k.c_yukawa != 0.0) v += k.c_yukawa / (k.m_yukawa * k.m_yukawa);
+    double v = g->kern.c_contact;
+    if (g->kern.c_yukawa != 0.0) v += g->kern.c_yukawa / g->mY2;
     return v;
 }
 
@@ -422,7 +426,7 @@ static void build_core(gsn_grid g)
         }
     }
     // nonlinear sub-step
-    const double K0 = kernel_k0(g->kern);
+    const double K0 = kernel_k0(g);
     for (int energy = 0; energy < 2; ++energy) {
         std::vector<Launch> &dst = energy ? g->energy_rho : g->nonlin;
         float2 *src = energy ? g->scratch : g->psi;
@@ -461,7 +465,7 @@ static void build_core(gsn_grid g)
             f.k2_p = g->k2[Z];
             f.cN = g->kern.c_newton;
             f.cY = g->kern.c_yukawa;
-            f.mY2 = g->kern.m_yukawa * g->kern.m_yukawa;
+            f.mY2 = g->mY2;
             f.c0 = g->kern.c_contact;
             dst.push_back(lm_launch(kz->lm_kern, kz, f, P_KERNEL));
             LmArgs gg = lm_base(g, g->tw[Y], 1.0);
@@ -479,7 +483,7 @@ static void build_core(gsn_grid g)
             f.k2_p = g->k2[Y];
             f.cN = g->kern.c_newton;
             f.cY = g->kern.c_yukawa;
-            f.mY2 = g->kern.m_yukawa * g->kern.m_yukawa;
+            f.mY2 = g->mY2;
             f.c0 = g->kern.c_contact;
             if (!energy) {
                 f.reduce = 1;
@@ -732,6 +736,7 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
     g->g = 0.0;
     g->dz = 0.0;
     std::memset(&g->kern, 0, sizeof(g->kern));
+    g->mY2 = 0.0;
     g->lp_cp = g->lp_cb = g->lp_floor = 0.0;
     g->lp_n = 1.0;
     g->local_on = g->bohm_on = false;
@@ -795,6 +800,65 @@ extern "C" gsn_status gsn_set_kernel(gsn_grid g, const gsn_kernel *k)
     if (k->c_yukawa != 0.0 && !(k->m_yukawa > 0.0))
         return fail(GSN_EINVAL, "m_yukawa must be > 0 when c_yukawa != 0");
     g->kern = *k;
+    g->mY2 = k->m_yukawa * k->m_yukawa;
+    build_schedule(g);
+    return GSN_OK;
+}
+
+// Whether some grid wavenumber has |k|^2 = C (relative tolerance 1e-12): the
+// per-axis |k_d|^2 values are sorted, and for every combination of the other
+// axes the remainder is looked up in the last axis.
+static bool resonant(gsn_grid g, double C)
+{
+    if (!(C > 0.0)) return false;
+    std::vector<std::vector<double>> ks(g->ndim);
+    for (int d = 0; d < g->ndim; ++d) {
+        for (int j = 0; j <= g->n[d] / 2; ++j) {
+            const double k = wavenumber(j, g->n[d], g->L[d]);
+            ks[d].push_back(k * k);
+        }
+        std::sort(ks[d].begin(), ks[d].end());
+    }
+    const double tol = 1e-12 * std::max(1.0, C);
+    const std::vector<double> &last = ks[g->ndim - 1];
+    auto hit = [&](double target) {
+        auto it = std::lower_bound(last.begin(), last.end(), target - tol);
+        return it != last.end() && *it <= target + tol;
+    };
+    if (g->ndim == 2) {
+        for (double a : ks[0])
+            if (hit(C - a)) return true;
+    } else {
+        for (double a : ks[0])
+            for (double b : ks[1])
+                if (hit(C - a - b)) return true;
+    }
+    return false;
+}
+
+extern "C" gsn_status gsn_set_equation(gsn_grid g, double A, double B, double C, double D)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (!std::isfinite(A) || !std::isfinite(B) || !std::isfinite(C) || !std::isfinite(D))
+        return fail(GSN_EINVAL, "A, B, C, D must be finite");
+    if (resonant(g, C))
+        return fail(GSN_EINVAL, "C equals |k|^2 of a grid wavenumber: Eq. (2) has no periodic solution");
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    std::memset(&g->kern, 0, sizeof(g->kern));
+    if (C == 0.0) {
+        g->kern.c_newton = B * D;
+        g->mY2 = 0.0;
+    } else {
+        g->kern.c_yukawa = B * D;
+        g->kern.m_yukawa = std::sqrt(std::fabs(C));
+        g->mY2 = -C;
+    }
+    g->a = -A;
+    if (g->have_dz) {
+        gsn_status s = upload_kinetic(g);
+        if (s) return s;
+    }
     build_schedule(g);
     return GSN_OK;
 }
@@ -1012,7 +1076,7 @@ extern "C" gsn_status gsn_energy(gsn_grid g, double e[4])
     if ((s = sum_device(g, g->epart, nphase, 4, 2, &gsum))) return s;
     if ((s = sum_device(g, g->epart, nphase, 4, 3, &slap))) return s;
     if ((s = sum_device(g, g->epart + 4 * g->max_density_blocks, nkin, 1, 0, &k2sum))) return s;
-    const double dV = cell_volume(g), P = (double)g->P, K0 = kernel_k0(g->kern);
+    const double dV = cell_volume(g), P = (double)g->P, K0 = kernel_k0(g);
     const double ekin = g->a * dV / P * k2sum;
     // Kerr, pressure (-c_p sum G) and Bohm (-(c_B/2) sum s lap s = (c_B/2) sum |grad s|^2)
     const double eloc = -0.5 * g->g * dV * rho2 - g->lp_cp * dV * gsum - 0.5 * g->lp_cb * dV * slap;

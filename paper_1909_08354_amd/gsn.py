@@ -44,6 +44,7 @@ _SIGNATURES = {
     "gsn_set_kernel": [vp, ctypes.POINTER(gsn_kernel)],
     "gsn_set_coefficients": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "gsn_set_local_terms": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "gsn_set_equation": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "gsn_set_psi": [vp, vp, ctypes.c_int, ctypes.c_int],
     "gsn_step": [vp, ctypes.c_int64],
     "gsn_sync": [vp],
@@ -213,6 +214,10 @@ class Grid:
     def set_coefficients(self, a, g, dz):
         check(load().gsn_set_coefficients(self.h, a, g, dz))
 
+    def set_equation(self, A, B, C, D):
+        """Eq. (1)-(2) constants: a = -A, K = B D / (|k|^2 - C)."""
+        check(load().gsn_set_equation(self.h, A, B, C, D))
+
     def set_local_terms(self, c_pressure=0.0, n_pressure=1.0, c_bohm=0.0, rho_floor=0.0):
         """Pressure and Bohm terms of Eq. (15) (all zero: the Kerr model)."""
         check(load().gsn_set_local_terms(self.h, c_pressure, n_pressure, c_bohm, rho_floor))
@@ -325,6 +330,23 @@ class Grid:
 
 
 BATCH_FAMILIES = ("kinetic", "x_density", "kernel", "x_phase", "x_fft")
+
+
+def equation_optics():
+    """(A, B) of Eq. (3) with k = k0 = 1: i psi_z = -lap psi / 2 - Delta n psi."""
+    return (-0.5, -1.0)
+
+
+def equation_thermo_optic(sigma, zeta, mu, kappa):
+    """(A, B, C, D) of a thermo-optical medium, Eq. (4):
+    lap Delta n - Delta n / sigma^2 = -(zeta mu / kappa) |E|^2."""
+    return equation_optics() + (-1.0 / sigma ** 2, -zeta * mu / kappa)
+
+
+def equation_nematic(nu, q):
+    """(A, B, C, D) of a nematic liquid crystal, Eq. (5) divided by nu:
+    lap theta - (2 q / nu) theta = -(2 / nu) |E|^2, with Delta n = theta."""
+    return equation_optics() + (-2.0 * q / nu, -2.0 / nu)
 
 
 def variant_names():
