@@ -46,6 +46,13 @@
  * Eq. (15) divided by nu is this form with a = nu/2, c_B = -nu, c_p = -w/nu and
  * phi = -(phi_N + phi_C)/nu.
  *
+ * Position-dependent source and static potential (Eq. (9)-(12)), optional:
+ * the kernel acts on s = gamma(x) rho + beta(x) lap(rho) instead of rho, and a
+ * static field V(x) joins the phase:  N(h): psi <- psi exp(i (U + phi + V) h).
+ * The pure non-minimal coupling of Eq. (12), lap phi_N = beta lap rho + gamma rho,
+ * with Eq. (9)-(11) for gamma(r), beta(r) and phi_C(r), is this with
+ * K = (1/nu)/|k|^2 and V = -phi_C/nu.
+ *
  * The FFT is an iterative radix-2 transform with twiddles from direct FP64
  * cos/sin of 2 pi m / n (never a recurrence).  Multi-dimensional transforms are
  * applied axis by axis.  OpenMP threads run independent 1-D lines in parallel;
@@ -355,6 +362,45 @@ static int laplacian_of_sqrt(double *lap, const double *rho, cx *tmp, const grid
     return ORC_OK;
 }
 
+/* lap(f) = Re IDFT[-|k|^2 DFT f] of a real field into lap, tmp scratch */
+static int laplacian_into(double *lap, const double *f, cx *tmp, const grid_t *g, int nt)
+{
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) tmp[q] = f[q];
+    int e = fft_nd(tmp, g, -1, nt);
+    if (e) return e;
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) tmp[q] *= -k_squared(g, q);
+    e = fft_nd(tmp, g, +1, nt);
+    if (e) return e;
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) lap[q] = creal(tmp[q]);
+    return ORC_OK;
+}
+
+/* Position-dependent source coefficients and static potential (NULL: absent;
+   gamma absent means gamma = 1, beta absent beta = 0, V absent V = 0). */
+typedef struct {
+    const double *gamma, *beta, *V;
+} fields_t;
+
+/* s = gamma rho + beta lap(rho) into s; tmp scratch */
+static int source_into(double *s_out, const double *rho, cx *tmp, const fields_t *fl, const grid_t *g, int nt)
+{
+    if (fl->beta) {
+        int e = laplacian_into(s_out, rho, tmp, g, nt);
+        if (e) return e;
+#pragma omp parallel for num_threads(nt) schedule(static)
+        for (long long q = 0; q < g->P; q++) s_out[q] *= fl->beta[q];
+    } else {
+#pragma omp parallel for num_threads(nt) schedule(static)
+        for (long long q = 0; q < g->P; q++) s_out[q] = 0.0;
+    }
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < g->P; q++) s_out[q] += (fl->gamma ? fl->gamma[q] : 1.0) * rho[q];
+    return ORC_OK;
+}
+
 /* U = g rho + polytropic + Bohm terms (see the header); tmp scratch */
 static int local_potential_into(double *U, const double *rho, cx *tmp, double gloc,
                                 const local_t *lt, const grid_t *g, int nt)
@@ -443,9 +489,12 @@ static int kinetic_step(cx *psi, const cx *prop, const grid_t *g, int nt)
     return fft_nd(psi, g, +1, nt);
 }
 
-/* nonlinear sub-step N(h): psi <- psi exp(i (U + phi) h), U the local potential */
-static int nonlinear_step(cx *psi, cx *tmp, double *rho, double *U, const double *Kk,
-                          double gloc, const local_t *lt, double h, const grid_t *g, int nt)
+/* nonlinear sub-step N(h): psi <- psi exp(i (U + phi + V) h), U the local
+   potential, phi the potential of rho (or of the source s when source fields
+   are given); src is scratch for s */
+static int nonlinear_step(cx *psi, cx *tmp, double *rho, double *U, double *src, const double *Kk,
+                          double gloc, const local_t *lt, const fields_t *fl, double h,
+                          const grid_t *g, int nt)
 {
 #pragma omp parallel for num_threads(nt) schedule(static)
     for (long long q = 0; q < g->P; q++) {
@@ -454,11 +503,16 @@ static int nonlinear_step(cx *psi, cx *tmp, double *rho, double *U, const double
     }
     int e = local_potential_into(U, rho, tmp, gloc, lt, g, nt);
     if (e) return e;
-    e = potential_into(tmp, rho, Kk, g, nt);
+    const double *s = rho;
+    if (fl && (fl->gamma || fl->beta)) {
+        if ((e = source_into(src, rho, tmp, fl, g, nt))) return e;
+        s = src;
+    }
+    e = potential_into(tmp, s, Kk, g, nt);
     if (e) return e;
 #pragma omp parallel for num_threads(nt) schedule(static)
     for (long long q = 0; q < g->P; q++) {
-        double th = (U[q] + creal(tmp[q])) * h;
+        double th = (U[q] + creal(tmp[q]) + (fl && fl->V ? fl->V[q] : 0.0)) * h;
         psi[q] *= cos(th) + sin(th) * I;
     }
     return ORC_OK;
@@ -473,8 +527,8 @@ static int nonlinear_step(cx *psi, cx *tmp, double *rho, double *U, const double
  * Returns 0 on success.
  */
 static int evolve_spec(double *psi_io, int ndim, const int *n, const double *L,
-                       const kspec_t *ks, double a, double gloc, const double *lp, double dz,
-                       long long nsteps, int merged, int nthreads)
+                       const kspec_t *ks, double a, double gloc, const double *lp,
+                       const fields_t *fl, double dz, long long nsteps, int merged, int nthreads)
 {
     grid_t g;
     local_t lt;
@@ -491,8 +545,9 @@ static int evolve_spec(double *psi_io, int ndim, const int *n, const double *L,
     double *Kk = (double *)malloc(sizeof(double) * P);
     double *rho = (double *)malloc(sizeof(double) * P);
     double *U = (double *)malloc(sizeof(double) * P);
+    double *src = (double *)malloc(sizeof(double) * P);
     int e = ORC_ENOMEM;
-    if (!half || !full || !tmp || !Kk || !rho || !U) goto done;
+    if (!half || !full || !tmp || !Kk || !rho || !U || !src) goto done;
     if ((e = kspec_table(Kk, ks, &g))) goto done;
 #pragma omp parallel for num_threads(nt) schedule(static)
     for (long long q = 0; q < g.P; q++) {
@@ -504,13 +559,13 @@ static int evolve_spec(double *psi_io, int ndim, const int *n, const double *L,
     if (!merged) {
         for (long long s = 0; s < nsteps; s++) {
             if ((e = kinetic_step(psi, half, &g, nt))) goto done;
-            if ((e = nonlinear_step(psi, tmp, rho, U, Kk, gloc, &lt, dz, &g, nt))) goto done;
+            if ((e = nonlinear_step(psi, tmp, rho, U, src, Kk, gloc, &lt, fl, dz, &g, nt))) goto done;
             if ((e = kinetic_step(psi, half, &g, nt))) goto done;
         }
     } else {
         if ((e = kinetic_step(psi, half, &g, nt))) goto done;
         for (long long s = 0; s < nsteps; s++) {
-            if ((e = nonlinear_step(psi, tmp, rho, U, Kk, gloc, &lt, dz, &g, nt))) goto done;
+            if ((e = nonlinear_step(psi, tmp, rho, U, src, Kk, gloc, &lt, fl, dz, &g, nt))) goto done;
             if ((e = kinetic_step(psi, s + 1 < nsteps ? full : half, &g, nt))) goto done;
         }
     }
@@ -522,6 +577,7 @@ done:
     free(Kk);
     free(rho);
     free(U);
+    free(src);
     return e;
 }
 
@@ -530,7 +586,72 @@ int orc_evolve_local(double *psi_io, int ndim, const int *n, const double *L,
                      long long nsteps, int merged, int nthreads)
 {
     kspec_t ks = {0, kp, 0.0, 0.0, 0.0};
-    return evolve_spec(psi_io, ndim, n, L, &ks, a, gloc, lp, dz, nsteps, merged, nthreads);
+    return evolve_spec(psi_io, ndim, n, L, &ks, a, gloc, lp, NULL, dz, nsteps, merged, nthreads);
+}
+
+/* orc_evolve_local with position-dependent source fields and a static
+   potential (any of gamma, beta, V may be NULL) */
+int orc_evolve_fields(double *psi_io, int ndim, const int *n, const double *L,
+                      const double *kp, double a, double gloc, const double *lp,
+                      const double *gamma, const double *beta, const double *V, double dz,
+                      long long nsteps, int merged, int nthreads)
+{
+    kspec_t ks = {0, kp, 0.0, 0.0, 0.0};
+    fields_t fl = {gamma, beta, V};
+    return evolve_spec(psi_io, ndim, n, L, &ks, a, gloc, lp, &fl, dz, nsteps, merged, nthreads);
+}
+
+/* phi = Re IDFT[K DFT s], s = gamma rho + beta lap(rho) */
+int orc_potential_fields(const double *rho, double *phi, int ndim, const int *n, const double *L,
+                         const double *kp, const double *gamma, const double *beta, int nthreads)
+{
+    grid_t g;
+    kspec_t ks = {0, kp, 0.0, 0.0, 0.0};
+    if (!rho || !phi || grid_init(&g, ndim, n, L) || kspec_check(&ks)) return ORC_EINVAL;
+    int nt = nthreads_or_default(nthreads);
+    fields_t fl = {gamma, beta, NULL};
+    cx *tmp = (cx *)malloc(sizeof(cx) * (size_t)g.P);
+    double *Kk = (double *)malloc(sizeof(double) * (size_t)g.P);
+    double *s = (double *)malloc(sizeof(double) * (size_t)g.P);
+    int e = ORC_ENOMEM;
+    if (tmp && Kk && s && !(e = kspec_table(Kk, &ks, &g)) && !(e = source_into(s, rho, tmp, &fl, &g, nt)) &&
+        !(e = potential_into(tmp, s, Kk, &g, nt)))
+        for (long long q = 0; q < g.P; q++) phi[q] = creal(tmp[q]);
+    free(tmp);
+    free(Kk);
+    free(s);
+    return e;
+}
+
+/*
+ * Fields of the pure non-minimal coupling, Eq. (9)-(11), on the grid: with
+ * r the (minimum-image) distance from the centre c and u = (r0/(r + r0))^lambda,
+ *   gamma = (1 - u)/2,   beta = lambda u / (r + r0),   phi_C = ln(1 - u),
+ * and V = -phi_C / nu (this file's sign and scale); phi_C diverges at r = 0, so
+ * it takes r = max(r, r_min).
+ */
+int orc_nmc_fields(int ndim, const int *n, const double *L, double lambda, double r0, double nu,
+                   const double *center, double r_min, double *gamma, double *beta, double *V)
+{
+    grid_t g;
+    if (grid_init(&g, ndim, n, L) || !center || !gamma || !beta || !V) return ORC_EINVAL;
+    if (!(lambda > 0.0) || !(r0 > 0.0) || !(nu != 0.0) || !(r_min > 0.0)) return ORC_EINVAL;
+    for (long long q = 0; q < g.P; q++) {
+        double r2 = 0.0;
+        for (int d = 0; d < g.ndim; d++) {
+            int j = (int)((q / g.stride[d]) % g.n[d]);
+            double x = -0.5 * g.L[d] + j * g.L[d] / g.n[d] - center[d];
+            x -= g.L[d] * floor(x / g.L[d] + 0.5);   /* minimum image */
+            r2 += x * x;
+        }
+        double r = sqrt(r2);
+        double u = pow(r0 / (r + r0), lambda);
+        gamma[q] = 0.5 * (1.0 - u);
+        beta[q] = lambda * u / (r + r0);
+        double rc = fmax(r, r_min);
+        V[q] = -log(1.0 - pow(r0 / (rc + r0), lambda)) / nu;
+    }
+    return ORC_OK;
 }
 
 /*
@@ -543,7 +664,7 @@ int orc_evolve_equation(double *psi_io, int ndim, const int *n, const double *L,
                         double dz, long long nsteps, int merged, int nthreads)
 {
     kspec_t ks = {1, NULL, B, C, D};
-    return evolve_spec(psi_io, ndim, n, L, &ks, -A, gloc, lp, dz, nsteps, merged, nthreads);
+    return evolve_spec(psi_io, ndim, n, L, &ks, -A, gloc, lp, NULL, dz, nsteps, merged, nthreads);
 }
 
 /* orc_evolve_local with the Kerr term only */

@@ -13,6 +13,9 @@ Conventions (arXiv:1909.08354 Sec. II Eq. (1)-(3), Sec. III):
   * ``eq`` = (A, B, C, D): Eq. (1)-(2) with their own constants,
     i psi_t = A lap psi + B phi psi + G psi, lap phi + C phi = D rho, so that
     a = -A and K = B D / (|k|^2 - C) (C > 0: Helmholtz, resonances rejected);
+  * ``fields`` = (gamma, beta, V) or None (each an array of the grid's shape or
+    None): the kernel acts on s = gamma rho + beta lap(rho) and V joins the
+    phase (position-dependent coupling of Eq. (9)-(12));
   * ``local`` = (c_p, n_p, c_B, rho_f) or None: the local terms of Eq. (15),
     U = g rho + c_p f_n(max(rho, rho_f)) + c_B lap(sqrt rho) / (2 max(sqrt rho,
     sqrt rho_f)) with f_1 = ln rho, f_n = n/(n-1) rho^(n-1) (Sec. II C).
@@ -58,11 +61,16 @@ def _load():
     lib.orc_potential_equation.argtypes = [dp, dp, ctypes.c_int, ip, dp, d, d, d, ctypes.c_int]
     lib.orc_observables_equation.argtypes = [dp, ctypes.c_int, ip, dp, d, d, d, d, d, dp, dp,
                                              ctypes.c_int]
+    lib.orc_evolve_fields.argtypes = [dp, ctypes.c_int, ip, dp, dp, d, d, dp, dp, dp, dp, d,
+                                      ctypes.c_longlong, ctypes.c_int, ctypes.c_int]
+    lib.orc_potential_fields.argtypes = [dp, dp, ctypes.c_int, ip, dp, dp, dp, dp, ctypes.c_int]
+    lib.orc_nmc_fields.argtypes = [ctypes.c_int, ip, dp, d, d, d, dp, d, dp, dp, dp]
     lib.orc_max_threads.argtypes = []
     for f in ("orc_fft", "orc_dft_brute", "orc_potential", "orc_evolve",
               "orc_observables", "orc_evolve_local", "orc_observables_local",
               "orc_local_potential", "orc_evolve_equation", "orc_potential_equation",
-              "orc_observables_equation", "orc_max_threads"):
+              "orc_observables_equation", "orc_evolve_fields", "orc_potential_fields",
+              "orc_nmc_fields", "orc_max_threads"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -215,3 +223,52 @@ def observables_equation(psi, L, eq, g, nthreads=0, local=None):
            "observables_equation")
     return {"mass": out[0], "kinetic": out[1], "local": out[2], "nonlocal": out[3],
             "total": out[4], "pressure": out[5], "bohm": out[6]}
+
+
+def _field(f, shape):
+    if f is None:
+        return None
+    a = np.ascontiguousarray(f, dtype=np.float64)
+    if a.shape != tuple(shape):
+        raise ValueError("field shape differs from the grid")
+    return a
+
+
+def evolve_fields(psi, L, kern, a, g, dz, nsteps, fields, merged=True, nthreads=0, local=None):
+    """evolve() with position-dependent source fields and a static potential."""
+    p = np.array(psi, dtype=np.complex128, order="C", copy=True)
+    n, Larr = _shape_args(p.shape, L)
+    k = np.ascontiguousarray(kern, dtype=np.float64)
+    lp = _local_arr(local)
+    gm, bt, V = (_field(f, p.shape) for f in fields)
+    ptr = lambda x: None if x is None else _dptr(x)
+    _check(_load().orc_evolve_fields(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a), float(g),
+                                     ptr(lp), ptr(gm), ptr(bt), ptr(V), float(dz), int(nsteps),
+                                     1 if merged else 0, nthreads), "evolve_fields")
+    return p
+
+
+def potential_fields(rho, L, kern, gamma=None, beta=None, nthreads=0):
+    """phi = Re IDFT[K DFT s], s = gamma rho + beta lap(rho)."""
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    phi = np.empty_like(r)
+    n, Larr = _shape_args(r.shape, L)
+    k = np.ascontiguousarray(kern, dtype=np.float64)
+    gm, bt = _field(gamma, r.shape), _field(beta, r.shape)
+    ptr = lambda x: None if x is None else _dptr(x)
+    _check(_load().orc_potential_fields(_dptr(r), _dptr(phi), r.ndim, n, _dptr(Larr), _dptr(k),
+                                        ptr(gm), ptr(bt), nthreads), "potential_fields")
+    return phi
+
+
+def nmc_fields(n, L, lam, r0, nu, center=None, r_min=None):
+    """(gamma, beta, V) of the pure non-minimal coupling, Eq. (9)-(11), with
+    V = -phi_C / nu and phi_C cut at r_min (default half the smallest spacing)."""
+    n = tuple(int(v) for v in n)
+    na, Larr = _shape_args(n, L)
+    c = np.zeros(len(n)) if center is None else np.ascontiguousarray(center, dtype=np.float64)
+    rmin = 0.5 * min(Ld / N for N, Ld in zip(n, L)) if r_min is None else float(r_min)
+    gm, bt, V = (np.empty(n) for _ in range(3))
+    _check(_load().orc_nmc_fields(len(n), na, _dptr(Larr), float(lam), float(r0), float(nu), _dptr(c),
+                                  rmin, _dptr(gm), _dptr(bt), _dptr(V)), "nmc_fields")
+    return gm, bt, V

@@ -566,3 +566,89 @@ def test_equation_energy_is_the_hamiltonian_with_helmholtz_kernel():
     Ep = orc.observables_equation(psi + e * eta, L, (A, B, C, D), g)["total"]
     Em = orc.observables_equation(psi - e * eta, L, (A, B, C, D), g)["total"]
     assert abs((Ep - Em) / (2 * e) - expect) < 1e-7 * max(1.0, abs(expect))
+
+
+# ---------------------------------------------------------------- Eq. (9)-(12) position-dependent coupling
+# The kernel acts on s = gamma(x) rho + beta(x) lap(rho); V(x) joins the phase.
+
+def test_constant_source_fields_are_the_newton_plus_contact_kernel():
+    """gamma = g0, beta = b0 constant: K_N s_hat = c_N (g0 - b0 |k|^2) rho_hat / |k|^2
+    for k != 0, i.e. the kernel family with c_N' = g0 c_N and c_0' = -b0 c_N, except
+    that the family's k = 0 term adds the uniform potential c_0' <rho>, a global
+    phase (the mass, hence <rho>, is conserved)."""
+    w = inputs.WORKLOADS["gsn2d_128_kerr_newton"]
+    psi0 = inputs.as_oracle_input(inputs.gaussian_2d_128())
+    L, a, g, dz, steps, cN = w["L"], w["a"], w["g"], w["dz"], 25, 0.8
+    g0, b0 = 0.45, 0.3
+    ones = np.ones(psi0.shape)
+    f = orc.evolve_fields(psi0, L, (cN, 0, 0, 0), a, g, dz, steps, (g0 * ones, b0 * ones, None))
+    c0 = -b0 * cN
+    k = orc.evolve(psi0, L, (g0 * cN, 0, 0, c0), a, g, dz, steps)
+    rho_mean = np.mean(np.abs(psi0) ** 2)
+    assert orc.rel_l2(f, k * np.exp(-1j * c0 * rho_mean * dz * steps)) < 1e-12
+
+
+@pytest.mark.parametrize("e", [0.3, None])
+def test_potential_of_cosine_fields_closed_form(e):
+    """rho = 1 + A cos(q.x), gamma = 1 + e cos(p.x), beta = d cos(p.x):
+    s = 1 + A cos q.x + e cos p.x + (e A - d |q|^2 A)/2 (cos (p+q).x + cos (p-q).x),
+    and phi = sum over these modes of K(k) times their amplitude (K = c_N/|k|^2,
+    the k = 0 mode dropped).  e = None: no gamma field, which means gamma = 1."""
+    n, L = (32, 64), (2 * np.pi * 2, 2 * np.pi * 4)
+    cN, A, d = 0.7, 0.4, 0.25
+    absent = e is None
+    e = 0.0 if absent else e
+    y = inputs.axis_coords(n[0], L[0])[:, None]
+    x = inputs.axis_coords(n[1], L[1])[None, :]
+    q = np.array([1.0, 0.5])    # wavevectors on the grid (2 pi m / L)
+    p = np.array([0.5, 1.25])
+    cq = np.cos(q[0] * y + q[1] * x)
+    cp = np.cos(p[0] * y + p[1] * x)
+    rho, gam, bet = 1 + A * cq, 1 + e * cp, d * cp
+    phi = orc.potential_fields(rho, L, (cN, 0, 0, 0), None if absent else gam, bet)
+    K = lambda v: cN / (v[0] ** 2 + v[1] ** 2)
+    c = 0.5 * (e * A - d * (q @ q) * A)
+    exact = (K(q) * A * cq + K(p) * e * cp + K(p + q) * c * np.cos((p + q)[0] * y + (p + q)[1] * x)
+             + K(p - q) * c * np.cos((p - q)[0] * y + (p - q)[1] * x))
+    assert np.max(np.abs(phi - exact)) < 1e-12
+
+
+def test_static_potential_harmonic_ground_state():
+    """V = -a |x|^2 / sigma^4 makes psi0 = exp(-|x|^2/(2 sigma^2)) an eigenstate:
+    -a lap psi0 - V psi0 = (a D / sigma^2) psi0, so psi(t) = psi0 exp(-i a D t / sigma^2);
+    the split step approaches it at second order."""
+    n, L, a, sig, T = (64, 64), (24.0, 24.0), 0.5, 1.5, 0.4
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    r2 = xs[0] ** 2 + xs[1] ** 2
+    psi0 = np.exp(-r2 / (2 * sig * sig)).astype(complex)
+    V = -a * r2 / sig ** 4
+    exact = psi0 * np.exp(-1j * a * 2 * T / sig ** 2)
+    errs = []
+    for steps in (20, 40):
+        out = orc.evolve_fields(psi0, L, (0, 0, 0, 0), a, 0.0, T / steps, steps, (None, None, V))
+        errs.append(orc.rel_l2(out, exact))
+    assert errs[0] < 1e-2
+    assert 3.5 < errs[0] / errs[1] < 4.5, errs
+    # the wrong sign of V spreads the state instead
+    out = orc.evolve_fields(psi0, L, (0, 0, 0, 0), a, 0.0, T / 40, 40, (None, None, -V))
+    assert orc.rel_l2(out, exact) > 0.1
+
+
+def test_nmc_fields_identities_and_gr_limit():
+    """Eq. (9)-(11): with u = (r0/(r+r0))^lambda, beta = 2 d(gamma)/dr (from
+    d u/dr = -lambda u/(r+r0)) and phi_C = ln(2 gamma); for lambda -> infinity the
+    coupling reaches General Relativity (gamma = 1/2, beta = 0, phi_C = 0) away
+    from the centre."""
+    n, L, r0, nu = (4096,), (64.0,), 2.0, 1.3
+    x = inputs.axis_coords(n[0], L[0])
+    dx = L[0] / n[0]
+    for lam in (1.0, 2.5):
+        gm, bt, V = orc.nmc_fields(n, L, lam, r0, nu)
+        sel = (x > 1.0) & (x < 30.0)
+        dg = (np.roll(gm, -1) - np.roll(gm, 1)) / (2 * dx)   # r = x on x > 0
+        assert np.max(np.abs(bt[sel] - 2 * dg[sel])) < 1e-4 * np.max(bt[sel])   # O(dx^2) difference
+        assert np.max(np.abs(-nu * V[sel] - np.log(2 * gm[sel]))) < 1e-13
+    gm, bt, V = orc.nmc_fields(n, L, 400.0, r0, nu)
+    far = np.abs(x) > 8.0
+    assert np.max(np.abs(gm[far] - 0.5)) < 1e-12 and np.max(bt[far]) < 1e-12
+    assert np.max(np.abs(V[far])) < 1e-12
