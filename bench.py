@@ -209,12 +209,14 @@ def corrector_bench(ntrain, epochs, neval, ncoarse, tol):
             "ms_coarse": 1e3 * ev["t_coarse"] / neval, "speedup": ev["t_fine"] / ev["t_corrected"]}
 
 
-def eq15_bench(steps, autotune_iters, profile_steps):
-    """The 256^3 Eq. (15) fluid (pressure and Bohm terms on): step rate, the
-    per-pass times and the roofline of its dominant pass, and its invariants."""
+def eq15_bench(steps, autotune_iters, profile_steps, workload="gsn3d_256_eq15"):
+    """A 256^3 Eq. (15) fluid (pressure and Bohm terms on; with "nmc" in the
+    workload also the position-dependent coupling of Eq. (9)-(12)): step rate,
+    the per-pass times and the roofline of its dominant pass, and its
+    invariants (no energy with source fields)."""
     import torch
     from paper_1909_08354_amd import gsn, inputs
-    w = inputs.WORKLOADS["gsn3d_256_eq15"]
+    w = inputs.WORKLOADS[workload]
     n, L = w["n"], w["L"]
     P = int(np.prod(n))
     psi0 = inputs.fluid_gaussian(n, L, w["mass"], w["waist"], seed=w["seed"])
@@ -222,12 +224,16 @@ def eq15_bench(steps, autotune_iters, profile_steps):
     grid.set_kernel(*w["kern"])
     grid.set_coefficients(w["a"], w["g"], w["dz"])
     grid.set_local_terms(*w["local"])
+    fields = None
+    if "nmc" in w:
+        fields = grid.nmc_fields(w["nmc"]["lam"], w["nmc"]["r0"], w["nmc"]["nu"])
+        grid.set_source_fields(*fields)
     dev0 = torch.from_numpy(inputs.to_c64(psi0)).cuda()
     grid.set_psi(dev0)
     schedule = grid.autotune(autotune_iters) if autotune_iters > 0 else grid.schedule()
     grid.set_psi(dev0)
     m0 = grid.mass()
-    e0 = grid.energy()
+    e0 = grid.energy() if fields is None else None
     grid.step(10)
     grid.sync()
     torch.cuda.synchronize()
@@ -237,7 +243,7 @@ def eq15_bench(steps, autotune_iters, profile_steps):
     elapsed = time.perf_counter() - t0
     grid.sync()
     m1 = grid.mass()
-    e1 = grid.energy()
+    e1 = grid.energy() if fields is None else None
     prof = grid.profile_passes(profile_steps)
     bpp = dict(zip(grid.pass_names(), grid.pass_bytes_per_point()))
     steady = {k: v for k, v in prof.items() if k not in ("x_entry_fft", "x_exit_ifft") and bpp[k] > 0}
@@ -245,9 +251,12 @@ def eq15_bench(steps, autotune_iters, profile_steps):
     achieved = bpp[dom] * P / (steady[dom] * 1e-3) / 1e9
     step_bytes = sum(bpp[k] for k in steady) * P
     ms = 1e3 * elapsed / steps
-    scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
     grid.close()
-    return {"workload": "gsn3d_256_eq15", "grid": list(n), "local": list(w["local"]),
+    edrift = None
+    if e0 is not None:
+        scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
+        edrift = abs(e1["total"] - e0["total"]) / scale
+    return {"workload": workload, "grid": list(n), "local": list(w["local"]), "nmc": w.get("nmc"),
             "kernel": list(w["kern"]), "steps": steps, "value": P * steps / elapsed,
             "unit": "grid-pt updates/s", "ms_per_step": ms,
             "model_bytes_per_point": step_bytes / P,
@@ -256,7 +265,7 @@ def eq15_bench(steps, autotune_iters, profile_steps):
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                          "algorithmic_bytes_per_launch": bpp[dom] * P, "avg_launch_ms": steady[dom]},
             "pass_ms": {k: round(v, 5) for k, v in steady.items()}, "schedule": schedule,
-            "norm_drift": abs(m1 / m0 - 1), "energy_drift": abs(e1["total"] - e0["total"]) / scale}
+            "norm_drift": abs(m1 / m0 - 1), "energy_drift": edrift}
 
 
 def main():
@@ -273,7 +282,8 @@ def main():
                     help="training trajectories of the corrector leg (0 skips it)")
     ap.add_argument("--corrector-epochs", type=int, default=4)
     ap.add_argument("--eq15-steps", type=int, default=200,
-                    help="steps of the 256^3 Eq. (15) fluid leg (0 skips it)")
+                    help="steps of the 256^3 Eq. (15) fluid legs, without and with the "
+                         "non-minimal coupling (0 skips them)")
     ap.add_argument("--corrector-eval", type=int, default=100)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
@@ -363,12 +373,15 @@ def main():
         "corrected_speedup": None,
         "corrected": None,
         "eq15": None,
+        "nmc": None,
     }
     if args.batch_steps > 0 or args.corrector_train > 0 or args.eq15_steps > 0:
         grid.close()
         del grid
     if args.eq15_steps > 0:
         line["eq15"] = eq15_bench(args.eq15_steps, min(args.autotune_iters, 5), args.profile_steps)
+        line["nmc"] = eq15_bench(args.eq15_steps, min(args.autotune_iters, 5), args.profile_steps,
+                                 "gsn3d_256_nmc")
     if args.batch_steps > 0:
         line["batched"] = batch_bench(args.batch_steps)
         line["batched_speedup"] = line["batched"]["speedup"]

@@ -123,6 +123,34 @@ gsn_status gsn_set_equation(gsn_grid grid, double A, double B, double C, double 
 gsn_status gsn_set_local_terms(gsn_grid grid, double c_pressure, double n_pressure, double c_bohm,
                                double rho_floor);
 
+/* Position-dependent coupling (Eq. (9)-(12)) and a static potential: the
+   kernel acts on the source s = gamma(x) rho + beta(x) lap(rho) instead of rho,
+   and V_ext(x) joins the phase, i psi_z = ... - (U + phi + V_ext) psi.  gamma,
+   beta and V_ext are device arrays of P floats in C order, owned by the caller;
+   the grid reads them on every step until they are replaced or cleared (pass
+   NULL for an absent field: gamma = 1, beta = 0, V_ext = 0), so they must stay
+   alive and unchanged meanwhile.  The pure non-minimal coupling of Eq. (12)
+   (alpha = 0), lap phi_N = beta lap rho + gamma rho, with phi_C of Eq. (11), is
+   c_newton = 1/nu with V_ext = -phi_C/nu (gsn_nmc_fields fills all three).
+   beta adds the passes "y_fwd_src", "lap_rho", "y_inv_src" and every source
+   field the x pass "x_source".  While gamma or beta is set the kernel must have
+   K(0) = 0 (no screened or contact part: stepping returns GSN_EUNSUPPORTED),
+   and gsn_energy, gsn_potential and gsn_step_corrected return
+   GSN_EUNSUPPORTED (gsn_energy also with V_ext alone).  Synchronising. */
+gsn_status gsn_set_source_fields(gsn_grid grid, const float *gamma, const float *beta, const float *V_ext);
+
+/* Fill caller device arrays of P floats with the fields of the pure
+   non-minimal coupling on this grid's points (Eq. (9)-(11)): with r the
+   periodic (minimum-image) distance from center (ndim doubles; NULL = the
+   origin) and u = (r0 / (r + r0))^lambda,
+     gamma = (1 - u) / 2,  beta = lambda u / (r + r0),  V_ext = -ln(1 - u) / nu,
+   the last with r raised to r_min, since phi_C = ln(1 - u) diverges at the
+   centre.  r0 = M / (4 pi) is the Schwarzschild radius of the mass M.  Any
+   output may be NULL.  lambda, r0, r_min > 0 and nu != 0, else GSN_EINVAL.
+   Synchronising. */
+gsn_status gsn_nmc_fields(gsn_grid grid, double lambda, double r0, double nu, const double *center,
+                          double r_min, float *gamma, float *beta, float *V_ext);
+
 /* Load psi (P complex values, C order) from host (src_on_device = 0) or
    device memory, as complex64 or complex128.  Resets the global phase and the
    step count.  Synchronising for host sources. */

@@ -88,16 +88,20 @@ const NKernels *kernels_for(int N, int v)
 
 
 // ------------------------------------------------------------------ passes
-// The last three carry sqrt(rho) to lap(sqrt rho) for the Bohm potential of
-// Eq. (15); they run only while that term is on (the 2-D grid uses only the
-// Laplacian column pass).
+// After the ten passes of the model: three that carry sqrt(rho) to
+// lap(sqrt rho) for the Bohm potential of Eq. (15), three that carry rho to
+// lap(rho) and the x pass that forms the source gamma rho + beta lap(rho) of the
+// position-dependent coupling; each runs only while its term is on (a 2-D
+// grid uses only the Laplacian column passes).
 enum PassId {
     P_ENTRY = 0, P_Y_FWD_PSI, P_KINETIC, P_Y_INV_PSI, P_DENSITY, P_Y_FWD_RHO, P_KERNEL,
-    P_Y_INV_PHI, P_PHASE, P_EXIT, P_Y_FWD_SQRT, P_LAPLACIAN, P_Y_INV_LAP, P_COUNT
+    P_Y_INV_PHI, P_PHASE, P_EXIT, P_Y_FWD_SQRT, P_LAPLACIAN, P_Y_INV_LAP, P_Y_FWD_SRC,
+    P_LAP_RHO, P_Y_INV_SRC, P_SOURCE, P_COUNT
 };
 static const char *kPassNames[P_COUNT] = {
     "x_entry_fft", "y_fwd_psi", "kinetic", "y_inv_psi", "x_density", "y_fwd_rho",
-    "kernel", "y_inv_phi", "x_phase", "x_exit_ifft", "y_fwd_sqrt", "laplacian", "y_inv_lap"};
+    "kernel", "y_inv_phi", "x_phase", "x_exit_ifft", "y_fwd_sqrt", "laplacian", "y_inv_lap",
+    "y_fwd_src", "lap_rho", "y_inv_src", "x_source"};
 
 struct Launch {
     const void *fn;
@@ -140,6 +144,8 @@ struct gsn_grid_ {
     double mY2;                // squared screening mass of K; -C of Eq. (2) (may be < 0)
     double lp_cp, lp_n, lp_cb, lp_floor;   // local terms of Eq. (15)
     bool local_on, bohm_on;
+    // position-dependent coupling: caller-owned device fields (null: absent)
+    const float *fld_gamma, *fld_beta, *fld_V;
     bool have_dz, have_psi;
     // launch schedules
     std::vector<Launch> entry, kin_half, kin_full, nonlin, exit_, energy_rho, energy_kin;
@@ -342,6 +348,9 @@ static EmArgs em_base(gsn_grid g, float2 *psi)
     a.scale = 1.0;
     a.half2 = g->half2;
     a.nyq2 = g->nyq2;
+    a.gam = g->fld_gamma;
+    a.bet = g->fld_beta;
+    a.vext = g->fld_V;
     if (g->local_on) {
         const double n = g->lp_n, fl = g->lp_floor;
         a.cp = g->lp_cp;
@@ -441,6 +450,48 @@ static void build_core(gsn_grid g)
             dst.push_back(em_launch(store ? KX(P_DENSITY)->density_store : KX(P_DENSITY)->density,
                                     KX(P_DENSITY), d, P_DENSITY));
         }
+        if (g->fld_gamma || g->fld_beta) {
+            // rho -> lap(rho) through the other axes, then the source pass
+            if (g->fld_beta) {
+                if (nd == 3) {
+                    const NKernels *ky = KY(P_Y_FWD_SRC), *ky2 = KY(P_Y_INV_SRC);
+                    const LKernels *lz = local_kernels_for(Nz, g->var[P_LAP_RHO]);
+                    LmArgs e = lm_base(g, g->tw[Y], 1.0);
+                    e.s0 = make_seg(g->half, H, 1, (long long)Ny * H, H, Nz, ky->lm_lines);
+                    e.s1 = make_seg(g->nyq, 1, Ny, 0, Nz, 1, ky->lm_lines);
+                    dst.push_back(lm_launch(ky->lm_fwd, ky, e, P_Y_FWD_SRC));
+                    LmArgs f = lm_base(g, g->tw[Z], 1.0 / ((double)Ny * Nz));
+                    f.s0 = make_seg(g->half, (long long)Ny * H, 1, H, H, Ny, KZ(P_LAP_RHO)->lm_lines);
+                    f.s0.c1l = 1;
+                    f.s0.c2o = 1;
+                    f.s1 = make_seg(g->nyq, Ny, 1, 0, Ny, 1, KZ(P_LAP_RHO)->lm_lines);
+                    f.s1.c1f = H;
+                    f.s1.c2l = 1;
+                    f.k2_1 = g->k2[X];
+                    f.k2_2 = g->k2[Y];
+                    f.k2_p = g->k2[Z];
+                    dst.push_back(lm_launch(lz->lm_lap, KZ(P_LAP_RHO), f, P_LAP_RHO));
+                    LmArgs gg = lm_base(g, g->tw[Y], 1.0);
+                    gg.s0 = make_seg(g->half, H, 1, (long long)Ny * H, H, Nz, ky2->lm_lines);
+                    gg.s1 = make_seg(g->nyq, 1, Ny, 0, Nz, 1, ky2->lm_lines);
+                    dst.push_back(lm_launch(ky2->lm_inv, ky2, gg, P_Y_INV_SRC));
+                } else {
+                    const LKernels *ly = local_kernels_for(Ny, g->var[P_LAP_RHO]);
+                    LmArgs f = lm_base(g, g->tw[Y], 1.0 / (double)Ny);
+                    f.s0 = make_seg(g->half, H, 1, 0, H, 1, KY(P_LAP_RHO)->lm_lines);
+                    f.s0.c1l = 1;
+                    f.s1 = make_seg(g->nyq, 1, 0, 0, 1, 1, KY(P_LAP_RHO)->lm_lines);
+                    f.s1.c1f = H;
+                    f.k2_1 = g->k2[X];
+                    f.k2_p = g->k2[Y];
+                    dst.push_back(lm_launch(ly->lm_lap, KY(P_LAP_RHO), f, P_LAP_RHO));
+                }
+            }
+            EmArgs sa = em_base(g, src);
+            sa.nlines = (int)(rows / 2);
+            const LKernels *lk = local_kernels_for(Nx, g->var[P_SOURCE]);
+            dst.push_back(em_launch(lk->source[store ? 1 : 0][g->fld_beta ? 1 : 0], KX(P_SOURCE), sa, P_SOURCE));
+        }
         if (nd == 3) {
             const NKernels *ky = KY(P_Y_FWD_RHO), *kz = KZ(P_KERNEL), *ky2 = KY(P_Y_INV_PHI);
             LmArgs e = lm_base(g, g->tw[Y], 1.0);
@@ -534,7 +585,7 @@ static void build_core(gsn_grid g)
         h.g = g->g;
         h.dz = g->dz;
         h.partials = g->epart;
-        if (g->local_on) {
+        if (g->local_on || g->fld_V) {
             const LKernels *lk = local_kernels_for(Nx, g->var[P_PHASE]);
             dst.push_back(em_launch(energy ? lk->phase_energy : store ? lk->phase_real : lk->phase,
                                     KX(P_PHASE), h, P_PHASE));
@@ -740,6 +791,7 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
     g->lp_cp = g->lp_cb = g->lp_floor = 0.0;
     g->lp_n = 1.0;
     g->local_on = g->bohm_on = false;
+    g->fld_gamma = g->fld_beta = g->fld_V = nullptr;
     if (hipGetDevice(&g->device) != hipSuccess) {
         delete g;
         return fail(GSN_EHIP, "hipGetDevice failed");
@@ -887,6 +939,37 @@ extern "C" gsn_status gsn_set_local_terms(gsn_grid g, double c_pressure, double 
     return GSN_OK;
 }
 
+extern "C" gsn_status gsn_set_source_fields(gsn_grid g, const float *gamma, const float *beta, const float *V_ext)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->fld_gamma = gamma;
+    g->fld_beta = beta;
+    g->fld_V = V_ext;
+    build_schedule(g);
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_nmc_fields(gsn_grid g, double lambda, double r0, double nu, const double *center,
+                                     double r_min, float *gamma, float *beta, float *V_ext)
+{
+    if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (!(std::isfinite(lambda) && lambda > 0.0) || !(std::isfinite(r0) && r0 > 0.0) || !std::isfinite(nu) ||
+        nu == 0.0 || !(std::isfinite(r_min) && r_min > 0.0))
+        return fail(GSN_EINVAL, "need lambda > 0, r0 > 0, nu != 0 and r_min > 0, all finite");
+    double c[3] = {0.0, 0.0, 0.0};
+    if (center)
+        for (int d = 0; d < g->ndim; ++d) {
+            if (!std::isfinite(center[d])) return fail(GSN_EINVAL, "centre must be finite");
+            c[d] = center[d];
+        }
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(launch_nmc_fields(g->ndim, g->n, g->L, c, lambda, r0, nu, r_min, gamma, beta, V_ext, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return GSN_OK;
+}
+
 extern "C" gsn_status gsn_set_coefficients(gsn_grid g, double a_kin, double g_local, double dz)
 {
     if (!g) return fail(GSN_EINVAL, "grid is NULL");
@@ -935,6 +1018,8 @@ static gsn_status ready(gsn_grid g)
     if (!g) return fail(GSN_EINVAL, "grid is NULL");
     if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
     if (!g->have_dz) return fail(GSN_ESTATE, "coefficients (dz) not set");
+    if ((g->fld_gamma || g->fld_beta) && kernel_k0(g) != 0.0)
+        return fail(GSN_EUNSUPPORTED, "source fields need a kernel with K(0) = 0 (no screened or contact part)");
     return GSN_OK;
 }
 
@@ -1057,6 +1142,8 @@ extern "C" gsn_status gsn_energy(gsn_grid g, double e[4])
     if (!e) return fail(GSN_EINVAL, "e is NULL");
     gsn_status s = g ? GSN_OK : fail(GSN_EINVAL, "grid is NULL");
     if (s) return s;
+    if (g->fld_gamma || g->fld_beta || g->fld_V)
+        return fail(GSN_EUNSUPPORTED, "no energy with position-dependent source fields or a static potential");
     if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
     HIP_TRY(hipSetDevice(g->device));
     HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, 8ull * g->P, hipMemcpyDeviceToDevice, g->stream));
@@ -1104,9 +1191,15 @@ extern "C" double gsn_pass_bytes_per_point(gsn_grid g, int i)
     case P_ENTRY: case P_EXIT: case P_Y_FWD_PSI: case P_Y_INV_PSI: case P_KINETIC: return 16.0;
     case P_DENSITY: return (g->store_psi ? 20.0 : 12.0) + (g->bohm_on ? 4.0 : 0.0);
     case P_Y_FWD_RHO: case P_KERNEL: case P_Y_INV_PHI: return 8.0;
-    case P_PHASE: return 20.0 + (g->bohm_on ? 4.0 : 0.0);
+    case P_PHASE: return 20.0 + (g->bohm_on ? 4.0 : 0.0) + (g->fld_V ? 4.0 : 0.0);
     case P_Y_FWD_SQRT: case P_Y_INV_LAP: return g->bohm_on && g->ndim == 3 ? 8.0 : 0.0;
     case P_LAPLACIAN: return g->bohm_on ? 8.0 : 0.0;
+    case P_Y_FWD_SRC: case P_Y_INV_SRC: return g->fld_beta && g->ndim == 3 ? 8.0 : 0.0;
+    case P_LAP_RHO: return g->fld_beta ? 8.0 : 0.0;
+    case P_SOURCE:
+        if (!(g->fld_gamma || g->fld_beta)) return 0.0;
+        // psi in, s spectrum out, lap(rho) spectrum and fields in
+        return 12.0 + (g->fld_beta ? 8.0 : 0.0) + (g->fld_gamma ? 4.0 : 0.0);
     default: return 0.0;
     }
 }
@@ -1255,6 +1348,7 @@ static std::string cache_key(gsn_grid g, int p)
     for (int d = 0; d < g->ndim; ++d) k << (d ? "x" : " ") << g->n[d];
     k << " " << (p < P_COUNT ? kPassNames[p] : "nonlinear_mode");
     if (g->local_on) k << (g->bohm_on ? "+eq15b" : "+eq15");
+    if (g->fld_gamma || g->fld_beta || g->fld_V) k << "+fields";
     return k.str();
 }
 
@@ -1398,6 +1492,7 @@ static gsn_status run_potential(gsn_grid g, float *dst)
 extern "C" gsn_status gsn_potential(gsn_grid g, float *phi_dev)
 {
     if (!g || !phi_dev) return fail(GSN_EINVAL, "NULL argument");
+    if (g->fld_gamma || g->fld_beta) return fail(GSN_EUNSUPPORTED, "no potential readout with source fields");
     if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
     HIP_TRY(hipSetDevice(g->device));
     return run_potential(g, phi_dev);
@@ -1432,6 +1527,7 @@ extern "C" gsn_status gsn_step_corrected(gsn_grid g, gsn_corrector c, int64_t nc
     if (s) return s;
     if (!c) return fail(GSN_EINVAL, "corrector is NULL");
     if (g->ndim != 2) return fail(GSN_EUNSUPPORTED, "the corrector works on 2-D grids");
+    if (g->fld_gamma || g->fld_beta) return fail(GSN_EUNSUPPORTED, "no corrected steps with source fields");
     if (corrector_height(c) != g->n[0] || corrector_width(c) != g->n[1])
         return fail(GSN_EINVAL, "corrector image size differs from the grid");
     if (g->coarse_ratio <= 0) return fail(GSN_ESTATE, "no coarse ratio set");

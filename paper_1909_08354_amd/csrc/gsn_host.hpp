@@ -96,8 +96,14 @@ struct LKernels {
     void (*phase_real)(EmArgs);
     void (*phase_energy)(EmArgs);
     void (*lm_lap)(LmArgs);          // FFT, -|k|^2, inverse FFT
+    void (*source[2][2])(EmArgs);    // [real-space psi in][lap(rho) in]
 };
 const LKernels *local_kernels_for(int N, int v = 0);
+
+// Fill the non-minimal-coupling fields (any output may be null) of an ndim
+// grid with extents n, lengths L and centre c on the stream.
+hipError_t launch_nmc_fields(int ndim, const int *n, const double *L, const double *c, double lambda, double r0,
+                             double nu, double r_min, float *gamma, float *beta, float *V, hipStream_t stream);
 
 // Blocks of kernel fn (threads per block) resident on the whole device at
 // once (occupancy x compute units): the grid of a persistent kernel; 0 if

@@ -56,6 +56,10 @@ struct EmArgs {
     double f_fl, F_fl;    // f and its antiderivative F at the floor (pressure energy)
     int pmode;            // 0: no pressure term, 1: ln rho, 2: power law
     int bohm;             // 1: Bohm term
+    // position-dependent coupling (Eq. (9)-(12)): the kernel acts on
+    // s = gam rho + bet lap(rho); vext joins the phase (real fields of P
+    // values, C order; null: gam = 1, bet = 0, vext = 0)
+    const float *gam, *bet, *vext;
 };
 
 template <int N, int E> struct EmShape {
@@ -389,6 +393,20 @@ __host__ __device__ __forceinline__ double exp_fp64(double y)
     return ldexp(p, (int)k);
 }
 
+// Fields of the pure non-minimal coupling, Eq. (9)-(11), at distance r from
+// the centre: u = (r0/(r + r0))^lambda, gamma = (1 - u)/2, beta = lambda u/(r + r0),
+// V = -ln(1 - u_c)/nu with u_c at max(r, r_min) (phi_C diverges at r = 0).
+__host__ __device__ __forceinline__ void nmc_point(double r, double lambda, double r0, double nu, double r_min,
+                                                   double *gamma, double *beta, double *V)
+{
+    const double u = exp_fp64(lambda * log_fp64(r0 / (r + r0)));
+    *gamma = 0.5 * (1.0 - u);
+    *beta = lambda * u / (r + r0);
+    const double rc = fmax(r, r_min);
+    const double uc = exp_fp64(lambda * log_fp64(r0 / (rc + r0)));
+    *V = -log_fp64(1.0 - uc) / nu;
+}
+
 // The table sincos_tab reads, computed in extended precision and rounded.
 inline void fill_sincos_table(double2 *tab)
 {
@@ -572,6 +590,11 @@ __device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, floa
 #pragma unroll
             for (int e = 0; e < E; ++e) lap[e] = half ? lap1[e] : lap0[e];
             local_potential<E>(a, rho, lap, U);
+            if (a.vext && act) {   // uniform pointer; rows past the grid read nothing
+                const float *vr = a.vext + (half ? r1 : r0) * N;
+#pragma unroll
+                for (int e = 0; e < E; ++e) U[e] += (double)vr[t + TPL * e];
+            }
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 double sn, cs;
@@ -599,6 +622,64 @@ __device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, floa
             a.partials[4 * tile + 3] = b3;
         }
     }
+}
+
+// Source pass of the position-dependent coupling (Eq. (12) with coefficient
+// fields): for two rows, s = gam rho + bet lap(rho) with rho = |psi|^2 (psi
+// x-spectral, or real-space with REAL_IN) and, with LAP, lap(rho) from the
+// rows' half spectra (already carried through the other axes with -|k|^2);
+// then the real transform of s replaces those half spectra in place (each
+// tile reads its own two rows before writing them).
+template <int N, int E, int LINES, bool REAL_IN, bool LAP>
+__device__ __forceinline__ void source_tile(const EmArgs &a, int tile, float2 *lds)
+{
+    constexpr int TPL = N / E;
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    const int pair = tile * LINES + l;
+    const bool act = pair < a.nlines;
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
+    const long long r0 = 2LL * pair, r1 = r0 + 1;
+    const double inv_n = 1.0 / N;
+    const double rs = REAL_IN ? 1.0 : inv_n * inv_n;
+    dc z[E];
+    float lap0[E], lap1[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        lap0[e] = 0.0f;
+        lap1[e] = 0.0f;
+    }
+    if constexpr (LAP) {
+        load_real_pair<N, E>(a.half, a.nyq, act, t, r0, r1, z);
+        fft<N, E, 1>(z, t, lay, lds, a.tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            lap0[e] = (float)(z[e].x * inv_n);
+            lap1[e] = (float)(z[e].y * inv_n);
+        }
+    }
+    double s0[E];
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        const long long r = h ? r1 : r0;
+        const float2 *p = a.psi + r * N;
+        dc v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+        if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = t + TPL * e;
+            const double rho = norm2(v[e]) * rs;
+            double sv = (a.gam && act) ? (double)a.gam[r * N + i] * rho : rho;
+            if constexpr (LAP) {
+                if (a.bet && act) sv = fma((double)a.bet[r * N + i], (double)(h ? lap1[e] : lap0[e]), sv);
+            }
+            if (h) z[e] = mk(s0[e], sv);
+            else s0[e] = sv;
+        }
+    }
+    fft<N, E, -1>(z, t, lay, lds, a.tw);
+    store_real_pair<N, E>(z, act, t, lay, lds, a.half, a.nyq, r0, r1);
 }
 
 // ---------------------------------------------------------------- LM passes
@@ -1234,6 +1315,12 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
     __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
     density_tile<N, E, LINES, STORE_PSI, false, BOHM>(a, blockIdx.x, lds, sh);
+}
+template <int N, int E, int LINES, bool REAL_IN, bool LAP>
+__global__ __launch_bounds__(LINES *(N / E)) void k_source(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    source_tile<N, E, LINES, REAL_IN, LAP>(a, blockIdx.x, lds);
 }
 template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
 __global__ __launch_bounds__(LINES *(N / E)) void k_phase_local(EmArgs a)

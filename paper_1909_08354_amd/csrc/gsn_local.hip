@@ -20,6 +20,10 @@ template <int N, int V> static LKernels make_local_kernels()
     k.phase_real = k_phase_local<N, E, EL, false, true>;
     k.phase_energy = k_phase_local<N, E, EL, true, false>;
     k.lm_lap = k_lm<N, E, LL, LM_LAP>;
+    k.source[0][0] = k_source<N, E, EL, false, false>;
+    k.source[0][1] = k_source<N, E, EL, false, true>;
+    k.source[1][0] = k_source<N, E, EL, true, false>;
+    k.source[1][1] = k_source<N, E, EL, true, true>;
     return k;
 }
 
@@ -29,6 +33,33 @@ template <int N> static const LKernels *local_table(int v)
     static const LKernels k[3] = {make_local_kernels<N, 0>(), make_local_kernels<N, 1>(),
                                   make_local_kernels<N, 4>()};
     return &k[v == 4 ? 2 : (v & 1)];
+}
+
+// Fields of the non-minimal coupling on a grid (see nmc_point): one thread
+// per point, x_j = -L/2 + j L/N per axis, minimum-image distance from c.
+__global__ void k_nmc_fields(int ndim, int n0, int n1, int n2, double L0, double L1, double L2, double c0,
+                             double c1, double c2, double lambda, double r0, double nu, double r_min,
+                             float *gamma, float *beta, float *V, long long P)
+{
+    const int n[3] = {n0, n1, n2};
+    const double L[3] = {L0, L1, L2}, c[3] = {c0, c1, c2};
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < P;
+         q += (long long)gridDim.x * blockDim.x) {
+        long long rem = q;
+        double r2 = 0.0;
+        for (int d = ndim - 1; d >= 0; --d) {
+            const int j = (int)(rem % n[d]);
+            rem /= n[d];
+            double x = -0.5 * L[d] + j * (L[d] / n[d]) - c[d];
+            x -= L[d] * floor(x / L[d] + 0.5);
+            r2 += x * x;
+        }
+        double gm, bt, v;
+        nmc_point(sqrt(r2), lambda, r0, nu, r_min, &gm, &bt, &v);
+        if (gamma) gamma[q] = (float)gm;
+        if (beta) beta[q] = (float)bt;
+        if (V) V[q] = (float)v;
+    }
 }
 
 const LKernels *local_kernels_for(int N, int v)
@@ -46,4 +77,21 @@ const LKernels *local_kernels_for(int N, int v)
     case 2048: return local_table<2048>(v);
     default: return nullptr;
     }
+}
+
+hipError_t launch_nmc_fields(int ndim, const int *n, const double *L, const double *c, double lambda, double r0,
+                             double nu, double r_min, float *gamma, float *beta, float *V, hipStream_t stream)
+{
+    long long P = 1;
+    int nn[3] = {1, 1, 1};
+    double LL[3] = {1.0, 1.0, 1.0}, cc[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < ndim; ++d) {
+        nn[d] = n[d];
+        LL[d] = L[d];
+        cc[d] = c[d];
+        P *= n[d];
+    }
+    hipLaunchKernelGGL(k_nmc_fields, dim3(2048), dim3(256), 0, stream, ndim, nn[0], nn[1], nn[2], LL[0], LL[1],
+                       LL[2], cc[0], cc[1], cc[2], lambda, r0, nu, r_min, gamma, beta, V, P);
+    return hipGetLastError();
 }

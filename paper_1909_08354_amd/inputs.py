@@ -105,6 +105,14 @@ WORKLOADS = {
         n=(256, 256, 256), L=(256.0, 256.0, 256.0), kern=(0.5, 0.0, 0.0, 0.0), a=0.5,
         g=0.0, local=(-1.02, 1.0, -1.0, 1e-10), dz=5e-4, steps=200, seed=5, mass=25.0,
         waist=6.0, ic="Gaussian number density, total mass 25, waist 6, phase noise 1e-3"),
+    # the same fluid under the pure non-minimal coupling (Eq. (9)-(12), alpha = 0,
+    # lambda = 1, r0 = M0 / (4 pi)), with c_newton = 1/nu acting on the source
+    # gamma rho + beta lap(rho) and V = -phi_C / nu
+    "gsn3d_256_nmc": dict(
+        n=(256, 256, 256), L=(256.0, 256.0, 256.0), kern=(1.0, 0.0, 0.0, 0.0), a=0.5,
+        g=0.0, local=(-1.02, 1.0, -1.0, 1e-10), dz=5e-4, steps=200, seed=5, mass=25.0,
+        waist=6.0, nmc=dict(lam=1.0, r0=25.0 / (4 * np.pi), nu=1.0),
+        ic="Gaussian number density, total mass 25, waist 6, phase noise 1e-3"),
     "gsn2d_512_corrector": dict(
         n=(512, 512), L=(512.0, 512.0), kern=(1.0, 0.0, 0.0, 0.0), a=0.5, g=-0.5,
         dz_fine=5e-3, ratio=8, train_seeds=(10000, 12000), heldout_seeds=(20000, 20100),
