@@ -569,6 +569,15 @@ __device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, floa
         dc v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+        // the static potential of the row, loaded before the transform
+        float vx[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) vx[e] = 0.0f;
+        if (!ENERGY && a.vext) {   // uniform pointer
+            const float *vr = a.vext + (act ? (half ? r1 : r0) * N + t : 0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) vx[e] = vr[TPL * e];
+        }
         if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
         double rho[E];
 #pragma unroll
@@ -590,11 +599,8 @@ __device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, floa
 #pragma unroll
             for (int e = 0; e < E; ++e) lap[e] = half ? lap1[e] : lap0[e];
             local_potential<E>(a, rho, lap, U);
-            if (a.vext && act) {   // uniform pointer; rows past the grid read nothing
-                const float *vr = a.vext + (half ? r1 : r0) * N;
 #pragma unroll
-                for (int e = 0; e < E; ++e) U[e] += (double)vr[t + TPL * e];
-            }
+            for (int e = 0; e < E; ++e) U[e] += (double)vx[e];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 double sn, cs;
@@ -665,15 +671,28 @@ __device__ __forceinline__ void source_tile(const EmArgs &a, int tile, float2 *l
         dc v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+        // the row's coefficients, loaded before the transform so the loads
+        // overlap it (uniform branches on the field pointers)
+        float gv[E], bv[E];
+        const long long fo = act ? r * N + t : 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            gv[e] = 1.0f;
+            bv[e] = 0.0f;
+        }
+        if (a.gam) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) gv[e] = a.gam[fo + TPL * e];
+        }
+        if (LAP && a.bet) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) bv[e] = a.bet[fo + TPL * e];
+        }
         if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int i = t + TPL * e;
-            const double rho = norm2(v[e]) * rs;
-            double sv = (a.gam && act) ? (double)a.gam[r * N + i] * rho : rho;
-            if constexpr (LAP) {
-                if (a.bet && act) sv = fma((double)a.bet[r * N + i], (double)(h ? lap1[e] : lap0[e]), sv);
-            }
+            double sv = (double)gv[e] * (norm2(v[e]) * rs);
+            if constexpr (LAP) sv = fma((double)bv[e], (double)(h ? lap1[e] : lap0[e]), sv);
             if (h) z[e] = mk(s0[e], sv);
             else s0[e] = sv;
         }
