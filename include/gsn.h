@@ -82,6 +82,19 @@ gsn_status gsn_workspace_bytes(int ndim, const int32_t n[], size_t *bytes);
    Defaults after creation: a = 1/2, g = 0, dz = 0 (must be set), kernel = 0. */
 gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], const double L[],
                       void *d_workspace, size_t bytes, void *hip_stream);
+
+/* The same for a grid whose values live in HBM as complex128 (storage =
+   GSN_C128): psi and the rho / phi half spectra in FP64 and every LDS
+   exchange in FP64, so no value of a step is rounded below double precision
+   (the precision of the paper's own runs); twice the bytes per point.
+   storage = GSN_C64 is gsn_workspace_bytes / gsn_create.  FP64-storage grids
+   run the one-tile-per-block passes in every schedule variant (p16 and p8 use
+   the tile configuration of e16 and e8); the Eq. (15) local terms, source
+   fields, potential readout and corrected steps stay complex64-only
+   (GSN_EUNSUPPORTED).  gsn_set_psi / gsn_get_psi convert either dtype. */
+gsn_status gsn_workspace_bytes_ex(int ndim, const int32_t n[], int storage, size_t *bytes);
+gsn_status gsn_create_ex(gsn_grid *out, int ndim, const int32_t n[], const double L[], int storage,
+                         void *d_workspace, size_t bytes, void *hip_stream);
 gsn_status gsn_destroy(gsn_grid grid);
 
 /* Set the nonlocal kernel (see gsn_kernel).  All values finite. */

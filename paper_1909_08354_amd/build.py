@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libgsn.so")
-SOURCES = ["gsn_api.hip", "gsn_batch.hip", "gsn_corrector.hip", "gsn_local.hip"]
+SOURCES = ["gsn_api.hip", "gsn_batch.hip", "gsn_corrector.hip", "gsn_local.hip", "gsn_c128.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -117,6 +117,8 @@ struct StepLists {
 };
 
 struct gsn_grid_ {
+    int storage;               // GSN_C64 or GSN_C128 (FP64 storage)
+    size_t esz;                // bytes per complex value in HBM (8 or 16)
     int ndim;
     int n[3];
     double L[3];
@@ -179,7 +181,7 @@ static int lm_tiles_main(int nlines, int lines_per_tile, int nouter)
     return ((nlines + lines_per_tile - 1) / lines_per_tile) * nouter;
 }
 
-static Layout compute_layout(int ndim, const int32_t n[])
+static Layout compute_layout(int ndim, const int32_t n[], size_t esz = 8)
 {
     Layout L{};
     const int Nx = n[ndim - 1], Ny = n[ndim - 2], Nz = ndim == 3 ? n[0] : 1;
@@ -199,12 +201,12 @@ static Layout compute_layout(int ndim, const int32_t n[])
     }
     L.lm_blocks_max = lmb;
     size_t off = 0;
-    L.psi = off; off = align256(off + 8ull * P);
-    L.scratch = off; off = align256(off + 8ull * P);
-    L.half = off; off = align256(off + 8ull * (P / 2));
-    L.nyq = off; off = align256(off + 8ull * rows);
-    L.half2 = off; off = align256(off + 8ull * (P / 2));
-    L.nyq2 = off; off = align256(off + 8ull * rows);
+    L.psi = off; off = align256(off + esz * P);
+    L.scratch = off; off = align256(off + esz * P);
+    L.half = off; off = align256(off + esz * (P / 2));
+    L.nyq = off; off = align256(off + esz * rows);
+    L.half2 = off; off = align256(off + esz * (P / 2));
+    L.nyq2 = off; off = align256(off + esz * rows);
     L.mass_parts = off; off = align256(off + 8ull * (size_t)(L.density_blocks > 1024 ? L.density_blocks : 1024));
     size_t ep = 4ull * (size_t)L.density_blocks + (size_t)lmb + 1024;
     L.epart = off; off = align256(off + 8ull * ep);
@@ -224,6 +226,18 @@ extern "C" gsn_status gsn_workspace_bytes(int ndim, const int32_t n[], size_t *b
     if (s) return s;
     if (!bytes) return fail(GSN_EINVAL, "bytes is NULL");
     *bytes = compute_layout(ndim, n).total;
+    return GSN_OK;
+}
+
+static size_t storage_bytes(int storage) { return storage == GSN_C128 ? 16 : 8; }
+
+extern "C" gsn_status gsn_workspace_bytes_ex(int ndim, const int32_t n[], int storage, size_t *bytes)
+{
+    gsn_status s = validate_shape(ndim, n);
+    if (s) return s;
+    if (!bytes) return fail(GSN_EINVAL, "bytes is NULL");
+    if (storage != GSN_C64 && storage != GSN_C128) return fail(GSN_EINVAL, "storage must be GSN_C64 or GSN_C128");
+    *bytes = compute_layout(ndim, n, storage_bytes(storage)).total;
     return GSN_OK;
 }
 
@@ -381,6 +395,12 @@ static double kernel_k0(gsn_grid g)
     return v;
 }
 
+// The kernel table of the grid's storage type.
+static const NKernels *kfor(gsn_grid g, int N, int v)
+{
+    return g->storage == GSN_C128 ? kernels_for_c128(N, v) : kernels_for(N, v);
+}
+
 // Build every launch list from the current parameters (pointers never move).
 static void build_core(gsn_grid g)
 {
@@ -388,10 +408,10 @@ static void build_core(gsn_grid g)
     const int X = nd - 1, Y = nd - 2, Z = 0;   // table indices by axis
     const long long rows = g->P / Nx;
     const int H = Nx / 2;
-    auto KX = [&](int pass) { return kernels_for(Nx, g->var[pass]); };
+    auto KX = [&](int pass) { return kfor(g, Nx, g->var[pass]); };
     g->density_blocks = (int)((rows / 2 + KX(P_DENSITY)->em_lines - 1) / KX(P_DENSITY)->em_lines);
-    auto KY = [&](int pass) { return kernels_for(Ny, g->var[pass]); };
-    auto KZ = [&](int pass) { return kernels_for(Nz, g->var[pass]); };
+    auto KY = [&](int pass) { return kfor(g, Ny, g->var[pass]); };
+    auto KZ = [&](int pass) { return kfor(g, Nz, g->var[pass]); };
     g->entry.clear(); g->kin_half.clear(); g->kin_full.clear(); g->nonlin.clear();
     g->exit_.clear(); g->energy_rho.clear(); g->energy_kin.clear();
 
@@ -657,6 +677,7 @@ static void build_schedule(gsn_grid g)
     // from real space (psi is only read), the potential passes, the C2R
     // readout kernel
     g->pot.clear();
+    if (g->storage == GSN_C128) return;   // no potential readout on FP64-storage grids
     {
         const NKernels *kx = kernels_for(g->Nx, g->var[P_DENSITY]);
         EmArgs d = em_base(g, g->psi);
@@ -755,10 +776,14 @@ static gsn_status upload_static_tables(gsn_grid g)
 }
 
 // ------------------------------------------------------------------ lifecycle
-extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], const double L[],
-                                 void *d_workspace, size_t bytes, void *hip_stream)
+extern "C" gsn_status gsn_create_ex(gsn_grid *out, int ndim, const int32_t n[], const double L[], int storage,
+                                    void *d_workspace, size_t bytes, void *hip_stream)
 {
     if (!out) return fail(GSN_EINVAL, "out is NULL");
+    if (storage != GSN_C64 && storage != GSN_C128) {
+        *out = nullptr;
+        return fail(GSN_EINVAL, "storage must be GSN_C64 or GSN_C128");
+    }
     *out = nullptr;
     gsn_status s = validate_shape(ndim, n);
     if (s) return s;
@@ -767,12 +792,14 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
         if (!(std::isfinite(L[d]) && L[d] > 0.0)) return fail(GSN_EINVAL, "box lengths must be finite and > 0");
     if (!d_workspace) return fail(GSN_EINVAL, "workspace is NULL");
     if (((uintptr_t)d_workspace & 255) != 0) return fail(GSN_EWORKSPACE, "workspace must be 256-byte aligned");
-    const Layout lay = compute_layout(ndim, n);
+    const Layout lay = compute_layout(ndim, n, storage_bytes(storage));
     if (bytes < lay.total)
         return fail(GSN_EWORKSPACE, "workspace too small: need " + std::to_string(lay.total) + " bytes");
 
     gsn_grid g = new (std::nothrow) gsn_grid_();
     if (!g) return fail(GSN_EINVAL, "out of host memory");
+    g->storage = storage;
+    g->esz = storage_bytes(storage);
     g->ndim = ndim;
     for (int d = 0; d < 3; ++d) { g->n[d] = d < ndim ? n[d] : 1; g->L[d] = d < ndim ? L[d] : 1.0; }
     g->Nx = n[ndim - 1];
@@ -833,6 +860,12 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
     build_schedule(g);
     *out = g;
     return GSN_OK;
+}
+
+extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], const double L[],
+                                 void *d_workspace, size_t bytes, void *hip_stream)
+{
+    return gsn_create_ex(out, ndim, n, L, GSN_C64, d_workspace, bytes, hip_stream);
 }
 
 extern "C" gsn_status gsn_destroy(gsn_grid g)
@@ -927,6 +960,8 @@ extern "C" gsn_status gsn_set_local_terms(gsn_grid g, double c_pressure, double 
         return fail(GSN_EINVAL, "the pressure law is defined for n = 1, n > 1 and n < 0");
     if (((c_pressure != 0.0 && n_pressure <= 1.0) || c_bohm != 0.0) && !(rho_floor > 0.0))
         return fail(GSN_EINVAL, "ln rho, negative powers of rho and the Bohm term need rho_floor > 0");
+    if (g->storage == GSN_C128 && (c_pressure != 0.0 || c_bohm != 0.0))
+        return fail(GSN_EUNSUPPORTED, "the Eq. (15) local terms run on complex64 grids");
     HIP_TRY(hipSetDevice(g->device));
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->lp_cp = c_pressure;
@@ -942,6 +977,8 @@ extern "C" gsn_status gsn_set_local_terms(gsn_grid g, double c_pressure, double 
 extern "C" gsn_status gsn_set_source_fields(gsn_grid g, const float *gamma, const float *beta, const float *V_ext)
 {
     if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (g->storage == GSN_C128 && (gamma || beta || V_ext))
+        return fail(GSN_EUNSUPPORTED, "source fields run on complex64 grids");
     HIP_TRY(hipSetDevice(g->device));
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->fld_gamma = gamma;
@@ -993,7 +1030,20 @@ extern "C" gsn_status gsn_set_psi(gsn_grid g, const void *src, int on_device, in
     if (dtype != GSN_C64 && dtype != GSN_C128) return fail(GSN_EINVAL, "dtype must be GSN_C64 or GSN_C128");
     HIP_TRY(hipSetDevice(g->device));
     const long long P = g->P;
-    if (dtype == GSN_C64) {
+    if (g->storage == GSN_C128) {
+        if (dtype == GSN_C128) {
+            HIP_TRY(hipMemcpyAsync(g->psi, src, 16ull * P, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                   g->stream));
+        } else if (on_device) {
+            HIP_TRY(launch_from_c64(src, g->psi, P, g->stream));
+        } else {
+            std::vector<double2> tmp((size_t)P);
+            const float *s = (const float *)src;
+            for (long long i = 0; i < P; ++i) tmp[i] = make_double2((double)s[2 * i], (double)s[2 * i + 1]);
+            HIP_TRY(hipMemcpyAsync(g->psi, tmp.data(), 16ull * P, hipMemcpyHostToDevice, g->stream));
+            HIP_TRY(hipStreamSynchronize(g->stream));
+        }
+    } else if (dtype == GSN_C64) {
         HIP_TRY(hipMemcpyAsync(g->psi, src, 8ull * P, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                g->stream));
     } else if (on_device) {
@@ -1075,6 +1125,24 @@ extern "C" gsn_status gsn_get_psi(gsn_grid g, void *dst, int on_device, int dtyp
     if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
     HIP_TRY(hipSetDevice(g->device));
     const long long P = g->P;
+    if (g->storage == GSN_C128) {
+        // through the scratch buffer (16 bytes per point) in chunks
+        const size_t osz = dtype == GSN_C128 ? 16 : 8;
+        const long long chunk = on_device ? P : (long long)((16ull * P) / osz);
+        for (long long off = 0; off < P; off += chunk) {
+            const long long cnt = P - off < chunk ? P - off : chunk;
+            const double2 *src = (const double2 *)g->psi + off;
+            if (on_device) {
+                HIP_TRY(launch_readout_c128(src, dst, dtype == GSN_C128, cnt, g->st, g->stream));
+            } else {
+                HIP_TRY(launch_readout_c128(src, g->scratch, dtype == GSN_C128, cnt, g->st, g->stream));
+                HIP_TRY(hipMemcpyAsync((char *)dst + off * osz, g->scratch, cnt * osz, hipMemcpyDeviceToHost,
+                                       g->stream));
+                HIP_TRY(hipStreamSynchronize(g->stream));
+            }
+        }
+        return gsn_sync(g);
+    }
     if (on_device) {
         if (dtype == GSN_C128) hipLaunchKernelGGL(k_readout<true>, dim3(1024), dim3(256), 0, g->stream, g->psi, dst, P, g->st);
         else hipLaunchKernelGGL(k_readout<false>, dim3(1024), dim3(256), 0, g->stream, g->psi, dst, P, g->st);
@@ -1127,8 +1195,12 @@ extern "C" gsn_status gsn_mass(gsn_grid g, double *mass)
     if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
     HIP_TRY(hipSetDevice(g->device));
     const int nb = 1024;
-    hipLaunchKernelGGL(k_mass<256>, dim3(nb), dim3(256), 0, g->stream, g->psi, g->P, g->epart);
-    HIP_TRY(hipGetLastError());
+    if (g->storage == GSN_C128) {
+        HIP_TRY(launch_mass_c128(g->psi, g->P, g->epart, nb, g->stream));
+    } else {
+        hipLaunchKernelGGL(k_mass<256>, dim3(nb), dim3(256), 0, g->stream, g->psi, g->P, g->epart);
+        HIP_TRY(hipGetLastError());
+    }
     double sum = 0.0;
     if ((s = sum_device(g, g->epart, nb, 1, 0, &sum))) return s;
     *mass = sum * cell_volume(g);
@@ -1146,7 +1218,7 @@ extern "C" gsn_status gsn_energy(gsn_grid g, double e[4])
         return fail(GSN_EUNSUPPORTED, "no energy with position-dependent source fields or a static potential");
     if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
     HIP_TRY(hipSetDevice(g->device));
-    HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, 8ull * g->P, hipMemcpyDeviceToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, g->esz * g->P, hipMemcpyDeviceToDevice, g->stream));
     for (const Launch &L : g->entry) {
         Launch c = L;
         c.ea.psi = g->scratch;
@@ -1183,9 +1255,17 @@ extern "C" const char *gsn_pass_name(gsn_grid, int i)
     return (i >= 0 && i < P_COUNT) ? kPassNames[i] : "";
 }
 
+static double pass_bytes_c64(gsn_grid g, int i);
+
 extern "C" double gsn_pass_bytes_per_point(gsn_grid g, int i)
 {
     if (!g) return 0.0;
+    // the model is written for complex64 values; FP64 storage doubles every byte
+    return pass_bytes_c64(g, i) * (double)(g->esz / 8);
+}
+
+static double pass_bytes_c64(gsn_grid g, int i)
+{
     // reads + writes of complex64 psi (8 B), half spectrum (4 B per point)
     switch (i) {
     case P_ENTRY: case P_EXIT: case P_Y_FWD_PSI: case P_Y_INV_PSI: case P_KINETIC: return 16.0;
@@ -1347,6 +1427,7 @@ static std::string cache_key(gsn_grid g, int p)
     k << arch << " " << g->ndim << "d";
     for (int d = 0; d < g->ndim; ++d) k << (d ? "x" : " ") << g->n[d];
     k << " " << (p < P_COUNT ? kPassNames[p] : "nonlinear_mode");
+    if (g->storage == GSN_C128) k << "+c128";
     if (g->local_on) k << (g->bohm_on ? "+eq15b" : "+eq15");
     if (g->fld_gamma || g->fld_beta || g->fld_V) k << "+fields";
     return k.str();
@@ -1373,9 +1454,9 @@ extern "C" gsn_status gsn_autotune(gsn_grid g, int iters)
     HIP_TRY(hipSetDevice(g->device));
     // realistic data for timing: a copy of psi (or zeros before psi is set)
     if (g->have_psi)
-        HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, 8ull * g->P, hipMemcpyDeviceToDevice, g->stream));
+        HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, g->esz * g->P, hipMemcpyDeviceToDevice, g->stream));
     else
-        HIP_TRY(hipMemsetAsync(g->scratch, 0, 8ull * g->P, g->stream));
+        HIP_TRY(hipMemsetAsync(g->scratch, 0, g->esz * g->P, g->stream));
     const char *cpath = std::getenv("GSN_AUTOTUNE_CACHE");
     std::map<std::string, int> cache;
     if (cpath && *cpath) cache = read_cache(cpath);
@@ -1493,6 +1574,7 @@ extern "C" gsn_status gsn_potential(gsn_grid g, float *phi_dev)
 {
     if (!g || !phi_dev) return fail(GSN_EINVAL, "NULL argument");
     if (g->fld_gamma || g->fld_beta) return fail(GSN_EUNSUPPORTED, "no potential readout with source fields");
+    if (g->storage == GSN_C128) return fail(GSN_EUNSUPPORTED, "no potential readout on FP64-storage grids");
     if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
     HIP_TRY(hipSetDevice(g->device));
     return run_potential(g, phi_dev);
@@ -1528,6 +1610,7 @@ extern "C" gsn_status gsn_step_corrected(gsn_grid g, gsn_corrector c, int64_t nc
     if (!c) return fail(GSN_EINVAL, "corrector is NULL");
     if (g->ndim != 2) return fail(GSN_EUNSUPPORTED, "the corrector works on 2-D grids");
     if (g->fld_gamma || g->fld_beta) return fail(GSN_EUNSUPPORTED, "no corrected steps with source fields");
+    if (g->storage == GSN_C128) return fail(GSN_EUNSUPPORTED, "the corrector works on complex64 grids");
     if (corrector_height(c) != g->n[0] || corrector_width(c) != g->n[1])
         return fail(GSN_EINVAL, "corrector image size differs from the grid");
     if (g->coarse_ratio <= 0) return fail(GSN_ESTATE, "no coarse ratio set");

@@ -86,6 +86,16 @@ template <int N, int V> struct Cfg {
 // model).
 const NKernels *kernels_for(int N, int v = 0);
 
+// Kernel table of the FP64-storage (complex128) grids, one tile per block in
+// the tile configuration of variant v (defined in gsn_c128.hip), and its
+// storage-specific helpers: mass partials, read-out with the global phase
+// (to complex128 or complex64), and complex64 input.
+const NKernels *kernels_for_c128(int N, int v = 0);
+hipError_t launch_mass_c128(const void *psi, long long P, double *partials, int nb, hipStream_t s);
+hipError_t launch_readout_c128(const void *psi, void *dst, int dst_c128, long long P, const DevState *st,
+                               hipStream_t s);
+hipError_t launch_from_c64(const void *src, void *dst, long long P, hipStream_t s);
+
 // Kernels of the local terms of Eq. (15) (pressure and Bohm potential) of
 // length N in the tile configuration of schedule variant v; one tile per block
 // (defined in gsn_local.hip).

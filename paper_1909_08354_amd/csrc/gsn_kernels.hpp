@@ -77,9 +77,23 @@ template <int N, int E, int LINES> struct LmTile {
     static constexpr int LDS = LINES * N;
 };
 
+// Complex values in HBM: complex64 (float2, the default everywhere) or
+// complex128 (double2, the FP64-storage grids).  The argument structs carry
+// complex64 pointers; an FP64-storage kernel reinterprets them as double2
+// arrays (the host sets them to double2 buffers), and its LDS slots are
+// double2 too, so no value is rounded below FP64 anywhere in the step.
+__device__ __forceinline__ dc ld_c(const float2 &v) { return from_f2(v); }
+__device__ __forceinline__ dc ld_c(const double2 &v) { return from_d2(v); }
+template <class ST> __device__ __forceinline__ ST st_c(dc v);
+template <> __device__ __forceinline__ float2 st_c<float2>(dc v) { return to_f2(v); }
+template <> __device__ __forceinline__ double2 st_c<double2>(dc v) { return make_double2(v.x, v.y); }
+// real values kept between stages of one pass (phi rows): float or double
+template <class ST> struct RealOf { using T = float; };
+template <> struct RealOf<double2> { using T = double; };
+
 // Plain row FFT (entry/exit of a run of steps, energy evaluation).
-template <int N, int E, int LINES, int S>
-__device__ __forceinline__ void em_fft_tile(const EmArgs &a, int tile, float2 *lds)
+template <int N, int E, int LINES, int S, class ST>
+__device__ __forceinline__ void em_fft_tile(const EmArgs &a, int tile, ST *lds)
 {
     constexpr int TPL = N / E;
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
@@ -87,13 +101,13 @@ __device__ __forceinline__ void em_fft_tile(const EmArgs &a, int tile, float2 *l
     const bool act = row < a.nlines;
     const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     dc v[E];
-    float2 *p = a.psi + (long long)row * N;
+    ST *p = (ST *)a.psi + (long long)row * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+    for (int e = 0; e < E; ++e) v[e] = act ? ld_c(p[t + TPL * e]) : mk(0.0, 0.0);
     fft<N, E, S>(v, t, lay, lds, a.tw);
     if (act) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) p[t + TPL * e] = to_f2(scl(v[e], a.scale));
+        for (int e = 0; e < E; ++e) p[t + TPL * e] = st_c<ST>(scl(v[e], a.scale));
     }
 }
 
@@ -110,37 +124,37 @@ __device__ __forceinline__ void em_fft_tile(const EmArgs &a, int tile, float2 *l
 // through LDS, so bin k can see bin N-k) into X_0[k] = (Z[k] + conj Z[N-k]) / 2,
 // X_1[k] = (Z[k] - conj Z[N-k]) / (2i); store bins 0..N/2-1 to the half rows
 // r0, r1 and the real bin N/2 to nyq.
-template <int N, int E>
+template <int N, int E, class LT, class ST>
 __device__ __forceinline__ void store_real_pair(const dc (&v)[E], bool act, int t, const EmLayout<N, E> &lay,
-                                                float2 *lds, float2 *half, float2 *nyq, long long r0, long long r1)
+                                                LT *lds, ST *half, ST *nyq, long long r0, long long r1)
 {
     constexpr int TPL = N / E;
 #pragma unroll
-    for (int e = 0; e < E; ++e) lds[lay(t + TPL * e)] = to_f2(v[e]);
+    for (int e = 0; e < E; ++e) lds_put(lds, lay(t + TPL * e), v[e]);
     exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
     if (act) {
-        float2 *h0 = half + r0 * (N / 2), *h1 = half + r1 * (N / 2);
+        ST *h0 = half + r0 * (N / 2), *h1 = half + r1 * (N / 2);
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {
             const int k = t + TPL * e;
             const dc z = v[e];
-            const dc zc = conj(from_f2(lds[lay((N - k) & (N - 1))]));
+            const dc zc = conj(lds_get(lds, lay((N - k) & (N - 1))));
             const dc s = add(z, zc), d = sub(z, zc);
-            h0[k] = to_f2(scl(s, 0.5));
-            h1[k] = to_f2(mk(0.5 * d.y, -0.5 * d.x));
+            h0[k] = st_c<ST>(scl(s, 0.5));
+            h1[k] = st_c<ST>(mk(0.5 * d.y, -0.5 * d.x));
         }
         if (t == 0) {
             const dc z = v[E / 2];   // bin N/2: both halves are real
-            nyq[r0] = make_float2((float)z.x, 0.0f);
-            nyq[r1] = make_float2((float)z.y, 0.0f);
+            nyq[r0] = st_c<ST>(mk(z.x, 0.0));
+            nyq[r1] = st_c<ST>(mk(z.y, 0.0));
         }
     }
 }
 
 // BOHM: also transform s = sqrt(rho) of both rows the same way into half2 /
 // nyq2 (the Bohm potential of Eq. (15) needs lap(s)).
-template <int N, int E, int LINES, bool STORE_PSI, bool REAL_IN = false, bool BOHM = false>
-__device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *lds, double *sh)
+template <int N, int E, int LINES, bool STORE_PSI, bool REAL_IN = false, bool BOHM = false, class ST>
+__device__ __forceinline__ void density_tile(const EmArgs &a, int tile, ST *lds, double *sh)
 {
     static_assert(!(STORE_PSI && REAL_IN), "real-space input is not stored back");
     constexpr int TPL = N / E, NT = LINES * TPL;
@@ -153,25 +167,25 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *
     const double rs = REAL_IN ? 1.0 : inv_n * inv_n;   // |psi|^2 scale
     dc v[E];
     double rho0[E];
-    float2 *p0 = a.psi + r0 * N, *p1 = a.psi + r1 * N;
+    ST *p0 = (ST *)a.psi + r0 * N, *p1 = (ST *)a.psi + r1 * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p0[t + TPL * e]) : mk(0.0, 0.0);
+    for (int e = 0; e < E; ++e) v[e] = act ? ld_c(p0[t + TPL * e]) : mk(0.0, 0.0);
     if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) rho0[e] = norm2(v[e]) * rs;
     if constexpr (STORE_PSI) {
         if (act) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) p0[t + TPL * e] = to_f2(scl(v[e], inv_n));
+            for (int e = 0; e < E; ++e) p0[t + TPL * e] = st_c<ST>(scl(v[e], inv_n));
         }
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p1[t + TPL * e]) : mk(0.0, 0.0);
+    for (int e = 0; e < E; ++e) v[e] = act ? ld_c(p1[t + TPL * e]) : mk(0.0, 0.0);
     if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
     if constexpr (STORE_PSI) {
         if (act) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) p1[t + TPL * e] = to_f2(scl(v[e], inv_n));
+            for (int e = 0; e < E; ++e) p1[t + TPL * e] = st_c<ST>(scl(v[e], inv_n));
         }
     }
     double msum = 0.0;
@@ -184,11 +198,11 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *
         v[e] = mk(rho0[e], rho1);
     }
     fft<N, E, -1>(v, t, lay, lds, a.tw);
-    store_real_pair<N, E>(v, act, t, lay, lds, a.half, a.nyq, r0, r1);
+    store_real_pair<N, E>(v, act, t, lay, lds, (ST *)a.half, (ST *)a.nyq, r0, r1);
     if constexpr (BOHM) {
         exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();   // the split above has read LDS
         fft<N, E, -1>(w, t, lay, lds, a.tw);
-        store_real_pair<N, E>(w, act, t, lay, lds, a.half2, a.nyq2, r0, r1);
+        store_real_pair<N, E>(w, act, t, lay, lds, (ST *)a.half2, (ST *)a.nyq2, r0, r1);
     }
     const double bs = block_sum<NT>(msum, sh);
     if (tid == 0) a.partials[tile] = bs;
@@ -196,39 +210,39 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, float2 *
 
 // Full x-spectrum Z = X_0 + i X_1 of two real rows r0, r1 from their half
 // spectra (X[N-k] = conj X[k]; the DC and Nyquist bins are real).
-template <int N, int E>
-__device__ __forceinline__ void load_real_pair(const float2 *half, const float2 *nyq, bool act, int t, long long r0,
+template <int N, int E, class ST>
+__device__ __forceinline__ void load_real_pair(const ST *half, const ST *nyq, bool act, int t, long long r0,
                                                long long r1, dc (&z)[E])
 {
     constexpr int TPL = N / E;
-    const float2 *h0 = half + r0 * (N / 2), *h1 = half + r1 * (N / 2);
+    const ST *h0 = half + r0 * (N / 2), *h1 = half + r1 * (N / 2);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         dc x0 = mk(0.0, 0.0), x1 = mk(0.0, 0.0);
         if (act) {
             if (e < E / 2) {
                 const int k = t + TPL * e;
-                x0 = from_f2(h0[k]);
-                x1 = from_f2(h1[k]);
+                x0 = ld_c(h0[k]);
+                x1 = ld_c(h1[k]);
                 if (k == 0) { x0.y = 0.0; x1.y = 0.0; }
             } else if (e == E / 2 && t == 0) {
                 x0 = mk((double)nyq[r0].x, 0.0);
                 x1 = mk((double)nyq[r1].x, 0.0);
             } else {
                 const int kk = N - (t + TPL * e);
-                x0 = conj(from_f2(h0[kk]));
-                x1 = conj(from_f2(h1[kk]));
+                x0 = conj(ld_c(h0[kk]));
+                x1 = conj(ld_c(h1[kk]));
             }
         }
         z[e] = mk(x0.x - x1.y, x0.y + x1.x);
     }
 }
 
-template <int N, int E>
+template <int N, int E, class ST = float2>
 __device__ __forceinline__ void load_phi_pair(const EmArgs &a, bool act, int t, long long r0, long long r1,
                                               dc (&z)[E])
 {
-    load_real_pair<N, E>(a.half, a.nyq, act, t, r0, r1, z);
+    load_real_pair<N, E>((const ST *)a.half, (const ST *)a.nyq, act, t, r0, r1, z);
 }
 
 // Potential readout: phi rows (without the uniform k = 0 part) as float.
@@ -419,10 +433,11 @@ inline void fill_sincos_table(double2 *tab)
 //
 // REAL_IN: the psi rows already hold psi in real space (written by the density
 // pass with STORE_PSI), so the inverse x transform is skipped.
-template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
-__device__ __forceinline__ void phase_tile(const EmArgs &a, int tile, float2 *lds, double *sh)
+template <int N, int E, int LINES, bool ENERGY, bool REAL_IN, class ST>
+__device__ __forceinline__ void phase_tile(const EmArgs &a, int tile, ST *lds, double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
+    using RT = typename RealOf<ST>::T;
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
     const int pair = tile * LINES + l;
     const bool act = pair < a.nlines;
@@ -430,22 +445,22 @@ __device__ __forceinline__ void phase_tile(const EmArgs &a, int tile, float2 *ld
     const long long r0 = 2LL * pair, r1 = r0 + 1;
     const double inv_n = 1.0 / N;
     dc z[E];
-    load_phi_pair<N, E>(a, act, t, r0, r1, z);
+    load_phi_pair<N, E, ST>(a, act, t, r0, r1, z);
     fft<N, E, 1>(z, t, lay, lds, a.tw);
-    // phi of both rows, kept as float (it is complex64-stored data already)
-    float phi0[E], phi1[E];
+    // phi of both rows, kept in the storage precision (float for complex64)
+    RT phi0[E], phi1[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        phi0[e] = (float)(z[e].x * inv_n);
-        phi1[e] = (float)(z[e].y * inv_n);
+        phi0[e] = (RT)(z[e].x * inv_n);
+        phi1[e] = (RT)(z[e].y * inv_n);
     }
     double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll 1
     for (int half = 0; half < 2; ++half) {
-        float2 *p = a.psi + (half ? r1 : r0) * N;
+        ST *p = (ST *)a.psi + (half ? r1 : r0) * N;
         dc v[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+        for (int e = 0; e < E; ++e) v[e] = act ? ld_c(p[t + TPL * e]) : mk(0.0, 0.0);
         if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -465,7 +480,7 @@ __device__ __forceinline__ void phase_tile(const EmArgs &a, int tile, float2 *ld
             fft<N, E, -1>(v, t, lay, lds, a.tw);
             if (act) {
 #pragma unroll
-                for (int e = 0; e < E; ++e) p[t + TPL * e] = to_f2(v[e]);
+                for (int e = 0; e < E; ++e) p[t + TPL * e] = st_c<ST>(v[e]);
             }
         }
     }
@@ -731,8 +746,8 @@ struct LmArgs {
     DevState *st;
 };
 
-template <int N, int E, int LINES, int MODE>
-__device__ __forceinline__ void lm_tile(const LmArgs &a, int tile_in, float2 *lds, double *sh)
+template <int N, int E, int LINES, int MODE, class ST>
+__device__ __forceinline__ void lm_tile(const LmArgs &a, int tile_in, ST *lds, double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
     const int tid = threadIdx.x, l = tid % LINES, t = tid / LINES;
@@ -743,12 +758,12 @@ __device__ __forceinline__ void lm_tile(const LmArgs &a, int tile_in, float2 *ld
     const int o = tile / sg.ngroups, grp = tile - o * sg.ngroups;
     const int lg = grp * LINES + l;
     const bool act = lg < sg.nlines;
-    float2 *base = sg.ptr + (long long)o * sg.os + (long long)lg * sg.ls;
+    ST *base = (ST *)sg.ptr + (long long)o * sg.os + (long long)lg * sg.ls;
     const LmLayout<LINES> lay{l};
     dc v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e)
-        v[e] = act ? from_f2(base[(long long)(t + TPL * e) * sg.es]) : mk(0.0, 0.0);
+        v[e] = act ? ld_c(base[(long long)(t + TPL * e) * sg.es]) : mk(0.0, 0.0);
 
     if constexpr (MODE == LM_FWD || MODE == LM_INV) {
         fft<N, E, MODE == LM_FWD ? -1 : 1>(v, t, lay, lds, a.tw);
@@ -800,7 +815,7 @@ __device__ __forceinline__ void lm_tile(const LmArgs &a, int tile_in, float2 *ld
     if constexpr (MODE != LM_KIN_ENERGY) {
         if (act) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) base[(long long)(t + TPL * e) * sg.es] = to_f2(v[e]);
+            for (int e = 0; e < E; ++e) base[(long long)(t + TPL * e) * sg.es] = st_c<ST>(v[e]);
         }
     }
     if (a.reduce && tile_in == 0) {
@@ -1322,16 +1337,16 @@ __device__ __forceinline__ void densityp_body(const Src &src, LT *lds, double2 *
 // One grid: block b is tile b.  Grouped: several instances of one shape in
 // one launch; block b is tile (b mod tpi) of instance (b / tpi), whose
 // arguments are read from a device array.
-template <int N, int E, int LINES, int S>
+template <int N, int E, int LINES, int S, class ST = float2>
 __global__ __launch_bounds__(LINES *(N / E)) void k_em_fft(EmArgs a)
 {
-    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ ST lds[EmTile<N, E, LINES>::LDS];
     em_fft_tile<N, E, LINES, S>(a, blockIdx.x, lds);
 }
-template <int N, int E, int LINES, bool STORE_PSI, bool BOHM = false>
+template <int N, int E, int LINES, bool STORE_PSI, bool BOHM = false, class ST = float2>
 __global__ __launch_bounds__(LINES *(N / E)) void k_density(EmArgs a)
 {
-    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ ST lds[EmTile<N, E, LINES>::LDS];
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
     density_tile<N, E, LINES, STORE_PSI, false, BOHM>(a, blockIdx.x, lds, sh);
 }
@@ -1355,10 +1370,10 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_density_real(EmArgs a)
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
     density_tile<N, E, LINES, false, true>(a, blockIdx.x, lds, sh);
 }
-template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
+template <int N, int E, int LINES, bool ENERGY, bool REAL_IN, class ST = float2>
 __global__ __launch_bounds__(LINES *(N / E)) void k_phase(EmArgs a)
 {
-    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ ST lds[EmTile<N, E, LINES>::LDS];
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
     phase_tile<N, E, LINES, ENERGY, REAL_IN>(a, blockIdx.x, lds, sh);
 }
@@ -1368,10 +1383,10 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_potential(EmArgs a)
     __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
     potential_tile<N, E, LINES>(a, blockIdx.x, lds);
 }
-template <int N, int E, int LINES, int MODE>
+template <int N, int E, int LINES, int MODE, class ST = float2>
 __global__ __launch_bounds__(LINES *(N / E)) void k_lm(LmArgs a)
 {
-    __shared__ float2 lds[LmTile<N, E, LINES>::LDS];
+    __shared__ ST lds[LmTile<N, E, LINES>::LDS];
     __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
     lm_tile<N, E, LINES, MODE>(a, blockIdx.x, lds, sh);
 }
@@ -1473,31 +1488,41 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phasep_g(const EmArgs *__res
 }
 
 // ---------------------------------------------------------------- small kernels
-template <int NT>
-__global__ __launch_bounds__(NT) void k_mass(const float2 *__restrict__ psi, long long P, double *partials)
+template <int NT, class ST = float2>
+__global__ __launch_bounds__(NT) void k_mass(const ST *__restrict__ psi, long long P, double *partials)
 {
     __shared__ double sh[NT / 64 + 1];
     double s = 0.0;
     for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < P; i += (long long)gridDim.x * NT) {
-        const float2 v = psi[i];
-        s += (double)v.x * v.x + (double)v.y * v.y;
+        const dc v = ld_c(psi[i]);
+        s += v.x * v.x + v.y * v.y;
     }
     s = block_sum<NT>(s, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 // dst = src * exp(i theta) in FP64, to complex64 or complex128
-template <bool C128>
-__global__ void k_readout(const float2 *__restrict__ src, void *dst, long long P, const DevState *st)
+template <bool C128, class ST = float2>
+__global__ void k_readout(const ST *__restrict__ src, void *dst, long long P, const DevState *st)
 {
     double s, c;
     sincos(st->theta, &s, &c);
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < P;
          i += (long long)gridDim.x * blockDim.x) {
-        const float2 v = src[i];
+        const dc v = ld_c(src[i]);
         const double re = c * v.x - s * v.y, im = s * v.x + c * v.y;
         if constexpr (C128) ((double2 *)dst)[i] = make_double2(re, im);
         else ((float2 *)dst)[i] = make_float2((float)re, (float)im);
+    }
+}
+
+// complex64 input into a complex128-storage grid
+static __global__ void k_from_c64(const float2 *__restrict__ src, double2 *dst, long long P)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < P;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float2 v = src[i];
+        dst[i] = make_double2((double)v.x, (double)v.y);
     }
 }
 

@@ -40,6 +40,8 @@ dp = ctypes.POINTER(ctypes.c_double)
 _SIGNATURES = {
     "gsn_workspace_bytes": [ctypes.c_int, i32p, ctypes.POINTER(ctypes.c_size_t)],
     "gsn_create": [ctypes.POINTER(vp), ctypes.c_int, i32p, dp, vp, ctypes.c_size_t, vp],
+    "gsn_workspace_bytes_ex": [ctypes.c_int, i32p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "gsn_create_ex": [ctypes.POINTER(vp), ctypes.c_int, i32p, dp, ctypes.c_int, vp, ctypes.c_size_t, vp],
     "gsn_destroy": [vp],
     "gsn_set_kernel": [vp, ctypes.POINTER(gsn_kernel)],
     "gsn_set_coefficients": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
@@ -143,10 +145,21 @@ def _f64(seq):
     return (ctypes.c_double * len(seq))(*[float(v) for v in seq])
 
 
-def gsn_workspace_bytes(n):
+def gsn_workspace_bytes(n, storage=None):
     out = ctypes.c_size_t(0)
-    check(load().gsn_workspace_bytes(len(n), _i32(n), ctypes.byref(out)))
+    if storage is None:
+        check(load().gsn_workspace_bytes(len(n), _i32(n), ctypes.byref(out)))
+    else:
+        check(load().gsn_workspace_bytes_ex(len(n), _i32(n), _storage_code(storage), ctypes.byref(out)))
     return out.value
+
+
+def _storage_code(storage):
+    if storage in (np.complex64, "c64"):
+        return GSN_C64
+    if storage in (np.complex128, "c128"):
+        return GSN_C128
+    raise ValueError("storage must be complex64 or complex128")
 
 
 def _torch():
@@ -179,15 +192,17 @@ def _ptr_and_flag(x):
 
 
 class Grid:
-    """One periodic 2-D or 3-D grid on the current HIP device (gsn_create)."""
+    """One periodic 2-D or 3-D grid on the current HIP device (gsn_create;
+    storage=np.complex128: gsn_create_ex with FP64 storage)."""
 
-    def __init__(self, n, L, stream=None):
+    def __init__(self, n, L, stream=None, storage=np.complex64):
         torch = _torch()
         lib = load()
         self.n = tuple(int(v) for v in n)
         self.L = tuple(float(v) for v in L)
         self.P = int(np.prod(self.n))
-        nbytes = gsn_workspace_bytes(self.n)
+        self.storage = _storage_code(storage)
+        nbytes = gsn_workspace_bytes(self.n, storage)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self._ws.data_ptr()
         aligned = (base + 255) & ~255
@@ -195,8 +210,8 @@ class Grid:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = vp()
-        check(lib.gsn_create(ctypes.byref(h), len(self.n), _i32(self.n), _f64(self.L),
-                             vp(aligned), nbytes, vp(stream.cuda_stream)))
+        check(lib.gsn_create_ex(ctypes.byref(h), len(self.n), _i32(self.n), _f64(self.L), self.storage,
+                                vp(aligned), nbytes, vp(stream.cuda_stream)))
         self.h = h
 
     def close(self):
