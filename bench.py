@@ -268,6 +268,53 @@ def eq15_bench(steps, autotune_iters, profile_steps, workload="gsn3d_256_eq15"):
             "norm_drift": abs(m1 / m0 - 1), "energy_drift": edrift}
 
 
+def fp64_bench(steps, autotune_iters, profile_steps):
+    """The 256^3 workload on an FP64-storage grid (complex128 in HBM and LDS):
+    step rate, per-pass times, the roofline of its dominant pass, invariants."""
+    import torch
+    from paper_1909_08354_amd import gsn, inputs
+    w = inputs.WORKLOADS[WORKLOAD]
+    n, L = w["n"], w["L"]
+    P = int(np.prod(n))
+    grid = gsn.Grid(n, L, storage=np.complex128)
+    grid.set_kernel(*w["kern"])
+    grid.set_coefficients(w["a"], w["g"], w["dz"])
+    dev0 = torch.from_numpy(inputs.as_oracle_input(inputs.gaussian_3d_256())).cuda()
+    grid.set_psi(dev0)
+    schedule = grid.autotune(autotune_iters) if autotune_iters > 0 else grid.schedule()
+    grid.set_psi(dev0)
+    m0 = grid.mass()
+    e0 = grid.energy()
+    grid.step(10)
+    grid.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    grid.sync()
+    m1 = grid.mass()
+    e1 = grid.energy()
+    prof = grid.profile_passes(profile_steps)
+    bpp = dict(zip(grid.pass_names(), grid.pass_bytes_per_point()))
+    steady = {k: v for k, v in prof.items() if k not in ("x_entry_fft", "x_exit_ifft") and bpp[k] > 0}
+    dom = max(steady, key=steady.get)
+    achieved = bpp[dom] * P / (steady[dom] * 1e-3) / 1e9
+    step_bytes = sum(bpp[k] for k in steady) * P
+    ms = 1e3 * elapsed / steps
+    scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
+    grid.close()
+    return {"workload": WORKLOAD, "storage": "c128", "grid": list(n), "steps": steps,
+            "value": P * steps / elapsed, "unit": "grid-pt updates/s", "ms_per_step": ms,
+            "model_bytes_per_point": step_bytes / P,
+            "model_step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                         "algorithmic_bytes_per_launch": bpp[dom] * P, "avg_launch_ms": steady[dom]},
+            "pass_ms": {k: round(v, 5) for k, v in steady.items()}, "schedule": schedule,
+            "norm_drift": abs(m1 / m0 - 1), "energy_drift": abs(e1["total"] - e0["total"]) / scale}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +328,8 @@ def main():
     ap.add_argument("--corrector-train", type=int, default=2000,
                     help="training trajectories of the corrector leg (0 skips it)")
     ap.add_argument("--corrector-epochs", type=int, default=4)
+    ap.add_argument("--fp64-steps", type=int, default=200,
+                    help="steps of the 256^3 FP64-storage leg (0 skips it)")
     ap.add_argument("--eq15-steps", type=int, default=200,
                     help="steps of the 256^3 Eq. (15) fluid legs, without and with the "
                          "non-minimal coupling (0 skips them)")
@@ -374,10 +423,13 @@ def main():
         "corrected": None,
         "eq15": None,
         "nmc": None,
+        "fp64": None,
     }
-    if args.batch_steps > 0 or args.corrector_train > 0 or args.eq15_steps > 0:
+    if args.batch_steps > 0 or args.corrector_train > 0 or args.eq15_steps > 0 or args.fp64_steps > 0:
         grid.close()
         del grid
+    if args.fp64_steps > 0:
+        line["fp64"] = fp64_bench(args.fp64_steps, min(args.autotune_iters, 5), args.profile_steps)
     if args.eq15_steps > 0:
         line["eq15"] = eq15_bench(args.eq15_steps, min(args.autotune_iters, 5), args.profile_steps)
         line["nmc"] = eq15_bench(args.eq15_steps, min(args.autotune_iters, 5), args.profile_steps,
