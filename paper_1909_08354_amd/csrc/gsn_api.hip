@@ -350,6 +350,16 @@ static Launch em_launch(void (*fn)(EmArgs), const NKernels *k, const EmArgs &a, 
     return L;
 }
 
+// A persistent EM kernel outside the table: grid = resident blocks (at most
+// one per tile).
+static Launch em_launch_persistent(void (*fn)(EmArgs), const NKernels *k, const EmArgs &a, int pass)
+{
+    Launch L = em_launch(fn, k, a, pass);
+    const int pb = persistent_blocks((const void *)fn, k->em_threads());
+    if (pb > 0 && pb < (int)L.grid.x) L.grid = dim3(pb);
+    return L;
+}
+
 static EmArgs em_base(gsn_grid g, float2 *psi)
 {
     EmArgs a;
@@ -465,7 +475,10 @@ static void build_core(gsn_grid g)
         const bool store = g->store_psi && !energy;
         if (g->bohm_on) {
             const LKernels *lk = local_kernels_for(Nx, g->var[P_DENSITY]);
-            dst.push_back(em_launch(store ? lk->density_store : lk->density, KX(P_DENSITY), d, P_DENSITY));
+            if (!energy && lk->density_p[store ? 1 : 0])
+                dst.push_back(em_launch_persistent(lk->density_p[store ? 1 : 0], KX(P_DENSITY), d, P_DENSITY));
+            else
+                dst.push_back(em_launch(store ? lk->density_store : lk->density, KX(P_DENSITY), d, P_DENSITY));
         } else {
             dst.push_back(em_launch(store ? KX(P_DENSITY)->density_store : KX(P_DENSITY)->density,
                                     KX(P_DENSITY), d, P_DENSITY));
@@ -607,8 +620,12 @@ static void build_core(gsn_grid g)
         h.partials = g->epart;
         if (g->local_on || g->fld_V) {
             const LKernels *lk = local_kernels_for(Nx, g->var[P_PHASE]);
-            dst.push_back(em_launch(energy ? lk->phase_energy : store ? lk->phase_real : lk->phase,
-                                    KX(P_PHASE), h, P_PHASE));
+            void (*pp)(EmArgs) = energy ? nullptr : lk->phase_p[store ? 1 : 0][g->bohm_on ? 1 : 0][g->fld_V ? 1 : 0];
+            if (pp)
+                dst.push_back(em_launch_persistent(pp, KX(P_PHASE), h, P_PHASE));
+            else
+                dst.push_back(em_launch(energy ? lk->phase_energy : store ? lk->phase_real : lk->phase,
+                                        KX(P_PHASE), h, P_PHASE));
         } else {
             dst.push_back(em_launch(energy ? KX(P_PHASE)->phase_energy
                                            : store ? KX(P_PHASE)->phase_real : KX(P_PHASE)->phase,

@@ -107,6 +107,10 @@ struct LKernels {
     void (*phase_energy)(EmArgs);
     void (*lm_lap)(LmArgs);          // FFT, -|k|^2, inverse FFT
     void (*source[2][2])(EmArgs);    // [real-space psi in][lap(rho) in]
+    // persistent prefetching forms (null outside the p16 / p8 variants):
+    // density with sqrt(rho) [stores psi]; phase [real-space psi][Bohm][static potential]
+    void (*density_p[2])(EmArgs);
+    void (*phase_p[2][2][2])(EmArgs);
 };
 const LKernels *local_kernels_for(int N, int v = 0);
 

@@ -1126,11 +1126,12 @@ template <int N, int E> struct PhiRaw {
 };
 
 template <int N, int E>
-__device__ __forceinline__ void em_fetch_phi(const EmArgs &a, int pair, int t, bool live, PhiRaw<N, E> &f)
+__device__ __forceinline__ void em_fetch_raw(float2 *half, const float2 *nyq, int pair, int t, bool live,
+                                             PhiRaw<N, E> &f)
 {
     constexpr int TPL = N / E, H = N / 2;
     const int pair0 = __builtin_amdgcn_readfirstlane(pair);
-    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.half + (long long)pair0 * 2 * H);
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(half + (long long)pair0 * 2 * H);
     const int row = live ? (pair - pair0) * 2 * H : 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1144,8 +1145,29 @@ __device__ __forceinline__ void em_fetch_phi(const EmArgs &a, int pair, int t, b
         f.h1[e] = buf_ld2(rs, vo, H * 8);
     }
     const long long r0 = live ? 2LL * pair : 2LL * pair0;
-    f.n0 = gld(a.nyq, r0);
-    f.n1 = gld(a.nyq, r0 + 1);
+    f.n0 = gld(nyq, r0);
+    f.n1 = gld(nyq, r0 + 1);
+}
+
+template <int N, int E>
+__device__ __forceinline__ void em_fetch_phi(const EmArgs &a, int pair, int t, bool live, PhiRaw<N, E> &f)
+{
+    em_fetch_raw<N, E>(a.half, a.nyq, pair, t, live, f);
+}
+
+// The static potential of both rows of a pair (E floats each; live = false:
+// the pair's first point, so the count of loads per iteration stays fixed).
+template <int N, int E>
+__device__ __forceinline__ void em_fetch_vext(const EmArgs &a, int pair, int t, bool live, float (&v0)[E],
+                                              float (&v1)[E])
+{
+    constexpr int TPL = N / E;
+    const auto b = gmem(a.vext) + (long long)pair * 2 * N + (live ? t : 0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        v0[e] = b[live ? TPL * e : 0];
+        v1[e] = b[live ? N + TPL * e : 0];
+    }
 }
 
 // The full spectrum Z = X_0 + i X_1 of the pair (conjugate symmetry; DC and
@@ -1253,8 +1275,106 @@ __device__ __forceinline__ void phasep_body(const Src &src, LT *lds, double2 *tw
     }
 }
 
+// Phase pass with the local terms of Eq. (15) and the static potential, in
+// the persistent prefetching form of phasep_body: the next tile's phi half
+// spectra, lap(sqrt rho) half spectra (BOHM), psi rows and static potential
+// (VEXT) are fetched while the current tile is transformed.
+template <int N, int E, int LINES, bool REAL_IN, bool BOHM, bool VEXT, class LT, class Src>
+__device__ __forceinline__ void phasep_local_body(const Src &src, LT *lds, double2 *twl, double2 *scl_tab)
+{
+    constexpr int TPL = N / E, NT = LINES * TPL;
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    for (int i = tid; i < kSinCosTable; i += NT) scl_tab[i] = gld(src.args(0).sct, i);
+    copy_twiddles<N, E, LINES>(src.args(0).tw, twl);
+    const int ntiles = src.ntiles();
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
+    const double inv_n = 1.0 / N;
+    PhiRaw<N, E> fp, fl;
+    float2 p0[E], p1[E];
+    float vx0[E], vx1[E];
+    int pair = em_pair<N, E, LINES>(src.args(tile), src.local(tile), l);
+    em_fetch_phi<N, E>(src.args(tile), pair, t, true, fp);
+    if constexpr (BOHM) em_fetch_raw<N, E>(src.args(tile).half2, src.args(tile).nyq2, pair, t, true, fl);
+    em_fetch_row<N, E>(src.args(tile), pair, 0, t, true, p0);
+    em_fetch_row<N, E>(src.args(tile), pair, 1, t, true, p1);
+    if constexpr (VEXT) em_fetch_vext<N, E>(src.args(tile), pair, t, true, vx0, vx1);
+    __builtin_amdgcn_s_waitcnt(0);
+    dc z[E];
+    em_build_z<N, E>(fp, t, z);
+    for (;;) {
+        const EmArgs &a = src.args(tile);
+        const int nxt = tile + gridDim.x;
+        const bool more = nxt < ntiles;
+        const EmArgs &an = src.args(more ? nxt : tile);
+        const int npair = more ? em_pair<N, E, LINES>(an, src.local(nxt), l) : pair;
+        fft<N, E, 1>(z, t, lay, lds, twl);
+        float phi0[E], phi1[E], lap0[E], lap1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            phi0[e] = (float)(z[e].x * inv_n);
+            phi1[e] = (float)(z[e].y * inv_n);
+            lap0[e] = 0.0f;
+            lap1[e] = 0.0f;
+        }
+        em_fetch_phi<N, E>(an, npair, t, more, fp);
+        if constexpr (BOHM) {
+            em_build_z<N, E>(fl, t, z);
+            fft<N, E, 1>(z, t, lay, lds, twl);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                lap0[e] = (float)(z[e].x * inv_n);
+                lap1[e] = (float)(z[e].y * inv_n);
+            }
+            em_fetch_raw<N, E>(an.half2, an.nyq2, npair, t, more, fl);
+        }
+        float vc0[E], vc1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            vc0[e] = VEXT ? vx0[e] : 0.0f;
+            vc1[e] = VEXT ? vx1[e] : 0.0f;
+        }
+        if constexpr (VEXT) em_fetch_vext<N, E>(an, npair, t, more, vx0, vx1);
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            dc v[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = from_f2(half ? p1[e] : p0[e]);
+            if (half) {
+                em_fetch_row<N, E>(an, npair, 0, t, more, p0);
+                em_fetch_row<N, E>(an, npair, 1, t, more, p1);
+            }
+            if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, twl);
+            double rho[E], U[E];
+            float lp[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if constexpr (!REAL_IN) v[e] = scl(v[e], inv_n);
+                rho[e] = norm2(v[e]);
+                lp[e] = half ? lap1[e] : lap0[e];
+            }
+            local_potential<E>(a, rho, lp, U);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double th = (U[e] + (double)(half ? vc1[e] : vc0[e]) + (double)(half ? phi1[e] : phi0[e])) * a.dz;
+                double sn, cs;
+                sincos_tab(th, scl_tab, &sn, &cs);
+                v[e] = cmul(v[e], mk(cs, sn));
+            }
+            fft<N, E, -1>(v, t, lay, lds, twl);
+            em_store_row<N, E>(a, pair, half, t, v, 1.0);
+        }
+        if (!more) break;
+        em_build_z<N, E>(fp, t, z);
+        pin_all(z, std::make_integer_sequence<int, E>{});
+        tile = nxt;
+        pair = npair;
+    }
+}
+
 // Density pass (as density_tile).
-template <int N, int E, int LINES, bool STORE_PSI, class LT, class Src>
+template <int N, int E, int LINES, bool STORE_PSI, class LT, class Src, bool BOHM = false>
 __device__ __forceinline__ void densityp_body(const Src &src, LT *lds, double2 *twl, double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL, H = N / 2;
@@ -1293,10 +1413,12 @@ __device__ __forceinline__ void densityp_body(const Src &src, LT *lds, double2 *
         fft<N, E, 1>(v, t, lay, lds, twl);
         if constexpr (STORE_PSI) em_store_row<N, E>(a, pair, 1, t, v, inv_n);
         double msum = 0.0;
+        dc w[BOHM ? E : 1];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const double rho1 = norm2(v[e]) * (inv_n * inv_n);
             msum += rho0[e] + rho1;
+            if constexpr (BOHM) w[e] = mk(sqrt(rho0[e]), sqrt(rho1));
             v[e] = mk(rho0[e], rho1);
         }
         fft<N, E, -1>(v, t, lay, lds, twl);
@@ -1324,6 +1446,31 @@ __device__ __forceinline__ void densityp_body(const Src &src, LT *lds, double2 *
         }
         // the LDS slots are rewritten by the next tile's first transform
         exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
+        if constexpr (BOHM) {
+            // sqrt(rho) of both rows, the same split into half2 / nyq2
+            fft<N, E, -1>(w, t, lay, lds, twl);
+#pragma unroll
+            for (int e = 0; e < E; ++e) lds_put(lds, lay(t + TPL * e), w[e]);
+            exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
+            const int pair0 = __builtin_amdgcn_readfirstlane(pair);
+            const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.half2 + (long long)pair0 * 2 * H);
+            const unsigned vo = (unsigned)(((pair - pair0) * 2 * H + t) * 8);
+#pragma unroll
+            for (int e = 0; e < E / 2; ++e) {
+                const int k = t + TPL * e;
+                const dc zz = w[e];
+                const dc zc = conj(lds_get(lds, lay((N - k) & (N - 1))));
+                const dc sm = add(zz, zc), df = sub(zz, zc);
+                buf_st2(to_f2(scl(sm, 0.5)), rs, vo, e * TPL * 8);
+                buf_st2(to_f2(mk(0.5 * df.y, -0.5 * df.x)), rs, vo, H * 8 + e * TPL * 8);
+            }
+            if (t == 0) {
+                const dc zn = w[E / 2];
+                gst(a.nyq2, 2LL * pair, make_float2((float)zn.x, 0.0f));
+                gst(a.nyq2, 2LL * pair + 1, make_float2((float)zn.y, 0.0f));
+            }
+            exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
+        }
         const double bs = block_sum<NT>(real ? msum : 0.0, sh);
         if (tid == 0) gmem(a.partials)[loc] = bs;
         if (!more) break;
@@ -1400,6 +1547,25 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phasep(EmArgs a)
     __shared__ double2 sct[kSinCosTable];
     const Src1<EmArgs> src{a, (a.nlines + LINES - 1) / LINES};
     phasep_body<N, E, LINES, REAL_IN, LT>(src, lds, twl, sct);
+}
+// Pipelined forms of the Eq. (15) density (also sqrt(rho)) and phase passes.
+template <int N, int E, int LINES, bool STORE_PSI>
+__global__ __launch_bounds__(LINES *(N / E)) void k_densityp_bohm(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double2 twl[N];
+    __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
+    const Src1<EmArgs> src{a, (a.nlines + LINES - 1) / LINES};
+    densityp_body<N, E, LINES, STORE_PSI, float2, Src1<EmArgs>, true>(src, lds, twl, sh);
+}
+template <int N, int E, int LINES, bool REAL_IN, bool BOHM, bool VEXT>
+__global__ __launch_bounds__(LINES *(N / E)) void k_phasep_local(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double2 twl[N];
+    __shared__ double2 sct[kSinCosTable];
+    const Src1<EmArgs> src{a, (a.nlines + LINES - 1) / LINES};
+    phasep_local_body<N, E, LINES, REAL_IN, BOHM, VEXT, float2>(src, lds, twl, sct);
 }
 template <int N, int E, int LINES, bool STORE_PSI, class LT = float2>
 __global__ __launch_bounds__(LINES *(N / E)) void k_densityp(EmArgs a)

@@ -24,15 +24,35 @@ template <int N, int V> static LKernels make_local_kernels()
     k.source[0][1] = k_source<N, E, EL, false, true>;
     k.source[1][0] = k_source<N, E, EL, true, false>;
     k.source[1][1] = k_source<N, E, EL, true, true>;
+    k.density_p[0] = k.density_p[1] = nullptr;
+    for (int i = 0; i < 8; ++i) k.phase_p[i >> 2][(i >> 1) & 1][i & 1] = nullptr;
+    if constexpr (C::PIPE) {
+        k.density_p[0] = k_densityp_bohm<N, E, EL, false>;
+        k.density_p[1] = k_densityp_bohm<N, E, EL, true>;
+    }
+    // the persistent phase pass holds two prefetched spectra, two rows and the
+    // static potential: only at 8 points per thread does that fit the registers
+    if constexpr (C::PIPE && E == 8) {
+        k.phase_p[0][0][0] = k_phasep_local<N, E, EL, false, false, false>;
+        k.phase_p[0][0][1] = k_phasep_local<N, E, EL, false, false, true>;
+        k.phase_p[0][1][0] = k_phasep_local<N, E, EL, false, true, false>;
+        k.phase_p[0][1][1] = k_phasep_local<N, E, EL, false, true, true>;
+        k.phase_p[1][0][0] = k_phasep_local<N, E, EL, true, false, false>;
+        k.phase_p[1][0][1] = k_phasep_local<N, E, EL, true, false, true>;
+        k.phase_p[1][1][0] = k_phasep_local<N, E, EL, true, true, false>;
+        k.phase_p[1][1][1] = k_phasep_local<N, E, EL, true, true, true>;
+    }
     return k;
 }
 
 template <int N> static const LKernels *local_table(int v)
 {
-    // variants 2 and 3 use the tile configuration of 0 and 1
-    static const LKernels k[3] = {make_local_kernels<N, 0>(), make_local_kernels<N, 1>(),
+    // the one-tile kernels of variants 2 and 3 are those of 0 and 1 (same
+    // tiles); 2 and 3 add the persistent forms
+    static const LKernels k[5] = {make_local_kernels<N, 0>(), make_local_kernels<N, 1>(),
+                                  make_local_kernels<N, 2>(), make_local_kernels<N, 3>(),
                                   make_local_kernels<N, 4>()};
-    return &k[v == 4 ? 2 : (v & 1)];
+    return &k[v];
 }
 
 // Fields of the non-minimal coupling on a grid (see nmc_point): one thread
