@@ -523,7 +523,12 @@ static void build_core(gsn_grid g)
             EmArgs sa = em_base(g, src);
             sa.nlines = (int)(rows / 2);
             const LKernels *lk = local_kernels_for(Nx, g->var[P_SOURCE]);
-            dst.push_back(em_launch(lk->source[store ? 1 : 0][g->fld_beta ? 1 : 0], KX(P_SOURCE), sa, P_SOURCE));
+            void (*sp)(EmArgs) = energy ? nullptr
+                                        : lk->source_p[store ? 1 : 0][g->fld_beta ? 1 : 0][g->fld_gamma ? 1 : 0];
+            if (sp)
+                dst.push_back(em_launch_persistent(sp, KX(P_SOURCE), sa, P_SOURCE));
+            else
+                dst.push_back(em_launch(lk->source[store ? 1 : 0][g->fld_beta ? 1 : 0], KX(P_SOURCE), sa, P_SOURCE));
         }
         if (nd == 3) {
             const NKernels *ky = KY(P_Y_FWD_RHO), *kz = KZ(P_KERNEL), *ky2 = KY(P_Y_INV_PHI);

@@ -111,6 +111,7 @@ struct LKernels {
     // density with sqrt(rho) [stores psi]; phase [real-space psi][Bohm][static potential]
     void (*density_p[2])(EmArgs);
     void (*phase_p[2][2][2])(EmArgs);
+    void (*source_p[2][2][2])(EmArgs);   // [real-space psi in][lap(rho) in][gamma field]
 };
 const LKernels *local_kernels_for(int N, int v = 0);
 

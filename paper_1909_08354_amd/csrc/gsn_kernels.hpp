@@ -1155,19 +1155,37 @@ __device__ __forceinline__ void em_fetch_phi(const EmArgs &a, int pair, int t, b
     em_fetch_raw<N, E>(a.half, a.nyq, pair, t, live, f);
 }
 
-// The static potential of both rows of a pair (E floats each; live = false:
-// the pair's first point, so the count of loads per iteration stays fixed).
+// A real field (static potential, coupling coefficients) at both rows of a
+// pair, E floats each; live = false: the pair's first point, so the count of
+// loads per iteration stays fixed.
 template <int N, int E>
-__device__ __forceinline__ void em_fetch_vext(const EmArgs &a, int pair, int t, bool live, float (&v0)[E],
-                                              float (&v1)[E])
+__device__ __forceinline__ void em_fetch_field(const float *f, int pair, int t, bool live, float (&v0)[E],
+                                               float (&v1)[E])
 {
     constexpr int TPL = N / E;
-    const auto b = gmem(a.vext) + (long long)pair * 2 * N + (live ? t : 0);
+    const auto b = gmem(f) + (long long)pair * 2 * N + (live ? t : 0);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         v0[e] = b[live ? TPL * e : 0];
         v1[e] = b[live ? N + TPL * e : 0];
     }
+}
+
+// one row of a pair only
+template <int N, int E>
+__device__ __forceinline__ void em_fetch_field_row(const float *f, int pair, int r, int t, bool live, float (&v)[E])
+{
+    constexpr int TPL = N / E;
+    const auto b = gmem(f) + (long long)pair * 2 * N + r * N + (live ? t : 0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = b[live ? TPL * e : 0];
+}
+
+template <int N, int E>
+__device__ __forceinline__ void em_fetch_vext(const EmArgs &a, int pair, int t, bool live, float (&v0)[E],
+                                              float (&v1)[E])
+{
+    em_fetch_field<N, E>(a.vext, pair, t, live, v0, v1);
 }
 
 // The full spectrum Z = X_0 + i X_1 of the pair (conjugate symmetry; DC and
@@ -1373,6 +1391,105 @@ __device__ __forceinline__ void phasep_local_body(const Src &src, LT *lds, doubl
     }
 }
 
+// Source pass (as source_tile) in the persistent prefetching form: the next
+// tile's lap(rho) half spectra (LAP), psi rows and coefficient fields are
+// fetched while the current tile is transformed; s's half spectra replace the
+// current tile's in place.
+template <int N, int E, int LINES, bool REAL_IN, bool LAP, bool GAM, class LT, class Src>
+__device__ __forceinline__ void sourcep_body(const Src &src, LT *lds, double2 *twl)
+{
+    constexpr int TPL = N / E, H = N / 2;
+    const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
+    copy_twiddles<N, E, LINES>(src.args(0).tw, twl);
+    const int ntiles = src.ntiles();
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
+    const double inv_n = 1.0 / N;
+    const double rs = REAL_IN ? 1.0 : inv_n * inv_n;
+    PhiRaw<N, E> fl;
+    float2 p0[E], p1[E];
+    float g0[E], g1[E], b0[E], b1[E];
+    int pair = em_pair<N, E, LINES>(src.args(tile), src.local(tile), l);
+    if constexpr (LAP) em_fetch_raw<N, E>(src.args(tile).half, src.args(tile).nyq, pair, t, true, fl);
+    em_fetch_row<N, E>(src.args(tile), pair, 0, t, true, p0);
+    em_fetch_row<N, E>(src.args(tile), pair, 1, t, true, p1);
+    if constexpr (GAM) em_fetch_field<N, E>(src.args(tile).gam, pair, t, true, g0, g1);
+    if constexpr (LAP) em_fetch_field<N, E>(src.args(tile).bet, pair, t, true, b0, b1);
+    __builtin_amdgcn_s_waitcnt(0);
+    for (;;) {
+        const EmArgs &a = src.args(tile);
+        const int nxt = tile + gridDim.x;
+        const bool more = nxt < ntiles;
+        const EmArgs &an = src.args(more ? nxt : tile);
+        const int npair = more ? em_pair<N, E, LINES>(an, src.local(nxt), l) : pair;
+        dc z[E];
+        float lap0[E], lap1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            lap0[e] = 0.0f;
+            lap1[e] = 0.0f;
+        }
+        if constexpr (LAP) {
+            em_build_z<N, E>(fl, t, z);
+            fft<N, E, 1>(z, t, lay, lds, twl);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                lap0[e] = (float)(z[e].x * inv_n);
+                lap1[e] = (float)(z[e].y * inv_n);
+            }
+            em_fetch_raw<N, E>(an.half, an.nyq, npair, t, more, fl);
+        }
+        double s0[E];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            dc v[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = from_f2(h ? p1[e] : p0[e]);
+            em_fetch_row<N, E>(an, npair, h, t, more, h ? p1 : p0);
+            if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, twl);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                double sv = norm2(v[e]) * rs;
+                if constexpr (GAM) sv *= (double)(h ? g1[e] : g0[e]);
+                if constexpr (LAP) sv = fma((double)(h ? b1[e] : b0[e]), (double)(h ? lap1[e] : lap0[e]), sv);
+                if (h) z[e] = mk(s0[e], sv);
+                else s0[e] = sv;
+            }
+            if constexpr (GAM) em_fetch_field_row<N, E>(an.gam, npair, h, t, more, h ? g1 : g0);
+            if constexpr (LAP) em_fetch_field_row<N, E>(an.bet, npair, h, t, more, h ? b1 : b0);
+        }
+        fft<N, E, -1>(z, t, lay, lds, twl);
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds_put(lds, lay(t + TPL * e), z[e]);
+        exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
+        {
+            const int pair0 = __builtin_amdgcn_readfirstlane(pair);
+            const __amdgpu_buffer_rsrc_t rsr = buf_rsrc(a.half + (long long)pair0 * 2 * H);
+            const unsigned vo = (unsigned)(((pair - pair0) * 2 * H + t) * 8);
+#pragma unroll
+            for (int e = 0; e < E / 2; ++e) {
+                const int k = t + TPL * e;
+                const dc zz = z[e];
+                const dc zc = conj(lds_get(lds, lay((N - k) & (N - 1))));
+                const dc sm = add(zz, zc), df = sub(zz, zc);
+                buf_st2(to_f2(scl(sm, 0.5)), rsr, vo, e * TPL * 8);
+                buf_st2(to_f2(mk(0.5 * df.y, -0.5 * df.x)), rsr, vo, H * 8 + e * TPL * 8);
+            }
+        }
+        if (t == 0) {
+            const dc zn = z[E / 2];
+            gst(a.nyq, 2LL * pair, make_float2((float)zn.x, 0.0f));
+            gst(a.nyq, 2LL * pair + 1, make_float2((float)zn.y, 0.0f));
+        }
+        // the LDS slots are rewritten by the next tile's first transform
+        exchange_sync<EmLayout<N, E>::WAVE_LOCAL>();
+        if (!more) break;
+        tile = nxt;
+        pair = npair;
+    }
+}
+
 // Density pass (as density_tile).
 template <int N, int E, int LINES, bool STORE_PSI, class LT, class Src, bool BOHM = false>
 __device__ __forceinline__ void densityp_body(const Src &src, LT *lds, double2 *twl, double *sh)
@@ -1557,6 +1674,14 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_densityp_bohm(EmArgs a)
     __shared__ double sh[EmTile<N, E, LINES>::NT / 64 + 1];
     const Src1<EmArgs> src{a, (a.nlines + LINES - 1) / LINES};
     densityp_body<N, E, LINES, STORE_PSI, float2, Src1<EmArgs>, true>(src, lds, twl, sh);
+}
+template <int N, int E, int LINES, bool REAL_IN, bool LAP, bool GAM>
+__global__ __launch_bounds__(LINES *(N / E)) void k_sourcep(EmArgs a)
+{
+    __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
+    __shared__ double2 twl[N];
+    const Src1<EmArgs> src{a, (a.nlines + LINES - 1) / LINES};
+    sourcep_body<N, E, LINES, REAL_IN, LAP, GAM, float2>(src, lds, twl);
 }
 template <int N, int E, int LINES, bool REAL_IN, bool BOHM, bool VEXT>
 __global__ __launch_bounds__(LINES *(N / E)) void k_phasep_local(EmArgs a)

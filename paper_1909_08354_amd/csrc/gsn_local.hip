@@ -25,7 +25,10 @@ template <int N, int V> static LKernels make_local_kernels()
     k.source[1][0] = k_source<N, E, EL, true, false>;
     k.source[1][1] = k_source<N, E, EL, true, true>;
     k.density_p[0] = k.density_p[1] = nullptr;
-    for (int i = 0; i < 8; ++i) k.phase_p[i >> 2][(i >> 1) & 1][i & 1] = nullptr;
+    for (int i = 0; i < 8; ++i) {
+        k.phase_p[i >> 2][(i >> 1) & 1][i & 1] = nullptr;
+        k.source_p[i >> 2][(i >> 1) & 1][i & 1] = nullptr;
+    }
     if constexpr (C::PIPE) {
         k.density_p[0] = k_densityp_bohm<N, E, EL, false>;
         k.density_p[1] = k_densityp_bohm<N, E, EL, true>;
@@ -41,6 +44,12 @@ template <int N, int V> static LKernels make_local_kernels()
         k.phase_p[1][0][1] = k_phasep_local<N, E, EL, true, false, true>;
         k.phase_p[1][1][0] = k_phasep_local<N, E, EL, true, true, false>;
         k.phase_p[1][1][1] = k_phasep_local<N, E, EL, true, true, true>;
+        k.source_p[0][0][1] = k_sourcep<N, E, EL, false, false, true>;
+        k.source_p[0][1][0] = k_sourcep<N, E, EL, false, true, false>;
+        k.source_p[0][1][1] = k_sourcep<N, E, EL, false, true, true>;
+        k.source_p[1][0][1] = k_sourcep<N, E, EL, true, false, true>;
+        k.source_p[1][1][0] = k_sourcep<N, E, EL, true, true, false>;
+        k.source_p[1][1][1] = k_sourcep<N, E, EL, true, true, true>;
     }
     return k;
 }
