@@ -149,7 +149,8 @@ gsn_status gsn_set_local_terms(gsn_grid grid, double c_pressure, double n_pressu
    field the x pass "x_source".  While gamma or beta is set the kernel must have
    K(0) = 0 (no screened or contact part: stepping returns GSN_EUNSUPPORTED),
    and gsn_energy, gsn_potential and gsn_step_corrected return
-   GSN_EUNSUPPORTED (gsn_energy also with V_ext alone).  Synchronising. */
+   GSN_EUNSUPPORTED; with V_ext alone the energy's local part includes
+   -dV sum V_ext rho.  Synchronising. */
 gsn_status gsn_set_source_fields(gsn_grid grid, const float *gamma, const float *beta, const float *V_ext);
 
 /* Fill caller device arrays of P floats with the fields of the pure
@@ -188,7 +189,7 @@ gsn_status gsn_mass(gsn_grid grid, double *mass);
    e[0] total, e[1] kinetic a dV/P sum |k|^2 |psi_hat|^2, e[2] local
    -(g/2) dV sum rho^2 - c_pressure dV sum G_n(rho) + (c_bohm/2) dV sum |grad sqrt rho|^2
    (G_n' = f_n(max(rho, rho_floor)); the Bohm part is evaluated as
-   -(c_bohm/2) dV sum sqrt(rho) lap(sqrt rho)), e[3] nonlocal
+   -(c_bohm/2) dV sum sqrt(rho) lap(sqrt rho)) - dV sum V_ext rho, e[3] nonlocal
    -(1/2) dV sum rho phi.  Synchronising. */
 gsn_status gsn_energy(gsn_grid grid, double e[4]);
 

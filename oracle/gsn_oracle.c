@@ -707,6 +707,7 @@ int orc_local_potential(const double *psi_in, int ndim, const int *n, const doub
  *   E_p   = -c_p dV sum G_n(rho),  G_n' = f_n(max(rho, rho_f))
  *   E_B   = (c_B/2) dV sum |grad s|^2 = -(c_B/2) dV sum s lap(s),  s = sqrt(rho)
  *   E_nl  = -(1/2) dV sum rho phi
+ * (with a static potential V, E_loc also holds -dV sum V rho)
  * E_total is the Hamiltonian of the equation above: its variation with
  * respect to conj(psi) is -a lap(psi) - U psi - phi psi (for the Bohm part
  * where rho >= rho_f, since the variation of sum |grad s|^2 with respect to rho
@@ -714,7 +715,7 @@ int orc_local_potential(const double *psi_in, int ndim, const int *n, const doub
  */
 static int observables_spec(const double *psi_in, int ndim, const int *n, const double *L,
                             const kspec_t *ks, double a, double gloc, const double *lp,
-                            double *out, int nthreads)
+                            const double *V, double *out, int nthreads)
 {
     grid_t g;
     local_t lt;
@@ -762,7 +763,12 @@ static int observables_spec(const double *psi_in, int ndim, const int *n, const 
     }
     out[0] = dV * mass;
     out[1] = a * dV / (double)g.P * ekin;
-    out[2] = -0.5 * gloc * dV * eloc + ep + eb;
+    double ev = 0.0;   /* static potential: -dV sum V rho */
+    if (V) {
+        for (long long q = 0; q < g.P; q++) ev += V[q] * rho[q];
+        ev *= -dV;
+    }
+    out[2] = -0.5 * gloc * dV * eloc + ep + eb + ev;
     out[3] = -0.5 * dV * enl;
     out[4] = out[1] + out[2] + out[3];
     out[5] = ep;
@@ -781,7 +787,17 @@ int orc_observables_local(const double *psi_in, int ndim, const int *n, const do
                           double *out, int nthreads)
 {
     kspec_t ks = {0, kp, 0.0, 0.0, 0.0};
-    return observables_spec(psi_in, ndim, n, L, &ks, a, gloc, lp, out, nthreads);
+    return observables_spec(psi_in, ndim, n, L, &ks, a, gloc, lp, NULL, out, nthreads);
+}
+
+/* orc_observables_local with a static potential V (the local energy then
+   includes -dV sum V rho); V == NULL: none */
+int orc_observables_vext(const double *psi_in, int ndim, const int *n, const double *L,
+                         const double *kp, double a, double gloc, const double *lp, const double *V,
+                         double *out, int nthreads)
+{
+    kspec_t ks = {0, kp, 0.0, 0.0, 0.0};
+    return observables_spec(psi_in, ndim, n, L, &ks, a, gloc, lp, V, out, nthreads);
 }
 
 /* observables of Eq. (1)-(2) with their own constants (a = -A) */
@@ -790,7 +806,7 @@ int orc_observables_equation(const double *psi_in, int ndim, const int *n, const
                              double *out, int nthreads)
 {
     kspec_t ks = {1, NULL, B, C, D};
-    return observables_spec(psi_in, ndim, n, L, &ks, -A, gloc, lp, out, nthreads);
+    return observables_spec(psi_in, ndim, n, L, &ks, -A, gloc, lp, NULL, out, nthreads);
 }
 
 /* orc_observables_local with the Kerr term only; out has 5 entries */

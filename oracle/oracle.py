@@ -65,12 +65,13 @@ def _load():
                                       ctypes.c_longlong, ctypes.c_int, ctypes.c_int]
     lib.orc_potential_fields.argtypes = [dp, dp, ctypes.c_int, ip, dp, dp, dp, dp, ctypes.c_int]
     lib.orc_nmc_fields.argtypes = [ctypes.c_int, ip, dp, d, d, d, dp, d, dp, dp, dp]
+    lib.orc_observables_vext.argtypes = [dp, ctypes.c_int, ip, dp, dp, d, d, dp, dp, dp, ctypes.c_int]
     lib.orc_max_threads.argtypes = []
     for f in ("orc_fft", "orc_dft_brute", "orc_potential", "orc_evolve",
               "orc_observables", "orc_evolve_local", "orc_observables_local",
               "orc_local_potential", "orc_evolve_equation", "orc_potential_equation",
               "orc_observables_equation", "orc_evolve_fields", "orc_potential_fields",
-              "orc_nmc_fields", "orc_max_threads"):
+              "orc_nmc_fields", "orc_observables_vext", "orc_max_threads"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -150,15 +151,22 @@ def evolve(psi, L, kern, a, g, dz, nsteps, merged=True, nthreads=0, local=None):
     return p
 
 
-def observables(psi, L, kern, a, g, nthreads=0, local=None):
+def observables(psi, L, kern, a, g, nthreads=0, local=None, V=None):
     """dict(mass, kinetic, local, nonlocal, total, pressure, bohm) of psi;
-    ``local`` (the total local energy) includes the pressure and Bohm parts."""
+    ``local`` (the total local energy) includes the pressure and Bohm parts and,
+    with a static potential V, -dV sum V rho."""
     p = np.ascontiguousarray(psi, dtype=np.complex128)
     n, Larr = _shape_args(p.shape, L)
     k = np.ascontiguousarray(kern, dtype=np.float64)
     out = np.zeros(7)
     lp = _local_arr(local)
-    if lp is None:
+    if V is not None:
+        Va = np.ascontiguousarray(V, dtype=np.float64)
+        if Va.shape != p.shape:
+            raise ValueError("V shape differs from the grid")
+        rc = _load().orc_observables_vext(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a), float(g),
+                                          None if lp is None else _dptr(lp), _dptr(Va), _dptr(out), nthreads)
+    elif lp is None:
         rc = _load().orc_observables(_dptr(p), p.ndim, n, _dptr(Larr), _dptr(k), float(a),
                                      float(g), _dptr(out), nthreads)
     else:

@@ -1236,8 +1236,8 @@ extern "C" gsn_status gsn_energy(gsn_grid g, double e[4])
     if (!e) return fail(GSN_EINVAL, "e is NULL");
     gsn_status s = g ? GSN_OK : fail(GSN_EINVAL, "grid is NULL");
     if (s) return s;
-    if (g->fld_gamma || g->fld_beta || g->fld_V)
-        return fail(GSN_EUNSUPPORTED, "no energy with position-dependent source fields or a static potential");
+    if (g->fld_gamma || g->fld_beta)
+        return fail(GSN_EUNSUPPORTED, "no energy with position-dependent source fields");
     if (!g->have_psi) return fail(GSN_ESTATE, "psi not set");
     HIP_TRY(hipSetDevice(g->device));
     HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, g->esz * g->P, hipMemcpyDeviceToDevice, g->stream));
@@ -1259,8 +1259,9 @@ extern "C" gsn_status gsn_energy(gsn_grid g, double e[4])
     if ((s = sum_device(g, g->epart + 4 * g->max_density_blocks, nkin, 1, 0, &k2sum))) return s;
     const double dV = cell_volume(g), P = (double)g->P, K0 = kernel_k0(g);
     const double ekin = g->a * dV / P * k2sum;
-    // Kerr, pressure (-c_p sum G) and Bohm (-(c_B/2) sum s lap s = (c_B/2) sum |grad s|^2)
-    const double eloc = -0.5 * g->g * dV * rho2 - g->lp_cp * dV * gsum - 0.5 * g->lp_cb * dV * slap;
+    // Kerr, pressure and static potential (-sum (c_p G + V rho)) and Bohm
+    // (-(c_B/2) sum s lap s = (c_B/2) sum |grad s|^2)
+    const double eloc = -0.5 * g->g * dV * rho2 - dV * gsum - 0.5 * g->lp_cb * dV * slap;
     const double enl = -0.5 * dV * (rho_phi + K0 * rho_sum * rho_sum / P);
     e[0] = ekin + eloc + enl;
     e[1] = ekin;

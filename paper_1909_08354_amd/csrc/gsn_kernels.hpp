@@ -546,7 +546,8 @@ __device__ __forceinline__ double pressure_energy_density(const EmArgs &a, doubl
 // Phase pass with the local terms of Eq. (15): as phase_tile, plus (a.bohm)
 // lap(s) of both rows from the half2 spectrum, and the local potential U of
 // local_potential in place of g rho.  ENERGY: per tile the sums of rho phi,
-// rho^2, G(rho) (pressure) and s lap(s) (Bohm).
+// rho^2, c_p G(rho) + V rho (pressure and static potential) and s lap(s)
+// (Bohm).
 template <int N, int E, int LINES, bool ENERGY, bool REAL_IN>
 __device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, float2 *lds, double *sh)
 {
@@ -588,7 +589,7 @@ __device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, floa
         float vx[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) vx[e] = 0.0f;
-        if (!ENERGY && a.vext) {   // uniform pointer
+        if (a.vext) {   // uniform pointer
             const float *vr = a.vext + (act ? (half ? r1 : r0) * N + t : 0);
 #pragma unroll
             for (int e = 0; e < E; ++e) vx[e] = vr[TPL * e];
@@ -605,7 +606,8 @@ __device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, floa
             for (int e = 0; e < E; ++e) {
                 acc0 += rho[e] * (double)(half ? phi1[e] : phi0[e]);
                 acc1 += rho[e] * rho[e];
-                if (a.pmode) acc2 += pressure_energy_density(a, rho[e]);
+                if (a.pmode) acc2 = fma(a.cp, pressure_energy_density(a, rho[e]), acc2);
+                acc2 = fma((double)vx[e], rho[e], acc2);
                 acc3 += sqrt(rho[e]) * (double)(half ? lap1[e] : lap0[e]);
             }
         } else {

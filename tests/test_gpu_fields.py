@@ -170,3 +170,30 @@ def test_nmc_256_full_size_matches_oracle():
     drift = abs(grid.mass() / m0 - 1)
     say(f"nmc 256^3: norm drift over {w['steps']} steps {drift:.3e}")
     assert drift < 1e-6
+
+
+@pytest.mark.parametrize("shape", ["2d", "3d"])
+def test_static_potential_energy_matches_oracle(shape):
+    """With V_ext alone the energy stays the Hamiltonian: its local part holds
+    -dV sum V rho (with the Eq. (15) terms on as well)."""
+    n, L = SHAPES[shape]
+    psi0 = inputs.fluid_gaussian(n, L, 25.0, 4.0, seed=15)
+    _, _, V = smooth_fields(n, L, 6)
+    kern, g, local = (0.8, 0.2, 0.4, 0.0), -0.2, (-0.5, 1.0, -1.0, 1e-10)
+    grid = gsn.Grid(n, L)
+    grid.set_kernel(*kern)
+    grid.set_coefficients(0.5, g, 1e-3)
+    grid.set_local_terms(*local)
+    keep = dev(V)
+    grid.set_source_fields(None, None, keep)
+    grid.set_psi(inputs.to_c64(psi0))
+    grid.step(6)
+    psi = grid.get_psi()
+    e = grid.energy()
+    eo = orc.observables(psi, L, kern, 0.5, g, local=local, V=host64(V))
+    scale = abs(eo["kinetic"]) + abs(eo["local"]) + abs(eo["nonlocal"])
+    for k in ("total", "kinetic", "local", "nonlocal"):
+        assert abs(e[k] - eo[k]) < 1e-6 * scale, k
+    ref = orc.evolve_fields(inputs.as_oracle_input(psi0), L, kern, 0.5, g, 1e-3, 6, (None, None, host64(V)),
+                            local=local)
+    assert orc.rel_l2(psi, ref) < REL_L2

@@ -652,3 +652,25 @@ def test_nmc_fields_identities_and_gr_limit():
     far = np.abs(x) > 8.0
     assert np.max(np.abs(gm[far] - 0.5)) < 1e-12 and np.max(bt[far]) < 1e-12
     assert np.max(np.abs(V[far])) < 1e-12
+
+
+def test_static_potential_energy_closed_form_and_conservation():
+    """psi0 = exp(-r^2/(2 sig^2)) in V = -a r^2/sig^4 (2-D): integral |grad psi0|^2 = pi
+    and -integral V rho = a pi, so E = 2 a pi and E/M = a D/sig^2, the eigenvalue;
+    a lump moving in the trap keeps E to O(dz^2)."""
+    n, L, a, sig = (128, 128), (24.0, 24.0), 0.5, 1.5
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    r2 = xs[0] ** 2 + xs[1] ** 2
+    psi0 = np.exp(-r2 / (2 * sig * sig)).astype(complex)
+    V = -a * r2 / sig ** 4
+    ob = orc.observables(psi0, L, (0, 0, 0, 0), a, 0.0, V=V)
+    assert abs(ob["kinetic"] - a * np.pi) < 1e-10
+    assert abs(ob["local"] - a * np.pi) < 1e-10
+    assert abs(ob["total"] / ob["mass"] - a * 2 / sig ** 2) < 1e-10
+    moving = psi0 * np.exp(1j * 0.8 * xs[1])
+    E0 = orc.observables(moving, L, (1.0, 0, 0, 0), a, -0.3, V=V)["total"]
+    drifts = []
+    for steps in (20, 40):
+        out = orc.evolve_fields(moving, L, (1.0, 0, 0, 0), a, -0.3, 0.4 / steps, steps, (None, None, V))
+        drifts.append(abs(orc.observables(out, L, (1.0, 0, 0, 0), a, -0.3, V=V)["total"] - E0))
+    assert 3.0 < drifts[0] / drifts[1] < 5.0, drifts
