@@ -139,7 +139,8 @@ gsn_status gsn_set_local_terms(gsn_grid grid, double c_pressure, double n_pressu
 /* Position-dependent coupling (Eq. (9)-(12)) and a static potential: the
    kernel acts on the source s = gamma(x) rho + beta(x) lap(rho) instead of rho,
    and V_ext(x) joins the phase, i psi_z = ... - (U + phi + V_ext) psi.  gamma,
-   beta and V_ext are device arrays of P floats in C order, owned by the caller;
+   beta and V_ext are device arrays of count = P floats in C order (any other
+   count with a field given: GSN_EINVAL), owned by the caller;
    the grid reads them on every step until they are replaced or cleared (pass
    NULL for an absent field: gamma = 1, beta = 0, V_ext = 0), so they must stay
    alive and unchanged meanwhile.  The pure non-minimal coupling of Eq. (12)
@@ -151,7 +152,8 @@ gsn_status gsn_set_local_terms(gsn_grid grid, double c_pressure, double n_pressu
    and gsn_energy, gsn_potential and gsn_step_corrected return
    GSN_EUNSUPPORTED; with V_ext alone the energy's local part includes
    -dV sum V_ext rho.  Synchronising. */
-gsn_status gsn_set_source_fields(gsn_grid grid, const float *gamma, const float *beta, const float *V_ext);
+gsn_status gsn_set_source_fields(gsn_grid grid, const float *gamma, const float *beta, const float *V_ext,
+                                 size_t count);
 
 /* Fill caller device arrays of P floats with the fields of the pure
    non-minimal coupling on this grid's points (Eq. (9)-(11)): with r the
@@ -160,10 +162,10 @@ gsn_status gsn_set_source_fields(gsn_grid grid, const float *gamma, const float 
      gamma = (1 - u) / 2,  beta = lambda u / (r + r0),  V_ext = -ln(1 - u) / nu,
    the last with r raised to r_min, since phi_C = ln(1 - u) diverges at the
    centre.  r0 = M / (4 pi) is the Schwarzschild radius of the mass M.  Any
-   output may be NULL.  lambda, r0, r_min > 0 and nu != 0, else GSN_EINVAL.
+   output may be NULL; count is the length of each output (at least P).  lambda, r0, r_min > 0 and nu != 0, else GSN_EINVAL.
    Synchronising. */
 gsn_status gsn_nmc_fields(gsn_grid grid, double lambda, double r0, double nu, const double *center,
-                          double r_min, float *gamma, float *beta, float *V_ext);
+                          double r_min, float *gamma, float *beta, float *V_ext, size_t count);
 
 /* Load psi (P complex values, C order) from host (src_on_device = 0) or
    device memory, as complex64 or complex128.  Resets the global phase and the

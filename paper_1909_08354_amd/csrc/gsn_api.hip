@@ -893,7 +893,7 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
 extern "C" gsn_status gsn_destroy(gsn_grid g)
 {
     if (!g) return fail(GSN_EINVAL, "grid is NULL");
-    hipStreamSynchronize(g->stream);
+    (void)hipStreamSynchronize(g->stream);
     delete g;
     return GSN_OK;
 }
@@ -996,9 +996,12 @@ extern "C" gsn_status gsn_set_local_terms(gsn_grid g, double c_pressure, double 
     return GSN_OK;
 }
 
-extern "C" gsn_status gsn_set_source_fields(gsn_grid g, const float *gamma, const float *beta, const float *V_ext)
+extern "C" gsn_status gsn_set_source_fields(gsn_grid g, const float *gamma, const float *beta, const float *V_ext,
+                                            size_t count)
 {
     if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if ((gamma || beta || V_ext) && count != (size_t)g->P)
+        return fail(GSN_EINVAL, "each field must hold exactly P = " + std::to_string(g->P) + " values");
     if (g->storage == GSN_C128 && (gamma || beta || V_ext))
         return fail(GSN_EUNSUPPORTED, "source fields run on complex64 grids");
     HIP_TRY(hipSetDevice(g->device));
@@ -1011,9 +1014,10 @@ extern "C" gsn_status gsn_set_source_fields(gsn_grid g, const float *gamma, cons
 }
 
 extern "C" gsn_status gsn_nmc_fields(gsn_grid g, double lambda, double r0, double nu, const double *center,
-                                     double r_min, float *gamma, float *beta, float *V_ext)
+                                     double r_min, float *gamma, float *beta, float *V_ext, size_t count)
 {
     if (!g) return fail(GSN_EINVAL, "grid is NULL");
+    if (count < (size_t)g->P) return fail(GSN_EINVAL, "outputs must hold P = " + std::to_string(g->P) + " values");
     if (!(std::isfinite(lambda) && lambda > 0.0) || !(std::isfinite(r0) && r0 > 0.0) || !std::isfinite(nu) ||
         nu == 0.0 || !(std::isfinite(r_min) && r_min > 0.0))
         return fail(GSN_EINVAL, "need lambda > 0, r0 > 0, nu != 0 and r_min > 0, all finite");
@@ -1337,7 +1341,7 @@ extern "C" gsn_status gsn_profile_passes(gsn_grid g, int64_t nsteps, double *ms,
         tot[seq[i]->pass] += t;
         cnt[seq[i]->pass] += 1;
     }
-    for (auto &e : ev) hipEventDestroy(e);
+    for (auto &e : ev) (void)hipEventDestroy(e);
     for (int i = 0; i < P_COUNT; ++i) ms[i] = cnt[i] ? tot[i] / cnt[i] : 0.0;
     return gsn_sync(g);
 }

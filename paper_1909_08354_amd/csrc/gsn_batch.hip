@@ -573,19 +573,19 @@ gsn_status capture_graph(gsn_batch b, int64_t nsteps)
     }
     hipGraph_t graph = nullptr;
     hipError_t ee = hipStreamEndCapture(b->stream, &graph);
-    hipEventDestroy(fork);
-    for (auto &e : join) hipEventDestroy(e);
+    (void)hipEventDestroy(fork);
+    for (auto &e : join) (void)hipEventDestroy(e);
     if (st) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return st;
     }
     if (he != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return fail(GSN_EHIP, std::string("graph capture: ") + hipGetErrorString(he));
     }
     if (ee != hipSuccess) return fail(GSN_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
     hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return fail(GSN_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     b->exec_steps = nsteps;
     b->dirty = false;
@@ -819,20 +819,20 @@ extern "C" gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, cons
     for (auto &st : b->side)
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             for (auto &x : b->side)
-                if (x) hipStreamDestroy(x);
+                if (x) (void)hipStreamDestroy(x);
             delete b;
             return fail(GSN_EHIP, "hipStreamCreate failed");
         }
     for (Instance &I : b->inst) {
         if ((s = upload_instance_tables(b, I))) {
-            for (auto &x : b->side) hipStreamDestroy(x);
+            for (auto &x : b->side) (void)hipStreamDestroy(x);
             delete b;
             return s;
         }
         hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, b->stream, I.st);
     }
     if ((s = build_batch(b))) {
-        for (auto &x : b->side) hipStreamDestroy(x);
+        for (auto &x : b->side) (void)hipStreamDestroy(x);
         delete b;
         return s;
     }

@@ -47,9 +47,9 @@ _SIGNATURES = {
     "gsn_set_coefficients": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "gsn_set_local_terms": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "gsn_set_equation": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
-    "gsn_set_source_fields": [vp, vp, vp, vp],
+    "gsn_set_source_fields": [vp, vp, vp, vp, ctypes.c_size_t],
     "gsn_nmc_fields": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
-                       ctypes.c_double, vp, vp, vp],
+                       ctypes.c_double, vp, vp, vp, ctypes.c_size_t],
     "gsn_set_psi": [vp, vp, ctypes.c_int, ctypes.c_int],
     "gsn_step": [vp, ctypes.c_int64],
     "gsn_sync": [vp],
@@ -249,7 +249,7 @@ class Grid:
         """Position-dependent coupling s = gamma rho + beta lap(rho) and a static
         potential V_ext (device float32 tensors; references are kept while set)."""
         ptrs = [self._field_ptr(f) for f in (gamma, beta, V_ext)]
-        check(load().gsn_set_source_fields(self.h, *ptrs))
+        check(load().gsn_set_source_fields(self.h, *ptrs, self.P))
         self._fields = (gamma, beta, V_ext)
 
     def nmc_fields(self, lam, r0, nu, center=None, r_min=None):
@@ -259,7 +259,7 @@ class Grid:
         out = [t.empty(tuple(self.n), dtype=t.float32, device="cuda") for _ in range(3)]
         c = None if center is None else _f64(center)
         rmin = 0.5 * min(Ld / N for N, Ld in zip(self.n, self.L)) if r_min is None else r_min
-        check(load().gsn_nmc_fields(self.h, lam, r0, nu, c, rmin, *[o.data_ptr() for o in out]))
+        check(load().gsn_nmc_fields(self.h, lam, r0, nu, c, rmin, *[o.data_ptr() for o in out], self.P))
         return tuple(out)
 
     def set_local_terms(self, c_pressure=0.0, n_pressure=1.0, c_bohm=0.0, rho_floor=0.0):

@@ -197,3 +197,16 @@ def test_static_potential_energy_matches_oracle(shape):
     ref = orc.evolve_fields(inputs.as_oracle_input(psi0), L, kern, 0.5, g, 1e-3, 6, (None, None, host64(V)),
                             local=local)
     assert orc.rel_l2(psi, ref) < REL_L2
+
+
+def test_field_counts_are_checked():
+    import ctypes
+    n, L = SHAPES["2d"]
+    grid = gsn.Grid(n, L)
+    f = dev(np.ones(n, np.float32))
+    lib = gsn.load()
+    P = int(np.prod(n))
+    assert lib.gsn_set_source_fields(grid.h, ctypes.c_void_p(f.data_ptr()), None, None, P - 1) == gsn.GSN_EINVAL
+    assert lib.gsn_set_source_fields(grid.h, None, None, None, 0) == gsn.GSN_OK
+    assert lib.gsn_nmc_fields(grid.h, 1.0, 2.0, 1.0, None, 0.5, ctypes.c_void_p(f.data_ptr()), None, None,
+                              P - 1) == gsn.GSN_EINVAL
