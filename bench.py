@@ -176,7 +176,7 @@ def corrector_bench(ntrain, epochs, neval, ncoarse, tol):
     """Learned corrector on 512^2 lump states: train on solver-generated pairs
     (seeds 10000..), then on held-out seeds (20000..) compare, after ncoarse
     coarse steps (ratio 8), the plain coarse solver and the corrected one with
-    the fine solver (the judge): relative L2 errors, share of seeds within tol,
+    the fine solver (the reference): relative L2 errors, share of seeds within tol,
     and device time of the fine and corrected runs."""
     from paper_1909_08354_amd import corrector_train as ct
     from paper_1909_08354_amd import gsn, inputs

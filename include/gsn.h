@@ -292,7 +292,7 @@ gsn_status gsn_batch_set_schedule(gsn_batch batch, const int *variants, int nfam
    residual psi_fine - psi_c of the equivalent ratio fine steps.  bfloat16
    weights and activations, FP32 accumulation on the matrix cores, FP32
    master weights and Adam moments.  This is not part of the paper's method:
-   the plain fine-step solver stays the judge of its error and its fallback.
+   the plain fine-step solver stays the reference for its error and its fallback.
    Flat FP32 parameter vector, per layer: w[tap][cout][cin] (tap = 3 dy + dx,
    input offset (dy-1, dx-1)) then bias[cout].  Images are H x W with H*W a
    multiple of 64; device buffers are psi complex64 H*W and phi float H*W. */

@@ -7,7 +7,7 @@ The corrector is a 4-layer 3x3 convolutional network with circular (periodic)
 padding, 3 -> 32 -> 32 -> 32 -> 2 channels, ReLU after the first three layers,
 trained with a mean-squared error and Adam.  The paper itself has no learned
 component: this network only corrects a coarse split step towards the fine
-one, and the plain fine-step solver stays the judge of its error.
+one, and the plain fine-step solver stays the reference for its error.
 
 Conventions (shared with the C ABI's flat parameter vector):
   * images are [B, H, W, C] (channels last);

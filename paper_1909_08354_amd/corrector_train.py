@@ -103,7 +103,7 @@ def train(corr, data, epochs=4, batch=8, lr=2e-3, lr_final=2e-4, seed=0, log=Non
 
 def evaluate(corr, seeds, ncoarse=10, w=None, ratio=None, audit_every=0, tol=0.0):
     """Relative L2 error after ncoarse steps of the plain coarse solver and of
-    the corrected one, both against ratio * ncoarse fine steps (the judge),
+    the corrected one, both against ratio * ncoarse fine steps (the reference),
     with device timings of the fine and corrected runs."""
     import torch
     w = w or inputs.WORKLOADS["gsn2d_512_corrector"]

@@ -1658,7 +1658,7 @@ extern "C" gsn_status gsn_step_corrected(gsn_grid g, gsn_corrector c, int64_t nc
         if ((s = run_potential(g, phi))) return s;
         if ((s = corrector_correct_inplace(c, g->psi, phi, &g->st->theta, g->stream))) return s;
         if (audit) {
-            // the fine solver from the same state is the judge of the corrected step
+            // the fine solver from the same state is the reference for the corrected step
             HIP_TRY(hipMemcpyAsync(corrected, g->psi, bytes, hipMemcpyDeviceToDevice, g->stream));
             HIP_TRY(hipMemcpyAsync(g->st_save[1], g->st, sizeof(DevState), hipMemcpyDeviceToDevice, g->stream));
             HIP_TRY(hipMemcpyAsync(g->psi, saved, bytes, hipMemcpyDeviceToDevice, g->stream));
