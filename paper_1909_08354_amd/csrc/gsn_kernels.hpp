@@ -1300,7 +1300,8 @@ __device__ __forceinline__ void phasep_body(const Src &src, LT *lds, double2 *tw
 // spectra, lap(sqrt rho) half spectra (BOHM), psi rows and static potential
 // (VEXT) are fetched while the current tile is transformed.
 template <int N, int E, int LINES, bool REAL_IN, bool BOHM, bool VEXT, class LT, class Src>
-__device__ __forceinline__ void phasep_local_body(const Src &src, LT *lds, double2 *twl, double2 *scl_tab)
+__device__ __forceinline__ void phasep_local_body(const Src &src, LT *lds, double2 *twl, double2 *scl_tab,
+                                                  float *stash)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
     const int tid = threadIdx.x, t = tid % TPL, l = tid / TPL;
@@ -1338,26 +1339,39 @@ __device__ __forceinline__ void phasep_local_body(const Src &src, LT *lds, doubl
             lap0[e] = 0.0f;
             lap1[e] = 0.0f;
         }
+        if constexpr (BOHM) {
+            // phi waits in LDS (each thread its own slots) during the lap
+            // transform and the rows: fewer live registers
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                stash[e * NT + tid] = phi0[e];
+                stash[(E + e) * NT + tid] = phi1[e];
+            }
+        }
         em_fetch_phi<N, E>(an, npair, t, more, fp);
         if constexpr (BOHM) {
             em_build_z<N, E>(fl, t, z);
             fft<N, E, 1>(z, t, lay, lds, twl);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                lap0[e] = (float)(z[e].x * inv_n);
-                lap1[e] = (float)(z[e].y * inv_n);
+                stash[(2 * E + e) * NT + tid] = (float)(z[e].x * inv_n);
+                stash[(3 * E + e) * NT + tid] = (float)(z[e].y * inv_n);
             }
-            em_fetch_raw<N, E>(an.half2, an.nyq2, npair, t, more, fl);
         }
-        float vc0[E], vc1[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            vc0[e] = VEXT ? vx0[e] : 0.0f;
-            vc1[e] = VEXT ? vx1[e] : 0.0f;
-        }
-        if constexpr (VEXT) em_fetch_vext<N, E>(an, npair, t, more, vx0, vx1);
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
+            if constexpr (BOHM) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if (half) {
+                        phi1[e] = stash[(E + e) * NT + tid];
+                        lap1[e] = stash[(3 * E + e) * NT + tid];
+                    } else {
+                        phi0[e] = stash[e * NT + tid];
+                        lap0[e] = stash[(2 * E + e) * NT + tid];
+                    }
+                }
+            }
             dc v[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = from_f2(half ? p1[e] : p0[e]);
@@ -1377,7 +1391,8 @@ __device__ __forceinline__ void phasep_local_body(const Src &src, LT *lds, doubl
             local_potential<E>(a, rho, lp, U);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const double th = (U[e] + (double)(half ? vc1[e] : vc0[e]) + (double)(half ? phi1[e] : phi0[e])) * a.dz;
+                const double vv = VEXT ? (double)(half ? vx1[e] : vx0[e]) : 0.0;
+                const double th = (U[e] + vv + (double)(half ? phi1[e] : phi0[e])) * a.dz;
                 double sn, cs;
                 sincos_tab(th, scl_tab, &sn, &cs);
                 v[e] = cmul(v[e], mk(cs, sn));
@@ -1385,6 +1400,11 @@ __device__ __forceinline__ void phasep_local_body(const Src &src, LT *lds, doubl
             fft<N, E, -1>(v, t, lay, lds, twl);
             em_store_row<N, E>(a, pair, half, t, v, 1.0);
         }
+        // the next tile's lap(sqrt rho) spectra and static potential, fetched
+        // only now: their registers are free while the rows are worked on,
+        // and the next tile's phi transform covers their latency
+        if constexpr (BOHM) em_fetch_raw<N, E>(an.half2, an.nyq2, npair, t, more, fl);
+        if constexpr (VEXT) em_fetch_vext<N, E>(an, npair, t, more, vx0, vx1);
         if (!more) break;
         em_build_z<N, E>(fp, t, z);
         pin_all(z, std::make_integer_sequence<int, E>{});
@@ -1691,8 +1711,9 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_phasep_local(EmArgs a)
     __shared__ float2 lds[EmTile<N, E, LINES>::LDS];
     __shared__ double2 twl[N];
     __shared__ double2 sct[kSinCosTable];
+    __shared__ float stash[BOHM ? 4 * E * LINES * (N / E) : 1];
     const Src1<EmArgs> src{a, (a.nlines + LINES - 1) / LINES};
-    phasep_local_body<N, E, LINES, REAL_IN, BOHM, VEXT, float2>(src, lds, twl, sct);
+    phasep_local_body<N, E, LINES, REAL_IN, BOHM, VEXT, float2>(src, lds, twl, sct, stash);
 }
 template <int N, int E, int LINES, bool STORE_PSI, class LT = float2>
 __global__ __launch_bounds__(LINES *(N / E)) void k_densityp(EmArgs a)
