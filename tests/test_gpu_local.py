@@ -196,3 +196,27 @@ def test_eq15_256_full_size_matches_oracle():
     drift = abs(grid.mass() / m0 - 1)
     say(f"eq15 256^3: norm drift over {w['steps']} steps {drift:.3e}")
     assert drift < 1e-6
+
+
+@pytest.mark.parametrize("n,L", [((16, 2048), (16.0, 128.0)), ((2048, 8), (128.0, 8.0)),
+                                 ((8, 16, 1024), (8.0, 16.0, 64.0))])
+@pytest.mark.parametrize("schedule,mode", [(3, 1), (3, 0), (2, 1)])
+def test_local_terms_extreme_row_lengths(n, L, schedule, mode):
+    """Rows of 2048 and of 8 points (one row per block, many rows per block)
+    with every Eq. (15) term and a static potential, persistent variants."""
+    kern, g, local = CASES["eq15"]
+    D = len(n)
+    psi0 = inputs.fluid_gaussian(n, L, 25.0, 3.0, seed=21)
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    V = (0.2 * np.cos(2 * np.pi * xs[-1] / L[-1])).astype(np.float32)
+    import torch
+    Vd = torch.from_numpy(V).cuda()
+    grid = make_grid(n, L, kern, g, local, 1e-3, schedule, mode)
+    grid.set_source_fields(None, None, Vd)
+    grid.set_psi(inputs.to_c64(psi0))
+    grid.step(10)
+    ref = orc.evolve_fields(inputs.as_oracle_input(psi0), L, kern, 0.5, g, 1e-3, 10,
+                            (None, None, V.astype(np.float64)), local=local)
+    err = orc.rel_l2(grid.get_psi(), ref)
+    say(f"eq15 extreme {n} schedule {schedule} mode {mode}: rel_l2 {err:.3e}")
+    assert err < REL_L2
