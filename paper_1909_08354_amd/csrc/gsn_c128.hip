@@ -12,7 +12,9 @@ template <int N, int V> static NKernels make_kernels_c128()
 {
     using C = Cfg<N, V>;
     using D = double2;
-    constexpr int E = C::E, LL = C::LM_LINES, EL = C::EM_LINES;
+    // complex128 LDS slots: a strided tile keeps within 128 KiB
+    constexpr int LL = 16L * C::LM_LINES * N > 131072L ? (int)(131072L / (16L * N)) : C::LM_LINES;
+    constexpr int E = C::E, EL = C::EM_LINES;
     NKernels k;
     k.E = E;
     k.TPL = C::TPL;

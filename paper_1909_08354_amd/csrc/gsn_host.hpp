@@ -60,7 +60,8 @@ struct NKernels {
 // block or persistent blocks that prefetch their next tile ("p16", "p8");
 // "s8" is the small-tile form for small grids.  The EM tile holds
 // 256/TPL rows (at most 64); the LM tile holds LINES columns chosen so that a
-// tile moves >= 64-byte contiguous segments per row.  The batched solver
+// tile moves 128-byte contiguous segments per row where the block's thread
+// budget allows (long lines get 64- or 32-byte segments).  The batched solver
 // offers the first kNumBatchVariants.
 constexpr int kNumVariants = 5;
 constexpr int kNumBatchVariants = 4;
@@ -75,8 +76,13 @@ template <int N, int V> struct Cfg {
     static constexpr bool PIPE = V == 2 || V == 3;
     static constexpr int E = N < E0 ? N : E0;
     static constexpr int TPL = N / E;
+    // 16 lines (128-byte row segments; more for very short lines) while the
+    // block stays within its thread budget: 512 threads at 16 points per
+    // thread (above that the registers spill), 1024 at 8
+    static constexpr int LM_MAXT = E0 >= 16 ? 512 : 1024;
+    static constexpr int LM_WANT = TPL <= 4 ? 64 : TPL <= 8 ? 32 : 16;
     static constexpr int LM_LINES = SMALL ? (TPL >= 16 ? 4 : 64 / TPL)
-                                          : TPL <= 4 ? 64 : TPL <= 8 ? 32 : TPL <= 32 ? 16 : TPL <= 64 ? 8 : 4;
+                                          : LM_WANT * TPL <= LM_MAXT ? LM_WANT : LM_MAXT / TPL;
     static constexpr int EM_LINES = SMALL ? (TPL >= 64 ? 1 : 64 / TPL)
                                           : (256 / TPL) > 64 ? 64 : (256 / TPL) < 1 ? 1 : 256 / TPL;
 };

@@ -989,11 +989,24 @@ __device__ __forceinline__ void reduce_mass(const LmArgs &a, double *sh)
     }
 }
 
+// LDS of a persistent LM block: the tile and the reduction scratch, then the
+// twiddles and the mode's per-axis table while they fit in the 160 KiB of a
+// CU (long lines with wide tiles leave no room: those tables are then read
+// from global memory, where every block reads the same few KiB).
+template <int N, int E, int LINES, int MODE, class LT> struct LmpLds {
+    static constexpr long kLimit = 160L * 1024;
+    static constexpr long BASE = (long)sizeof(LT) * LmTile<N, E, LINES>::LDS + 8L * (LmTile<N, E, LINES>::NT / 64 + 1);
+    static constexpr long TAB = MODE == LM_KIN ? 16L * N : MODE == LM_KERN ? 8L * N : 0;
+    static constexpr bool TW = BASE + 16L * N + TAB <= kLimit;   // twiddles in LDS
+    static constexpr bool TB = BASE + TAB + (TW ? 16L * N : 0) <= kLimit;   // mode table in LDS
+};
+
 // Tables shared by every tile (and, in a group, by every instance: the host
-// only groups instances whose tables are identical) go to LDS once.
-template <int N, int E, int LINES, int MODE, class LT, class Src>
-__device__ __forceinline__ void lmp_body(const Src &src, LT *lds, double2 *twl, double2 *kpl, double *k2l,
-                                         double *sh)
+// only groups instances whose tables are identical) go to LDS once (TW_L,
+// TB_L); otherwise twl / kpl / k2l point at the global tables.
+template <int N, int E, int LINES, int MODE, class LT, class Src, bool TW_L = true, bool TB_L = true>
+__device__ __forceinline__ void lmp_body(const Src &src, LT *lds, const double2 *twl, const double2 *kpl,
+                                         const double *k2l, double *sh)
 {
     constexpr int TPL = N / E, NT = LINES * TPL;
     static_assert(MODE == LM_FWD || MODE == LM_INV || MODE == LM_KIN || MODE == LM_KERN, "mode");
@@ -1001,9 +1014,9 @@ __device__ __forceinline__ void lmp_body(const Src &src, LT *lds, double2 *twl, 
     {
         const LmArgs &a0 = src.args(0);
         for (int i = tid; i < N; i += NT) {
-            twl[i] = gld(a0.tw, i);
-            if constexpr (MODE == LM_KIN) kpl[i] = gld(a0.kinp, i);
-            if constexpr (MODE == LM_KERN) k2l[i] = gmem(a0.k2_p)[i];
+            if constexpr (TW_L) const_cast<double2 *>(twl)[i] = gld(a0.tw, i);
+            if constexpr (MODE == LM_KIN && TB_L) const_cast<double2 *>(kpl)[i] = gld(a0.kinp, i);
+            if constexpr (MODE == LM_KERN && TB_L) const_cast<double *>(k2l)[i] = gmem(a0.k2_p)[i];
         }
         if constexpr (!Src::GROUPED) {
             if (a0.reduce && blockIdx.x == 0) reduce_mass<NT>(a0, sh);
@@ -1728,13 +1741,15 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_densityp(EmArgs a)
 template <int N, int E, int LINES, int MODE, class LT>
 __global__ __launch_bounds__(LINES *(N / E)) void k_lmp(LmArgs a)
 {
+    using B = LmpLds<N, E, LINES, MODE, LT>;
     __shared__ LT lds[LmTile<N, E, LINES>::LDS];
-    __shared__ double2 twl[N];
-    __shared__ double2 kpl[MODE == LM_KIN ? N : 1];
-    __shared__ double k2l[MODE == LM_KERN ? N : 1];
+    __shared__ double2 twl[B::TW ? N : 1];
+    __shared__ double2 kpl[MODE == LM_KIN && B::TB ? N : 1];
+    __shared__ double k2l[MODE == LM_KERN && B::TB ? N : 1];
     __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
     const Src1<LmArgs> src{a, a.s0.ntiles + a.s1.ntiles};
-    lmp_body<N, E, LINES, MODE, LT>(src, lds, twl, kpl, k2l, sh);
+    lmp_body<N, E, LINES, MODE, LT, Src1<LmArgs>, B::TW, B::TB>(src, lds, B::TW ? twl : a.tw,
+                                                                  B::TB ? kpl : a.kinp, B::TB ? k2l : a.k2_p, sh);
 }
 
 template <int N, int E, int LINES, int S>
@@ -1774,13 +1789,16 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lm_g(const LmArgs *__restric
 template <int N, int E, int LINES, int MODE>
 __global__ __launch_bounds__(LINES *(N / E)) void k_lmp_g(const LmArgs *__restrict__ args, int tpi, int count)
 {
+    using B = LmpLds<N, E, LINES, MODE, float2>;
     __shared__ float2 lds[LmTile<N, E, LINES>::LDS];
-    __shared__ double2 twl[N];
-    __shared__ double2 kpl[MODE == LM_KIN ? N : 1];
-    __shared__ double k2l[MODE == LM_KERN ? N : 1];
+    __shared__ double2 twl[B::TW ? N : 1];
+    __shared__ double2 kpl[MODE == LM_KIN && B::TB ? N : 1];
+    __shared__ double k2l[MODE == LM_KERN && B::TB ? N : 1];
     __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
     const SrcG<LmArgs> src{args, tpi, count};
-    lmp_body<N, E, LINES, MODE, float2>(src, lds, twl, kpl, k2l, sh);
+    const LmArgs &a0 = src.args(0);
+    lmp_body<N, E, LINES, MODE, float2, SrcG<LmArgs>, B::TW, B::TB>(src, lds, B::TW ? twl : a0.tw,
+                                                                     B::TB ? kpl : a0.kinp, B::TB ? k2l : a0.k2_p, sh);
 }
 template <int N, int E, int LINES, bool STORE_PSI>
 __global__ __launch_bounds__(LINES *(N / E)) void k_densityp_g(const EmArgs *__restrict__ args, int tpi, int count)
