@@ -378,7 +378,8 @@ def main():
     value = P * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
 
-    # per-pass durations with HIP events on the solver's stream
+    # per-pass kernel durations: HIP events bound to each pass's dispatch on
+    # the solver's stream, the launches back to back as in the timed steps
     prof = grid.profile_passes(args.profile_steps)
     bpp = dict(zip(grid.pass_names(), grid.pass_bytes_per_point()))
     steady = {k: v for k, v in prof.items() if k not in ("x_entry_fft", "x_exit_ifft")}
@@ -413,6 +414,7 @@ def main():
         "model_step_gbps": step_bytes / (ms_per_step * 1e-3) / 1e9,
         "model_step_hbm_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
         "pass_ms": {k: round(v, 5) for k, v in prof.items()},
+        "pass_sum_ms_per_step": sum(steady.values()),
         "schedule": schedule,
         "nonlinear_mode": grid.nonlinear_mode(),
         "norm_drift": abs(m1 / m0 - 1),

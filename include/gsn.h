@@ -198,9 +198,12 @@ gsn_status gsn_energy(gsn_grid grid, double e[4]);
 /* Global phase accumulated since gsn_set_psi (FP64) and steps taken. */
 gsn_status gsn_phase(gsn_grid grid, double *theta, int64_t *steps);
 
-/* Per-pass timing: runs nsteps steady-state steps with HIP events around every
-   pass on the grid's stream and writes the average milliseconds per launch of
-   each pass into ms[] (npass entries, order as gsn_pass_name()).  The state is
+/* Per-pass timing: runs nsteps steady-state steps on the grid's stream, each
+   pass launched with a start and a stop HIP event bound to its dispatch
+   (hipExtLaunchKernel), so that an event pair spans the kernel's own
+   execution and the launches follow each other as in gsn_step, with no
+   marker between them; writes the average milliseconds per launch of each
+   pass into ms[] (npass entries, order as gsn_pass_name()).  The state is
    advanced exactly as gsn_step(nsteps) would.  Synchronising. */
 gsn_status gsn_profile_passes(gsn_grid grid, int64_t nsteps, double *ms, int npass);
 int gsn_pass_count(gsn_grid grid);

@@ -4,6 +4,7 @@
 // tables (twiddles, per-axis |k|^2 and kinetic factors, all generated on the
 // host with double cos/sin), the per-step pass schedule and its launches.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -719,13 +720,17 @@ static void build_schedule(gsn_grid g)
     }
 }
 
-static hipError_t launch(const Launch &L, hipStream_t s)
+// With t0/t1 given, the two events are bound to the dispatch itself
+// (hipExtLaunchKernel): they record the kernel's own start and end, and no
+// marker is queued between this launch and its neighbours.
+static hipError_t launch(const Launch &L, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
 {
     void *args[1];
     EmArgs ea = L.ea;
     LmArgs la = L.la;
     if (L.em) args[0] = &ea;
     else args[0] = &la;
+    if (t0 || t1) return hipExtLaunchKernel(L.fn, L.grid, L.block, args, 0, s, t0, t1, 0);
     return hipLaunchKernel(L.fn, L.grid, L.block, args, 0, s);
 }
 
@@ -1325,23 +1330,27 @@ extern "C" gsn_status gsn_profile_passes(gsn_grid g, int64_t nsteps, double *ms,
         for (const Launch &L : (i + 1 < nsteps ? g->kin_full : g->kin_half)) seq.push_back(&L);
     }
     for (const Launch &L : g->exit_) seq.push_back(&L);
-    std::vector<hipEvent_t> ev(seq.size() + 1);
-    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-    HIP_TRY(hipEventRecord(ev[0], g->stream));
-    for (size_t i = 0; i < seq.size(); ++i) {
-        HIP_TRY(launch(*seq[i], g->stream));
-        HIP_TRY(hipEventRecord(ev[i + 1], g->stream));
-    }
+    // a start and a stop event per launch, destroyed on every return path
+    struct Events {
+        std::vector<hipEvent_t> ev;
+        ~Events()
+        {
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } E;
+    E.ev.assign(2 * seq.size(), nullptr);
+    for (auto &e : E.ev) HIP_TRY(hipEventCreate(&e));
+    for (size_t i = 0; i < seq.size(); ++i) HIP_TRY(launch(*seq[i], g->stream, E.ev[2 * i], E.ev[2 * i + 1]));
     HIP_TRY(hipStreamSynchronize(g->stream));
     std::vector<double> tot(P_COUNT, 0.0);
     std::vector<int> cnt(P_COUNT, 0);
     for (size_t i = 0; i < seq.size(); ++i) {
         float t = 0.f;
-        HIP_TRY(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+        HIP_TRY(hipEventElapsedTime(&t, E.ev[2 * i], E.ev[2 * i + 1]));
         tot[seq[i]->pass] += t;
         cnt[seq[i]->pass] += 1;
     }
-    for (auto &e : ev) (void)hipEventDestroy(e);
     for (int i = 0; i < P_COUNT; ++i) ms[i] = cnt[i] ? tot[i] / cnt[i] : 0.0;
     return gsn_sync(g);
 }
