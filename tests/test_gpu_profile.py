@@ -72,3 +72,46 @@ def test_profile_pass_durations_add_up_to_the_step_time():
     # time (timer noise aside), and back-to-back launches leave little idle
     assert steady < 1.05 * wall
     assert steady > 0.8 * wall
+
+
+def test_profile_passes_advances_like_step_with_eq15_terms_and_fields():
+    import torch
+    n, L = (32, 32, 64), (32.0, 32.0, 64.0)
+    psi0 = inputs.fluid_gaussian(n, L, 25.0, 4.0, noise=1e-3, seed=12)
+    xs = np.meshgrid(*[inputs.axis_coords(N, Ld) for N, Ld in zip(n, L)], indexing="ij")
+    V = torch.from_numpy((0.1 * np.cos(2 * np.pi * xs[2] / L[2])).astype(np.float32)).cuda()
+    grids = []
+    for _ in range(2):
+        grid = gsn.Grid(n, L)
+        grid.set_kernel(0.5, 0.0, 0.0, 0.0)
+        grid.set_coefficients(0.5, 0.0, 1e-3)
+        grid.set_local_terms(-1.02, 1.0, -1.0, 1e-10)
+        grid.set_source_fields(None, None, V)
+        grid.set_schedule(3)
+        grid.set_psi(inputs.to_c64(psi0))
+        grids.append(grid)
+    grids[0].step(5)
+    prof = grids[1].profile_passes(5)
+    say("profile eq15", {k: round(v, 4) for k, v in prof.items() if v > 0})
+    assert np.array_equal(grids[0].get_psi(np.complex64), grids[1].get_psi(np.complex64))
+    for name in ("y_fwd_sqrt", "laplacian", "y_inv_lap", "x_phase", "x_density"):
+        assert prof[name] > 0.0, name
+
+
+def test_profile_passes_advances_like_step_on_fp64_storage():
+    n, L = (16, 32, 64), (16.0, 32.0, 64.0)
+    rng = np.random.default_rng(5)
+    cs, ws, vs = inputs.random_lumps(rng, n, L, 2, (3.0, 5.0))
+    psi0 = inputs.lumps(n, L, cs, ws, vs)
+    grids = []
+    for _ in range(2):
+        grid = gsn.Grid(n, L, storage=np.complex128)
+        grid.set_kernel(1.0, 0.3, 0.4, 0.0)
+        grid.set_coefficients(0.5, -0.2, 1e-3)
+        grid.set_psi(psi0)
+        grids.append(grid)
+    grids[0].step(4)
+    prof = grids[1].profile_passes(4)
+    assert np.array_equal(grids[0].get_psi(np.complex128), grids[1].get_psi(np.complex128))
+    assert grids[0].mass() == grids[1].mass()
+    assert prof["kernel"] > 0.0 and prof["x_phase"] > 0.0
