@@ -1322,15 +1322,10 @@ extern "C" gsn_status gsn_profile_passes(gsn_grid g, int64_t nsteps, double *ms,
     if (s) return s;
     if (!ms || npass < P_COUNT || nsteps < 1) return fail(GSN_EINVAL, "bad profile arguments");
     HIP_TRY(hipSetDevice(g->device));
-    std::vector<const Launch *> seq;
-    for (const Launch &L : g->entry) seq.push_back(&L);
-    for (const Launch &L : g->kin_half) seq.push_back(&L);
-    for (int64_t i = 0; i < nsteps; ++i) {
-        for (const Launch &L : g->nonlin) seq.push_back(&L);
-        for (const Launch &L : (i + 1 < nsteps ? g->kin_full : g->kin_half)) seq.push_back(&L);
-    }
-    for (const Launch &L : g->exit_) seq.push_back(&L);
-    // a start and a stop event per launch, destroyed on every return path
+    // a start and a stop event per launch in flight, kChunk launches between
+    // synchronisations (so any nsteps needs a fixed number of events),
+    // destroyed on every return path
+    constexpr size_t kChunk = 256;
     struct Events {
         std::vector<hipEvent_t> ev;
         ~Events()
@@ -1339,18 +1334,39 @@ extern "C" gsn_status gsn_profile_passes(gsn_grid g, int64_t nsteps, double *ms,
                 if (e) (void)hipEventDestroy(e);
         }
     } E;
-    E.ev.assign(2 * seq.size(), nullptr);
+    E.ev.assign(2 * kChunk, nullptr);
     for (auto &e : E.ev) HIP_TRY(hipEventCreate(&e));
-    for (size_t i = 0; i < seq.size(); ++i) HIP_TRY(launch(*seq[i], g->stream, E.ev[2 * i], E.ev[2 * i + 1]));
-    HIP_TRY(hipStreamSynchronize(g->stream));
     std::vector<double> tot(P_COUNT, 0.0);
-    std::vector<int> cnt(P_COUNT, 0);
-    for (size_t i = 0; i < seq.size(); ++i) {
-        float t = 0.f;
-        HIP_TRY(hipEventElapsedTime(&t, E.ev[2 * i], E.ev[2 * i + 1]));
-        tot[seq[i]->pass] += t;
-        cnt[seq[i]->pass] += 1;
+    std::vector<long long> cnt(P_COUNT, 0);
+    std::vector<int> pend;   // pass of each launch since the last synchronisation
+    pend.reserve(kChunk);
+    auto harvest = [&]() -> hipError_t {
+        hipError_t e = hipStreamSynchronize(g->stream);
+        for (size_t j = 0; e == hipSuccess && j < pend.size(); ++j) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, E.ev[2 * j], E.ev[2 * j + 1]);
+            tot[pend[j]] += t;
+            cnt[pend[j]] += 1;
+        }
+        pend.clear();
+        return e;
+    };
+    auto timed = [&](const Launch &L) -> hipError_t {
+        const size_t j = pend.size();
+        const hipError_t e = launch(L, g->stream, E.ev[2 * j], E.ev[2 * j + 1]);
+        if (e != hipSuccess) return e;
+        pend.push_back(L.pass);
+        return pend.size() == kChunk ? harvest() : hipSuccess;
+    };
+    // the launch sequence of gsn_step(nsteps)
+    for (const Launch &L : g->entry) HIP_TRY(timed(L));
+    for (const Launch &L : g->kin_half) HIP_TRY(timed(L));
+    for (int64_t i = 0; i < nsteps; ++i) {
+        for (const Launch &L : g->nonlin) HIP_TRY(timed(L));
+        for (const Launch &L : (i + 1 < nsteps ? g->kin_full : g->kin_half)) HIP_TRY(timed(L));
     }
+    for (const Launch &L : g->exit_) HIP_TRY(timed(L));
+    HIP_TRY(harvest());
     for (int i = 0; i < P_COUNT; ++i) ms[i] = cnt[i] ? tot[i] / cnt[i] : 0.0;
     return gsn_sync(g);
 }

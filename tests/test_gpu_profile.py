@@ -27,15 +27,17 @@ def make(n, L, psi0, schedule=None):
     return grid
 
 
-@pytest.mark.parametrize("schedule", [0, 2])
-def test_profile_passes_advances_like_step(schedule):
+@pytest.mark.parametrize("schedule,steps", [(0, 6), (2, 6), (2, 70)])
+def test_profile_passes_advances_like_step(schedule, steps):
+    """70 steps: more launches than one batch of timing events (256), so the
+    events are reused after a synchronisation."""
     n, L = (32, 64, 64), (32.0, 64.0, 64.0)
     rng = np.random.default_rng(3)
     cs, ws, vs = inputs.random_lumps(rng, n, L, 2, (5.0, 8.0))
     psi0 = inputs.lumps(n, L, cs, ws, vs)
     a, b = make(n, L, psi0, schedule), make(n, L, psi0, schedule)
-    a.step(6)
-    prof = b.profile_passes(6)
+    a.step(steps)
+    prof = b.profile_passes(steps)
     say("profile", schedule, {k: round(v, 4) for k, v in prof.items() if v > 0})
     assert np.array_equal(a.get_psi(np.complex64), b.get_psi(np.complex64))
     assert a.mass() == b.mass()
