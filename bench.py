@@ -33,10 +33,14 @@ WORKLOAD = "gsn3d_256_newton_yukawa"
 PASS_SOURCES = ("gsn_api.hip", "gsn_fft.hpp", "gsn_host.hpp", "gsn_kernels.hpp")
 
 
-def csrc_hash():
+# the Eq. (15) and coupling-field legs also run the kernels of gsn_local.hip
+LEG_SOURCES = PASS_SOURCES + ("gsn_local.hip",)
+
+
+def csrc_hash(files=PASS_SOURCES):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1909_08354_amd", "csrc")
-    for f in PASS_SOURCES:
+    for f in files:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -56,6 +60,21 @@ def measured_traffic(kernel_pass, variant):
     if rec.get("csrc_hash") != csrc_hash():
         return None
     return rec.get("passes", {}).get(kernel_pass, {}).get(variant)
+
+
+def measured_leg_traffic(workload, kernel_pass, variant):
+    """The same for a pass of the Eq. (15) / coupling-field legs."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+    except ValueError:
+        return None
+    legs = rec.get("legs", {})
+    if legs.get("legs_hash") != csrc_hash(LEG_SOURCES):
+        return None
+    return legs.get(workload, {}).get(kernel_pass, {}).get(variant)
 
 
 def cpu_baseline(w, psi0_c128, budget_s=30.0):
@@ -262,7 +281,8 @@ def eq15_bench(steps, autotune_iters, profile_steps, workload="gsn3d_256_eq15"):
             "model_bytes_per_point": step_bytes / P,
             "model_step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
             "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                         "traffic": measured_leg_traffic(workload, dom, schedule.get(dom)),
                          "algorithmic_bytes_per_launch": bpp[dom] * P, "avg_launch_ms": steady[dom]},
             "pass_ms": {k: round(v, 5) for k, v in steady.items()}, "schedule": schedule,
             "norm_drift": abs(m1 / m0 - 1), "energy_drift": edrift}
