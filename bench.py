@@ -33,8 +33,10 @@ WORKLOAD = "gsn3d_256_newton_yukawa"
 PASS_SOURCES = ("gsn_api.hip", "gsn_fft.hpp", "gsn_host.hpp", "gsn_kernels.hpp")
 
 
-# the Eq. (15) and coupling-field legs also run the kernels of gsn_local.hip
-LEG_SOURCES = PASS_SOURCES + ("gsn_local.hip",)
+# the Eq. (15) and coupling-field legs also run the kernels of gsn_local.hip,
+# the FP64-storage leg those of gsn_c128.hip
+LEG_SOURCES = PASS_SOURCES + ("gsn_local.hip", "gsn_c128.hip")
+FP64_LEG = "gsn3d_256_newton_yukawa:c128"
 
 
 def csrc_hash(files=PASS_SOURCES):
@@ -329,7 +331,8 @@ def fp64_bench(steps, autotune_iters, profile_steps):
             "model_bytes_per_point": step_bytes / P,
             "model_step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
             "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                         "traffic": measured_leg_traffic(FP64_LEG, dom, schedule.get(dom)),
                          "algorithmic_bytes_per_launch": bpp[dom] * P, "avg_launch_ms": steady[dom]},
             "pass_ms": {k: round(v, 5) for k, v in steady.items()}, "schedule": schedule,
             "norm_drift": abs(m1 / m0 - 1), "energy_drift": abs(e1["total"] - e0["total"]) / scale}
