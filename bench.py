@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the split-step Schroedinger-Newton hot path on one MI355X.
 
-Workload: one 3-D instance, 256^3 periodic grid (dx = 1), complex64 storage
-with FP64 arithmetic, centred Gaussian cloud of waist 6, Newtonian kernel plus
-a Yukawa correction 0.3/(k^2 + 0.1^2), g = 0, dz = 5e-4.  A "step" is one
-symmetric split step over the whole grid (8 HBM passes).  The timed region is
-one gsn_step(K) call with psi already resident in HBM.
+Headline workload: one 3-D instance on a 512^3 periodic grid (dx = 1),
+complex64 storage with FP64 arithmetic, 8 Gaussian lumps (waist U[4,10],
+seeded centres and phase-gradient velocities), Newtonian kernel plus a Yukawa
+correction 0.3/(k^2 + 0.1^2), g = 0, dz = 2.5e-4.  A "step" is one symmetric
+split step over the whole grid (8 HBM passes).  The timed region is one
+gsn_step(K) call with psi already resident in HBM.
 
 Prints ONE JSON line.  Besides throughput it reports the dominant pass's
 roofline (algorithmic bytes / HIP-event duration on the solver's stream), the
-norm and energy drift of the timed run, and the FP64 CPU oracle timed on a
-bounded sample on this host (a baseline, not a target).
+step's HBM fraction on the method's pass model (104 B per point), the norm and
+energy drift of the timed run, and secondary legs: the 256^3 single grid, the
+FP64-storage grid, the Eq. (15) fluids, the batched sweep and the learned
+corrector; last, the FP64 CPU oracle timed on a bounded sample on this host
+(a baseline, not a target).
 """
 import argparse
 import hashlib
@@ -25,7 +29,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-WORKLOAD = "gsn3d_256_newton_yukawa"
+# the headline workload (the largest single-GPU configuration: 8 moving lumps
+# on 512^3) and the secondary single-grid leg (a centred cloud on 256^3)
+WORKLOAD = "gsn3d_512_lumps"
+WORKLOAD_256 = "gsn3d_256_newton_yukawa"
+# bytes per grid point of one 3-D step in the pass model of the method
+# (8 HBM passes: reads 56 + writes 48)
+MODEL_BPP = 104.0
 
 
 # the sources of the single-grid passes (the batched and corrector files do
@@ -48,10 +58,10 @@ def csrc_hash(files=PASS_SOURCES):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_pass, variant):
-    """HBM bytes per launch of a pass in a schedule variant, from committed
-    rocprofv3 counter runs, only when they were taken on the current kernel
-    sources."""
+def measured_traffic(kernel_pass, variant, workload):
+    """HBM bytes per launch of a pass in a schedule variant on a workload, from
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (profiles/traffic.json),
+    only when they were taken on the current kernel sources; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -61,7 +71,13 @@ def measured_traffic(kernel_pass, variant):
         return None
     if rec.get("csrc_hash") != csrc_hash():
         return None
-    return rec.get("passes", {}).get(kernel_pass, {}).get(variant)
+    b = rec.get("workloads", {}).get(workload, {}).get("passes", {}).get(kernel_pass, {}).get(variant)
+    if b is None:
+        return None
+    return {"bytes": b, "source": "rocprofv3 FETCH_SIZE x %.3g + WRITE_SIZE x %.3g per launch, "
+            "committed in profiles/traffic.json for these kernel sources (hash %s), not re-measured "
+            "in this run" % (rec["calibration"]["fetch_factor"], rec["calibration"]["write_factor"],
+                             rec["csrc_hash"])}
 
 
 def measured_leg_traffic(workload, kernel_pass, variant):
@@ -79,29 +95,129 @@ def measured_leg_traffic(workload, kernel_pass, variant):
     return legs.get(workload, {}).get(kernel_pass, {}).get(variant)
 
 
-def cpu_baseline(w, psi0_c128, budget_s=30.0):
-    """Oracle step rate on this host: time evolve(1) and evolve(3) on the same
-    input; the difference is two merged steps without table setup."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and logical CPU count."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": name, "logical_cpus": os.cpu_count()}
+
+
+def oracle_step_rate(w, psi0_c128, nthreads):
+    """Oracle step rate with nthreads threads: evolve(1) and evolve(2) on the
+    same input; the difference is one merged step without table setup."""
     from oracle import oracle as orc
-    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
     args = (w["L"], w["kern"], w["a"], w["g"], w["dz"])
     t0 = time.perf_counter()
     orc.evolve(psi0_c128, *args, 1, nthreads=nthreads)
     t1 = time.perf_counter()
-    if (t1 - t0) * 3 > budget_s:
-        per_step = t1 - t0
-        sample = "1 merged step incl. table setup (budget)"
-    else:
-        orc.evolve(psi0_c128, *args, 3, nthreads=nthreads)
-        t2 = time.perf_counter()
-        per_step = max((t2 - t1) - (t1 - t0), 1e-9) / 2
-        sample = "2 merged 256^3 steps (evolve(3) - evolve(1))"
-    P = int(np.prod(w["n"]))
-    return {"value": P / per_step, "unit": "grid-pt updates/s", "cores": nthreads,
-            "kind": "oracle", "sample": sample}
+    orc.evolve(psi0_c128, *args, 2, nthreads=nthreads)
+    t2 = time.perf_counter()
+    per_step = max((t2 - t1) - (t1 - t0), 1e-9)
+    return int(np.prod(w["n"])) / per_step
 
 
-def batch_bench(steps):
+def cpu_baseline(legs):
+    """The FP64 oracle's step rate on this host (a baseline, not a target).
+    legs: (name, workload dict, complex128 input, thread counts); the first
+    leg at its first thread count is the headline figure.  The thread share
+    is OMP_NUM_THREADS when set (the GPU host's share), else every logical CPU."""
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    out = dict(cpu_model())
+    out["thread_share"] = share
+    runs = []
+    for name, w, psi, threads in legs:
+        for nt in threads:
+            nt = share if nt == 0 else nt
+            t0 = time.perf_counter()
+            rate = oracle_step_rate(w, psi, nt)
+            runs.append({"workload": name, "threads": nt, "value": rate,
+                         "unit": "grid-pt updates/s", "seconds": time.perf_counter() - t0})
+    head = runs[0]
+    out.update({"value": head["value"], "unit": "grid-pt updates/s", "cores": head["threads"],
+                "kind": "oracle",
+                "sample": f"one merged step of {head['workload']} (evolve(2) - evolve(1)) "
+                          f"with {head['threads']} threads; the other runs listed in 'runs'",
+                "runs": runs})
+    return out
+
+
+def single_grid_leg(name, psi0, steps, warmup, autotune_iters, profile_steps, traffic=True):
+    """One grid of a workload: autotune, warm up, time gsn_step(steps) with psi
+    resident in HBM, then the per-pass kernel durations (HIP events bound to
+    each dispatch on the solver's stream) for the dominant pass's roofline,
+    and the norm and energy drift of the timed run."""
+    import torch
+    from paper_1909_08354_amd import gsn, inputs
+    w = inputs.WORKLOADS[name]
+    n, L = w["n"], w["L"]
+    P = int(np.prod(n))
+    grid = gsn.Grid(n, L)
+    grid.set_kernel(*w["kern"])
+    grid.set_coefficients(w["a"], w["g"], w["dz"])
+    dev0 = torch.from_numpy(psi0).cuda()
+    grid.set_psi(dev0)
+    schedule = grid.autotune(autotune_iters) if autotune_iters > 0 else grid.schedule()
+    grid.set_psi(dev0)
+    del dev0
+    m0 = grid.mass()
+    e0 = grid.energy()
+    if warmup:
+        grid.step(warmup)
+    grid.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    grid.sync()
+    elapsed = t1 - t0
+    m1 = grid.mass()
+    e1 = grid.energy()
+    ms_per_step = 1e3 * elapsed / steps
+    prof = grid.profile_passes(profile_steps)
+    bpp = dict(zip(grid.pass_names(), grid.pass_bytes_per_point()))
+    steady = {k: v for k, v in prof.items() if k not in ("x_entry_fft", "x_exit_ifft")}
+    dom = max(steady, key=steady.get)
+    achieved = bpp[dom] * P / (steady[dom] * 1e-3) / 1e9
+    executed = sum(bpp[k] for k in steady)
+    scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
+    mode = grid.nonlinear_mode()
+    grid.close()
+    tr = measured_traffic(dom, schedule.get(dom), name) if traffic else None
+    return {
+        "workload": name, "grid": list(n), "steps": steps, "warmup": warmup,
+        "value": P * steps / elapsed, "unit": "grid-pt updates/s", "ms_per_step": ms_per_step,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": None if tr is None else tr["bytes"],
+                     "traffic_source": None if tr is None else tr["source"],
+                     "algorithmic_bytes_per_launch": bpp[dom] * P,
+                     "avg_launch_ms": steady[dom]},
+        # the pass model of the method: 104 B per point per 3-D step
+        "model_bytes_per_point": MODEL_BPP,
+        "model_step_gbps": MODEL_BPP * P / (ms_per_step * 1e-3) / 1e9,
+        "model_step_hbm_frac": MODEL_BPP * P / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        # what the chosen schedule moves (stored real-space psi: +8 B per point)
+        "executed_bytes_per_point": executed,
+        "executed_step_hbm_frac": executed * P / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "pass_ms": {k: round(v, 5) for k, v in prof.items()},
+        "pass_sum_ms_per_step": sum(steady.values()),
+        "schedule": schedule, "nonlinear_mode": mode,
+        "kernel": {"c_newton": w["kern"][0], "c_yukawa": w["kern"][1], "m_yukawa": w["kern"][2]},
+        "dz": w["dz"], "g": w["g"], "ic": w["ic"],
+        "norm_drift": abs(m1 / m0 - 1),
+        "energy_drift": abs(e1["total"] - e0["total"]) / scale,
+    }
+
+
+def batch_bench(steps, autotune_iters=0):
     """The 64-instance sweep (256^2/512^2/1024^2, per-instance Yukawa couplings):
     one gsn_batch_step graph launch vs the same instances run one after another
     through gsn_step, with the batch's schedule (bit-identical results) and with
@@ -295,7 +411,7 @@ def fp64_bench(steps, autotune_iters, profile_steps):
     step rate, per-pass times, the roofline of its dominant pass, invariants."""
     import torch
     from paper_1909_08354_amd import gsn, inputs
-    w = inputs.WORKLOADS[WORKLOAD]
+    w = inputs.WORKLOADS[WORKLOAD_256]
     n, L = w["n"], w["L"]
     P = int(np.prod(n))
     grid = gsn.Grid(n, L, storage=np.complex128)
@@ -326,7 +442,7 @@ def fp64_bench(steps, autotune_iters, profile_steps):
     ms = 1e3 * elapsed / steps
     scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
     grid.close()
-    return {"workload": WORKLOAD, "storage": "c128", "grid": list(n), "steps": steps,
+    return {"workload": WORKLOAD_256, "storage": "c128", "grid": list(n), "steps": steps,
             "value": P * steps / elapsed, "unit": "grid-pt updates/s", "ms_per_step": ms,
             "model_bytes_per_point": step_bytes / P,
             "model_step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
@@ -341,13 +457,18 @@ def fp64_bench(steps, autotune_iters, profile_steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=500,
+                    help="timed steps of the 512^3 headline workload")
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-steps", type=int, default=20)
-    ap.add_argument("--autotune-iters", type=int, default=10)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--autotune-iters", type=int, default=5)
+    ap.add_argument("--steps-256", type=int, default=1000,
+                    help="timed steps of the 256^3 single-grid leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=500,
                     help="steps of the 64-instance batched sweep (0 skips it)")
+    ap.add_argument("--batch-autotune-iters", type=int, default=3,
+                    help="iterations per variant of the batch autotuner (0: default schedule)")
     ap.add_argument("--corrector-train", type=int, default=2000,
                     help="training trajectories of the corrector leg (0 skips it)")
     ap.add_argument("--corrector-epochs", type=int, default=4)
@@ -359,6 +480,8 @@ def main():
     ap.add_argument("--corrector-eval", type=int, default=100)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--only-256", action="store_true",
+                    help="run the 256^3 leg in place of the 512^3 headline (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -366,7 +489,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1909_08354_amd import gsn, inputs
+    from paper_1909_08354_amd import inputs
 
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -374,85 +497,47 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = inputs.WORKLOADS[WORKLOAD]
-    n, L = w["n"], w["L"]
-    P = int(np.prod(n))
-    psi0 = inputs.gaussian_3d_256()
-    grid = gsn.Grid(n, L)
-    grid.set_kernel(*w["kern"])
-    grid.set_coefficients(w["a"], w["g"], w["dz"])
-    grid.set_psi(torch.from_numpy(inputs.to_c64(psi0)).cuda())
-    schedule = grid.autotune(args.autotune_iters) if args.autotune_iters > 0 else grid.schedule()
-    m0 = grid.mass()
-    e0 = grid.energy()
-
-    if args.warmup:
-        grid.step(args.warmup)
-    grid.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    grid.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    grid.sync()
-    elapsed = t1 - t0
-    m1 = grid.mass()
-    e1 = grid.energy()
-    value = P * args.steps / elapsed
-    ms_per_step = 1e3 * elapsed / args.steps
-
-    # per-pass kernel durations: HIP events bound to each pass's dispatch on
-    # the solver's stream, the launches back to back as in the timed steps
-    prof = grid.profile_passes(args.profile_steps)
-    bpp = dict(zip(grid.pass_names(), grid.pass_bytes_per_point()))
-    steady = {k: v for k, v in prof.items() if k not in ("x_entry_fft", "x_exit_ifft")}
-    dom = max(steady, key=steady.get)
-    achieved = bpp[dom] * P / (steady[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(dom, schedule.get(dom))
-    step_bytes = sum(bpp[k] for k in steady) * P
-    scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
-
+    psi256 = inputs.to_c64(inputs.gaussian_3d_256())
+    if args.only_256:
+        head_name, head_psi, head_steps = WORKLOAD_256, psi256, args.steps
+    else:
+        w = inputs.WORKLOADS[WORKLOAD]
+        head_name, head_steps = WORKLOAD, args.steps
+        head_psi = inputs.lumps_3d(w["n"], w["seed"], 8, dtype=np.complex64)
+    head = single_grid_leg(head_name, head_psi, head_steps, args.warmup, args.autotune_iters,
+                           args.profile_steps)
+    w = inputs.WORKLOADS[head_name]
     line = {
         "metric": "split-step grid-pt updates/s + %HBM peak; batched/corrected speedup at fixed err",
-        "value": value,
+        "value": head["value"],
         "unit": "grid-pt updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": head_steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "storage": "c64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "grid": list(n), "dz": w["dz"],
-                   "kernel": {"c_newton": w["kern"][0], "c_yukawa": w["kern"][1],
-                              "m_yukawa": w["kern"][2]},
-                   "g": w["g"], "ic": w["ic"], "passes_per_step": len(steady)},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bpp[dom] * P,
-                     "avg_launch_ms": steady[dom]},
-        "model_step_gbps": step_bytes / (ms_per_step * 1e-3) / 1e9,
-        "model_step_hbm_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-        "pass_ms": {k: round(v, 5) for k, v in prof.items()},
-        "pass_sum_ms_per_step": sum(steady.values()),
-        "schedule": schedule,
-        "nonlinear_mode": grid.nonlinear_mode(),
-        "norm_drift": abs(m1 / m0 - 1),
-        "energy_drift": abs(e1["total"] - e0["total"]) / scale,
-        "batched_speedup": None,
-        "batched": None,
-        "corrected_speedup": None,
-        "corrected": None,
-        "eq15": None,
-        "nmc": None,
-        "fp64": None,
+        "config": {"workload": head_name, "grid": list(w["n"]), "dz": w["dz"],
+                   "kernel": head["kernel"], "g": w["g"], "ic": w["ic"],
+                   "passes_per_step": len([k for k in head["pass_ms"]
+                                           if k not in ("x_entry_fft", "x_exit_ifft")])},
+        "roofline": head["roofline"],
     }
-    if args.batch_steps > 0 or args.corrector_train > 0 or args.eq15_steps > 0 or args.fp64_steps > 0:
-        grid.close()
-        del grid
+    for k in ("model_bytes_per_point", "model_step_gbps", "model_step_hbm_frac",
+              "executed_bytes_per_point", "executed_step_hbm_frac", "pass_ms",
+              "pass_sum_ms_per_step", "schedule", "nonlinear_mode", "norm_drift", "energy_drift"):
+        line[k] = head[k]
+    line.update({"single_256": None, "batched_speedup": None, "batched": None,
+                 "corrected_speedup": None, "corrected": None, "eq15": None, "nmc": None,
+                 "fp64": None})
+    del head_psi
+    if args.steps_256 > 0 and not args.only_256:
+        line["single_256"] = single_grid_leg(WORKLOAD_256, psi256, args.steps_256, args.warmup,
+                                             args.autotune_iters, args.profile_steps)
     if args.fp64_steps > 0:
         line["fp64"] = fp64_bench(args.fp64_steps, min(args.autotune_iters, 5), args.profile_steps)
     if args.eq15_steps > 0:
@@ -460,14 +545,21 @@ def main():
         line["nmc"] = eq15_bench(args.eq15_steps, min(args.autotune_iters, 5), args.profile_steps,
                                  "gsn3d_256_nmc")
     if args.batch_steps > 0:
-        line["batched"] = batch_bench(args.batch_steps)
+        line["batched"] = batch_bench(args.batch_steps, args.batch_autotune_iters)
         line["batched_speedup"] = line["batched"]["speedup"]
     if args.corrector_train > 0:
         line["corrected"] = corrector_bench(args.corrector_train, args.corrector_epochs,
                                             args.corrector_eval, 10, 1e-4)
         line["corrected_speedup"] = line["corrected"]["speedup"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, inputs.as_oracle_input(psi0))
+        legs = []
+        if not args.only_256:
+            w4 = inputs.WORKLOADS[WORKLOAD]
+            psi4 = inputs.lumps_3d(w4["n"], w4["seed"], 8, dtype=np.complex64).astype(np.complex128)
+            legs.append((WORKLOAD, w4, psi4, (0,)))
+        w2 = inputs.WORKLOADS[WORKLOAD_256]
+        legs.append((WORKLOAD_256, w2, psi256.astype(np.complex128), (0, 1)))
+        line["cpu_baseline"] = cpu_baseline(legs)
     print(json.dumps(line), flush=True)
 
 

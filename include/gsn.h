@@ -287,6 +287,22 @@ gsn_status gsn_batch_set_queue_limits(gsn_batch batch, unsigned spin_limit, long
    always one tile per block), and the nonlinear mode (as
    gsn_set_nonlinear_mode). */
 gsn_status gsn_batch_set_schedule(gsn_batch batch, const int *variants, int nfam, int nonlinear_mode);
+/* Autotuner of the batched launch (the best FFT tile and radix schedule
+   depends on the mesh size, Sec. III): for every shape group, times each
+   variant of each pass family with the other families fixed -- the column
+   passes first, then the density and phase passes under both nonlinear modes,
+   then the x entry/exit pair -- over iters (1..10000) whole split steps of
+   that group alone, and keeps the fastest per group.  The timed passes run in
+   place on the instances' own buffers, so every instance must be set
+   (GSN_ESTATE otherwise); their psi and global phase are saved to host memory
+   first and restored afterwards, so the states are unchanged.  With the
+   environment variable GSN_AUTOTUNE_CACHE naming a file, choices are read
+   from it (keyed by GPU architecture, shape and family) and new ones
+   appended.  Synchronising. */
+gsn_status gsn_batch_autotune(gsn_batch batch, int iters);
+/* The schedule of instance i's shape group: variants[5] per family as in
+   gsn_batch_set_schedule (nfam >= 5) and its nonlinear mode. */
+gsn_status gsn_batch_get_schedule(gsn_batch batch, int i, int *variants, int nfam, int *nonlinear_mode);
 
 /* ---------------------------------------------------------------- learned corrector
    A 4-layer 3x3 convolutional network with circular padding (3 -> 32 -> 32 ->

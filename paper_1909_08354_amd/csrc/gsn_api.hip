@@ -1414,6 +1414,16 @@ static bool timing_launch(gsn_grid g, int p, Launch *out)
                     if (out->la.s0.ptr == g->psi) out->la.s0.ptr = g->scratch;
                     out->la.reduce = 0;
                 }
+                // the plain transforms are unnormalised in the step (their
+                // scale sits in another pass); repeated in place they would
+                // grow the data by up to N per launch and reach Inf.  Timed
+                // with the unitary scale 1/sqrt(N) they keep its norm, and the
+                // scale multiply costs the same
+                if (p == P_ENTRY || p == P_EXIT) out->ea.scale = 1.0 / std::sqrt((double)g->Nx);
+                const bool ftrans = p == P_Y_FWD_PSI || p == P_Y_INV_PSI || p == P_Y_FWD_RHO ||
+                                    p == P_Y_INV_PHI || p == P_Y_FWD_SQRT || p == P_Y_INV_LAP ||
+                                    p == P_Y_FWD_SRC || p == P_Y_INV_SRC;
+                if (ftrans) out->la.scale = 1.0 / std::sqrt((double)g->Ny);   // the y axis (3-D only)
                 return true;
             }
     return false;
@@ -1530,6 +1540,9 @@ extern "C" gsn_status gsn_autotune(gsn_grid g, int iters)
             Launch L;
             if (!timing_launch(g, p, &L)) break;
             present = true;
+            // every variant starts from the same data
+            if (g->have_psi)
+                HIP_TRY(hipMemcpyAsync(g->scratch, g->psi, g->esz * g->P, hipMemcpyDeviceToDevice, g->stream));
             double ms = 0.0;
             gsn_status s = time_launch(g, L, iters, &ms);
             if (s) return s;

@@ -14,7 +14,9 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <string>
 #include <vector>
@@ -251,6 +253,11 @@ struct GLaunch {
 struct Group {
     int ny, nx;
     std::vector<int> members;
+    // schedule of this shape group: variant per pass family, nonlinear mode
+    // (1: the density pass stores real-space psi); set for every group by
+    // gsn_batch_set_schedule, per group by gsn_batch_autotune
+    int var[F_NFAM];
+    int store_psi;
     GLaunch launch[B_NKIND];
     void *args_dev[B_NKIND];   // device arrays (inside the workspace)
 };
@@ -427,7 +434,7 @@ Seg seg_of(float2 *ptr, long long es, long long ls, long long os, int nlines, in
     return s;
 }
 
-LmArgs lm_args(gsn_batch b, const Instance &I, int kind, int lpt)
+LmArgs lm_args(gsn_batch b, const Instance &I, int kind, int lpt, int var_density)
 {
     LmArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -456,7 +463,7 @@ LmArgs lm_args(gsn_batch b, const Instance &I, int kind, int lpt)
         a.c0 = I.kern.c_contact;
         a.reduce = 1;
         a.mass_parts = I.mass_parts;
-        const NKernels *kx = kernels_for(I.nx, b->var[F_DENSITY]);
+        const NKernels *kx = kernels_for(I.nx, var_density);
         a.nmass = (I.ny / 2 + kx->em_lines - 1) / kx->em_lines;
         a.k0_dz_over_P = kernel_k0(I.kern) * I.dz / (double)I.P;
     }
@@ -476,17 +483,17 @@ bool same_tables(gsn_batch b, const Group &G)
     return true;
 }
 
-// Rebuild every group's launch descriptors and upload the argument arrays.
-gsn_status build_batch(gsn_batch b)
+// Rebuild one group's launch descriptors and upload its argument arrays.
+gsn_status build_group(gsn_batch b, Group &G)
 {
-    for (Group &G : b->groups) {
+    {
         const int cnt = (int)G.members.size();
         const bool uniform = same_tables(b, G);
         for (int kind = 0; kind < B_NKIND; ++kind) {
             const int fam = kFamOf[kind];
             const bool is_lm = (kind == B_KIN_HALF || kind == B_KIN_FULL || kind == B_KERNEL);
             const int N = is_lm ? G.ny : G.nx;
-            int var = b->var[fam];
+            int var = G.var[fam];
             if (var >= 2 && !uniform) var -= 2;   // same radix plan, one tile per block
             const GKernels *k = gkernels_for(N, var);
             GLaunch &L = G.launch[kind];
@@ -494,7 +501,8 @@ gsn_status build_batch(gsn_batch b)
             L.count = cnt;
             if (is_lm) {
                 std::vector<LmArgs> v(cnt);
-                for (int m = 0; m < cnt; ++m) v[m] = lm_args(b, b->inst[G.members[m]], kind, k->lm_lines);
+                for (int m = 0; m < cnt; ++m)
+                    v[m] = lm_args(b, b->inst[G.members[m]], kind, k->lm_lines, G.var[F_DENSITY]);
                 gsn_status s = upload_sync(b->stream, G.args_dev[kind], v.data(), sizeof(LmArgs) * cnt);
                 if (s) return s;
                 L.tpi = v[0].s0.ntiles + v[0].s1.ntiles;
@@ -506,7 +514,7 @@ gsn_status build_batch(gsn_batch b)
                 gsn_status s = upload_sync(b->stream, G.args_dev[kind], v.data(), sizeof(EmArgs) * cnt);
                 if (s) return s;
                 L.tpi = (v[0].nlines + k->em_lines - 1) / k->em_lines;
-                const bool st = b->store_psi != 0;
+                const bool st = G.store_psi != 0;
                 L.fn = kind == B_ENTRY ? k->em_fwd
                      : kind == B_EXIT ? k->em_inv
                      : kind == B_DENSITY ? (st ? k->density_store : k->density)
@@ -521,6 +529,17 @@ gsn_status build_batch(gsn_batch b)
             L.grid = dim3(grid);
             L.args = G.args_dev[kind];
         }
+    }
+    b->dirty = true;
+    return GSN_OK;
+}
+
+// Rebuild every group's launch descriptors and upload the argument arrays.
+gsn_status build_batch(gsn_batch b)
+{
+    for (Group &G : b->groups) {
+        gsn_status s = build_group(b, G);
+        if (s) return s;
     }
     b->dirty = true;
     b->q_built = false;
@@ -633,7 +652,7 @@ gsn_status build_persistent(gsn_batch b)
             const int kind = kQtoB[q];
             const bool is_lm = (kind == B_KIN_HALF || kind == B_KIN_FULL || kind == B_KERNEL);
             if (is_lm) {
-                P.lm[q] = lm_args(b, I, kind, ll_y);
+                P.lm[q] = lm_args(b, I, kind, ll_y, b->var[F_DENSITY]);   // nmass set below
                 if (kind == B_KERNEL) P.lm[q].nmass = dens_tiles;
                 tiles[q][i] = P.lm[q].s0.ntiles + P.lm[q].s1.ntiles;
             } else {
@@ -792,6 +811,8 @@ extern "C" gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, cons
             Group G;
             G.ny = I.ny;
             G.nx = I.nx;
+            for (int f = 0; f < F_NFAM; ++f) G.var[f] = b->var[f];
+            G.store_psi = b->store_psi;
             b->groups.push_back(G);
         }
         b->groups[gidx[key]].members.push_back(i);
@@ -1012,7 +1033,184 @@ extern "C" gsn_status gsn_batch_set_schedule(gsn_batch b, const int *variants, i
     HIP_TRY(hipStreamSynchronize(b->stream));
     for (int i = 0; i < F_NFAM; ++i) b->var[i] = variants[i];
     b->store_psi = nonlinear_mode;
+    for (Group &G : b->groups) {
+        for (int i = 0; i < F_NFAM; ++i) G.var[i] = variants[i];
+        G.store_psi = nonlinear_mode;
+    }
     return build_batch(b);
+}
+
+// ---------------------------------------------------------------- batch autotuner
+namespace {
+
+// Average time of one step of a group's chain (density, kernel, phase,
+// kinetic), or of one entry + exit transform pair (xfft), over iters
+// repetitions after one untimed one, on the batch's stream.
+gsn_status time_group(gsn_batch b, Group &G, int iters, bool xfft, double *ms)
+{
+    gsn_status s = build_group(b, G);
+    if (s) return s;
+    auto chain = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        if (xfft) {
+            if ((e = glaunch(G.launch[B_ENTRY], b->stream)) != hipSuccess) return e;
+            return glaunch(G.launch[B_EXIT], b->stream);
+        }
+        const int kinds[4] = {B_DENSITY, B_KERNEL, B_PHASE, B_KIN_FULL};
+        for (int k : kinds)
+            if ((e = glaunch(G.launch[k], b->stream)) != hipSuccess) return e;
+        return e;
+    };
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t he = chain();
+    if (he == hipSuccess) he = hipEventRecord(e0, b->stream);
+    for (int i = 0; i < iters && he == hipSuccess; ++i) he = chain();
+    if (he == hipSuccess) he = hipEventRecord(e1, b->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (he != hipSuccess) return fail(GSN_EHIP, std::string("batch autotune timing: ") + hipGetErrorString(he));
+    *ms = (double)t / iters;
+    return GSN_OK;
+}
+
+std::string batch_cache_key(gsn_batch b, const Group &G, const char *what)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    return arch + " batch 2d " + std::to_string(G.ny) + "x" + std::to_string(G.nx) + " " + what;
+}
+
+const char *kFamNames[F_NFAM] = {"kinetic", "x_density", "kernel", "x_phase", "x_fft"};
+
+// Choose the fastest variant of family fam for group G (others fixed).
+gsn_status tune_family(gsn_batch b, Group &G, int fam, int iters, double *best_ms)
+{
+    int best = G.var[fam];
+    double bms = 1e300;
+    for (int v = 0; v < kNumBatchVariants; ++v) {
+        G.var[fam] = v;
+        double ms = 0.0;
+        gsn_status s = time_group(b, G, iters, fam == F_XFFT, &ms);
+        if (s) return s;
+        if (ms < bms) { bms = ms; best = v; }
+    }
+    G.var[fam] = best;
+    *best_ms = bms;
+    return GSN_OK;
+}
+
+}  // namespace
+
+extern "C" gsn_status gsn_batch_autotune(gsn_batch b, int iters)
+{
+    if (!b) return fail(GSN_EINVAL, "batch is NULL");
+    if (iters < 1 || iters > 10000) return fail(GSN_EINVAL, "iters must be in [1, 10000]");
+    for (const Instance &I : b->inst)
+        if (!I.set) return fail(GSN_ESTATE, "every instance must be set before autotuning");
+    HIP_TRY(hipSetDevice(b->device));
+    HIP_TRY(hipStreamSynchronize(b->user));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    // the timed passes run in place on the instances' buffers (realistic
+    // data, bounded: whole split steps, and forward / inverse transform
+    // pairs); the states are saved to host memory and put back at the end
+    std::vector<std::vector<float2>> keep(b->count);
+    std::vector<DevState> keep_st(b->count);
+    for (int i = 0; i < b->count; ++i) {
+        const Instance &I = b->inst[i];
+        keep[i].resize((size_t)I.P);
+        HIP_TRY(hipMemcpyAsync(keep[i].data(), I.psi, 8ull * I.P, hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipMemcpyAsync(&keep_st[i], I.st, sizeof(DevState), hipMemcpyDeviceToHost, b->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const char *cpath = std::getenv("GSN_AUTOTUNE_CACHE");
+    std::map<std::string, int> cache;
+    if (cpath && *cpath) {
+        std::ifstream f(cpath);
+        std::string line;
+        while (std::getline(f, line)) {
+            const size_t sp = line.rfind(' ');
+            if (sp == std::string::npos) continue;
+            cache[line.substr(0, sp)] = std::atoi(line.c_str() + sp + 1);
+        }
+    }
+    std::vector<std::string> fresh;
+    gsn_status s = GSN_OK;
+    for (Group &G : b->groups) {
+        bool cached = true;
+        int cv[F_NFAM], cm = 0;
+        for (int f = 0; f < F_NFAM && cached; ++f) {
+            auto it = cache.find(batch_cache_key(b, G, kFamNames[f]));
+            cached = it != cache.end() && it->second >= 0 && it->second < kNumBatchVariants;
+            if (cached) cv[f] = it->second;
+        }
+        auto mit = cache.find(batch_cache_key(b, G, "nonlinear_mode"));
+        cached = cached && mit != cache.end() && (mit->second == 0 || mit->second == 1);
+        if (cached) {
+            cm = mit->second;
+            for (int f = 0; f < F_NFAM; ++f) G.var[f] = cv[f];
+            G.store_psi = cm;
+            continue;
+        }
+        double ms = 0.0;
+        // the column passes do not depend on the nonlinear mode
+        if ((s = tune_family(b, G, F_KIN, iters, &ms)) || (s = tune_family(b, G, F_KERNEL, iters, &ms))) break;
+        // the density and phase passes change together with the mode
+        int bv[2][2];
+        double bm[2];
+        for (int m = 0; m < 2 && !s; ++m) {
+            G.store_psi = m;
+            if ((s = tune_family(b, G, F_DENSITY, iters, &ms)) || (s = tune_family(b, G, F_PHASE, iters, &ms)))
+                break;
+            bv[m][0] = G.var[F_DENSITY];
+            bv[m][1] = G.var[F_PHASE];
+            bm[m] = ms;
+        }
+        if (s) break;
+        const int m = bm[1] < bm[0] ? 1 : 0;
+        G.store_psi = m;
+        G.var[F_DENSITY] = bv[m][0];
+        G.var[F_PHASE] = bv[m][1];
+        if ((s = tune_family(b, G, F_XFFT, iters, &ms))) break;
+        for (int f = 0; f < F_NFAM; ++f)
+            fresh.push_back(batch_cache_key(b, G, kFamNames[f]) + " " + std::to_string(G.var[f]));
+        fresh.push_back(batch_cache_key(b, G, "nonlinear_mode") + " " + std::to_string(G.store_psi));
+    }
+    // put the states back (also after a failed timing)
+    for (int i = 0; i < b->count; ++i) {
+        const Instance &I = b->inst[i];
+        HIP_TRY(hipMemcpyAsync(I.psi, keep[i].data(), 8ull * I.P, hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(I.st, &keep_st[i], sizeof(DevState), hipMemcpyHostToDevice, b->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (s) return s;
+    if ((s = build_batch(b))) return s;
+    if (cpath && *cpath && !fresh.empty()) {
+        std::ofstream f(cpath, std::ios::app);
+        for (const std::string &l : fresh) f << l << "\n";
+    }
+    return GSN_OK;
+}
+
+extern "C" gsn_status gsn_batch_get_schedule(gsn_batch b, int i, int *variants, int nfam, int *nonlinear_mode)
+{
+    if (!b || !variants || !nonlinear_mode || nfam < F_NFAM) return fail(GSN_EINVAL, "bad schedule arguments");
+    if (i < 0 || i >= b->count) return fail(GSN_EINVAL, "instance index out of range");
+    for (const Group &G : b->groups)
+        for (int m : G.members)
+            if (m == i) {
+                for (int f = 0; f < F_NFAM; ++f) variants[f] = G.var[f];
+                *nonlinear_mode = G.store_psi;
+                return GSN_OK;
+            }
+    return fail(GSN_EINVAL, "instance not in any group");
 }
 
 extern "C" gsn_status gsn_batch_phase(gsn_batch b, int i, double *theta, int64_t *steps)

@@ -1038,7 +1038,13 @@ extern "C" gsn_status gsn_corrector_apply(gsn_corrector c, int b, const void *ps
 gsn_status corrector_correct_inplace(gsn_corrector c, float2 *psi, const float *phi, const double *theta,
                                      hipStream_t s)
 {
-    hipStream_t keep = c->stream;
+    // the corrector runs on the caller's stream for this call only; the guard
+    // puts its own stream back on every return path
+    struct StreamGuard {
+        gsn_corrector c;
+        hipStream_t keep;
+        ~StreamGuard() { c->stream = keep; }
+    } guard{c, c->stream};
     c->stream = s;
     gsn_status st = GSN_OK;
     if (tiled(c)) {
@@ -1067,7 +1073,6 @@ gsn_status corrector_correct_inplace(gsn_corrector c, float2 *psi, const float *
             if (hipGetLastError() != hipSuccess) st = fail(GSN_EHIP, "corrector apply launch failed");
         }
     }
-    c->stream = keep;
     return st;
 }
 

@@ -92,6 +92,9 @@ _SIGNATURES = {
     "gsn_batch_set_mode": [vp, ctypes.c_int],
     "gsn_batch_set_queue_limits": [vp, ctypes.c_uint, ctypes.c_longlong],
     "gsn_batch_set_schedule": [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int],
+    "gsn_batch_autotune": [vp, ctypes.c_int],
+    "gsn_batch_get_schedule": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_int)],
     "gsn_get_nonlinear_mode": [vp, ctypes.POINTER(ctypes.c_int)],
 }
 
@@ -473,6 +476,17 @@ class Batch:
     def set_schedule(self, variants, nonlinear_mode=0):
         v = (ctypes.c_int * len(variants))(*variants)
         check(load().gsn_batch_set_schedule(self.h, v, len(variants), int(nonlinear_mode)))
+
+    def autotune(self, iters=3):
+        check(load().gsn_batch_autotune(self.h, int(iters)))
+
+    def schedule(self, i):
+        """(variant index per family in BATCH_FAMILIES, nonlinear mode) of
+        instance i's shape group."""
+        v = (ctypes.c_int * len(BATCH_FAMILIES))()
+        m = ctypes.c_int(0)
+        check(load().gsn_batch_get_schedule(self.h, int(i), v, len(BATCH_FAMILIES), ctypes.byref(m)))
+        return list(v), m.value
 
 
 CORRECTOR_NPARAMS = 19970

@@ -86,6 +86,60 @@ def test_batch_equals_independent_grids(variants, nlmode, dz, grid_variants):
             assert orc.rel_l2(b.get(i), ref) < 1e-5
 
 
+def test_batch_autotune_keeps_states_and_matches_independent_grids():
+    """gsn_batch_autotune picks a schedule per shape group; the instances'
+    states are unchanged by it, and afterwards every instance equals an
+    independent gsn_grid run with its group's tuned schedule bit for bit,
+    and a subset matches the FP64 oracle at the solver's bar."""
+    inst = make_instances(SHAPES, 11, 2e-3)
+    b = gsn.Batch([d["n"] for d in inst], [d["L"] for d in inst])
+    for i, d in enumerate(inst):
+        b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+    b.step(3)
+    before = [b.get(i, np.complex64) for i in range(len(inst))]
+    ph_before = [b.phase(i) for i in range(len(inst))]
+    b.autotune(2)
+    for i in range(len(inst)):
+        assert np.array_equal(b.get(i, np.complex64), before[i])
+        assert b.phase(i) == ph_before[i]
+    scheds = {}
+    for i, d in enumerate(inst):
+        scheds.setdefault(d["n"], b.schedule(i))
+        assert b.schedule(i) == scheds[d["n"]]
+    say("tuned batch schedules:", scheds)
+    for i, d in enumerate(inst):
+        b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+    steps = 17
+    b.step(steps)
+    masses = b.masses()
+    for i, d in enumerate(inst):
+        variants, nlmode = b.schedule(i)
+        g = gsn.Grid(d["n"], d["L"])
+        g.set_kernel(*d["kern"])
+        g.set_coefficients(d["a"], d["g"], d["dz"])
+        g.set_schedule(grid_schedule(g, variants))
+        g.set_nonlinear_mode(nlmode)
+        g.set_psi(inputs.to_c64(d["psi"]))
+        g.step(steps)
+        assert np.array_equal(b.get(i, np.complex64), g.get_psi(np.complex64)), (i, d["n"], variants)
+        assert b.phase(i) == g.phase()
+        assert masses[i] == g.mass()
+        g.close()
+        if i < 3:
+            ref = orc.evolve(inputs.as_oracle_input(d["psi"]), d["L"], d["kern"], d["a"], d["g"],
+                             d["dz"], steps)
+            assert orc.rel_l2(b.get(i), ref) < 1e-5
+
+
+def test_batch_autotune_needs_every_state():
+    inst = make_instances(SHAPES[:2], 3, 2e-3)
+    b = gsn.Batch([d["n"] for d in inst], [d["L"] for d in inst])
+    b.set(0, inst[0]["kern"], 0.5, -0.5, 2e-3, inputs.to_c64(inst[0]["psi"]))
+    with pytest.raises(gsn.GsnError) as ei:
+        b.autotune(1)
+    assert ei.value.status == gsn.GSN_ESTATE
+
+
 def test_graph_replays_and_direct_mode_agree():
     """Several replays of one captured graph, with eager work in between, equal
     the same steps issued as direct launches."""

@@ -15,6 +15,9 @@ import pytest
 from oracle import oracle as orc
 from paper_1909_08354_amd import gsn, inputs
 
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import goldens  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -106,9 +109,10 @@ def test_fp64_storage_unsupported_calls():
 
 def test_fp64_storage_256_matches_oracle_after_1000_steps():
     """The 256^3 workload from the same complex128(complex64(psi0)) bits as the
-    stored 1000-step oracle result, on an FP64-storage grid."""
+    stored 1000-step oracle result, on an FP64-storage grid: the three whole
+    central planes element by element, the central x line and the mass."""
     import torch
-    rec = json.load(open(os.path.join(HERE, "golden", "gsn3d_256_newton_yukawa.json")))
+    rec, ref = goldens.load("gsn3d_256_newton_yukawa")
     w = inputs.WORKLOADS["gsn3d_256_newton_yukawa"]
     grid = gsn.Grid(w["n"], w["L"], storage=np.complex128)
     grid.set_kernel(*w["kern"])
@@ -119,17 +123,18 @@ def test_fp64_storage_256_matches_oracle_after_1000_steps():
     grid.set_psi(dev0)
     grid.step(w["steps"])
     out = grid.get_psi(np.complex128, device=True)
-    idx = [tuple(s[0]) for s in rec["samples"]]
-    ref = np.array([s[1] + 1j * s[2] for s in rec["samples"]])
-    zi, yi, xi = (torch.tensor([i[a] for i in idx], device="cuda") for a in range(3))
-    got = out[zi, yi, xi].cpu().numpy()
+    res = goldens.compare(goldens.device_planes(out, rec), ref)
     xl = rec["x_line"]
     ref_line = np.array(xl["re"]) + 1j * np.array(xl["im"])
     got_line = out[xl["z"], xl["y"], :].cpu().numpy()
-    rel_s = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    del out
     rel_l = np.linalg.norm(got_line - ref_line) / np.linalg.norm(ref_line)
     m = grid.mass()
     drift = abs(m / rec["observables_start"]["mass"] - 1)
-    say(f"fp64 256^3: rel_l2 samples {rel_s:.3e} line {rel_l:.3e} drift {drift:.3e}")
-    assert rel_s < 1e-10 and rel_l < 1e-10
+    for k, (r, mx) in res.items():
+        say(f"fp64 256^3 plane {k}: rel_l2 {r:.3e} max|diff|/max|psi| {mx:.3e}")
+    say(f"fp64 256^3: rel_l2 line {rel_l:.3e} drift {drift:.3e}")
+    for k, (r, mx) in res.items():
+        assert r < 1e-10 and mx < 1e-10, (k, r, mx)
+    assert rel_l < 1e-10
     assert drift < 1e-12
