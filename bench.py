@@ -523,8 +523,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": head_name, "grid": list(w["n"]), "dz": w["dz"],
                    "kernel": head["kernel"], "g": w["g"], "ic": w["ic"],
-                   "passes_per_step": len([k for k in head["pass_ms"]
-                                           if k not in ("x_entry_fft", "x_exit_ifft")])},
+                   "passes_per_step": len([k for k, v in head["pass_ms"].items()
+                                           if v > 0 and k not in ("x_entry_fft", "x_exit_ifft")])},
         "roofline": head["roofline"],
     }
     for k in ("model_bytes_per_point", "model_step_gbps", "model_step_hbm_frac",

@@ -59,6 +59,14 @@ template <int N, int V> static NKernels make_kernels()
         k.lmp[LM_INV] = k_lmp<N, E, LL, LM_INV, float2>;
         k.lmp[LM_KIN] = k_lmp<N, E, LL, LM_KIN, float2>;
         k.lmp[LM_KERN] = k_lmp<N, E, LL, LM_KERN, float2>;
+        constexpr int TPL = N / E;
+        if constexpr (C::WAVE && TPL <= 64 && 64 % TPL == 0 && N > E && (LL * TPL) % 64 == 0 &&
+                      LmwLds<N, E, LL, LM_KIN>::FITS) {
+            k.lmp[LM_FWD] = k_lmw<N, E, LL, LM_FWD>;
+            k.lmp[LM_INV] = k_lmw<N, E, LL, LM_INV>;
+            k.lmp[LM_KIN] = k_lmw<N, E, LL, LM_KIN>;
+            k.lmp[LM_KERN] = k_lmw<N, E, LL, LM_KERN>;
+        }
     }
     return k;
 }
@@ -66,7 +74,8 @@ template <int N, int V> static NKernels make_kernels()
 template <int N> static const NKernels *variant_table(int v)
 {
     static const NKernels k[kNumVariants] = {make_kernels<N, 0>(), make_kernels<N, 1>(), make_kernels<N, 2>(),
-                                             make_kernels<N, 3>(), make_kernels<N, 4>()};
+                                             make_kernels<N, 3>(), make_kernels<N, 4>(), make_kernels<N, 5>(),
+                                             make_kernels<N, 6>()};
     return &k[v];
 }
 
@@ -95,12 +104,12 @@ const NKernels *kernels_for(int N, int v)
 // position-dependent coupling; each runs only while its term is on (a 2-D
 // grid uses only the Laplacian column passes).
 enum PassId {
-    P_ENTRY = 0, P_Y_FWD_PSI, P_KINETIC, P_Y_INV_PSI, P_DENSITY, P_Y_FWD_RHO, P_KERNEL,
+    P_ENTRY = 0, P_KIN_Y, P_KINETIC, P_DENSITY, P_Y_FWD_RHO, P_KERNEL,
     P_Y_INV_PHI, P_PHASE, P_EXIT, P_Y_FWD_SQRT, P_LAPLACIAN, P_Y_INV_LAP, P_Y_FWD_SRC,
     P_LAP_RHO, P_Y_INV_SRC, P_SOURCE, P_COUNT
 };
 static const char *kPassNames[P_COUNT] = {
-    "x_entry_fft", "y_fwd_psi", "kinetic", "y_inv_psi", "x_density", "y_fwd_rho",
+    "x_entry_fft", "kinetic_y", "kinetic", "x_density", "y_fwd_rho",
     "kernel", "y_inv_phi", "x_phase", "x_exit_ifft", "y_fwd_sqrt", "laplacian", "y_inv_lap",
     "y_fwd_src", "lap_rho", "y_inv_src", "x_source"};
 
@@ -440,21 +449,22 @@ static void build_core(gsn_grid g)
         std::vector<Launch> &dst = half ? g->kin_half : g->kin_full;
         double2 *const *kin = half ? g->kinH : g->kinF;
         if (nd == 3) {
-            const NKernels *ky = KY(P_Y_FWD_PSI), *kz = KZ(P_KINETIC), *ky2 = KY(P_Y_INV_PSI);
-            LmArgs a = lm_base(g, g->tw[Y], 1.0);
+            // the propagator exp(-i a |k|^2 h) is a product of per-axis
+            // factors, so the kinetic sub-step is L_x L_y L_z with 1-D
+            // operators that commute: one y pass applies
+            // G_y exp(-i a (kx^2 + ky^2) h) F_y / Ny to the x-spectral psi
+            // (kx per line), one z pass G_z exp(-i a kz^2 h) F_z / Nz
+            const NKernels *ky = KY(P_KIN_Y), *kz = KZ(P_KINETIC);
+            LmArgs a = lm_base(g, g->tw[Y], 1.0 / (double)Ny);
             a.s0 = make_seg(g->psi, Nx, 1, (long long)Ny * Nx, Nx, Nz, ky->lm_lines);
-            dst.push_back(lm_launch(ky->lm_fwd, ky, a, P_Y_FWD_PSI));
-            LmArgs b = lm_base(g, g->tw[Z], 1.0 / ((double)Ny * Nz));
+            a.s0.c1l = 1;  // c1 = x = line
+            a.kin1 = kin[X];
+            a.kinp = kin[Y];
+            dst.push_back(lm_launch(ky->lm_kin, ky, a, P_KIN_Y));
+            LmArgs b = lm_base(g, g->tw[Z], 1.0 / (double)Nz);
             b.s0 = make_seg(g->psi, (long long)Ny * Nx, 1, Nx, Nx, Ny, kz->lm_lines);
-            b.s0.c1l = 1;  // c1 = x = line
-            b.s0.c2o = 1;  // c2 = y = outer
-            b.kin1 = kin[X];
-            b.kin2 = kin[Y];
             b.kinp = kin[Z];
             dst.push_back(lm_launch(kz->lm_kin, kz, b, P_KINETIC));
-            LmArgs c = lm_base(g, g->tw[Y], 1.0);
-            c.s0 = make_seg(g->psi, Nx, 1, (long long)Ny * Nx, Nx, Nz, ky2->lm_lines);
-            dst.push_back(lm_launch(ky2->lm_inv, ky2, c, P_Y_INV_PSI));
         } else {
             const NKernels *ky = KY(P_KINETIC);
             LmArgs b = lm_base(g, g->tw[Y], 1.0 / (double)Ny);
@@ -642,10 +652,10 @@ static void build_core(gsn_grid g)
     {
         const int ep_off = 4 * g->max_density_blocks;
         if (nd == 3) {
-            const NKernels *ky = KY(P_Y_FWD_PSI), *kz = KZ(P_KINETIC);
+            const NKernels *ky = KY(P_KIN_Y), *kz = KZ(P_KINETIC);
             LmArgs a = lm_base(g, g->tw[Y], 1.0);
             a.s0 = make_seg(g->scratch, Nx, 1, (long long)Ny * Nx, Nx, Nz, ky->lm_lines);
-            g->energy_kin.push_back(lm_launch(ky->lm_fwd, ky, a, P_Y_FWD_PSI));
+            g->energy_kin.push_back(lm_launch(ky->lm_fwd, ky, a, P_KIN_Y));
             LmArgs b = lm_base(g, g->tw[Z], 1.0);
             b.s0 = make_seg(g->scratch, (long long)Ny * Nx, 1, Nx, Nx, Ny, kz->lm_lines);
             b.s0.c1l = 1;
@@ -1300,7 +1310,8 @@ static double pass_bytes_c64(gsn_grid g, int i)
 {
     // reads + writes of complex64 psi (8 B), half spectrum (4 B per point)
     switch (i) {
-    case P_ENTRY: case P_EXIT: case P_Y_FWD_PSI: case P_Y_INV_PSI: case P_KINETIC: return 16.0;
+    case P_ENTRY: case P_EXIT: case P_KINETIC: return 16.0;
+    case P_KIN_Y: return g->ndim == 3 ? 16.0 : 0.0;
     case P_DENSITY: return (g->store_psi ? 20.0 : 12.0) + (g->bohm_on ? 4.0 : 0.0);
     case P_Y_FWD_RHO: case P_KERNEL: case P_Y_INV_PHI: return 8.0;
     case P_PHASE: return 20.0 + (g->bohm_on ? 4.0 : 0.0) + (g->fld_V ? 4.0 : 0.0);
@@ -1420,7 +1431,7 @@ static bool timing_launch(gsn_grid g, int p, Launch *out)
                 // with the unitary scale 1/sqrt(N) they keep its norm, and the
                 // scale multiply costs the same
                 if (p == P_ENTRY || p == P_EXIT) out->ea.scale = 1.0 / std::sqrt((double)g->Nx);
-                const bool ftrans = p == P_Y_FWD_PSI || p == P_Y_INV_PSI || p == P_Y_FWD_RHO ||
+                const bool ftrans = p == P_Y_FWD_RHO ||
                                     p == P_Y_INV_PHI || p == P_Y_FWD_SQRT || p == P_Y_INV_LAP ||
                                     p == P_Y_FWD_SRC || p == P_Y_INV_SRC;
                 if (ftrans) out->la.scale = 1.0 / std::sqrt((double)g->Ny);   // the y axis (3-D only)

@@ -205,13 +205,13 @@ class Grid:
         self.L = tuple(float(v) for v in L)
         self.P = int(np.prod(self.n))
         self.storage = _storage_code(storage)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
         nbytes = gsn_workspace_bytes(self.n, storage)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self._ws.data_ptr()
         aligned = (base + 255) & ~255
-        if stream is None:
-            stream = torch.cuda.current_stream()
-        self.stream = stream
         h = vp()
         check(lib.gsn_create_ex(ctypes.byref(h), len(self.n), _i32(self.n), _f64(self.L), self.storage,
                                 vp(aligned), nbytes, vp(stream.cuda_stream)))

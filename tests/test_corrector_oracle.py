@@ -55,6 +55,23 @@ def test_adam_first_step_is_sign_times_lr():
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
 
 
+def test_adam_bias_correction_after_the_first_step():
+    """Closed forms of the bias-corrected moments: a constant gradient g gives
+    mhat = g and vhat = g^2 at every t, so every step is -lr g/(|g| + eps);
+    gradients g then -g give at t = 2 mhat = -(1-b1)/(1+b1) g and vhat = g^2."""
+    lr, b1 = 0.01, 0.9
+    g = np.array([0.3, -2.0, 1.5e-2])
+    th, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in (1, 2, 3):
+        prev = th
+        th, m, v = co.adam(th, g, m, v, t, lr)
+        assert np.allclose(th - prev, -lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15), t
+    th, m, v = co.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr)
+    th2, _, _ = co.adam(th, -g, m, v, 2, lr)
+    step = lr * (1 - b1) / (1 + b1) * g / (np.abs(g) + 1e-8)
+    assert np.allclose(th2 - th, step, rtol=1e-9, atol=1e-15)
+
+
 def test_bf16_rounding():
     vals = np.array([1.0, 1.00390625, 1.005859375, -3.14159, 0.0, 65504.0])
     r = co.bf16_round(vals)

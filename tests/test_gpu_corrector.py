@@ -130,6 +130,32 @@ def test_corrector_adam_step_and_determinism():
     assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
 
 
+def test_corrector_three_adam_steps_match_oracle():
+    """Adam's bias correction after the first step: three training steps, each
+    compared with the oracle's Adam step fed the gradient the kernels compute
+    at the same weights (moments carried over on both sides)."""
+    import torch
+    B, H, W = 2, 16, 32
+    c, theta = make(B, H, W, 14)
+    psi, phi, tpsi, tphi = random_fields(B, H, W, 15)
+    tfine = tpsi * 1.02
+    for b in range(B):
+        c.pack(b, tpsi[b], tphi[b])
+        c.pack_target(b, tfine[b], tpsi[b])
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    ref = theta.copy()
+    lr = 2e-3
+    for t in (1, 2, 3):
+        _, g = c.gradients(B)
+        c.train_step(B, lr)
+        ref, m, v = co.adam(ref, g.astype(np.float64), m, v, t, lr)
+        got = c.get_weights().astype(np.float64)
+        err = np.max(np.abs(got - ref))
+        say(f"Adam step {t}: max |w - oracle| {err:.2e}")
+        assert err < 1e-6, (t, err)
+
+
 @pytest.mark.parametrize("n", [(64, 128), (16, 32, 64)])
 def test_potential_matches_oracle(n):
     rng = np.random.default_rng(8)

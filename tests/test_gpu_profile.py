@@ -42,7 +42,7 @@ def test_profile_passes_advances_like_step(schedule, steps):
     assert np.array_equal(a.get_psi(np.complex64), b.get_psi(np.complex64))
     assert a.mass() == b.mass()
     assert a.phase() == b.phase()
-    for name in ("y_fwd_psi", "kinetic", "y_inv_psi", "x_density", "y_fwd_rho", "kernel", "y_inv_phi",
+    for name in ("kinetic_y", "kinetic", "x_density", "y_fwd_rho", "kernel", "y_inv_phi",
                  "x_phase"):
         assert prof[name] > 0.0, name
     for name in ("y_fwd_sqrt", "laplacian", "x_source"):
