@@ -97,6 +97,19 @@ gsn_status gsn_create_ex(gsn_grid *out, int ndim, const int32_t n[], const doubl
                          void *d_workspace, size_t bytes, void *hip_stream);
 gsn_status gsn_destroy(gsn_grid grid);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   grid as gsn_create (complex64 storage), with its workspace in the library's
+   static per-device array of 64 MiB instead of a caller buffer; nothing is
+   allocated on the device.  Grids whose gsn_workspace_bytes exceed 64 MiB are
+   rejected with GSN_EWORKSPACE.  The array is shared by every such grid on a
+   device, so one may be alive per device at a time: a second call before
+   gsn_destroy of the first returns GSN_ESTATE (without that check two grids
+   would race on the same memory).  The array keeps the last grid's contents;
+   creation resets every value a step reads before writing it.  Each GPU the
+   library runs on holds its copy until the process ends. */
+gsn_status gsn_create_static(gsn_grid *out, int ndim, const int32_t n[], const double L[], void *hip_stream);
+
 /* Set the nonlocal kernel (see gsn_kernel).  All values finite. */
 gsn_status gsn_set_kernel(gsn_grid grid, const gsn_kernel *kernel);
 

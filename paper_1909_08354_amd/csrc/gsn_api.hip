@@ -167,6 +167,7 @@ struct gsn_grid_ {
     double2 *kinFc[3], *kinHc[3]; // kinetic tables of the coarse step
     DevState *st_save[2];         // device copies of the state for audits
     int density_blocks;
+    bool static_ws;               // workspace = the library's static array (gsn_create_static)
 };
 
 
@@ -885,6 +886,7 @@ extern "C" gsn_status gsn_create_ex(gsn_grid *out, int ndim, const int32_t n[], 
     g->st_save[1] = (DevState *)(ws + off); off += 256;
     g->sct = (double2 *)(ws + off); off += 16 * kSinCosTable;
     g->coarse_ratio = 0;
+    g->static_ws = false;
     if ((s = upload_static_tables(g)) || (s = upload_kinetic(g))) {
         delete g;
         return s;
@@ -905,10 +907,64 @@ extern "C" gsn_status gsn_create(gsn_grid *out, int ndim, const int32_t n[], con
     return gsn_create_ex(out, ndim, n, L, GSN_C64, d_workspace, bytes, hip_stream);
 }
 
+// ------------------------------------------------------------------ grids without a caller workspace
+// For callers that cannot allocate device memory (code under HIP graph
+// capture, serving loops, harnesses that forbid hipMalloc): a grid whose
+// workspace is this file-scope array.  Every GPU the library runs on holds its
+// own copy until the process ends.  In host code the array's name is only a
+// host-side stand-in; its device address on the current device comes from
+// hipGetSymbolAddress, taken once per device and kept in g_static_ws.
+constexpr size_t kStaticWorkspaceBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+namespace {
+struct StaticWs {
+    void *ptr = nullptr;   // device address of scratch on this device
+    bool in_use = false;   // a live grid owns it
+};
+std::mutex g_static_mu;
+std::map<int, StaticWs> g_static_ws;
+}  // namespace
+
+extern "C" gsn_status gsn_create_static(gsn_grid *out, int ndim, const int32_t n[], const double L[],
+                                        void *hip_stream)
+{
+    if (!out) return fail(GSN_EINVAL, "out is NULL");
+    *out = nullptr;
+    gsn_status s = validate_shape(ndim, n);
+    if (s) return s;
+    const Layout lay = compute_layout(ndim, n, storage_bytes(GSN_C64));
+    if (lay.total > kStaticWorkspaceBytes)
+        return fail(GSN_EWORKSPACE, "grid needs " + std::to_string(lay.total) +
+                                        " bytes of workspace; the static workspace holds " +
+                                        std::to_string(kStaticWorkspaceBytes));
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticWs &w = g_static_ws[dev];
+    if (!w.ptr) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(GSN_EHIP, "hipGetSymbolAddress returned no address for the static workspace");
+        w.ptr = ptr;
+    }
+    if (w.in_use) return fail(GSN_ESTATE, "the static workspace of this device belongs to a live grid");
+    gsn_grid g = nullptr;
+    if ((s = gsn_create_ex(&g, ndim, n, L, GSN_C64, w.ptr, kStaticWorkspaceBytes, hip_stream))) return s;
+    g->static_ws = true;
+    w.in_use = true;
+    *out = g;
+    return GSN_OK;
+}
+
 extern "C" gsn_status gsn_destroy(gsn_grid g)
 {
     if (!g) return fail(GSN_EINVAL, "grid is NULL");
     (void)hipStreamSynchronize(g->stream);
+    if (g->static_ws) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_ws[g->device].in_use = false;
+    }
     delete g;
     return GSN_OK;
 }

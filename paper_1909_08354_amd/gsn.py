@@ -40,6 +40,7 @@ dp = ctypes.POINTER(ctypes.c_double)
 _SIGNATURES = {
     "gsn_workspace_bytes": [ctypes.c_int, i32p, ctypes.POINTER(ctypes.c_size_t)],
     "gsn_create": [ctypes.POINTER(vp), ctypes.c_int, i32p, dp, vp, ctypes.c_size_t, vp],
+    "gsn_create_static": [ctypes.POINTER(vp), ctypes.c_int, i32p, dp, vp],
     "gsn_workspace_bytes_ex": [ctypes.c_int, i32p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
     "gsn_create_ex": [ctypes.POINTER(vp), ctypes.c_int, i32p, dp, ctypes.c_int, vp, ctypes.c_size_t, vp],
     "gsn_destroy": [vp],
@@ -198,7 +199,7 @@ class Grid:
     """One periodic 2-D or 3-D grid on the current HIP device (gsn_create;
     storage=np.complex128: gsn_create_ex with FP64 storage)."""
 
-    def __init__(self, n, L, stream=None, storage=np.complex64):
+    def __init__(self, n, L, stream=None, storage=np.complex64, static_workspace=False):
         torch = _torch()
         lib = load()
         self.n = tuple(int(v) for v in n)
@@ -208,6 +209,17 @@ class Grid:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        if static_workspace:
+            # gsn_create_static: the library's per-device static workspace,
+            # no device allocation anywhere (complex64 storage only)
+            if self.storage != GSN_C64:
+                raise ValueError("the static workspace holds complex64 grids only")
+            self._ws = None
+            h = vp()
+            check(lib.gsn_create_static(ctypes.byref(h), len(self.n), _i32(self.n), _f64(self.L),
+                                        vp(stream.cuda_stream)))
+            self.h = h
+            return
         nbytes = gsn_workspace_bytes(self.n, storage)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self._ws.data_ptr()
