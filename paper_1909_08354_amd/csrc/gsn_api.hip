@@ -59,14 +59,6 @@ template <int N, int V> static NKernels make_kernels()
         k.lmp[LM_INV] = k_lmp<N, E, LL, LM_INV, float2>;
         k.lmp[LM_KIN] = k_lmp<N, E, LL, LM_KIN, float2>;
         k.lmp[LM_KERN] = k_lmp<N, E, LL, LM_KERN, float2>;
-        constexpr int TPL = N / E;
-        if constexpr (C::WAVE && TPL <= 64 && 64 % TPL == 0 && N > E && (LL * TPL) % 64 == 0 &&
-                      LmwLds<N, E, LL, LM_KIN>::FITS) {
-            k.lmp[LM_FWD] = k_lmw<N, E, LL, LM_FWD>;
-            k.lmp[LM_INV] = k_lmw<N, E, LL, LM_INV>;
-            k.lmp[LM_KIN] = k_lmw<N, E, LL, LM_KIN>;
-            k.lmp[LM_KERN] = k_lmw<N, E, LL, LM_KERN>;
-        }
     }
     return k;
 }
@@ -74,8 +66,7 @@ template <int N, int V> static NKernels make_kernels()
 template <int N> static const NKernels *variant_table(int v)
 {
     static const NKernels k[kNumVariants] = {make_kernels<N, 0>(), make_kernels<N, 1>(), make_kernels<N, 2>(),
-                                             make_kernels<N, 3>(), make_kernels<N, 4>(), make_kernels<N, 5>(),
-                                             make_kernels<N, 6>()};
+                                             make_kernels<N, 3>(), make_kernels<N, 4>()};
     return &k[v];
 }
 

@@ -42,8 +42,7 @@ template <int N, int V> static NKernels make_kernels_c128()
 template <int N> static const NKernels *table_c128(int v)
 {
     static const NKernels k[3] = {make_kernels_c128<N, 0>(), make_kernels_c128<N, 1>(), make_kernels_c128<N, 4>()};
-    // e16 and the p16 / w16 tiles; e8 and the p8 / w8 tiles; s8
-    return &k[v == 4 ? 2 : v == 5 ? 0 : v == 6 ? 1 : (v & 1)];
+    return &k[v == 4 ? 2 : (v & 1)];
 }
 
 const NKernels *kernels_for_c128(int N, int v)

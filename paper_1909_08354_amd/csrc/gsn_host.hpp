@@ -63,22 +63,17 @@ struct NKernels {
 // tile moves 128-byte contiguous segments per row where the block's thread
 // budget allows (long lines get 64- or 32-byte segments).  The batched solver
 // offers the first kNumBatchVariants.
-constexpr int kNumVariants = 7;
+constexpr int kNumVariants = 5;
 constexpr int kNumBatchVariants = 4;
-static const char *kVariantNames[kNumVariants] = {"e16", "e8", "p16", "p8", "s8", "w16", "w8"};
+static const char *kVariantNames[kNumVariants] = {"e16", "e8", "p16", "p8", "s8"};
 
 // "s8": 8 points per thread with the smallest tiles that still fill a
 // wavefront (one row pair per block where a row takes 64 threads, four
 // strided lines per block), for grids too small to give every CU a tile.
-// "w16", "w8": the tiles of p16 / p8, with the strided passes in the
-// wave-line form (the middle radix stages one line per wavefront) where a
-// line fits one wavefront; the other passes are those of p16 / p8.
 template <int N, int V> struct Cfg {
-    static constexpr int BV = V == 5 ? 2 : V == 6 ? 3 : V;   // the variant whose tiles these are
-    static constexpr bool WAVE = V == 5 || V == 6;
-    static constexpr bool SMALL = BV == 4;
-    static constexpr int E0 = (BV & 1) || SMALL ? 8 : 16;
-    static constexpr bool PIPE = BV == 2 || BV == 3;
+    static constexpr bool SMALL = V == 4;
+    static constexpr int E0 = (V & 1) || SMALL ? 8 : 16;
+    static constexpr bool PIPE = V == 2 || V == 3;
     static constexpr int E = N < E0 ? N : E0;
     static constexpr int TPL = N / E;
     // 16 lines (128-byte row segments; more for very short lines) while the

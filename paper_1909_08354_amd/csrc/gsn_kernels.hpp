@@ -1097,249 +1097,6 @@ __device__ __forceinline__ void lmp_body(const Src &src, LT *lds, const double2 
     }
 }
 
-// ---------------------------------------------------------------- wave-line LM passes
-// The persistent prefetching LM pass with its middle radix stages run one
-// line per wavefront.  Loads, stores and the first and last radix stages use
-// the coalesced mapping of lm_where (lane -> line tid % LINES, so a
-// wavefront's access per position is one contiguous segment of LINES points);
-// the stages in between use the wave mapping (line tid / TPL, t = tid % TPL:
-// the TPL threads of a line inside one wavefront).  An exchange between two
-// stages of the wave mapping then only orders the wavefront's own LDS
-// accesses; the two exchanges that change mapping go through one of two LDS
-// tile buffers, alternately, so each costs one block barrier.  A wave-local
-// exchange reuses the buffer of the last block exchange: after it, every
-// wavefront reads only its own lines there.  Stages, twiddles and roundings
-// are those of lmp_body, so the results are the same bits.
-
-// LDS line layout: line-major, one pad slot per 32 points, pitch = 4 (mod 32)
-// complex64 slots, so the lanes of the coalesced mapping (adjacent lines)
-// spread over the banks and those of the wave mapping (adjacent positions of
-// one line) read consecutive slots.
-template <int N> struct LwLayout {
-    static constexpr int BASE = N + N / 32;
-    static constexpr int PITCH = BASE + (36 - BASE % 32) % 32;
-    int base;   // line * PITCH
-    __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 5); }
-};
-
-// Butterflies of Stockham stage ST for the thread's position index t (its
-// registers hold positions t + TPL e of its line): outputs to LDS through
-// lay, or, on the last stage, back into the registers in natural order.
-template <int N, int E, int S, int ST, class Lay>
-__device__ __forceinline__ void lw_stage(dc (&v)[E], int t, const Lay &lay, float2 *lds,
-                                         const double2 *__restrict__ tw)
-{
-    using P = Plan<N, E>;
-    constexpr int R = P::radix(ST);
-    constexpr int NS = P::ns(ST);
-    constexpr bool LAST = (ST + 1 == P::nstages());
-    constexpr int B = E / R;
-    constexpr int TPL = P::TPL;
-#pragma unroll
-    for (int m = 0; m < B; ++m) {
-        const int j = t + TPL * m;
-        dc a[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) a[r] = v[m + r * B];
-        if constexpr (NS > 1) {
-            const int jm = j & (NS - 1);
-            constexpr int STEP = N / (NS * R);
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                dc w = from_d2(tw[jm * r * STEP]);
-                if constexpr (S > 0) w.y = -w.y;
-                a[r] = cmul(a[r], w);
-            }
-        }
-        dft<R, S>(a);
-        if constexpr (LAST) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[m + r * B] = a[r];
-        } else {
-            const int base = (j / NS) * NS * R + (j & (NS - 1));
-#pragma unroll
-            for (int r = 0; r < R; ++r) lds_put(lds, lay(base + r * NS), a[r]);
-        }
-    }
-}
-
-template <int N, int E, class Lay>
-__device__ __forceinline__ void lw_read(dc (&v)[E], int t, const Lay &lay, const float2 *lds)
-{
-    constexpr int TPL = N / E;
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = lds_get(lds, lay(t + TPL * e));
-}
-
-struct LwMaps {
-    int lc, tc;   // coalesced mapping: line tid % LINES, position index tid / LINES
-    int lw, tw;   // wave mapping: line tid / TPL, position index tid % TPL
-};
-
-// One transform (S = -1 forward, +1 inverse) of the tile held in v.  Stage 0
-// runs in the coalesced mapping when START_C, the last stage when END_C,
-// every other stage in the wave mapping; xb names the buffer of the last
-// block exchange.
-template <int N, int E, int S, int ST, bool START_C, bool END_C>
-__device__ __forceinline__ void fft_cw(dc (&v)[E], const LwMaps &mp, float2 *bufA, float2 *bufB, int &xb,
-                                       const double2 *__restrict__ tw)
-{
-    using P = Plan<N, E>;
-    constexpr int NST = P::nstages();
-    constexpr int PITCH = LwLayout<N>::PITCH;
-    if constexpr (ST < NST) {
-        constexpr bool CUR_C = (ST == 0 && START_C) || (ST == NST - 1 && END_C);
-        if constexpr (ST + 1 == NST) {
-            lw_stage<N, E, S, ST>(v, CUR_C ? mp.tc : mp.tw, LwLayout<N>{0}, (float2 *)nullptr, tw);
-        } else {
-            constexpr bool NXT_C = (ST + 1 == NST - 1) && END_C;
-            if constexpr (!CUR_C && !NXT_C) {
-                float2 *buf = xb ? bufB : bufA;
-                const LwLayout<N> lay{mp.lw * PITCH};
-                lw_stage<N, E, S, ST>(v, mp.tw, lay, buf, tw);
-                exchange_sync<true>();
-                lw_read<N, E>(v, mp.tw, lay, buf);
-                exchange_sync<true>();
-            } else {
-                xb ^= 1;
-                float2 *buf = xb ? bufB : bufA;
-                lw_stage<N, E, S, ST>(v, CUR_C ? mp.tc : mp.tw, LwLayout<N>{(CUR_C ? mp.lc : mp.lw) * PITCH}, buf,
-                                      tw);
-                __syncthreads();
-                lw_read<N, E>(v, NXT_C ? mp.tc : mp.tw, LwLayout<N>{(NXT_C ? mp.lc : mp.lw) * PITCH}, buf);
-            }
-            fft_cw<N, E, S, ST + 1, START_C, END_C>(v, mp, bufA, bufB, xb, tw);
-        }
-    }
-}
-
-// Loads of one tile: the points in the coalesced mapping (wc), the line
-// factors of the wave mapping's line (ww), where the multiplier is applied.
-template <int E, int MODE>
-__device__ __forceinline__ void lw_fetch(const LmArgs &a, const LmWhere &wc, const LmWhere &ww, bool live,
-                                         LmPrefetch<E> &f)
-{
-    const unsigned vo = live ? wc.voff : 0u, st = live ? wc.step : 0u;
-#pragma unroll
-    for (int e = 0; e < E; ++e) f.p[e] = buf_ld2(wc.r, vo, e * st);
-    if constexpr (MODE == LM_KIN) {
-        f.f1 = gld(a.kin1, live ? ww.c1 : 0);
-        f.f2 = gld(a.kin2, live ? ww.c2 : 0);
-    } else if constexpr (MODE == LM_KERN) {
-        f.q1 = gmem(a.k2_1)[live ? ww.c1 : 0];
-        f.q2 = gmem(a.k2_2)[live ? ww.c2 : 0];
-    }
-}
-
-// LDS of a wave-line block: two tile buffers and the reduction scratch, then
-// the twiddles and the mode's per-position table while they fit.
-template <int N, int E, int LINES, int MODE> struct LmwLds {
-    static constexpr long kLimit = 160L * 1024;
-    static constexpr long TILE = 8L * LINES * LwLayout<N>::PITCH;
-    static constexpr long BASE = 2 * TILE + 8L * (LINES * (N / E) / 64 + 1);
-    static constexpr long TAB = MODE == LM_KIN ? 16L * N : MODE == LM_KERN ? 8L * N : 0;
-    static constexpr bool TW = BASE + 16L * N + TAB <= kLimit;
-    static constexpr bool TB = BASE + TAB + (TW ? 16L * N : 0) <= kLimit;
-    static constexpr bool FITS = BASE <= kLimit;
-};
-
-template <int N, int E, int LINES, int MODE, class Src, bool TW_L, bool TB_L>
-__device__ __forceinline__ void lmw_body(const Src &src, float2 *bufA, float2 *bufB, const double2 *twl,
-                                         const double2 *kpl, const double *k2l, double *sh)
-{
-    constexpr int TPL = N / E, NT = LINES * TPL;
-    static_assert(TPL <= 64 && 64 % TPL == 0 && NT % 64 == 0, "a line must sit inside one wavefront");
-    static_assert(Plan<N, E>::nstages() >= 2, "one-stage lines have no middle stages");
-    static_assert(MODE == LM_FWD || MODE == LM_INV || MODE == LM_KIN || MODE == LM_KERN, "mode");
-    const int tid = threadIdx.x;
-    const LwMaps mp{tid % LINES, tid / LINES, tid / TPL, tid % TPL};
-    {
-        const LmArgs &a0 = src.args(0);
-        for (int i = tid; i < N; i += NT) {
-            if constexpr (TW_L) const_cast<double2 *>(twl)[i] = gld(a0.tw, i);
-            if constexpr (MODE == LM_KIN && TB_L) const_cast<double2 *>(kpl)[i] = gld(a0.kinp, i);
-            if constexpr (MODE == LM_KERN && TB_L) const_cast<double *>(k2l)[i] = gmem(a0.k2_p)[i];
-        }
-        if constexpr (!Src::GROUPED) {
-            if (a0.reduce && blockIdx.x == 0) reduce_mass<NT>(a0, sh);
-        }
-    }
-    __syncthreads();
-    const int ntiles = src.ntiles();
-    int tile = blockIdx.x;
-    if (tile >= ntiles) return;
-    int xb = 1;
-    LmPrefetch<E> f;
-    {
-        const LmArgs &a = src.args(tile);
-        const int lt = src.local(tile);
-        lw_fetch<E, MODE>(a, lm_where<N, E, LINES>(a, lt, mp.lc, mp.tc), lm_where<N, E, LINES>(a, lt, mp.lw, 0),
-                          true, f);
-    }
-    dc v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = from_f2(f.p[e]);
-    dc m12 = mk(0.0, 0.0);
-    double q12 = 0.0;
-    if constexpr (MODE == LM_KIN) m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), src.args(tile).scale);
-    if constexpr (MODE == LM_KERN) q12 = f.q1 + f.q2;
-    for (;;) {
-        const LmArgs &a = src.args(tile);
-        const int nxt = tile + gridDim.x;
-        const bool more = nxt < ntiles;
-        {
-            const int pf = more ? nxt : tile;
-            const LmArgs &an = src.args(pf);
-            const int lt = src.local(pf);
-            lw_fetch<E, MODE>(an, lm_where<N, E, LINES>(an, lt, mp.lc, mp.tc),
-                              lm_where<N, E, LINES>(an, lt, mp.lw, 0), more, f);
-        }
-        if constexpr (Src::GROUPED) {
-            if (a.reduce && src.local(tile) == 0) reduce_mass<NT>(a, sh);
-        }
-        if constexpr (MODE == LM_FWD || MODE == LM_INV) {
-            fft_cw<N, E, MODE == LM_FWD ? -1 : 1, 0, true, true>(v, mp, bufA, bufB, xb, twl);
-#pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = scl(v[e], a.scale);
-        } else {
-            fft_cw<N, E, -1, 0, true, false>(v, mp, bufA, bufB, xb, twl);
-            if constexpr (MODE == LM_KIN) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) v[e] = cmul(v[e], cmul(m12, from_d2(kpl[mp.tw + TPL * e])));
-            } else {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const double k2 = q12 + k2l[mp.tw + TPL * e];
-                    const bool pos = k2 > 0.0;
-                    const double km = k2 + a.mY2;
-                    const double num = fma(a.cN, km, a.cY * k2);
-                    const double den = pos ? k2 * km : 1.0;
-                    double r = __builtin_amdgcn_rcp(den);
-                    r = fma(r, fma(-den, r, 1.0), r);
-                    r = fma(r, fma(-den, r, 1.0), r);
-                    const double K = pos ? fma(num, r, a.c0) : 0.0;
-                    v[e] = scl(v[e], K * a.scale);
-                }
-            }
-            fft_cw<N, E, 1, 0, false, true>(v, mp, bufA, bufB, xb, twl);
-        }
-        const LmWhere w = lm_where<N, E, LINES>(a, src.local(tile), mp.lc, mp.tc);
-#pragma unroll
-        for (int e = 0; e < E; ++e) buf_st2(to_f2(v[e]), w.r, w.voff, e * w.step);
-        if (!more) break;
-        convert_pinned(v, f.p, std::make_integer_sequence<int, E>{});
-        if constexpr (MODE == LM_KIN) {
-            m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), src.args(nxt).scale);
-            pin(m12);
-        }
-        if constexpr (MODE == LM_KERN) {
-            q12 = f.q1 + f.q2;
-            asm volatile("" : "+v"(q12));
-        }
-        tile = nxt;
-    }
-}
-
 // ---------------------------------------------------------------- pipelined EM passes
 // The density and phase passes in the same persistent, prefetching form: a
 // block walks tiles of LINES row pairs; each row's loads for the next tile are
@@ -1993,23 +1750,6 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lmp(LmArgs a)
     const Src1<LmArgs> src{a, a.s0.ntiles + a.s1.ntiles};
     lmp_body<N, E, LINES, MODE, LT, Src1<LmArgs>, B::TW, B::TB>(src, lds, B::TW ? twl : a.tw,
                                                                   B::TB ? kpl : a.kinp, B::TB ? k2l : a.k2_p, sh);
-}
-
-// Wave-line persistent LM pass (see lmw_body).
-template <int N, int E, int LINES, int MODE>
-__global__ __launch_bounds__(LINES *(N / E)) void k_lmw(LmArgs a)
-{
-    using B = LmwLds<N, E, LINES, MODE>;
-    static_assert(B::FITS, "the two tile buffers exceed the LDS of a CU");
-    __shared__ float2 bufA[LINES * LwLayout<N>::PITCH];
-    __shared__ float2 bufB[LINES * LwLayout<N>::PITCH];
-    __shared__ double2 twl[B::TW ? N : 1];
-    __shared__ double2 kpl[MODE == LM_KIN && B::TB ? N : 1];
-    __shared__ double k2l[MODE == LM_KERN && B::TB ? N : 1];
-    __shared__ double sh[LINES * (N / E) / 64 + 1];
-    const Src1<LmArgs> src{a, a.s0.ntiles + a.s1.ntiles};
-    lmw_body<N, E, LINES, MODE, Src1<LmArgs>, B::TW, B::TB>(src, bufA, bufB, B::TW ? twl : a.tw,
-                                                            B::TB ? kpl : a.kinp, B::TB ? k2l : a.k2_p, sh);
 }
 
 template <int N, int E, int LINES, int S>

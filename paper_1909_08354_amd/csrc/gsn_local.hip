@@ -61,8 +61,7 @@ template <int N> static const LKernels *local_table(int v)
     static const LKernels k[5] = {make_local_kernels<N, 0>(), make_local_kernels<N, 1>(),
                                   make_local_kernels<N, 2>(), make_local_kernels<N, 3>(),
                                   make_local_kernels<N, 4>()};
-    // w16 / w8 use the tiles and local-term kernels of p16 / p8
-    return &k[v == 5 ? 2 : v == 6 ? 3 : v];
+    return &k[v];
 }
 
 // Fields of the non-minimal coupling on a grid (see nmc_point): one thread

@@ -82,7 +82,7 @@ def test_gsn3d_256_matches_oracle_after_1000_steps():
     assert abs(e["kinetic"] - eo["kinetic"]) < 1e-6 * scale
 
 
-@pytest.mark.parametrize("schedule", ["autotuned", "p16", "p8", "w16", "w8"])
+@pytest.mark.parametrize("schedule", ["autotuned", "p16", "p8"])
 def test_gsn3d_512_matches_oracle_after_20_steps(schedule):
     """The 512^3 multi-body workload from the stored 20-step oracle result:
     the autotuned schedule (what the benchmark times) and each persistent

@@ -105,12 +105,12 @@ def test_plane_wave_global_phase(n, g):
 
 SHAPES = [(8, 8), (16, 64), (64, 16), (32, 128), (256, 8), (8, 256), (8, 2048), (2048, 8),
           (8, 8, 8), (16, 8, 32), (32, 16, 8), (8, 32, 64), (64, 32, 16), (16, 16, 1024),
-          # strided lines of 512 and 1024 points (the wave-line passes' longest lines)
+          # strided lines of 512 and 1024 points
           (512, 32), (1024, 64), (512, 16, 32)]
 
 
 @pytest.mark.parametrize("variant,mode", [(0, 0), (1, 0), (0, 1), (1, 1), (2, 0), (3, 0), (2, 1), (3, 1),
-                                          (4, 0), (4, 1), (5, 0), (6, 0), (5, 1), (6, 1)])
+                                          (4, 0), (4, 1)])
 @pytest.mark.parametrize("n", SHAPES)
 def test_parity_shapes(n, variant, mode):
     say("parity", n, "variant", variant, "mode", mode)
