@@ -95,6 +95,11 @@ def measured_leg_traffic(workload, kernel_pass, variant):
     return legs.get(workload, {}).get(kernel_pass, {}).get(variant)
 
 
+def progress(msg):
+    """One line on stderr as each leg ends (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo) and logical CPU count."""
     name = None
@@ -139,6 +144,7 @@ def cpu_baseline(legs):
             rate = oracle_step_rate(w, psi, nt)
             runs.append({"workload": name, "threads": nt, "value": rate,
                          "unit": "grid-pt updates/s", "seconds": time.perf_counter() - t0})
+            progress(f"oracle {name} with {nt} threads: {rate:.3e} grid-pt updates/s")
     head = runs[0]
     out.update({"value": head["value"], "unit": "grid-pt updates/s", "cores": head["threads"],
                 "kind": "oracle",
@@ -219,47 +225,63 @@ def single_grid_leg(name, psi0, steps, warmup, autotune_iters, profile_steps, tr
 
 def batch_bench(steps, autotune_iters=0):
     """The 64-instance sweep (256^2/512^2/1024^2, per-instance Yukawa couplings):
-    one gsn_batch_step graph launch vs the same instances run one after another
-    through gsn_step, with the batch's schedule (bit-identical results) and with
-    each shape's autotuned schedule."""
+    one gsn_batch_step graph launch, with the schedule gsn_batch_autotune picks
+    per shape group, vs the same instances run one after another through
+    gsn_step (a) with each group's batch schedule (bit-identical results,
+    checked on one instance per shape) and (b) with each shape's own
+    single-grid autotuned schedule."""
     import torch
     from paper_1909_08354_amd import gsn, inputs
     w = inputs.WORKLOADS["gsn2d_batch64_sweep"]
     inst = inputs.batch_sweep(w["count"], w["seed"], w["sizes"])
     total_pts = sum(int(np.prod(d["n"])) for d in inst)
     b = gsn.Batch([d["n"] for d in inst], [d["L"] for d in inst])
-    for i, d in enumerate(inst):
-        b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+
+    def reset():
+        for i, d in enumerate(inst):
+            b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+
+    reset()
     m0 = b.masses()
+    t_tune = 0.0
+    if autotune_iters > 0:
+        t0 = time.perf_counter()
+        b.autotune(autotune_iters)
+        t_tune = time.perf_counter() - t0
+    names = gsn.variant_names()
+    scheds = {}
+    for i, d in enumerate(inst):
+        if d["n"] not in scheds:
+            v, m = b.schedule(i)
+            scheds[d["n"]] = (v, m)
     b.step(steps)            # captures and instantiates the graph
     b.sync()
-    for i, d in enumerate(inst):
-        b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+    reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(steps)
     b.sync()
     t_batch = time.perf_counter() - t0
     drift = float(np.max(np.abs(b.masses() / m0 - 1)))
+    first = {}
+    for i, d in enumerate(inst):
+        first.setdefault(d["n"], i)
+    batch_out = {n: b.get(i, np.complex64) for n, i in first.items()}
     t_pers = None
     if all(256 <= n[0] <= 1024 and 256 <= n[1] <= 1024 for n in (d["n"] for d in inst)):
         b.set_mode(1)
-        for i, d in enumerate(inst):
-            b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+        reset()
         b.step(2)
         b.sync()
-        for i, d in enumerate(inst):
-            b.set(i, d["kern"], d["a"], d["g"], d["dz"], inputs.to_c64(d["psi"]))
+        reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.step(steps)
         b.sync()
         t_pers = time.perf_counter() - t0
-    # the plain form: every instance through gsn_step, (a) with the batch's own
-    # schedule (the batch default: persistent kinetic/kernel p16, density/phase
-    # p8, x entry/exit e16, stored real-space psi), bit-identical results;
-    # (b) with each shape's own autotuned schedule
-    fam = {"kinetic": 2, "x_density": 3, "kernel": 2, "x_phase": 3}
+        b.set_mode(0)
+    # family order of the batch schedule: kinetic, density, kernel, phase, x entry/exit
+    fam_pass = (("kinetic",), ("x_density",), ("kernel",), ("x_phase",), ("x_entry_fft", "x_exit_ifft"))
 
     def make_grids(tuned):
         out, sched = [], {}
@@ -268,17 +290,22 @@ def batch_bench(steps, autotune_iters=0):
             g.set_kernel(*d["kern"])
             g.set_coefficients(d["a"], d["g"], d["dz"])
             g.set_psi(inputs.to_c64(d["psi"]))
+            pn = g.pass_names()
             if not tuned:
-                g.set_schedule([fam.get(nm, 0) for nm in g.pass_names()])
-                g.set_nonlinear_mode(1)
+                v, m = scheds[d["n"]]
+                sv = [0] * len(pn)
+                for fv, passes in zip(v, fam_pass):
+                    for nm in passes:
+                        sv[pn.index(nm)] = fv
+                g.set_schedule(sv)
+                g.set_nonlinear_mode(m)
             elif d["n"] not in sched:
                 g.autotune(5)
                 sched[d["n"]] = (g.schedule(), g.nonlinear_mode())
             else:
-                names = g.pass_names()
-                vn = {nm: v for v, nm in enumerate(gsn.variant_names())}
+                vn = {nm: v for v, nm in enumerate(names)}
                 s0, m = sched[d["n"]]
-                g.set_schedule([vn[s0[nm]] for nm in names])
+                g.set_schedule([vn[s0[nm]] for nm in pn])
                 g.set_nonlinear_mode(m)
             out.append(g)
         return out
@@ -294,19 +321,36 @@ def batch_bench(steps, autotune_iters=0):
 
     grids = make_grids(False)
     t_seq = time_seq(grids)
+    # the first instance of every shape again, from its initial state: equal
+    # bits to the batch run
+    same = True
+    for n, i in first.items():
+        d = inst[i]
+        grids[i].set_psi(inputs.to_c64(d["psi"]))
+        grids[i].step(steps)
+        same = same and bool(np.array_equal(grids[i].get_psi(np.complex64), batch_out[n]))
     del grids
     grids = make_grids(True)
     t_tuned = time_seq(grids)
     del grids
+    model_bytes = 56.0 * total_pts * steps
     return {"workload": "gsn2d_batch64_sweep", "instances": len(inst), "steps": steps,
             "grid_points": total_pts, "value": total_pts * steps / t_batch,
             "unit": "grid-pt updates/s", "ms_batch_graph": 1e3 * t_batch,
+            "model_bytes_per_point": 56.0,
+            "model_hbm_frac": model_bytes / t_batch / 1e9 / HBM_PEAK_GBPS,
+            "autotune_iters": autotune_iters, "autotune_s": t_tune,
+            "schedules": {"%dx%d" % n: {"families": dict(zip(("kinetic", "x_density", "kernel", "x_phase",
+                                                                "x_fft"), [names[x] for x in v])),
+                                          "nonlinear_mode": m} for n, (v, m) in scheds.items()},
             "ms_sequential_gsn_step": 1e3 * t_seq, "speedup": t_seq / t_batch,
             "ms_sequential_autotuned": 1e3 * t_tuned, "speedup_vs_autotuned": t_tuned / t_batch,
             "ms_batch_persistent": None if t_pers is None else 1e3 * t_pers,
             "speedup_persistent": None if t_pers is None else t_seq / t_pers,
             "max_norm_drift": drift,
-            "accuracy": "bit-identical to the sequential runs (same kernels and schedule)"}
+            "bit_identical_to_sequential": same,
+            "accuracy": "bit-identical to the sequential runs with the same schedule (checked on the "
+                        "first instance of every shape)"}
 
 
 def corrector_bench(ntrain, epochs, neval, ncoarse, tol):
@@ -504,8 +548,10 @@ def main():
         w = inputs.WORKLOADS[WORKLOAD]
         head_name, head_steps = WORKLOAD, args.steps
         head_psi = inputs.lumps_3d(w["n"], w["seed"], 8, dtype=np.complex64)
+    progress(f"{head_name}: state built")
     head = single_grid_leg(head_name, head_psi, head_steps, args.warmup, args.autotune_iters,
                            args.profile_steps)
+    progress(f"{head_name}: {head['ms_per_step']:.4f} ms/step")
     w = inputs.WORKLOADS[head_name]
     line = {
         "metric": "split-step grid-pt updates/s + %HBM peak; batched/corrected speedup at fixed err",
@@ -538,19 +584,24 @@ def main():
     if args.steps_256 > 0 and not args.only_256:
         line["single_256"] = single_grid_leg(WORKLOAD_256, psi256, args.steps_256, args.warmup,
                                              args.autotune_iters, args.profile_steps)
+        progress("256^3 leg done")
     if args.fp64_steps > 0:
         line["fp64"] = fp64_bench(args.fp64_steps, min(args.autotune_iters, 5), args.profile_steps)
+        progress("FP64-storage leg done")
     if args.eq15_steps > 0:
         line["eq15"] = eq15_bench(args.eq15_steps, min(args.autotune_iters, 5), args.profile_steps)
         line["nmc"] = eq15_bench(args.eq15_steps, min(args.autotune_iters, 5), args.profile_steps,
                                  "gsn3d_256_nmc")
+        progress("Eq. (15) legs done")
     if args.batch_steps > 0:
         line["batched"] = batch_bench(args.batch_steps, args.batch_autotune_iters)
         line["batched_speedup"] = line["batched"]["speedup"]
+        progress("batched leg done")
     if args.corrector_train > 0:
         line["corrected"] = corrector_bench(args.corrector_train, args.corrector_epochs,
                                             args.corrector_eval, 10, 1e-4)
         line["corrected_speedup"] = line["corrected"]["speedup"]
+        progress("corrector leg done")
     if not args.no_cpu_baseline:
         legs = []
         if not args.only_256:

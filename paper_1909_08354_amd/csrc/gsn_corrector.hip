@@ -315,6 +315,253 @@ __global__ __launch_bounds__(256) void k_conv1_t(const u16 *__restrict__ X, cons
     }
 }
 
+// ---------------------------------------------------------------- fused inference
+// The four layers of one corrected step on a 4 x 64 output tile in one
+// kernel: every layer computes the region the next one reads (a halo of 4
+// pixels for the first, 3, 2, 1 after it), so the hidden activations stay in
+// LDS and HBM sees only (psi, phi) in and psi out: 20 bytes per pixel
+// instead of 4 layers' NHWC round trips.  Per pixel the arithmetic is that
+// of k_conv1_t / k_conv_fwd_t / the last layer's APPLY (same MFMA sequence,
+// same bf16 roundings), so results equal the layer-by-layer path.  The
+// output goes to psi_out (other blocks still read psi for their halos).
+// Layout (coordinates relative to the tile origin y0, x0): features at rows
+// -4 .. 7 and columns -4 .. 79; layer l's activations at rows -(4 - l) ..
+// 3 + (4 - l) and columns -(4 - l) .. 75 + (4 - l) (5 M-tiles of 16 per
+// row; a 3 x 3 window at the right edge of a row reads two pixels of the next
+// row, or of the next buffer after the last row, and the columns past
+// 67 - l it reaches feed only outputs that are never used).  The weights of
+// all four layers sit in LDS for the block's lifetime (persistent blocks walk
+// the tiles), each wave runs two M-tiles at a time, and the next tile's
+// (psi, phi) halo is loaded into registers while the current tile is
+// computed.  Activation pixels are 80 bytes apart (64 bytes of channels and
+// 16 of padding): the 16-byte operand reads of 8 consecutive pixels then hit
+// 8 different bank groups, and the 9 taps of a window are fixed offsets from
+// one address.  The features and the last layer's outputs share the layer-2
+// buffer, which is free while they are live.
+constexpr int kFusedThreads = 512;
+constexpr int kFRows = kTH + 8, kFCols = kTW + 20;   // 12 x 84 feature pixels
+constexpr int kACols = kTW + 16;                     // 80 activation columns
+constexpr int kPixU = 5;                             // 16-byte units per activation pixel
+constexpr int kMT = 5;                               // M-tiles per row, layers 1-3
+constexpr int kFSlots = (kFRows * kFCols + kFusedThreads - 1) / kFusedThreads;   // halo pixels per thread
+constexpr int kW1 = 9 * 32 * 4, kW23 = 9 * 32 * 32, kW4 = 9 * 16 * 32;          // bf16 weights per layer
+
+__device__ inline int wrapmod(int v, int n) { v %= n; return v < 0 ? v + n : v; }
+
+constexpr int kActU1 = (kTH + 6) * kACols * kPixU, kActU2 = (kTH + 4) * kACols * kPixU;   // 16-byte units
+
+// The weights' 64-byte rows (tap, output channel) in LDS: chunk c of row p
+// sits at slot c ^ ((p >> 1) & 3), so the 16-byte reads of 16 consecutive
+// rows spread over the LDS banks.
+__device__ inline int w_slot(int p, int c) { return p * 4 + (c ^ ((p >> 1) & 3)); }
+// 8-byte group g (channels 4g .. 4g + 3) of activation pixel p
+__device__ inline int act_u2(int p, int g) { return p * (2 * kPixU) + g; }
+
+// LDS barrier that leaves global loads in flight (the next tile's prefetch)
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// max(acc + b, 0) of 4 values to 4 bf16 (round to nearest even; the same
+// rounding as f2bf), packed into 8 bytes
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+__device__ inline uint2 relu_bf16x4(f32x4 acc, const float (&b)[4])
+{
+    const f32x2v lo = {fmaxf(acc[0] + b[0], 0.f), fmaxf(acc[1] + b[1], 0.f)};
+    const f32x2v hi = {fmaxf(acc[2] + b[2], 0.f), fmaxf(acc[3] + b[3], 0.f)};
+    return make_uint2(__builtin_bit_cast(unsigned, __builtin_convertvector(lo, bf16x2v)),
+                      __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bf16x2v)));
+}
+
+// One hidden layer (32 -> 32, ReLU): ROWS x kMT M-tiles of the output region
+// from the input region one row and column further out; two M-tiles (mt and
+// mt + 8) per wave at a time.
+template <int ROWS>
+__device__ inline void fused_hidden(const u32x4v *__restrict__ in, uint2 *__restrict__ out, const u16 *Ws,
+                                    const float *__restrict__ bias, int wave, int i16, int q)
+{
+    constexpr int NW = kFusedThreads / 64, NMT = ROWS * kMT;
+    bf16x8 wb[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+            wb[t][nb] = __builtin_bit_cast(bf16x8, ((const u32x4v *)Ws)[w_slot(t * 32 + nb * 16 + i16, q)]);
+    // D^T = W X^T: lane (i16, q) ends with pixel i16 of the M-tile and the 4
+    // channels nb*16 + 4q .. +3, stored together as 8 bytes
+    float bch[2][4];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) bch[nb][rr] = bias[nb * 16 + 4 * q + rr];
+    for (int mt0 = wave; mt0 < NMT; mt0 += 2 * NW) {
+        const bool two = mt0 + NW < NMT;
+        int base[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int mt = (u == 0 || two) ? mt0 + u * NW : mt0;
+            const int r = mt / kMT, m = mt - r * kMT;
+            base[u] = r * kACols + m * 16 + i16;
+        }
+        f32x4 acc[2][2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[u][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int off = (t / 3) * kACols + t % 3;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const bf16x8 av = __builtin_bit_cast(bf16x8, in[(base[u] + off) * kPixU + q]);
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+                    acc[u][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[t][nb], av, acc[u][nb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !two) break;
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+                out[act_u2(base[u], nb * 4 + q)] = relu_bf16x4(acc[u][nb], bch[nb]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFusedThreads) void k_corr_fused(
+    const float2 *__restrict__ psi, const float *__restrict__ phi, float2 *__restrict__ psi_out, float s0, float s1,
+    float s2, float s_out, const u16 *__restrict__ W1, const u16 *__restrict__ W2, const u16 *__restrict__ W3,
+    const u16 *__restrict__ W4, const float *__restrict__ b1, const float *__restrict__ b2,
+    const float *__restrict__ b3, const float *__restrict__ b4, int H, int W, int ntiles, const double *theta)
+{
+    typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
+    // one LDS array: layer 1 / layer 3 activations, layer 2 activations (the
+    // features, 4 bf16 per pixel, at its start; the last layer's outputs at
+    // 8 KiB), the weights
+    static_assert(kFRows * kFCols * 8 <= 8192 && 8192 + kTH * kTW * 8 <= kActU2 * 16, "layer-2 buffer overlays");
+    __shared__ u32x4v lds[kActU1 + kActU2 + (kW1 + 2 * kW23 + kW4) / 8];
+    u32x4v *const act1 = lds, *const act2 = lds + kActU1, *const wsh = act2 + kActU2;
+    u32x2v *const fin = (u32x2v *)act2;
+    float2 *const res = (float2 *)((char *)act2 + 8192);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i16 = lane & 15, q = lane >> 4;
+    const u32x2v zero2 = {0u, 0u};
+    const float2 e = phase_of(theta);
+    const int tx = W / kTW;
+    u16 *const Ws1 = (u16 *)wsh, *const Ws2 = Ws1 + kW1, *const Ws3 = Ws2 + kW23, *const Ws4 = Ws3 + kW23;
+    {
+        const u32x4v *src[4] = {(const u32x4v *)W1, (const u32x4v *)W2, (const u32x4v *)W3, (const u32x4v *)W4};
+        u32x4v *dst[4] = {(u32x4v *)Ws1, (u32x4v *)Ws2, (u32x4v *)Ws3, (u32x4v *)Ws4};
+        const int n16[4] = {kW1 / 8, kW23 / 8, kW23 / 8, kW4 / 8};
+        for (int i = tid; i < n16[0]; i += kFusedThreads) dst[0][i] = src[0][i];
+        for (int l = 1; l < 4; ++l)   // 64-byte rows (tap, output channel), swizzled like the activations
+            for (int i = tid; i < n16[l]; i += kFusedThreads) dst[l][w_slot(i >> 2, i & 3)] = src[l][i];
+    }
+    // the (psi, phi) halo of a tile: this thread's pixels c = tid + slot * threads
+    float2 fp[kFSlots];
+    float ff[kFSlots];
+    float2 pc = make_float2(0.f, 0.f);   // psi at this thread's output pixel (tid < 256)
+    auto fetch = [&](int t) {
+        const int y0 = (t / tx) * kTH, x0 = (t % tx) * kTW;
+#pragma unroll
+        for (int sl = 0; sl < kFSlots; ++sl) {
+            const int c = tid + sl * kFusedThreads;
+            if (c < kFRows * kFCols) {
+                const int rr = c / kFCols, cc = c - rr * kFCols;
+                const long long pix = (long long)wrapmod(y0 - 4 + rr, H) * W + wrapmod(x0 - 4 + cc, W);
+                fp[sl] = psi[pix];
+                ff[sl] = phi[pix];
+            }
+        }
+        if (tid < kTH * kTW) pc = psi[(long long)(y0 + tid / kTW) * W + x0 + tid % kTW];
+    };
+    int tile = blockIdx.x;
+    if (tile < ntiles) fetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int y0 = (tile / tx) * kTH, x0 = (tile % tx) * kTW;
+        // this tile's features to LDS (the previous tile's layer 1 is done with fin)
+#pragma unroll
+        for (int sl = 0; sl < kFSlots; ++sl) {
+            const int c = tid + sl * kFusedThreads;
+            if (c < kFRows * kFCols) {
+                const float2 v = rot(fp[sl], e);
+                fin[c] = u32x2v{(unsigned)f2bf(v.x * s0) | ((unsigned)f2bf(v.y * s1) << 16), (unsigned)f2bf(ff[sl] * s2)};
+            }
+        }
+        const float2 pcur = pc;
+        lds_barrier();
+        if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);   // lands while this tile computes
+        // layer 1 (3 -> 32, ReLU): K = 9 taps x 4 channels in two chunks,
+        // taps 2q and 2q + 1 in the first, tap 8 (q = 0) in the second
+        {
+            bf16x8 wb[2][2];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const int co = nb * 16 + i16;
+                const u32x2v lo = *(const u32x2v *)(Ws1 + ((2 * q) * 32 + co) * 4);
+                const u32x2v hi = *(const u32x2v *)(Ws1 + ((2 * q + 1) * 32 + co) * 4);
+                wb[0][nb] = __builtin_bit_cast(bf16x8, u32x4v{lo.x, lo.y, hi.x, hi.y});
+                const u32x2v l8 = q == 0 ? *(const u32x2v *)(Ws1 + (8 * 32 + co) * 4) : zero2;
+                wb[1][nb] = __builtin_bit_cast(bf16x8, u32x4v{l8.x, l8.y, 0u, 0u});
+            }
+            float bch[2][4];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) bch[nb][rr] = b1[nb * 16 + 4 * q + rr];
+            const int t0 = 2 * q, t1 = 2 * q + 1;
+            uint2 *const out = (uint2 *)act1;
+            for (int mt = wave; mt < (kTH + 6) * kMT; mt += kFusedThreads / 64) {
+                const int r = mt / kMT, m = mt - r * kMT, col = m * 16 + i16;
+                const u32x2v a0 = fin[(r + t0 / 3) * kFCols + col + t0 % 3];
+                const u32x2v a1 = fin[(r + t1 / 3) * kFCols + col + t1 % 3];
+                const u32x2v a8 = q == 0 ? fin[(r + 2) * kFCols + col + 2] : zero2;
+                const bf16x8 av0 = __builtin_bit_cast(bf16x8, u32x4v{a0.x, a0.y, a1.x, a1.y});
+                const bf16x8 av1 = __builtin_bit_cast(bf16x8, u32x4v{a8.x, a8.y, 0u, 0u});
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) {
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[0][nb], av0, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[1][nb], av1, acc, 0, 0, 0);
+                    out[act_u2(r * kACols + col, nb * 4 + q)] = relu_bf16x4(acc, bch[nb]);
+                }
+            }
+        }
+        lds_barrier();
+        fused_hidden<kTH + 4>(act1, (uint2 *)act2, Ws2, b2, wave, i16, q);   // layer 2
+        lds_barrier();
+        fused_hidden<kTH + 2>(act2, (uint2 *)act1, Ws3, b3, wave, i16, q);   // layer 3
+        lds_barrier();
+        // layer 4 (32 -> 2, padded to 16 output channels, no ReLU)
+        {
+            bf16x8 wb[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) wb[t] = __builtin_bit_cast(bf16x8, ((const u32x4v *)Ws4)[w_slot(t * 16 + i16, q)]);
+            // D^T: lanes with q = 0 hold channels 0 .. 3 of pixel i16
+            const float b40 = b4[0], b41 = b4[1];
+            for (int mt = wave; mt < kTH * (kTW / 16); mt += kFusedThreads / 64) {
+                const int r = mt / (kTW / 16), m = mt - r * (kTW / 16);
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    const int dy = t / 3, dx = t % 3;
+                    const bf16x8 av =
+                        __builtin_bit_cast(bf16x8, act1[((r + dy) * kACols + m * 16 + i16 + dx) * kPixU + q]);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[t], av, acc, 0, 0, 0);
+                }
+                if (q == 0) res[r * kTW + m * 16 + i16] = make_float2(acc[0] + b40, acc[1] + b41);
+            }
+        }
+        lds_barrier();
+        // psi_out = psi + s e^{-i theta} (r0 + i r1) for the tile's pixels
+        if (tid < kTH * kTW) {
+            const long long pix = (long long)(y0 + tid / kTW) * W + x0 + tid % kTW;
+            const float2 rv = rot(res[tid], make_float2(e.x, -e.y));
+            psi_out[pix] = make_float2(pcur.x + s_out * rv.x, pcur.y + s_out * rv.y);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- backward data
 // dX[q][ci] = sum_tap sum_co dZ[q - off(tap)][co] W[tap][co][ci], masked by the
 // ReLU of the layer below (Aprev > 0), written as bf16.
@@ -1048,20 +1295,21 @@ gsn_status corrector_correct_inplace(gsn_corrector c, float2 *psi, const float *
     c->stream = s;
     gsn_status st = GSN_OK;
     if (tiled(c)) {
-        // features straight from (psi, phi) into the first layer; the last
-        // layer adds s_out * output to psi (it reads only the third layer's
-        // activations, so writing psi in place is safe)
+        // the four layers fused: features from (psi, phi), the corrected
+        // state into the output buffer (other tiles still read psi for their
+        // halos), then copied back over psi
         HIP_TRY(hipSetDevice(c->device));
         const int ntiles = (int)(c->P / (kTW * kTH));
-        const dim3 tg = tiled_grid(c, ntiles);
-        hipLaunchKernelGGL((k_conv1_t<true>), tg, dim3(256), 0, c->stream, (const u16 *)nullptr, (const float2 *)psi,
-                           phi, c->in_scale[0], c->in_scale[1], c->in_scale[2], c->wf[0], c->bias[0], c->a[0], c->H,
-                           c->W, ntiles, theta);
-        hidden_tiled(c, tg, ntiles);
-        hipLaunchKernelGGL((k_conv_fwd_t<16, 2, false, true, true>), tg, dim3(256), 0, c->stream, c->a[2], c->wf[3],
-                           c->bias[3], (void *)nullptr, c->H, c->W, ntiles, (const float2 *)psi, psi, c->out_scale,
-                           theta);
-        if (hipGetLastError() != hipSuccess) st = fail(GSN_EHIP, "corrector inference launch failed");
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
+            cus = 256;
+        float2 *tmp = (float2 *)c->out;   // 8 bytes per pixel, unused by inference
+        hipLaunchKernelGGL(k_corr_fused, dim3((unsigned)std::min(ntiles, cus)), dim3(kFusedThreads), 0, c->stream,
+                           (const float2 *)psi, phi, tmp, c->in_scale[0], c->in_scale[1], c->in_scale[2],
+                           c->out_scale, c->wf[0], c->wf[1], c->wf[2], c->wf[3], c->bias[0], c->bias[1], c->bias[2],
+                           c->bias[3], c->H, c->W, ntiles, theta);
+        if (hipGetLastError() != hipSuccess) return fail(GSN_EHIP, "corrector inference launch failed");
+        HIP_TRY(hipMemcpyAsync(psi, tmp, 8ull * c->P, hipMemcpyDeviceToDevice, c->stream));
     } else {
         HIP_TRY(hipSetDevice(c->device));
         hipLaunchKernelGGL(k_pack, dim3(512), dim3(256), 0, c->stream, (const float2 *)psi, phi, c->x0, c->P,
