@@ -316,39 +316,49 @@ __global__ __launch_bounds__(256) void k_conv1_t(const u16 *__restrict__ X, cons
 }
 
 // ---------------------------------------------------------------- fused inference
-// The four layers of one corrected step on a 4 x 64 output tile in one
-// kernel: every layer computes the region the next one reads (a halo of 4
-// pixels for the first, 3, 2, 1 after it), so the hidden activations stay in
-// LDS and HBM sees only (psi, phi) in and psi out: 20 bytes per pixel
+// The four layers of one corrected step in one kernel.  A block owns a
+// segment of S output tiles (4 x 64 pixels each) stacked down one 64-column
+// strip and walks it top to bottom.  Each layer keeps its last six rows in
+// an LDS ring, so a step of 4 output rows computes 4 new rows per layer and
+// reuses the two rows it shares with the step above.  With rows counted from
+// the segment's first row, a warm-up fills the rings (features -4 .. 3,
+// layer 1 -3 .. 2, layer 2 -2 .. 1, layer 3 -1 .. 0); step k then adds
+// feature rows 4k+4 .. 4k+7, layer-1 rows 4k+3 .. 4k+6, layer-2 rows
+// 4k+2 .. 4k+5 and layer-3 rows 4k+1 .. 4k+4, and writes output rows
+// 4k .. 4k+3.  HBM sees (psi, phi) in and psi out: about 20 bytes per pixel
 // instead of 4 layers' NHWC round trips.  Per pixel the arithmetic is that
 // of k_conv1_t / k_conv_fwd_t / the last layer's APPLY (same MFMA sequence,
 // same bf16 roundings), so results equal the layer-by-layer path.  The
 // output goes to psi_out (other blocks still read psi for their halos).
-// Layout (coordinates relative to the tile origin y0, x0): features at rows
-// -4 .. 7 and columns -4 .. 79; layer l's activations at rows -(4 - l) ..
-// 3 + (4 - l) and columns -(4 - l) .. 75 + (4 - l) (5 M-tiles of 16 per
-// row; a 3 x 3 window at the right edge of a row reads two pixels of the next
-// row, or of the next buffer after the last row, and the columns past
-// 67 - l it reaches feed only outputs that are never used).  The weights of
-// all four layers sit in LDS for the block's lifetime (persistent blocks walk
-// the tiles), each wave runs two M-tiles at a time, and the next tile's
-// (psi, phi) halo is loaded into registers while the current tile is
-// computed.  Activation pixels are 80 bytes apart (64 bytes of channels and
-// 16 of padding): the 16-byte operand reads of 8 consecutive pixels then hit
-// 8 different bank groups, and the 9 taps of a window are fixed offsets from
-// one address.  The features and the last layer's outputs share the layer-2
-// buffer, which is free while they are live.
+// Columns relative to the strip origin x0: features -4 .. 79, layer l
+// -(4 - l) .. 75 + (4 - l) (5 M-tiles of 16 per row).  A 3 x 3 window at the
+// right edge of a row reads two pixels of the next ring row (of the next
+// buffer after the last one); the columns past 67 - l it reaches feed only
+// outputs that are never used, and ring rows not yet written feed only rows
+// that are rewritten before they are read.  Activation pixels are 80 bytes
+// apart (64 bytes of channels and 16 of padding): the 16-byte operand reads
+// of 8 consecutive pixels hit 8 different bank groups, and the taps of one
+// window row are fixed offsets from one address.  The weights sit in LDS for
+// the block's lifetime (the last layer's only for its two live output
+// channels), each wave runs two M-tiles at a time, and the next step's
+// feature rows are loaded into registers while the current step computes.
 constexpr int kFusedThreads = 512;
-constexpr int kFRows = kTH + 8, kFCols = kTW + 20;   // 12 x 84 feature pixels
+constexpr int kRing = 6, kFRing = 8;                 // activation / feature rows kept
+constexpr int kFCols = kTW + 20;                     // 84 feature columns
 constexpr int kACols = kTW + 16;                     // 80 activation columns
 constexpr int kPixU = 5;                             // 16-byte units per activation pixel
 constexpr int kMT = 5;                               // M-tiles per row, layers 1-3
-constexpr int kFSlots = (kFRows * kFCols + kFusedThreads - 1) / kFusedThreads;   // halo pixels per thread
-constexpr int kW1 = 9 * 32 * 4, kW23 = 9 * 32 * 32, kW4 = 9 * 16 * 32;          // bf16 weights per layer
+constexpr int kRingU = kRing * kACols * kPixU;       // 16-byte units per activation ring
+constexpr int kW1 = 9 * 32 * 4, kW23 = 9 * 32 * 32, kW4L = 9 * 2 * 32;   // bf16 weights in LDS per layer
+constexpr int kFNew = 4 * kFCols;                    // feature pixels per step
+constexpr int kLdsU = 3 * kRingU + (kW1 + 2 * kW23 + kW4L) / 8 + kFRing * kFCols / 2 + kTH * kTW / 2;
+static_assert(kLdsU * 16 <= 163840, "fused inference LDS");
+static_assert(kFNew <= kFusedThreads && kTH * kTW <= kFusedThreads, "one feature / output pixel per thread");
 
 __device__ inline int wrapmod(int v, int n) { v %= n; return v < 0 ? v + n : v; }
-
-constexpr int kActU1 = (kTH + 6) * kACols * kPixU, kActU2 = (kTH + 4) * kACols * kPixU;   // 16-byte units
+// ring slots of row r (r >= -24)
+__device__ inline int rslot(int r) { return (r + 4 * kRing) % kRing; }
+__device__ inline int fslot(int r) { return (r + 3 * kFRing) & (kFRing - 1); }
 
 // The weights' 64-byte rows (tap, output channel) in LDS: chunk c of row p
 // sits at slot c ^ ((p >> 1) & 3), so the 16-byte reads of 16 consecutive
@@ -357,7 +367,7 @@ __device__ inline int w_slot(int p, int c) { return p * 4 + (c ^ ((p >> 1) & 3))
 // 8-byte group g (channels 4g .. 4g + 3) of activation pixel p
 __device__ inline int act_u2(int p, int g) { return p * (2 * kPixU) + g; }
 
-// LDS barrier that leaves global loads in flight (the next tile's prefetch)
+// LDS barrier that leaves global loads in flight (the next step's prefetch)
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // max(acc + b, 0) of 4 values to 4 bf16 (round to nearest even; the same
@@ -372,14 +382,14 @@ __device__ inline uint2 relu_bf16x4(f32x4 acc, const float (&b)[4])
                       __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bf16x2v)));
 }
 
-// One hidden layer (32 -> 32, ReLU): ROWS x kMT M-tiles of the output region
-// from the input region one row and column further out; two M-tiles (mt and
-// mt + 8) per wave at a time.
-template <int ROWS>
-__device__ inline void fused_hidden(const u32x4v *__restrict__ in, uint2 *__restrict__ out, const u16 *Ws,
-                                    const float *__restrict__ bias, int wave, int i16, int q)
+// Rows r0 .. r0 + NROWS - 1 of a hidden layer (32 -> 32, ReLU) from rows
+// r0 - 1 .. r0 + NROWS of the input ring; two M-tiles (mt and mt + 8) per
+// wave at a time.
+template <int NROWS>
+__device__ inline void ring_hidden(const u32x4v *__restrict__ in, uint2 *__restrict__ out, const u16 *Ws,
+                                   const float *__restrict__ bias, int r0, int wave, int i16, int q)
 {
-    constexpr int NW = kFusedThreads / 64, NMT = ROWS * kMT;
+    constexpr int NW = kFusedThreads / 64, NMT = NROWS * kMT;
     bf16x8 wb[9][2];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
@@ -395,12 +405,14 @@ __device__ inline void fused_hidden(const u32x4v *__restrict__ in, uint2 *__rest
         for (int rr = 0; rr < 4; ++rr) bch[nb][rr] = bias[nb * 16 + 4 * q + rr];
     for (int mt0 = wave; mt0 < NMT; mt0 += 2 * NW) {
         const bool two = mt0 + NW < NMT;
-        int base[2];
+        int ib[2][3], ob[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int mt = (u == 0 || two) ? mt0 + u * NW : mt0;
-            const int r = mt / kMT, m = mt - r * kMT;
-            base[u] = r * kACols + m * 16 + i16;
+            const int rr = mt / kMT, px = (mt - rr * kMT) * 16 + i16, r = r0 + rr;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) ib[u][dy] = (rslot(r - 1 + dy) * kACols + px) * kPixU + q;
+            ob[u] = rslot(r) * kACols + px;
         }
         f32x4 acc[2][2];
 #pragma unroll
@@ -409,10 +421,9 @@ __device__ inline void fused_hidden(const u32x4v *__restrict__ in, uint2 *__rest
             for (int nb = 0; nb < 2; ++nb) acc[u][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const int off = (t / 3) * kACols + t % 3;
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const bf16x8 av = __builtin_bit_cast(bf16x8, in[(base[u] + off) * kPixU + q]);
+                const bf16x8 av = __builtin_bit_cast(bf16x8, in[ib[u][t / 3] + (t % 3) * kPixU]);
 #pragma unroll
                 for (int nb = 0; nb < 2; ++nb)
                     acc[u][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[t][nb], av, acc[u][nb], 0, 0, 0);
@@ -422,8 +433,7 @@ __device__ inline void fused_hidden(const u32x4v *__restrict__ in, uint2 *__rest
         for (int u = 0; u < 2; ++u) {
             if (u == 1 && !two) break;
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
-                out[act_u2(base[u], nb * 4 + q)] = relu_bf16x4(acc[u][nb], bch[nb]);
+            for (int nb = 0; nb < 2; ++nb) out[act_u2(ob[u], nb * 4 + q)] = relu_bf16x4(acc[u][nb], bch[nb]);
         }
     }
 }
@@ -432,132 +442,143 @@ __global__ __launch_bounds__(kFusedThreads) void k_corr_fused(
     const float2 *__restrict__ psi, const float *__restrict__ phi, float2 *__restrict__ psi_out, float s0, float s1,
     float s2, float s_out, const u16 *__restrict__ W1, const u16 *__restrict__ W2, const u16 *__restrict__ W3,
     const u16 *__restrict__ W4, const float *__restrict__ b1, const float *__restrict__ b2,
-    const float *__restrict__ b3, const float *__restrict__ b4, int H, int W, int ntiles, const double *theta)
+    const float *__restrict__ b3, const float *__restrict__ b4, int H, int W, int seg, int nseg, const double *theta)
 {
     typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
-    // one LDS array: layer 1 / layer 3 activations, layer 2 activations (the
-    // features, 4 bf16 per pixel, at its start; the last layer's outputs at
-    // 8 KiB), the weights
-    static_assert(kFRows * kFCols * 8 <= 8192 && 8192 + kTH * kTW * 8 <= kActU2 * 16, "layer-2 buffer overlays");
-    __shared__ u32x4v lds[kActU1 + kActU2 + (kW1 + 2 * kW23 + kW4) / 8];
-    u32x4v *const act1 = lds, *const act2 = lds + kActU1, *const wsh = act2 + kActU2;
-    u32x2v *const fin = (u32x2v *)act2;
-    float2 *const res = (float2 *)((char *)act2 + 8192);
+    // one LDS array: the three activation rings, the weights, the feature
+    // ring (4 bf16 per pixel), the last layer's outputs
+    __shared__ u32x4v lds[kLdsU];
+    u32x4v *const ring1 = lds, *const ring2 = ring1 + kRingU, *const ring3 = ring2 + kRingU;
+    u16 *const Ws1 = (u16 *)(ring3 + kRingU), *const Ws2 = Ws1 + kW1, *const Ws3 = Ws2 + kW23, *const Ws4 = Ws3 + kW23;
+    u32x2v *const fin = (u32x2v *)(Ws4 + kW4L);
+    float2 *const res = (float2 *)(fin + kFRing * kFCols);
+    constexpr int NW = kFusedThreads / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i16 = lane & 15, q = lane >> 4;
     const u32x2v zero2 = {0u, 0u};
     const float2 e = phase_of(theta);
     const int tx = W / kTW;
-    u16 *const Ws1 = (u16 *)wsh, *const Ws2 = Ws1 + kW1, *const Ws3 = Ws2 + kW23, *const Ws4 = Ws3 + kW23;
-    {
-        const u32x4v *src[4] = {(const u32x4v *)W1, (const u32x4v *)W2, (const u32x4v *)W3, (const u32x4v *)W4};
-        u32x4v *dst[4] = {(u32x4v *)Ws1, (u32x4v *)Ws2, (u32x4v *)Ws3, (u32x4v *)Ws4};
-        const int n16[4] = {kW1 / 8, kW23 / 8, kW23 / 8, kW4 / 8};
-        for (int i = tid; i < n16[0]; i += kFusedThreads) dst[0][i] = src[0][i];
-        for (int l = 1; l < 4; ++l)   // 64-byte rows (tap, output channel), swizzled like the activations
-            for (int i = tid; i < n16[l]; i += kFusedThreads) dst[l][w_slot(i >> 2, i & 3)] = src[l][i];
+    for (int i = tid; i < kW1 / 8; i += kFusedThreads) ((u32x4v *)Ws1)[i] = ((const u32x4v *)W1)[i];
+    for (int i = tid; i < kW23 / 8; i += kFusedThreads) {   // 64-byte rows (tap, output channel), swizzled
+        ((u32x4v *)Ws2)[w_slot(i >> 2, i & 3)] = ((const u32x4v *)W2)[i];
+        ((u32x4v *)Ws3)[w_slot(i >> 2, i & 3)] = ((const u32x4v *)W3)[i];
     }
-    // the (psi, phi) halo of a tile: this thread's pixels c = tid + slot * threads
-    float2 fp[kFSlots];
-    float ff[kFSlots];
-    float2 pc = make_float2(0.f, 0.f);   // psi at this thread's output pixel (tid < 256)
-    auto fetch = [&](int t) {
-        const int y0 = (t / tx) * kTH, x0 = (t % tx) * kTW;
-#pragma unroll
-        for (int sl = 0; sl < kFSlots; ++sl) {
-            const int c = tid + sl * kFusedThreads;
-            if (c < kFRows * kFCols) {
-                const int rr = c / kFCols, cc = c - rr * kFCols;
-                const long long pix = (long long)wrapmod(y0 - 4 + rr, H) * W + wrapmod(x0 - 4 + cc, W);
-                fp[sl] = psi[pix];
-                ff[sl] = phi[pix];
-            }
+    for (int i = tid; i < kW4L / 8; i += kFusedThreads)     // output channels 0 and 1 of each tap
+        ((u32x4v *)Ws4)[i] = ((const u32x4v *)W4)[((i >> 3) * 16 + ((i >> 2) & 1)) * 4 + (i & 3)];
+
+    // feature rows ra .. ra + 3 of the segment at (Y0, x0): one pixel per
+    // thread, fetched into registers, then rotated, scaled and stored
+    float2 fp = make_float2(0.f, 0.f);
+    float ff = 0.f;
+    auto fetch = [&](int Y0, int x0, int ra) {
+        if (tid < kFNew) {
+            const int rr = tid / kFCols, cc = tid - rr * kFCols;
+            const long long pix = (long long)wrapmod(Y0 + ra + rr, H) * W + wrapmod(x0 - 4 + cc, W);
+            fp = psi[pix];
+            ff = phi[pix];
         }
-        if (tid < kTH * kTW) pc = psi[(long long)(y0 + tid / kTW) * W + x0 + tid % kTW];
     };
-    int tile = blockIdx.x;
-    if (tile < ntiles) fetch(tile);
-    for (; tile < ntiles; tile += gridDim.x) {
-        const int y0 = (tile / tx) * kTH, x0 = (tile % tx) * kTW;
-        // this tile's features to LDS (the previous tile's layer 1 is done with fin)
-#pragma unroll
-        for (int sl = 0; sl < kFSlots; ++sl) {
-            const int c = tid + sl * kFusedThreads;
-            if (c < kFRows * kFCols) {
-                const float2 v = rot(fp[sl], e);
-                fin[c] = u32x2v{(unsigned)f2bf(v.x * s0) | ((unsigned)f2bf(v.y * s1) << 16), (unsigned)f2bf(ff[sl] * s2)};
-            }
+    auto stash = [&](int ra) {
+        if (tid < kFNew) {
+            const int rr = tid / kFCols, cc = tid - rr * kFCols;
+            const float2 v = rot(fp, e);
+            fin[fslot(ra + rr) * kFCols + cc] =
+                u32x2v{(unsigned)f2bf(v.x * s0) | ((unsigned)f2bf(v.y * s1) << 16), (unsigned)f2bf(ff * s2)};
         }
-        const float2 pcur = pc;
-        lds_barrier();
-        if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);   // lands while this tile computes
-        // layer 1 (3 -> 32, ReLU): K = 9 taps x 4 channels in two chunks,
-        // taps 2q and 2q + 1 in the first, tap 8 (q = 0) in the second
-        {
-            bf16x8 wb[2][2];
+    };
+    // layer 1 (3 -> 32, ReLU), rows r0 .. r0 + nrows - 1: K = 9 taps x 4
+    // channels in two chunks, taps 2q and 2q + 1 in the first, tap 8 (q = 0)
+    // in the second; tap t reads feature row r - 1 + t / 3, column col + t % 3
+    auto layer1 = [&](int r0, int nrows) {
+        bf16x8 wb[2][2];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const int co = nb * 16 + i16;
+            const u32x2v lo = *(const u32x2v *)(Ws1 + ((2 * q) * 32 + co) * 4);
+            const u32x2v hi = *(const u32x2v *)(Ws1 + ((2 * q + 1) * 32 + co) * 4);
+            wb[0][nb] = __builtin_bit_cast(bf16x8, u32x4v{lo.x, lo.y, hi.x, hi.y});
+            const u32x2v l8 = q == 0 ? *(const u32x2v *)(Ws1 + (8 * 32 + co) * 4) : zero2;
+            wb[1][nb] = __builtin_bit_cast(bf16x8, u32x4v{l8.x, l8.y, 0u, 0u});
+        }
+        float bch[2][4];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) bch[nb][rr] = b1[nb * 16 + 4 * q + rr];
+        const int t0 = 2 * q, t1 = 2 * q + 1;
+        uint2 *const out = (uint2 *)ring1;
+        for (int mt = wave; mt < nrows * kMT; mt += NW) {
+            const int rr = mt / kMT, col = (mt - rr * kMT) * 16 + i16, r = r0 + rr;
+            const u32x2v a0 = fin[fslot(r - 1 + t0 / 3) * kFCols + col + t0 % 3];
+            const u32x2v a1 = fin[fslot(r - 1 + t1 / 3) * kFCols + col + t1 % 3];
+            const u32x2v a8 = q == 0 ? fin[fslot(r + 1) * kFCols + col + 2] : zero2;
+            const bf16x8 av0 = __builtin_bit_cast(bf16x8, u32x4v{a0.x, a0.y, a1.x, a1.y});
+            const bf16x8 av1 = __builtin_bit_cast(bf16x8, u32x4v{a8.x, a8.y, 0u, 0u});
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
-                const int co = nb * 16 + i16;
-                const u32x2v lo = *(const u32x2v *)(Ws1 + ((2 * q) * 32 + co) * 4);
-                const u32x2v hi = *(const u32x2v *)(Ws1 + ((2 * q + 1) * 32 + co) * 4);
-                wb[0][nb] = __builtin_bit_cast(bf16x8, u32x4v{lo.x, lo.y, hi.x, hi.y});
-                const u32x2v l8 = q == 0 ? *(const u32x2v *)(Ws1 + (8 * 32 + co) * 4) : zero2;
-                wb[1][nb] = __builtin_bit_cast(bf16x8, u32x4v{l8.x, l8.y, 0u, 0u});
-            }
-            float bch[2][4];
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) bch[nb][rr] = b1[nb * 16 + 4 * q + rr];
-            const int t0 = 2 * q, t1 = 2 * q + 1;
-            uint2 *const out = (uint2 *)act1;
-            for (int mt = wave; mt < (kTH + 6) * kMT; mt += kFusedThreads / 64) {
-                const int r = mt / kMT, m = mt - r * kMT, col = m * 16 + i16;
-                const u32x2v a0 = fin[(r + t0 / 3) * kFCols + col + t0 % 3];
-                const u32x2v a1 = fin[(r + t1 / 3) * kFCols + col + t1 % 3];
-                const u32x2v a8 = q == 0 ? fin[(r + 2) * kFCols + col + 2] : zero2;
-                const bf16x8 av0 = __builtin_bit_cast(bf16x8, u32x4v{a0.x, a0.y, a1.x, a1.y});
-                const bf16x8 av1 = __builtin_bit_cast(bf16x8, u32x4v{a8.x, a8.y, 0u, 0u});
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[0][nb], av0, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[1][nb], av1, acc, 0, 0, 0);
-                    out[act_u2(r * kACols + col, nb * 4 + q)] = relu_bf16x4(acc, bch[nb]);
-                }
-            }
-        }
-        lds_barrier();
-        fused_hidden<kTH + 4>(act1, (uint2 *)act2, Ws2, b2, wave, i16, q);   // layer 2
-        lds_barrier();
-        fused_hidden<kTH + 2>(act2, (uint2 *)act1, Ws3, b3, wave, i16, q);   // layer 3
-        lds_barrier();
-        // layer 4 (32 -> 2, padded to 16 output channels, no ReLU)
-        {
-            bf16x8 wb[9];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) wb[t] = __builtin_bit_cast(bf16x8, ((const u32x4v *)Ws4)[w_slot(t * 16 + i16, q)]);
-            // D^T: lanes with q = 0 hold channels 0 .. 3 of pixel i16
-            const float b40 = b4[0], b41 = b4[1];
-            for (int mt = wave; mt < kTH * (kTW / 16); mt += kFusedThreads / 64) {
-                const int r = mt / (kTW / 16), m = mt - r * (kTW / 16);
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int t = 0; t < 9; ++t) {
-                    const int dy = t / 3, dx = t % 3;
-                    const bf16x8 av =
-                        __builtin_bit_cast(bf16x8, act1[((r + dy) * kACols + m * 16 + i16 + dx) * kPixU + q]);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[t], av, acc, 0, 0, 0);
-                }
-                if (q == 0) res[r * kTW + m * 16 + i16] = make_float2(acc[0] + b40, acc[1] + b41);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[0][nb], av0, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[1][nb], av1, acc, 0, 0, 0);
+                out[act_u2(rslot(r) * kACols + col, nb * 4 + q)] = relu_bf16x4(acc, bch[nb]);
             }
         }
+    };
+
+    for (int sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const int Y0 = (sg / tx) * seg * kTH, x0 = (sg % tx) * kTW;
+        // warm-up
+        fetch(Y0, x0, -4);
+        stash(-4);
+        fetch(Y0, x0, 0);
+        stash(0);
+        fetch(Y0, x0, 4);   // step 0's rows land while the warm-up computes
         lds_barrier();
-        // psi_out = psi + s e^{-i theta} (r0 + i r1) for the tile's pixels
-        if (tid < kTH * kTW) {
-            const long long pix = (long long)(y0 + tid / kTW) * W + x0 + tid % kTW;
-            const float2 rv = rot(res[tid], make_float2(e.x, -e.y));
-            psi_out[pix] = make_float2(pcur.x + s_out * rv.x, pcur.y + s_out * rv.y);
+        layer1(-3, 6);
+        lds_barrier();
+        ring_hidden<4>(ring1, (uint2 *)ring2, Ws2, b2, -2, wave, i16, q);
+        lds_barrier();
+        ring_hidden<2>(ring2, (uint2 *)ring3, Ws3, b3, -1, wave, i16, q);
+        for (int k = 0; k < seg; ++k) {
+            // the new feature rows overwrite rows that layer 1 has finished with
+            stash(4 * k + 4);
+            float2 pc = make_float2(0.f, 0.f);   // psi at this thread's output pixel
+            if (tid < kTH * kTW) pc = psi[(long long)(Y0 + 4 * k + tid / kTW) * W + x0 + tid % kTW];
+            lds_barrier();
+            if (k + 1 < seg) fetch(Y0, x0, 4 * k + 8);
+            layer1(4 * k + 3, 4);
+            lds_barrier();
+            ring_hidden<4>(ring1, (uint2 *)ring2, Ws2, b2, 4 * k + 2, wave, i16, q);
+            lds_barrier();
+            ring_hidden<4>(ring2, (uint2 *)ring3, Ws3, b3, 4 * k + 1, wave, i16, q);
+            lds_barrier();
+            // layer 4 (32 -> 2: output channels 0 and 1 of a 16-row A operand,
+            // no ReLU); D^T: lanes with q = 0 hold channels 0 .. 3 of pixel i16
+            {
+                bf16x8 wb[9];
+#pragma unroll
+                for (int t = 0; t < 9; ++t)
+                    wb[t] = i16 < 2 ? __builtin_bit_cast(bf16x8, ((const u32x4v *)Ws4)[(t * 2 + i16) * 4 + q])
+                                    : bf16x8{};
+                const float b40 = b4[0], b41 = b4[1];
+                for (int mt = wave; mt < kTH * (kTW / 16); mt += NW) {
+                    const int rr = mt / (kTW / 16), px = (mt - rr * (kTW / 16)) * 16 + i16, r = 4 * k + rr;
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) {
+                        const bf16x8 av = __builtin_bit_cast(
+                            bf16x8, ring3[(rslot(r - 1 + t / 3) * kACols + px + t % 3) * kPixU + q]);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[t], av, acc, 0, 0, 0);
+                    }
+                    if (q == 0) res[rr * kTW + px] = make_float2(acc[0] + b40, acc[1] + b41);
+                }
+            }
+            lds_barrier();
+            // psi_out = psi + s e^{-i theta} (r0 + i r1) for the step's pixels
+            if (tid < kTH * kTW) {
+                const long long pix = (long long)(Y0 + 4 * k + tid / kTW) * W + x0 + tid % kTW;
+                const float2 rv = rot(res[tid], make_float2(e.x, -e.y));
+                psi_out[pix] = make_float2(pc.x + s_out * rv.x, pc.y + s_out * rv.y);
+            }
         }
     }
 }
@@ -1299,15 +1320,20 @@ gsn_status corrector_correct_inplace(gsn_corrector c, float2 *psi, const float *
         // state into the output buffer (other tiles still read psi for their
         // halos), then copied back over psi
         HIP_TRY(hipSetDevice(c->device));
-        const int ntiles = (int)(c->P / (kTW * kTH));
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
             cus = 256;
+        // segments of seg tiles down a 64-column strip, about one per CU
+        // (longer segments amortise the warm-up, more segments fill the chip)
+        const int th = c->H / kTH, tw = c->W / kTW;
+        int seg = std::max(1, th * tw / cus);
+        while (th % seg) --seg;
+        const int nseg = th / seg * tw;
         float2 *tmp = (float2 *)c->out;   // 8 bytes per pixel, unused by inference
-        hipLaunchKernelGGL(k_corr_fused, dim3((unsigned)std::min(ntiles, cus)), dim3(kFusedThreads), 0, c->stream,
+        hipLaunchKernelGGL(k_corr_fused, dim3((unsigned)std::min(nseg, cus)), dim3(kFusedThreads), 0, c->stream,
                            (const float2 *)psi, phi, tmp, c->in_scale[0], c->in_scale[1], c->in_scale[2],
                            c->out_scale, c->wf[0], c->wf[1], c->wf[2], c->wf[3], c->bias[0], c->bias[1], c->bias[2],
-                           c->bias[3], c->H, c->W, ntiles, theta);
+                           c->bias[3], c->H, c->W, seg, nseg, theta);
         if (hipGetLastError() != hipSuccess) return fail(GSN_EHIP, "corrector inference launch failed");
         HIP_TRY(hipMemcpyAsync(psi, tmp, 8ull * c->P, hipMemcpyDeviceToDevice, c->stream));
     } else {

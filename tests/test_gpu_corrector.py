@@ -235,15 +235,16 @@ def test_corrected_stepping_semantics():
     assert nfb == 0 and np.array_equal(g5.get_psi(np.complex64), g1.get_psi(np.complex64))
 
 
-def test_fused_inference_equals_pack_forward_apply():
+@pytest.mark.parametrize("n", [(64, 128), (512, 512), (2048, 256)])
+def test_fused_inference_equals_pack_forward_apply(n):
     """On tiled shapes the corrected step runs the features, the four layers
-    and the residual update as four kernels (first layer reading psi and phi,
-    last layer updating psi in place); the result equals the step-by-step
-    path (pack, forward, apply) on the same coarse state as the caller reads
-    it (the Yukawa term gives a nonzero global phase, which the network sees
-    applied)."""
+    and the residual update in one kernel whose blocks walk segments of 1
+    (64 x 128), 4 (512^2) or 8 (2048 x 256) tiles down a strip on a 256-CU
+    device; the result equals the step-by-step path (pack, forward, apply) on
+    the same coarse state as the caller reads it (the Yukawa term gives a
+    nonzero global phase, which the network sees applied)."""
     import torch
-    n, L = (64, 128), (64.0, 128.0)
+    L = tuple(float(v) for v in n)
     rng = np.random.default_rng(12)
     cs, ws, vs = inputs.random_lumps(rng, n, L, 2, (4.0, 6.0))
     psi0 = inputs.to_c64(inputs.lumps(n, L, cs, ws, vs))
