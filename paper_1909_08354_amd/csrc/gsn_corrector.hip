@@ -627,6 +627,94 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const u16 *__restrict__ d
     }
 }
 
+// Data gradients of a 32 -> 32 layer on tiled shapes, in the forward
+// kernel's tiling: dX[p][ci] = sum_tap sum_co dZ[p - off(tap)][co]
+// W[tap][co][ci] is a forward convolution of dZ with the taps mirrored and
+// the weights transposed.  D^T = W^T dZ^T: lane (i16, q) ends with pixel i16
+// of an M-tile and the channels nb*16 + 4q .. +3, staged as 8 bytes in LDS;
+// each wave then writes its row of 64 pixels as 16-byte pieces, zeroed where
+// the layer below's ReLU was inactive (Aprev <= 0).  Taps accumulate in the
+// order 0 .. 8, each one K chunk of the 32 output channels.
+__global__ __launch_bounds__(256) void k_conv_bwd_data_t(const u16 *__restrict__ dZ, const u16 *__restrict__ Wb,
+                                                         const u16 *__restrict__ Aprev, u16 *__restrict__ dX,
+                                                         int H, int W, int ntiles)
+{
+    __shared__ u32x4v xin[kHP * kWP * 4];        // dZ halo, 16-byte quarters of 64-byte pixels
+    __shared__ u32x4v yst[4][kTW * 64 / 16];     // per-wave output staging, 64 bytes per pixel
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i16 = lane & 15, q = lane >> 4;
+    // A fragments: rows ci = nb*16 + i16 of W[tap]^T, K = co 8q .. 8q + 7
+    bf16x8 wa[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+            wa[t][nb] = *(const bf16x8 *)(Wb + ((long long)(t * 32 + nb * 16 + i16)) * 32 + 8 * q);
+    const int tx = W / kTW, ty = H / kTH;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int img = tile / (tx * ty), r0 = tile - img * tx * ty;
+        const int y0 = (r0 / tx) * kTH, x0 = (r0 % tx) * kTW;
+        const u16 *Zi = dZ + (long long)img * H * W * 32;
+        __syncthreads();   // the previous tile's readers are done with xin
+        for (int c = tid; c < kHP * kWP * 4; c += 256) {
+            const int pq = c & 3, pix = c >> 2, rr = pix / kWP, cc = pix - rr * kWP;
+            int ys = y0 + rr - 1, xs = x0 + cc - 1;
+            ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+            xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+            xin[c] = *(const u32x4v *)(Zi + ((long long)ys * W + xs) * 32 + pq * 8);
+        }
+        __syncthreads();
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            // dZ at p - off(t): the staged halo at row offset 2 - t/3, column offset 2 - t%3
+            const int dy = 2 - t / 3, dx = 2 - t % 3;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const bf16x8 av = __builtin_bit_cast(bf16x8, xin[((wave + dy) * kWP + m * 16 + i16 + dx) * 4 + q]);
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+                    acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nb], av, acc[m][nb], 0, 0, 0);
+            }
+        }
+        uint2 *ys = (uint2 *)yst[wave];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const f32x2v lo = {acc[m][nb][0], acc[m][nb][1]}, hi = {acc[m][nb][2], acc[m][nb][3]};
+                ys[(m * 16 + i16) * 8 + nb * 4 + q] =
+                    make_uint2(__builtin_bit_cast(unsigned, __builtin_convertvector(lo, bf16x2v)),
+                               __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bf16x2v)));
+            }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // row (y0 + wave), pixels x0 .. x0 + 63: 4 KiB contiguous in dX and Aprev
+        const long long p0 = ((long long)img * H + y0 + wave) * W + x0;
+        const u32x4v *arow = (const u32x4v *)(Aprev + p0 * 32);
+        u32x4v *drow = (u32x4v *)(dX + p0 * 32);
+#pragma unroll
+        for (int c = lane; c < kTW * 64 / 16; c += 64) {
+            const u32x4v a = arow[c];
+            u32x4v v = yst[wave][c];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const unsigned keep = (__uint_as_float(a[w] << 16) > 0.f ? 0xffffu : 0u) |
+                                      (__uint_as_float(a[w] & 0xffff0000u) > 0.f ? 0xffff0000u : 0u);
+                v[w] &= keep;
+            }
+            drow[c] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // ---------------------------------------------------------------- backward weights
 // Per block, over its chunks of 64 flat pixels: dW[tap][co][ci] += dZ^T Xs and
 // db[co] += sum dZ, staged through LDS transposed (channel-major) so every
@@ -1229,7 +1317,12 @@ static gsn_status gradients(gsn_corrector c, int B, float *loss)
                            np);
     hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
                        kBwBlocks, pstride_h, 32, 32, 32, 32, c->grad + offs[2]);
-    hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dza, c->wb[2], c->a[1], c->dzb, H, W, np);
+    if (tl)
+        hipLaunchKernelGGL(k_conv_bwd_data_t, tiled_grid(c, ntl), block, 0, c->stream, c->dza, c->wb[2], c->a[1], c->dzb,
+                           H, W, ntl);
+    else
+        hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dza, c->wb[2], c->a[1], c->dzb, H, W,
+                           np);
     // layer 2
     if (tl)
         hipLaunchKernelGGL((k_conv_bwd_w_t<32, 32>), dim3(kBwBlocks), dim3(512), 0, c->stream, c->a[0], c->dzb, c->part,
@@ -1239,7 +1332,12 @@ static gsn_status gradients(gsn_corrector c, int B, float *loss)
                            np);
     hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
                        kBwBlocks, pstride_h, 32, 32, 32, 32, c->grad + offs[1]);
-    hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dzb, c->wb[1], c->a[0], c->dza, H, W, np);
+    if (tl)
+        hipLaunchKernelGGL(k_conv_bwd_data_t, tiled_grid(c, ntl), block, 0, c->stream, c->dzb, c->wb[1], c->a[0], c->dza,
+                           H, W, ntl);
+    else
+        hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dzb, c->wb[1], c->a[0], c->dza, H, W,
+                           np);
     // layer 1 (3 -> 32, input padded to 4 channels; no data gradient needed)
     if (tl)
         hipLaunchKernelGGL((k_conv_bwd_w_t<4, 32>), dim3(kBwBlocks), dim3(512), 0, c->stream, c->x0, c->dza, c->part, H,

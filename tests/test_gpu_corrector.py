@@ -78,8 +78,10 @@ def test_corrector_forward_matches_oracle(B, H, W):
     assert rel < 2e-3
 
 
-@pytest.mark.parametrize("B,H,W", [(2, 16, 32), (2, 8, 64)])
+@pytest.mark.parametrize("B,H,W", [(2, 16, 32), (2, 8, 64), (1, 64, 128)])
 def test_corrector_gradients_match_oracle(B, H, W):
+    """16 x 32: the one-wave kernels; 8 x 64 and 64 x 128: the tiled weight-
+    and data-gradient kernels (halos wrap across tiles and images)."""
     import torch
     scales = (0.7, 0.7, 0.2)
     c, theta = make(B, H, W, 3, scales)
