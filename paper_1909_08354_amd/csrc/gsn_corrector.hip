@@ -791,105 +791,229 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const u16 *__restrict__ X, c
     if (tid < COUT_P) out[9 * COUT_P * CINN + tid] = dbias;
 }
 
-// Weight gradients on tiled shapes: a block walks tiles of 4 rows x 64
+// Weight gradients on tiled shapes: dW[tap][co][ci] = sum_px dZ[px][co]
+// X[px + off(tap)][ci] and db[co] = sum_px dZ[px][co] as implicit GEMMs with
+// K = pixels on v_mfma_f32_16x16x32_bf16.  A block walks tiles of 4 x 64
 // pixels (fixed tiles per block, fixed order: deterministic partials).  Per
-// tile the 6 x 66 input halo is read once and stored channel-major in LDS in
-// three copies shifted by the tap column (so every 8-pixel run of a tap is an
-// aligned 16-byte read), dZ channel-major beside it, and
-// dW[tap][co][ci] += sum_px dZ[px][co] X[px + off(tap)][ci] runs on
-// v_mfma_f32_16x16x32_bf16 with K = 32 pixels per chunk.
+// tile the 6 x 66 input halo (6 x 72 staged) and the tile's dZ arrive with
+// coalesced 16-byte loads into pixel-major LDS (8 bytes of padding per
+// pixel), then each lane turns 4 pixels x 4 channels around into 4 channel
+// rows with 8-byte reads and writes: channel-major copies whose channel
+// strides (880 and 528 bytes) put the 16-byte operand reads of 16 channels
+// on distinct banks.  K is split over the waves: wave w owns pixels
+// 32w .. 32w + 31 of every tile and accumulates all 9 x MB x NB output
+// blocks.  Per window row one 16-byte read and the 4 bytes after it give the
+// operands of all three tap columns (the shifted ones by a funnel shift),
+// and the bias gradient is one more MFMA against ones.  The next tile's
+// inputs are loaded into registers while the current one is computed; at
+// the end the waves' sums are added in LDS in a fixed order and written as
+// the block's partial.
 template <int CIN_P, int COUT_P>
 __global__ __launch_bounds__(512) void k_conv_bwd_w_t(const u16 *__restrict__ X, const u16 *__restrict__ dZ,
                                                       float *__restrict__ part, int H, int W, int ntiles)
 {
     constexpr int CINN = CIN_P < 16 ? 16 : CIN_P;
-    constexpr int MB = COUT_P / 16, NB = CINN / 16, NBLK = 9 * MB * NB;
-    constexpr int NWAVE = 8, PER_WAVE = (NBLK + NWAVE - 1) / NWAVE;
+    constexpr int MB = COUT_P / 16, NB = CINN / 16;
     constexpr int PSTRIDE = 9 * COUT_P * CINN + COUT_P;
-    constexpr int TPX = kTH * kTW;
-    constexpr int XQ = CIN_P / 4;   // 8-byte pieces (4 channels) per input pixel
+    constexpr int XROW = 72, XCH = kHP * XROW + 8;   // u16: staged halo row (66 used), channel stride
+    constexpr int ZCH = kTH * kTW + 8;               // u16: dZ channel stride
+    constexpr int XPS = CIN_P == 4 ? 4 : CIN_P + 4;  // u16 per pixel, pixel-major halo
+    constexpr int ZPS = COUT_P + 4;                  // u16 per pixel, pixel-major dZ
+    constexpr int XQ = CIN_P / 4, ZQ = COUT_P / 4;   // 4-channel quads per pixel
+    // coalesced loads: 16 bytes (two quads) where a pixel has them
+    constexpr int XLQ = XQ >= 2 ? 2 : 1, XLOADS = kHP * XROW * XQ / XLQ, ZLOADS = kTH * kTW * ZQ / 2;
+    constexpr int XLS = (XLOADS + 511) / 512, ZLS = (ZLOADS + 511) / 512;
+    // turn-around items (quad p, row, 4-pixel group j): 16 lanes = JL groups x PL quads
+    constexpr int XPL = XQ < 4 ? XQ : 4, XJL = 16 / XPL, XJH = (XROW / 4 + XJL - 1) / XJL;
+    constexpr int XT = XQ * kHP * XJH * XJL, XTS = (XT + 511) / 512;
+    constexpr int ZJH = (kTH * kTW / 4) / 4, ZT = ZQ * ZJH * 4, ZTS = (ZT + 511) / 512;
+    constexpr int XRAW = kHP * XROW * XPS, ZRAW = kTH * kTW * ZPS;
+    constexpr int SMU = XRAW + ZRAW + CIN_P * XCH + COUT_P * ZCH;
+    static_assert(SMU * 2 >= 8 * NB * 256 * 4 && SMU * 2 >= 8 * COUT_P * 4, "reduction buffer");
+    static_assert(ZQ % 4 == 0 && (XQ == 1 || XQ % 4 == 0), "quad layouts");
     typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
-    __shared__ __align__(16) u16 xt[3][CIN_P][kHP][kTW];
-    __shared__ __align__(16) u16 dzt[COUT_P][TPX];
+    __shared__ __align__(16) u16 sm[SMU];
+    u16 *const xraw = sm, *const zraw = xraw + XRAW, *const xt = zraw + ZRAW, *const dzt = xt + CIN_P * XCH;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i16 = lane & 15, q = lane >> 4;
-    f32x4 acc[PER_WAVE];
+    f32x4 acc[9][MB][NB], accb[MB];
 #pragma unroll
-    for (int i = 0; i < PER_WAVE; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float dbias = 0.f;
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[t][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) accb[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, u32x4v{0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u});
     const int tx = W / kTW, ty = H / kTH;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // the next tile's inputs in registers: load l of this thread is piece
+    // (l * 512 + tid) of the pixel-major halo / dZ, XLQ or 2 quads each
+    u32x4v xr[XLS], zr[ZLS];
+    auto fetch = [&](int tile) {
         const int img = tile / (tx * ty), r0 = tile - img * tx * ty;
         const int y0 = (r0 / tx) * kTH, x0 = (r0 % tx) * kTW;
         const long long ib = (long long)img * H * W;
-        __syncthreads();   // the previous tile's readers are done
-        for (int it = tid; it < kHP * kWP * XQ; it += 512) {
-            const int piece = it % XQ, pix = it / XQ, rr = pix / kWP, cc = pix - rr * kWP;
-            int ys = y0 + rr - 1, xs = x0 + cc - 1;
-            ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
-            xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
-            const u32x2v v = *(const u32x2v *)(X + (ib + (long long)ys * W + xs) * CIN_P + 4 * piece);
-            const u16 h[4] = {(u16)(v.x & 0xffffu), (u16)(v.x >> 16), (u16)(v.y & 0xffffu), (u16)(v.y >> 16)};
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const int c = cc - dx;
-                if (c >= 0 && c < kTW) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) xt[dx][4 * piece + k][rr][c] = h[k];
+        for (int l = 0; l < XLS; ++l) {
+            const int it = tid + l * 512;
+            if (it < XLOADS) {
+                const int pc = it % (XQ / XLQ), px = (it / (XQ / XLQ)) % XROW, rr = it / (XQ / XLQ * XROW);
+                int ys = y0 + rr - 1, xs = x0 - 1 + px;
+                ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+                xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+                const u16 *src = X + (ib + (long long)ys * W + xs) * CIN_P + 4 * XLQ * pc;
+                if constexpr (XLQ == 2) {
+                    xr[l] = *(const u32x4v *)src;
+                } else {
+                    const u32x2v v = *(const u32x2v *)src;
+                    xr[l] = u32x4v{v.x, v.y, 0u, 0u};
                 }
             }
         }
-        for (int it = tid; it < TPX * (COUT_P / 4); it += 512) {
-            const int piece = it % (COUT_P / 4), px = it / (COUT_P / 4);
-            const int r = px / kTW, c = px - r * kTW;
-            const u32x2v v = *(const u32x2v *)(dZ + (ib + (long long)(y0 + r) * W + x0 + c) * COUT_P + 4 * piece);
-            dzt[4 * piece + 0][px] = (u16)(v.x & 0xffffu);
-            dzt[4 * piece + 1][px] = (u16)(v.x >> 16);
-            dzt[4 * piece + 2][px] = (u16)(v.y & 0xffffu);
-            dzt[4 * piece + 3][px] = (u16)(v.y >> 16);
-        }
-        __syncthreads();
-        if (tid < COUT_P) {
-            float sb = 0.f;
-            for (int px = 0; px < TPX; px += 8) {
-                const u32x4v w = *(const u32x4v *)&dzt[tid][px];
-                const unsigned u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-                for (int k = 0; k < 4; ++k) sb += bf2f((u16)(u[k] & 0xffffu)) + bf2f((u16)(u[k] >> 16));
+        for (int l = 0; l < ZLS; ++l) {
+            const int it = tid + l * 512;
+            if (it < ZLOADS) {
+                const int pc = it % (ZQ / 2), px = it / (ZQ / 2), r = px / kTW, c = px - r * kTW;
+                zr[l] = *(const u32x4v *)(dZ + (ib + (long long)(y0 + r) * W + x0 + c) * COUT_P + 8 * pc);
             }
-            dbias += sb;
+        }
+    };
+    auto stash_raw = [&]() {
+#pragma unroll
+        for (int l = 0; l < XLS; ++l) {
+            const int it = tid + l * 512;
+            if (it < XLOADS) {
+                const int pc = it % (XQ / XLQ), pix = it / (XQ / XLQ);
+                u16 *dst = xraw + pix * XPS + 4 * XLQ * pc;
+                *(u32x2v *)dst = u32x2v{xr[l].x, xr[l].y};
+                if constexpr (XLQ == 2) *(u32x2v *)(dst + 4) = u32x2v{xr[l].z, xr[l].w};
+            }
         }
 #pragma unroll
-        for (int i = 0; i < PER_WAVE; ++i) {
-            const int blk = wave + NWAVE * i;
-            if (blk < NBLK) {
-                const int tap = blk / (MB * NB), mb = (blk / NB) % MB, nb = blk % NB;
-                const int dy = tap / 3, dx = tap % 3, ci = nb * 16 + i16;
+        for (int l = 0; l < ZLS; ++l) {
+            const int it = tid + l * 512;
+            if (it < ZLOADS) {
+                u16 *dst = zraw + (it / (ZQ / 2)) * ZPS + 8 * (it % (ZQ / 2));
+                *(u32x2v *)dst = u32x2v{zr[l].x, zr[l].y};
+                *(u32x2v *)(dst + 4) = u32x2v{zr[l].z, zr[l].w};
+            }
+        }
+    };
+    // 4 pixels x 4 channels (pixel-major, pixel stride ps) -> 4 channel rows
+    // of 4 pixels (8 bytes each, channel stride cs)
+    auto turn = [&](const u16 *src, int ps, u16 *dst, int cs) {
+        u32x2v v[4];
 #pragma unroll
-                for (int kc = 0; kc < TPX / 32; ++kc) {
-                    const int px0 = kc * 32 + 8 * q, r = px0 / kTW, c = px0 - r * kTW;
-                    const bf16x8 av = *(const bf16x8 *)&dzt[mb * 16 + i16][px0];
-                    bf16x8 bv = __builtin_bit_cast(bf16x8, u32x4v{0u, 0u, 0u, 0u});
-                    if (ci < CIN_P) bv = *(const bf16x8 *)&xt[dx][ci][r + dy][c];
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+        for (int e = 0; e < 4; ++e) v[e] = *(const u32x2v *)(src + e * ps);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int wd = k >> 1;
+            const unsigned a0 = wd ? v[0].y : v[0].x, a1 = wd ? v[1].y : v[1].x;
+            const unsigned a2 = wd ? v[2].y : v[2].x, a3 = wd ? v[3].y : v[3].x;
+            const unsigned lo = (k & 1) ? (a0 >> 16) | (a1 & 0xffff0000u) : (a0 & 0xffffu) | (a1 << 16);
+            const unsigned hi = (k & 1) ? (a2 >> 16) | (a3 & 0xffff0000u) : (a2 & 0xffffu) | (a3 << 16);
+            *(u32x2v *)(dst + k * cs) = u32x2v{lo, hi};
+        }
+    };
+    auto transpose = [&]() {
+#pragma unroll
+        for (int s = 0; s < XTS; ++s) {
+            const int it = tid + s * 512;
+            if (it < XT) {
+                const int pl = it % XPL, jl = (it / XPL) % XJL, jh = (it / 16) % XJH, rr = (it / (16 * XJH)) % kHP;
+                const int p = (it / (16 * XJH * kHP)) * XPL + pl, j = jh * XJL + jl;
+                if (j < XROW / 4) turn(xraw + (rr * XROW + 4 * j) * XPS + 4 * p, XPS, xt + 4 * p * XCH + rr * XROW + 4 * j, XCH);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < ZTS; ++s) {
+            const int it = tid + s * 512;
+            if (it < ZT) {
+                const int pl = it % 4, jl = (it / 4) % 4, jh = (it / 16) % ZJH;
+                const int p = (it / (16 * ZJH)) * 4 + pl, j = jh * 4 + jl;
+                turn(zraw + 4 * j * ZPS + 4 * p, ZPS, dzt + 4 * p * ZCH + 4 * j, ZCH);
+            }
+        }
+    };
+    // this wave's K slice: tile pixels 32 wave + 8q .. +7, row r, column c
+    const int px0 = 32 * wave + 8 * q, r = px0 / kTW, c = px0 - r * kTW;
+    if (blockIdx.x < ntiles) fetch(blockIdx.x);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        stash_raw();      // the previous tile's turn-around reads are done
+        lds_barrier();    // ... and so are its MFMA operand reads
+        transpose();
+        lds_barrier();
+        if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);   // lands while this tile computes
+        bf16x8 av[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            av[mb] = *(const bf16x8 *)(dzt + (mb * 16 + i16) * ZCH + px0);
+            accb[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mb], ones, accb[mb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int ci = nb * 16 + i16;
+                u32x4v w = {0u, 0u, 0u, 0u};
+                unsigned w4 = 0u;
+                if (ci < CIN_P) {
+                    const u16 *src = xt + ci * XCH + (r + dy) * XROW + c;
+                    w = *(const u32x4v *)src;
+                    w4 = *(const unsigned *)(src + 8);
                 }
+                // halo columns c + dx .. c + dx + 7 for tap columns dx = 0, 1, 2
+                const bf16x8 bv[3] = {
+                    __builtin_bit_cast(bf16x8, w),
+                    __builtin_bit_cast(bf16x8, u32x4v{__builtin_amdgcn_alignbit(w.y, w.x, 16),
+                                                      __builtin_amdgcn_alignbit(w.z, w.y, 16),
+                                                      __builtin_amdgcn_alignbit(w.w, w.z, 16),
+                                                      __builtin_amdgcn_alignbit(w4, w.w, 16)}),
+                    __builtin_bit_cast(bf16x8, u32x4v{w.y, w.z, w.w, w4})};
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+                        acc[dy * 3 + dx][mb][nb] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mb], bv[dx], acc[dy * 3 + dx][mb][nb], 0, 0, 0);
             }
-        }
     }
+    // the eight waves' sums, added in wave order, one (tap, mb) at a time
+    float *const red = (float *)sm;
     float *out = part + (long long)blockIdx.x * PSTRIDE;
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PER_WAVE; ++i) {
-        const int blk = wave + NWAVE * i;
-        if (blk < NBLK) {
-            const int tap = blk / (MB * NB), mb = (blk / NB) % MB, nb = blk % NB;
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int co = mb * 16 + 4 * q + r, ci = nb * 16 + i16;
-                out[(tap * COUT_P + co) * CINN + ci] = acc[i][r];
+        for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                *(f32x4 *)(red + ((wave * NB + nb) * 64 + lane) * 4) = acc[t][mb][nb];
+            __syncthreads();
+            if (tid < NB * 256) {
+                const int nb = tid >> 8, e = tid & 255, ln = e >> 2, rr = e & 3;
+                float s = 0.f;
+                for (int w8 = 0; w8 < 8; ++w8) s += red[((w8 * NB + nb) * 64) * 4 + e];
+                const int co = mb * 16 + 4 * (ln >> 4) + rr, ci = nb * 16 + (ln & 15);
+                out[(t * COUT_P + co) * CINN + ci] = s;
             }
+            __syncthreads();
         }
+    // bias: column 0 of D holds sum_k dZ[k][co] for co = mb*16 + 4q + r
+    if (i16 == 0) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) red[wave * COUT_P + mb * 16 + 4 * q + rr] = accb[mb][rr];
     }
-    if (tid < COUT_P) out[9 * COUT_P * CINN + tid] = dbias;
+    __syncthreads();
+    if (tid < COUT_P) {
+        float s = 0.f;
+        for (int w8 = 0; w8 < 8; ++w8) s += red[w8 * COUT_P + tid];
+        out[9 * COUT_P * CINN + tid] = s;
+    }
 }
 
 // Sum the per-block partials of one layer into the flat gradient (fixed order).
@@ -906,9 +1030,14 @@ __global__ void k_reduce_grad(const float *__restrict__ part, int nparts, int ps
     } else {
         src = 9 * coutp * cinn + (i - nw);
     }
-    float s = 0.f;
-    for (int b = 0; b < nparts; ++b) s += part[(long long)b * pstride + src];
-    gflat[i] = s;
+    // 8 independent chains keep 8 loads in flight; combined in a fixed order
+    float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int b = 0;
+    for (; b + 8 <= nparts; b += 8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s8[k] += part[(long long)(b + k) * pstride + src];
+    for (; b < nparts; ++b) s8[0] += part[(long long)b * pstride + src];
+    gflat[i] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
 }
 
 // ---------------------------------------------------------------- loss, Adam, packing
