@@ -90,6 +90,20 @@ template <> __device__ __forceinline__ double2 st_c<double2>(dc v) { return make
 // real values kept between stages of one pass (phi rows): float or double
 template <class ST> struct RealOf { using T = float; };
 template <> struct RealOf<double2> { using T = double; };
+// The E points q[(t + TPL e) es] of one line, every load issued before any
+// is used: a line past the grid's last (act false) reads the line at `safe`
+// instead of branching around its loads, and is zeroed.  A branch per load
+// would make the thread wait for each load in turn.
+template <int E, int TPL, class ST>
+__device__ __forceinline__ void load_line(const ST *q, const ST *safe, long long es, bool act, int t, dc (&v)[E])
+{
+    const ST *src = act ? q : safe;
+    ST raw[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) raw[e] = src[(long long)(t + TPL * e) * es];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = act ? ld_c(raw[e]) : mk(0.0, 0.0);
+}
 
 // Plain row FFT (entry/exit of a run of steps, energy evaluation).
 template <int N, int E, int LINES, int S, class ST>
@@ -102,8 +116,7 @@ __device__ __forceinline__ void em_fft_tile(const EmArgs &a, int tile, ST *lds)
     const EmLayout<N, E> lay{l * EmLayout<N, E>::PITCH};
     dc v[E];
     ST *p = (ST *)a.psi + (long long)row * N;
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = act ? ld_c(p[t + TPL * e]) : mk(0.0, 0.0);
+    load_line<E, TPL>(p, (const ST *)a.psi, 1, act, t, v);
     fft<N, E, S>(v, t, lay, lds, a.tw);
     if (act) {
 #pragma unroll
@@ -168,8 +181,7 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, ST *lds,
     dc v[E];
     double rho0[E];
     ST *p0 = (ST *)a.psi + r0 * N, *p1 = (ST *)a.psi + r1 * N;
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = act ? ld_c(p0[t + TPL * e]) : mk(0.0, 0.0);
+    load_line<E, TPL>(p0, (const ST *)a.psi, 1, act, t, v);
     if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) rho0[e] = norm2(v[e]) * rs;
@@ -179,8 +191,7 @@ __device__ __forceinline__ void density_tile(const EmArgs &a, int tile, ST *lds,
             for (int e = 0; e < E; ++e) p0[t + TPL * e] = st_c<ST>(scl(v[e], inv_n));
         }
     }
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = act ? ld_c(p1[t + TPL * e]) : mk(0.0, 0.0);
+    load_line<E, TPL>(p1, (const ST *)a.psi, 1, act, t, v);
     if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
     if constexpr (STORE_PSI) {
         if (act) {
@@ -215,25 +226,38 @@ __device__ __forceinline__ void load_real_pair(const ST *half, const ST *nyq, bo
                                                long long r1, dc (&z)[E])
 {
     constexpr int TPL = N / E;
+    // every load issued before any is used (rows past the grid's last read
+    // pair 0 and are zeroed; the lane that takes the Nyquist bin reads bin 0
+    // there); a branch per bin would make the thread wait for each in turn
+    if (!act) {
+        r0 = 0;
+        r1 = 1;
+    }
     const ST *h0 = half + r0 * (N / 2), *h1 = half + r1 * (N / 2);
+    ST a0[E], a1[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        dc x0 = mk(0.0, 0.0), x1 = mk(0.0, 0.0);
-        if (act) {
-            if (e < E / 2) {
-                const int k = t + TPL * e;
-                x0 = ld_c(h0[k]);
-                x1 = ld_c(h1[k]);
-                if (k == 0) { x0.y = 0.0; x1.y = 0.0; }
-            } else if (e == E / 2 && t == 0) {
-                x0 = mk((double)nyq[r0].x, 0.0);
-                x1 = mk((double)nyq[r1].x, 0.0);
-            } else {
-                const int kk = N - (t + TPL * e);
-                x0 = conj(ld_c(h0[kk]));
-                x1 = conj(ld_c(h1[kk]));
-            }
+        const int k = t + TPL * e;
+        const int idx = e < E / 2 ? k : (N - k) & (N / 2 - 1);
+        a0[e] = h0[idx];
+        a1[e] = h1[idx];
+    }
+    const ST n0 = nyq[r0], n1 = nyq[r1];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        dc x0, x1;
+        if (e < E / 2) {
+            x0 = ld_c(a0[e]);
+            x1 = ld_c(a1[e]);
+            if (t + TPL * e == 0) { x0.y = 0.0; x1.y = 0.0; }
+        } else if (e == E / 2 && t == 0) {
+            x0 = mk((double)n0.x, 0.0);
+            x1 = mk((double)n1.x, 0.0);
+        } else {
+            x0 = conj(ld_c(a0[e]));
+            x1 = conj(ld_c(a1[e]));
         }
+        if (!act) x0 = x1 = mk(0.0, 0.0);
         z[e] = mk(x0.x - x1.y, x0.y + x1.x);
     }
 }
@@ -459,8 +483,7 @@ __device__ __forceinline__ void phase_tile(const EmArgs &a, int tile, ST *lds, d
     for (int half = 0; half < 2; ++half) {
         ST *p = (ST *)a.psi + (half ? r1 : r0) * N;
         dc v[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = act ? ld_c(p[t + TPL * e]) : mk(0.0, 0.0);
+        load_line<E, TPL>(p, (const ST *)a.psi, 1, act, t, v);
         if constexpr (!REAL_IN) fft<N, E, 1>(v, t, lay, lds, a.tw);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -583,8 +606,7 @@ __device__ __forceinline__ void phase_local_tile(const EmArgs &a, int tile, floa
     for (int half = 0; half < 2; ++half) {
         float2 *p = a.psi + (half ? r1 : r0) * N;
         dc v[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+        load_line<E, TPL>(p, (const float2 *)a.psi, 1, act, t, v);
         // the static potential of the row, loaded before the transform
         float vx[E];
 #pragma unroll
@@ -686,8 +708,7 @@ __device__ __forceinline__ void source_tile(const EmArgs &a, int tile, float2 *l
         const long long r = h ? r1 : r0;
         const float2 *p = a.psi + r * N;
         dc v[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = act ? from_f2(p[t + TPL * e]) : mk(0.0, 0.0);
+        load_line<E, TPL>(p, (const float2 *)a.psi, 1, act, t, v);
         // the row's coefficients, loaded before the transform so the loads
         // overlap it (uniform branches on the field pointers)
         float gv[E], bv[E];
@@ -763,9 +784,7 @@ __device__ __forceinline__ void lm_tile(const LmArgs &a, int tile_in, ST *lds, d
     ST *base = (ST *)sg.ptr + (long long)o * sg.os + (long long)lg * sg.ls;
     const LmLayout<LINES> lay{l};
     dc v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e)
-        v[e] = act ? ld_c(base[(long long)(t + TPL * e) * sg.es]) : mk(0.0, 0.0);
+    load_line<E, TPL>(base, (const ST *)sg.ptr, sg.es, act, t, v);
 
     if constexpr (MODE == LM_FWD || MODE == LM_INV) {
         fft<N, E, MODE == LM_FWD ? -1 : 1>(v, t, lay, lds, a.tw);
