@@ -58,10 +58,11 @@ def csrc_hash(files=PASS_SOURCES):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_pass, variant, workload):
-    """HBM bytes per launch of a pass in a schedule variant on a workload, from
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (profiles/traffic.json),
-    only when they were taken on the current kernel sources; else None."""
+def measured_traffic(kernel_pass, variant, workload, mode=None):
+    """HBM bytes per launch of a pass in a schedule variant (and, for the
+    density and phase passes, nonlinear mode) on a workload, from committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (profiles/traffic.json), only when
+    they were taken on the current kernel sources; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -71,7 +72,8 @@ def measured_traffic(kernel_pass, variant, workload):
         return None
     if rec.get("csrc_hash") != csrc_hash():
         return None
-    b = rec.get("workloads", {}).get(workload, {}).get("passes", {}).get(kernel_pass, {}).get(variant)
+    by_variant = rec.get("workloads", {}).get(workload, {}).get("passes", {}).get(kernel_pass, {})
+    b = by_variant.get(f"{variant}:m{mode}", by_variant.get(variant))
     if b is None:
         return None
     return {"bytes": b, "source": "rocprofv3 FETCH_SIZE x %.3g + WRITE_SIZE x %.3g per launch, "
@@ -196,7 +198,7 @@ def single_grid_leg(name, psi0, steps, warmup, autotune_iters, profile_steps, tr
     scale = abs(e0["kinetic"]) + abs(e0["local"]) + abs(e0["nonlocal"])
     mode = grid.nonlinear_mode()
     grid.close()
-    tr = measured_traffic(dom, schedule.get(dom), name) if traffic else None
+    tr = measured_traffic(dom, schedule.get(dom), name, mode) if traffic else None
     return {
         "workload": name, "grid": list(n), "steps": steps, "warmup": warmup,
         "value": P * steps / elapsed, "unit": "grid-pt updates/s", "ms_per_step": ms_per_step,
