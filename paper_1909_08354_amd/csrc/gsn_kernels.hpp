@@ -979,6 +979,7 @@ template <class A> struct Src1 {
     A a;   // by value: the fields then stay scalar values after inlining
     int n;
     __device__ __forceinline__ int ntiles() const { return n; }
+    __device__ __forceinline__ int per_instance() const { return n; }
     __device__ __forceinline__ const A &args(int) const { return a; }
     __device__ __forceinline__ int local(int tile) const { return tile; }
 };
@@ -987,9 +988,35 @@ template <class A> struct SrcG {
     const A *__restrict__ arr;
     int tpi, count;
     __device__ __forceinline__ int ntiles() const { return tpi * count; }
+    __device__ __forceinline__ int per_instance() const { return tpi; }
     __device__ __forceinline__ const A &args(int tile) const { return arr[tile / tpi]; }
     __device__ __forceinline__ int local(int tile) const { return tile - (tile / tpi) * tpi; }
 };
+
+// Tile order for strided tiles narrower than a 128-byte line (LINES x 8 bytes
+// < 128): blocks are dispatched round-robin over the 8 XCDs and a persistent
+// grid is a multiple of 16, so tiles t and t + 8 run at the same time on two
+// blocks of one XCD.  Within each run of 16 tiles of an instance they get
+// adjacent line groups: the line the two tiles share is then fetched into
+// that XCD's L2 once, not into two L2s (every tile still runs once; the order
+// only pairs them up).
+template <class Src> struct SrcPaired {
+    static constexpr bool GROUPED = Src::GROUPED;
+    Src s;
+    __device__ __forceinline__ int ntiles() const { return s.ntiles(); }
+    __device__ __forceinline__ int per_instance() const { return s.per_instance(); }
+    __device__ __forceinline__ const auto &args(int t) const { return s.args(t); }
+    __device__ __forceinline__ int local(int t) const
+    {
+        const int l = s.local(t), base = l & ~15;
+        return base + 16 > s.per_instance() ? l : base + 2 * (l & 7) + ((l >> 3) & 1);
+    }
+};
+template <int LINES, class Src> __device__ __forceinline__ auto lm_order(const Src &s)
+{
+    if constexpr (LINES * 8 < 128) return SrcPaired<Src>{s};
+    else return s;
+}
 
 // FP64 sum of the density pass's mass partials, folded into the state
 // (global phase, step count, non-finite flag); every thread of the block calls it.
@@ -1766,9 +1793,9 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lmp(LmArgs a)
     __shared__ double2 kpl[MODE == LM_KIN && B::TB ? N : 1];
     __shared__ double k2l[MODE == LM_KERN && B::TB ? N : 1];
     __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
-    const Src1<LmArgs> src{a, a.s0.ntiles + a.s1.ntiles};
-    lmp_body<N, E, LINES, MODE, LT, Src1<LmArgs>, B::TW, B::TB>(src, lds, B::TW ? twl : a.tw,
-                                                                  B::TB ? kpl : a.kinp, B::TB ? k2l : a.k2_p, sh);
+    const auto src = lm_order<LINES>(Src1<LmArgs>{a, a.s0.ntiles + a.s1.ntiles});
+    lmp_body<N, E, LINES, MODE, LT, decltype(src), B::TW, B::TB>(src, lds, B::TW ? twl : a.tw,
+                                                                   B::TB ? kpl : a.kinp, B::TB ? k2l : a.k2_p, sh);
 }
 
 template <int N, int E, int LINES, int S>
@@ -1814,10 +1841,10 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lmp_g(const LmArgs *__restri
     __shared__ double2 kpl[MODE == LM_KIN && B::TB ? N : 1];
     __shared__ double k2l[MODE == LM_KERN && B::TB ? N : 1];
     __shared__ double sh[LmTile<N, E, LINES>::NT / 64 + 1];
-    const SrcG<LmArgs> src{args, tpi, count};
+    const auto src = lm_order<LINES>(SrcG<LmArgs>{args, tpi, count});
     const LmArgs &a0 = src.args(0);
-    lmp_body<N, E, LINES, MODE, float2, SrcG<LmArgs>, B::TW, B::TB>(src, lds, B::TW ? twl : a0.tw,
-                                                                     B::TB ? kpl : a0.kinp, B::TB ? k2l : a0.k2_p, sh);
+    lmp_body<N, E, LINES, MODE, float2, decltype(src), B::TW, B::TB>(src, lds, B::TW ? twl : a0.tw,
+                                                                      B::TB ? kpl : a0.kinp, B::TB ? k2l : a0.k2_p, sh);
 }
 template <int N, int E, int LINES, bool STORE_PSI>
 __global__ __launch_bounds__(LINES *(N / E)) void k_densityp_g(const EmArgs *__restrict__ args, int tpi, int count)
