@@ -281,10 +281,12 @@ gsn_status gsn_batch_mass(gsn_batch batch, double *masses);
 gsn_status gsn_batch_phase(gsn_batch batch, int i, double *theta, int64_t *steps);
 /* Execution mode: 0 = one captured hipGraph per step count (default);
    1 = one persistent kernel: 512-thread blocks pull (phase, instance, tile)
-   work items from a device queue in order and wait (bounded) on per-instance
-   completion counters, so instances overlap across passes; extents 128..1024
-   only (GSN_EUNSUPPORTED otherwise), and a wait that exceeds its spin limit is
-   reported as GSN_EHIP by the next synchronising call;
+   work items in order from the queue of the XCD they run on (each instance
+   belongs to one XCD's queue, the instances spread by size) and wait
+   (bounded) on per-instance completion counters, so instances overlap across
+   passes; extents 128..1024 only (GSN_EUNSUPPORTED otherwise); a wait that
+   exceeds its spin limit, or a queue left undrained because no block ran on
+   its XCD, is reported as GSN_EHIP by the next synchronising call;
    2 = the grouped launches of mode 0 issued directly. */
 gsn_status gsn_batch_set_mode(gsn_batch batch, int mode);
 /* Persistent-mode wait bound (iterations of ~50 ns, default 2^22) and a test

@@ -42,11 +42,18 @@ struct PInst {
     int nx, ny;
 };
 
+// One queue per XCD: an instance's items all run on one XCD, whose L2 every
+// CU of the XCD shares, so a tile hand-off needs only the producer's stores
+// acknowledged (vmcnt 0) and the consumer's L1 invalidated - not an L2
+// write-back and invalidate across XCDs, which made every hand-off cost more
+// than the tile.
+constexpr int kNQ = 8;
 struct PArgs {
     const PInst *inst;
-    QTables T;
-    unsigned long long total;
-    unsigned long long *head;
+    QTables T[kNQ];                 // queue x: its instances' tile prefixes
+    const int *list[kNQ];           // queue x: local instance -> instance
+    unsigned long long total[kNQ];  // queue x: items
+    unsigned long long *head;       // kNQ counters
     unsigned long long *done;
     unsigned *err;
     unsigned spin_limit;
@@ -79,39 +86,44 @@ template <int N> __device__ __noinline__ void p_lm(int kind, const LmArgs &a, in
 __global__ void k_queue_reset(unsigned long long *head, unsigned long long *done, unsigned *err, int count)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        *head = 0;
-        *err = 0;
-    }
+    if (i < kNQ) head[i] = 0;
+    if (i == 0) *err = 0;
     if (i < count) done[i] = 0;
 }
 
-// Blocks pull items in increasing order; an item waits (bounded) until its
-// instance has completed every tile of the earlier phases.  Exit: the queue is
-// exhausted, or a wait exceeded spin_limit (then err is set and every block
-// leaves at its next wait).
+// Blocks pull items of their XCD's queue in increasing order; an item waits
+// (bounded) until its instance has completed every tile of the earlier phases.
+// Exit: the queue is exhausted, or a wait exceeded spin_limit (then err is set
+// and every block leaves at its next wait).  The host checks after the run
+// that every non-empty queue was drained (a queue whose XCD ran no block).
 __global__ __launch_bounds__(kPThreads) void k_batch_persistent(PArgs a)
 {
     __shared__ float2 lds[kPLds];
     __shared__ double sh[kPThreads / 64 + 1];
     __shared__ unsigned long long s_item;
-    __shared__ int s_stop;
+    __shared__ int s_stop, s_q;
+    if (threadIdx.x == 0) s_q = (int)(__builtin_amdgcn_s_getreg(6164) & (kNQ - 1));   // HW_REG_XCC_ID
+    __syncthreads();
+    const int q = s_q;
+    if (a.T[q].count == 0) return;
+    const QTables &T = a.T[q];
     for (;;) {
         if (threadIdx.x == 0) {
             int stop = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             unsigned long long x = 0;
             if (!stop) {
-                x = atomicAdd(a.head, 1ull);
-                stop = x >= a.total;
+                x = atomicAdd(&a.head[q], 1ull);
+                stop = x >= a.total[q];
                 if (x == a.fail_item) {
                     atomicOr(a.err, 1u);
                     stop = 1;
                 }
             }
             if (!stop) {
-                const QItem it = qdecode(a.T, x);
+                const QItem it = qdecode(T, x);
+                const int inst = a.list[q][it.inst];
                 unsigned n = 0;
-                while (__hip_atomic_load(&a.done[it.inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it.need) {
+                while (__hip_atomic_load(&a.done[inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it.need) {
                     if (++n > a.spin_limit || __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                         atomicOr(a.err, 1u);
                         stop = 1;
@@ -119,15 +131,18 @@ __global__ __launch_bounds__(kPThreads) void k_batch_persistent(PArgs a)
                     }
                     __builtin_amdgcn_s_sleep(2);
                 }
+                // acquire within the XCD: drop this CU's L1 copies, so the
+                // tiles the counter covers are read from the shared L2
+                asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
             }
             s_item = x;
             s_stop = stop;
         }
         __syncthreads();
         if (s_stop) break;
-        __threadfence();   // acquire: see the tiles the counter covers
-        const QItem it = qdecode(a.T, s_item);
-        const PInst &I = a.inst[it.inst];
+        const QItem it = qdecode(T, s_item);
+        const int inst = a.list[q][it.inst];
+        const PInst &I = a.inst[inst];
         const bool lm = it.kind == Q_KIN_HALF || it.kind == Q_KIN_FULL || it.kind == Q_KERNEL;
         if (lm) {
             switch (I.ny) {
@@ -144,9 +159,11 @@ __global__ __launch_bounds__(kPThreads) void k_batch_persistent(PArgs a)
             default: p_em<1024>(it.kind, I.em[it.kind], it.tile, lds, sh, a.store_psi); break;
             }
         }
-        __threadfence();   // release: this tile's stores before the count
+        // release within the XCD: this thread's stores acknowledged by the L2
+        // before the block's count goes up
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (threadIdx.x == 0) atomicAdd(&a.done[it.inst], 1ull);
+        if (threadIdx.x == 0) atomicAdd(&a.done[inst], 1ull);
         __syncthreads();   // s_item / s_stop are rewritten next iteration
     }
 }
@@ -291,7 +308,9 @@ struct gsn_batch_ {
     unsigned long long *q_head, *q_done;
     unsigned *q_err, *q_prefix;
     PInst *q_inst;
-    std::vector<unsigned> h_prefix;
+    std::vector<unsigned> h_prefix;   // per queue: tile prefixes, then (at list_off) its instances
+    int q_count[kNQ], q_pre_off[kNQ], q_list_off[kNQ];
+    unsigned long long q_total[kNQ];   // items of the last run, per queue
     bool q_built;
     unsigned spin_limit;
     long long fail_item;
@@ -343,7 +362,7 @@ gsn_status compute_blayout(int count, const int32_t *n, BLayout *L)
     L->unit_off = off;
     off += 512 + 16 * kSinCosTable;
     L->queue_off = off;
-    off += align256(256) + align256(8ull * count) + align256(4ull * Q_NKIND * (count + 1)) +
+    off += align256(256) + align256(8ull * count) + align256(4ull * (Q_NKIND * (count + kNQ) + count)) +
            align256(sizeof(PInst) * (size_t)count);
     L->total = off;
     return GSN_OK;
@@ -661,10 +680,37 @@ gsn_status build_persistent(gsn_batch b)
             }
         }
     }
-    b->h_prefix.assign(Q_NKIND * (count + 1), 0);
-    for (int q = 0; q < Q_NKIND; ++q)
-        for (int i = 0; i < count; ++i)
-            b->h_prefix[q * (count + 1) + i + 1] = b->h_prefix[q * (count + 1) + i] + tiles[q][i];
+    // instances to the XCD queues, largest first onto the least loaded queue
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (long long)b->inst[x].nx * b->inst[x].ny > (long long)b->inst[y].nx * b->inst[y].ny;
+    });
+    std::vector<std::vector<int>> ql(kNQ);
+    long long load[kNQ] = {0};
+    for (int i : order) {
+        int best = 0;
+        for (int x = 1; x < kNQ; ++x)
+            if (load[x] < load[best]) best = x;
+        ql[best].push_back(i);
+        load[best] += (long long)b->inst[i].nx * b->inst[i].ny;
+    }
+    b->h_prefix.assign(Q_NKIND * (count + kNQ) + count, 0);
+    int off = 0;
+    for (int x = 0; x < kNQ; ++x) {
+        std::sort(ql[x].begin(), ql[x].end());
+        const int cx = (int)ql[x].size();
+        b->q_count[x] = cx;
+        b->q_pre_off[x] = off;
+        for (int q = 0; q < Q_NKIND; ++q)
+            for (int j = 0; j < cx; ++j)
+                b->h_prefix[off + q * (cx + 1) + j + 1] = b->h_prefix[off + q * (cx + 1) + j] + tiles[q][ql[x][j]];
+        off += Q_NKIND * (cx + 1);
+    }
+    for (int x = 0; x < kNQ; ++x) {
+        b->q_list_off[x] = off;
+        for (int i : ql[x]) b->h_prefix[off++] = (unsigned)i;
+    }
     gsn_status s = upload_sync(b->stream, b->q_inst, pin.data(), sizeof(PInst) * count);
     if (s) return s;
     s = upload_sync(b->stream, b->q_prefix, b->h_prefix.data(), 4ull * b->h_prefix.size());
@@ -675,12 +721,15 @@ gsn_status build_persistent(gsn_batch b)
 
 gsn_status enqueue_persistent(gsn_batch b, int64_t nsteps, hipStream_t st)
 {
-    QTables T{b->count, (long long)nsteps, b->q_prefix};
-    QTables Th{b->count, (long long)nsteps, b->h_prefix.data()};
     PArgs a;
     a.inst = b->q_inst;
-    a.T = T;
-    a.total = qtotal_items(Th);
+    for (int x = 0; x < kNQ; ++x) {
+        a.T[x] = QTables{b->q_count[x], (long long)nsteps, b->q_prefix + b->q_pre_off[x]};
+        const QTables Th{b->q_count[x], (long long)nsteps, b->h_prefix.data() + b->q_pre_off[x]};
+        a.total[x] = b->q_count[x] ? qtotal_items(Th) : 0;
+        a.list[x] = (const int *)(b->q_prefix + b->q_list_off[x]);
+        b->q_total[x] = a.total[x];
+    }
     a.head = b->q_head;
     a.done = b->q_done;
     a.err = b->q_err;
@@ -689,8 +738,8 @@ gsn_status enqueue_persistent(gsn_batch b, int64_t nsteps, hipStream_t st)
     a.fail_item = b->fail_item < 0 ? ~0ull : (unsigned long long)b->fail_item;
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
-    hipLaunchKernelGGL(k_queue_reset, dim3((b->count + 255) / 256), dim3(256), 0, st, b->q_head, b->q_done,
-                       b->q_err, b->count);
+    hipLaunchKernelGGL(k_queue_reset, dim3((std::max(b->count, kNQ) + 255) / 256), dim3(256), 0, st, b->q_head,
+                       b->q_done, b->q_err, b->count);
     hipLaunchKernelGGL(k_batch_persistent, dim3(2 * cus), dim3(kPThreads), 0, st, a);
     HIP_TRY(hipGetLastError());
     return GSN_OK;
@@ -752,9 +801,13 @@ extern "C" gsn_status gsn_batch_create(gsn_batch *out, int count, int ndim, cons
         b->q_done = (unsigned long long *)q;
         q += align256(8ull * count);
         b->q_prefix = (unsigned *)q;
-        q += align256(4ull * Q_NKIND * (count + 1));
+        q += align256(4ull * (Q_NKIND * (count + kNQ) + count));
         b->q_inst = (PInst *)q;
         b->q_built = false;
+        for (int x = 0; x < kNQ; ++x) {
+            b->q_count[x] = b->q_pre_off[x] = b->q_list_off[x] = 0;
+            b->q_total[x] = 0;
+        }
         b->spin_limit = 1u << 22;
         b->fail_item = -1;
     }
@@ -962,6 +1015,11 @@ extern "C" gsn_status gsn_batch_sync(gsn_batch b)
         unsigned err = 0;
         HIP_TRY(hipMemcpy(&err, b->q_err, 4, hipMemcpyDeviceToHost));
         if (err) return fail(GSN_EHIP, "persistent batch queue: a wait exceeded its spin limit");
+        unsigned long long head[kNQ];
+        HIP_TRY(hipMemcpy(head, b->q_head, sizeof(head), hipMemcpyDeviceToHost));
+        for (int x = 0; x < kNQ; ++x)
+            if (b->q_count[x] && head[x] < b->q_total[x])
+                return fail(GSN_EHIP, "persistent batch queue: an XCD's queue was not drained (no block ran there)");
     }
     for (const Instance &I : b->inst) {
         DevState st;
