@@ -48,6 +48,7 @@ struct PInst {
 // write-back and invalidate across XCDs, which made every hand-off cost more
 // than the tile.
 constexpr int kNQ = 8;
+constexpr unsigned kQRun = 4;
 struct PArgs {
     const PInst *inst;
     QTables T[kNQ];                 // queue x: its instances' tile prefixes
@@ -107,12 +108,20 @@ __global__ __launch_bounds__(kPThreads) void k_batch_persistent(PArgs a)
     const int q = s_q;
     if (a.T[q].count == 0) return;
     const QTables &T = a.T[q];
+    unsigned long long next = 0, end = 0;   // thread 0: this block's current run of items
     for (;;) {
         if (threadIdx.x == 0) {
             int stop = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             unsigned long long x = 0;
             if (!stop) {
-                x = atomicAdd(&a.head[q], 1ull);
+                // kQRun consecutive items per atomic on the queue head; a run
+                // keeps the order (its items depend only on smaller numbers,
+                // all handed out before it)
+                if (next == end) {
+                    next = atomicAdd(&a.head[q], (unsigned long long)kQRun);
+                    end = next + kQRun;
+                }
+                x = next++;
                 stop = x >= a.total[q];
                 if (x == a.fail_item) {
                     atomicOr(a.err, 1u);
