@@ -153,6 +153,7 @@ struct gsn_grid_ {
     // launch schedules
     std::vector<Launch> entry, kin_half, kin_full, nonlin, exit_, energy_rho, energy_kin;
     std::vector<Launch> pot;      // potential readout (phi pointer set per call)
+    std::vector<Launch> pot_spec; // the same from x-spectral psi, ending a coarse step (see gsn_step_corrected)
     StepLists coarse;             // one coarse step of coarse_ratio * dz
     int coarse_ratio;             // 0 = no coarse schedule
     double2 *kinFc[3], *kinHc[3]; // kinetic tables of the coarse step
@@ -719,6 +720,19 @@ static void build_schedule(gsn_grid g)
         EmArgs a = em_base(g, g->scratch);
         a.nlines = (int)(g->P / g->Nx / 2);
         g->pot.push_back(em_launch(kx->potential, kx, a, P_PHASE));
+    }
+    // the same readout taking x-spectral psi at the end of a coarse step: the
+    // density pass that stores real-space psi back does the run's closing
+    // inverse x transform and the density in one pass (not with the Bohm
+    // term, whose density pass also transforms sqrt(rho))
+    g->pot_spec.clear();
+    if (!g->bohm_on && !g->pot.empty()) {
+        const NKernels *kx = kernels_for(g->Nx, g->var[P_DENSITY]);
+        EmArgs d = em_base(g, g->psi);
+        d.nlines = (int)(g->P / g->Nx / 2);
+        d.partials = g->mass_parts;
+        g->pot_spec.push_back(em_launch(kx->density_store, kx, d, P_DENSITY));
+        for (size_t i = 1; i < g->pot.size(); ++i) g->pot_spec.push_back(g->pot[i]);
     }
 }
 
@@ -1750,8 +1764,21 @@ extern "C" gsn_status gsn_step_corrected(gsn_grid g, gsn_corrector c, int64_t nc
             HIP_TRY(hipMemcpyAsync(saved, g->psi, bytes, hipMemcpyDeviceToDevice, g->stream));
             HIP_TRY(hipMemcpyAsync(g->st_save[0], g->st, sizeof(DevState), hipMemcpyDeviceToDevice, g->stream));
         }
-        if ((s = run_lists(g, g->coarse, 1))) return s;
-        if ((s = run_potential(g, phi))) return s;
+        if (!g->pot_spec.empty()) {
+            // one coarse step without its closing inverse x transform, which
+            // the readout's first pass performs while it forms the density
+            const StepLists &C = g->coarse;
+            if ((s = run_list(g, C.entry)) || (s = run_list(g, C.kin_half)) || (s = run_list(g, C.nonlin)) ||
+                (s = run_list(g, C.kin_half)))
+                return s;
+            for (Launch L : g->pot_spec) {
+                if (L.em) L.ea.phi = phi;
+                HIP_TRY(launch(L, g->stream));
+            }
+        } else {
+            if ((s = run_lists(g, g->coarse, 1))) return s;
+            if ((s = run_potential(g, phi))) return s;
+        }
         if ((s = corrector_correct_inplace(c, g->psi, phi, &g->st->theta, g->stream))) return s;
         if (audit) {
             // the fine solver from the same state is the reference for the corrected step
