@@ -59,6 +59,15 @@ template <int N, int V> static NKernels make_kernels()
         k.lmp[LM_INV] = k_lmp<N, E, LL, LM_INV, float2>;
         k.lmp[LM_KIN] = k_lmp<N, E, LL, LM_KIN, float2>;
         k.lmp[LM_KERN] = k_lmp<N, E, LL, LM_KERN, float2>;
+        // 512-point lines: the two-butterfly form of the same plan (two
+        // blocks per CU instead of one)
+        if constexpr (V == 3 && N == 512) {
+            k.lmp[LM_FWD] = k_lmp2<N, LL, LM_FWD>;
+            k.lmp[LM_INV] = k_lmp2<N, LL, LM_INV>;
+            k.lmp[LM_KIN] = k_lmp2<N, LL, LM_KIN>;
+            k.lmp[LM_KERN] = k_lmp2<N, LL, LM_KERN>;
+            k.lmp_threads = LL * (N / 16);
+        }
     }
     return k;
 }
@@ -320,15 +329,16 @@ static Launch lm_launch(void (*fn)(LmArgs), const NKernels *k, const LmArgs &a, 
     else if (fn == k->lm_kin) mode = LM_KIN;
     else if (fn == k->lm_kern) mode = LM_KERN;
     const int N = k->E * k->TPL;
-    int grid = ntiles;
+    int grid = ntiles, threads = k->lm_threads();
     if (mode >= 0 && k->lmp[mode] && lm_fits(a.s0, N, k->lm_lines) && lm_fits(a.s1, N, k->lm_lines)) {
         fn = k->lmp[mode];
-        const int pb = persistent_blocks((const void *)fn, k->lm_threads());
+        if (k->lmp_threads > 0) threads = k->lmp_threads;
+        const int pb = persistent_blocks((const void *)fn, threads);
         if (pb > 0 && pb < grid) grid = pb;
     }
     L.fn = (const void *)fn;
     L.grid = dim3(grid);
-    L.block = dim3(k->lm_threads());
+    L.block = dim3(threads);
     L.em = false;
     L.la = a;
     L.pass = pass;

@@ -49,6 +49,7 @@ struct NKernels {
     void (*lm_kin_energy)(LmArgs);
     // pipelined persistent forms of LM_FWD .. LM_KERN (null: not in this variant)
     void (*lmp[4])(LmArgs);
+    int lmp_threads = 0;   // their block size when it is not lm_threads()
     // density / phase entries are the pipelined persistent kernels
     bool em_pipe;
     int lm_threads() const { return lm_lines * TPL; }
@@ -61,8 +62,11 @@ struct NKernels {
 // "s8" is the small-tile form for small grids.  The EM tile holds
 // 256/TPL rows (at most 64); the LM tile holds LINES columns chosen so that a
 // tile moves 128-byte contiguous segments per row where the block's thread
-// budget allows (long lines get 64- or 32-byte segments).  The batched solver
-// offers the first kNumBatchVariants.
+// budget allows (long lines get 64- or 32-byte segments).  On 512-point lines
+// the strided passes of "p8" run in the two-butterfly form (16 points per
+// thread of the same 8-point plan, two 512-thread blocks per CU, the next tile
+// loaded after the stores), bitwise equal to the one-butterfly form.  The
+// batched solver offers the first kNumBatchVariants.
 constexpr int kNumVariants = 5;
 constexpr int kNumBatchVariants = 4;
 static const char *kVariantNames[kNumVariants] = {"e16", "e8", "p16", "p8", "s8"};

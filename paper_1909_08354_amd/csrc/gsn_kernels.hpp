@@ -1143,6 +1143,213 @@ __device__ __forceinline__ void lmp_body(const Src &src, LT *lds, const double2 
     }
 }
 
+// ---------------------------------------------------------------- two-butterfly LM pass
+// The persistent strided pass for lines of N = 8^S points with 16 points per
+// thread: each thread runs two radix-8 butterflies per stage, so a 16-line
+// tile of 512-point lines takes 512 threads.  Between stages the values stay
+// in registers as the complex64 numbers the LDS exchange holds (widened to
+// FP64 one butterfly at a time); the forward transform's last stage, the
+// pointwise multiplier and the inverse transform's first stage run back to
+// back per butterfly in FP64, and the last stage stores its outputs directly.
+// At N = 512 a thread then fits 128 VGPRs and a block's LDS (tile, twiddles,
+// per-axis table) 80 KiB, so two blocks share a CU and one block's barriers
+// and memory waits are covered by the other's work; the next tile is loaded
+// after the stores, not prefetched.  Every butterfly, twiddle and rounding
+// point is that of the 8-point plan (Plan<N, 8>), so the results are bitwise
+// those of the one-butterfly passes k_lm / k_lmp with E = 8.
+template <int N> struct R8 {
+    static constexpr int E = 16, TPL = N / E;
+    static constexpr int stages()
+    {
+        int s = 0;
+        long p = 1;
+        while (p < N) { p *= 8; ++s; }
+        return s;
+    }
+    static constexpr bool POW8 = [] { long p = 1; while (p < N) p *= 8; return p == N; }();
+    static constexpr int ns(int st)
+    {
+        int p = 1;
+        for (int i = 0; i < st; ++i) p *= 8;
+        return p;
+    }
+    // twiddle indices (j mod Ns) r N / (8 Ns) stay below this
+    static constexpr int TWN = (N / 8 - 1) * 7 + 1;
+};
+
+// Butterfly m (0 or 1) of stage ST: j = t + TPL m takes positions j + r N / 8,
+// held in u[m + 2 r]; twiddled and transformed in FP64 into a.
+template <int N, int S, int ST>
+__device__ __forceinline__ void r8_in(const float2 (&u)[16], int m, int t, const double2 *__restrict__ tw, dc (&a)[8])
+{
+    constexpr int NS = R8<N>::ns(ST), STEP = N / (NS * 8);
+    const int j = t + R8<N>::TPL * m;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) a[r] = from_f2(u[m + 2 * r]);
+    if constexpr (NS > 1) {
+        const int jm = j & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < 8; ++r) {
+            dc w = from_d2(tw[jm * r * STEP]);
+            if constexpr (S > 0) w.y = -w.y;
+            a[r] = cmul(a[r], w);
+        }
+    }
+    dft<8, S>(a);
+}
+
+// Outputs of butterfly m of a stage that is not the last: LDS positions
+// expand(j) + r Ns.
+template <int N, int ST, class Lay>
+__device__ __forceinline__ void r8_out(const dc (&a)[8], int m, int t, const Lay &lay, float2 *lds)
+{
+    constexpr int NS = R8<N>::ns(ST);
+    const int j = t + R8<N>::TPL * m;
+    const int base = (j / NS) * NS * 8 + (j & (NS - 1));
+#pragma unroll
+    for (int r = 0; r < 8; ++r) lds_put(lds, lay(base + r * NS), a[r]);
+}
+
+// The exchange after a stage: u[e] takes position t + TPL e.
+template <int N, class Lay>
+__device__ __forceinline__ void r8_exchange(float2 (&u)[16], int t, const Lay &lay, const float2 *lds)
+{
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u[e] = lds[lay(t + R8<N>::TPL * e)];
+    __syncthreads();
+}
+
+// Stages ST .. STOP - 1 of a transform, each ending in an exchange.
+template <int N, int S, int ST, int STOP, class Lay>
+__device__ __forceinline__ void r8_stages(float2 (&u)[16], int t, const Lay &lay, float2 *lds,
+                                          const double2 *__restrict__ tw)
+{
+    if constexpr (ST < STOP) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            dc a[8];
+            r8_in<N, S, ST>(u, m, t, tw, a);
+            r8_out<N, ST>(a, m, t, lay, lds);
+        }
+        r8_exchange<N>(u, t, lay, lds);
+        r8_stages<N, S, ST + 1, STOP>(u, t, lay, lds, tw);
+    }
+}
+
+__device__ __forceinline__ void pin_f2(float2 &x) { asm volatile("" : "+v"(x.x), "+v"(x.y)); }
+
+template <int N, int LINES, int MODE, class Src>
+__device__ __forceinline__ void lmp2_body(const Src &src, float2 *lds, double2 *twl, double2 *kpl, double *k2l,
+                                          double *sh)
+{
+    using P = R8<N>;
+    constexpr int E = P::E, TPL = P::TPL, NT = LINES * TPL, LAST = P::stages() - 1;
+    static_assert(P::POW8 && LAST >= 1, "two-butterfly pass: N = 8^S, S >= 2");
+    static_assert(MODE == LM_FWD || MODE == LM_INV || MODE == LM_KIN || MODE == LM_KERN, "mode");
+    const int tid = threadIdx.x, l = tid % LINES, t = tid / LINES;
+    {
+        const LmArgs &a0 = src.args(0);
+        for (int i = tid; i < N; i += NT) {
+            if (i < P::TWN) twl[i] = gld(a0.tw, i);
+            if constexpr (MODE == LM_KIN) kpl[i] = gld(a0.kinp, i);
+            if constexpr (MODE == LM_KERN) k2l[i] = gmem(a0.k2_p)[i];
+        }
+        if constexpr (!Src::GROUPED) {
+            if (a0.reduce && blockIdx.x == 0) reduce_mass<NT>(a0, sh);
+        }
+    }
+    __syncthreads();
+    const int ntiles = src.ntiles();
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const LmLayout<LINES> lay{l};
+    LmPrefetch<E> f;
+    lm_fetch<N, E, LINES, MODE>(src.args(tile), lm_where<N, E, LINES>(src.args(tile), src.local(tile), l, t), true, f);
+    float2 u[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = f.p[e];
+    dc m12 = mk(0.0, 0.0);
+    double q12 = 0.0;
+    if constexpr (MODE == LM_KIN) m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), src.args(tile).scale);
+    if constexpr (MODE == LM_KERN) q12 = f.q1 + f.q2;
+    for (;;) {
+        const LmArgs &a = src.args(tile);
+        const int nxt = tile + gridDim.x;
+        const bool more = nxt < ntiles;
+        if constexpr (Src::GROUPED) {
+            if (a.reduce && src.local(tile) == 0) reduce_mass<NT>(a, sh);
+        }
+        constexpr int SF = MODE == LM_INV ? 1 : -1;   // sign of the (first) transform
+        r8_stages<N, SF, 0, LAST>(u, t, lay, lds, twl);
+        if constexpr (MODE == LM_KIN || MODE == LM_KERN) {
+            // forward last stage, multiplier, inverse first stage (no twiddles)
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                dc z[8];
+                r8_in<N, -1, LAST>(u, m, t, twl, z);
+                const int j = t + TPL * m;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int pos = j + (N / 8) * r;
+                    if constexpr (MODE == LM_KIN) {
+                        z[r] = cmul(z[r], cmul(m12, from_d2(kpl[pos])));
+                    } else {
+                        // branch-free: k = 0 divides by 1 and is then zeroed
+                        const double k2 = q12 + k2l[pos];
+                        const bool pos_k = k2 > 0.0;
+                        const double km = k2 + a.mY2;
+                        const double num = fma(a.cN, km, a.cY * k2);
+                        const double den = pos_k ? k2 * km : 1.0;
+                        double rc = __builtin_amdgcn_rcp(den);
+                        rc = fma(rc, fma(-den, rc, 1.0), rc);
+                        rc = fma(rc, fma(-den, rc, 1.0), rc);
+                        const double K = pos_k ? fma(num, rc, a.c0) : 0.0;
+                        z[r] = scl(z[r], K * a.scale);
+                    }
+                }
+                dft<8, 1>(z);
+                r8_out<N, 0>(z, m, t, lay, lds);
+            }
+            r8_exchange<N>(u, t, lay, lds);
+            r8_stages<N, 1, 1, LAST>(u, t, lay, lds, twl);
+        }
+        constexpr int SL = MODE == LM_FWD ? -1 : 1;   // sign of the last stage
+        const LmWhere w = lm_where<N, E, LINES>(a, src.local(tile), l, t);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            dc z[8];
+            r8_in<N, SL, LAST>(u, m, t, twl, z);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                if constexpr (MODE == LM_FWD || MODE == LM_INV) z[r] = scl(z[r], a.scale);
+                buf_st2(to_f2(z[r]), w.r, w.voff, (m + 2 * r) * w.step);
+            }
+        }
+        if (!more) break;
+        // the next tile: no register prefetch (it would not fit 128 VGPRs);
+        // the other block on the CU works while this one waits
+        {
+            const LmArgs &an = src.args(nxt);
+            lm_fetch<N, E, LINES, MODE>(an, lm_where<N, E, LINES>(an, src.local(nxt), l, t), true, f);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            u[e] = f.p[e];
+            pin_f2(u[e]);
+        }
+        if constexpr (MODE == LM_KIN) {
+            m12 = scl(cmul(from_d2(f.f1), from_d2(f.f2)), src.args(nxt).scale);
+            pin(m12);
+        }
+        if constexpr (MODE == LM_KERN) {
+            q12 = f.q1 + f.q2;
+            asm volatile("" : "+v"(q12));
+        }
+        tile = nxt;
+    }
+}
+
 // ---------------------------------------------------------------- pipelined EM passes
 // The density and phase passes in the same persistent, prefetching form: a
 // block walks tiles of LINES row pairs; each row's loads for the next tile are
@@ -1796,6 +2003,20 @@ __global__ __launch_bounds__(LINES *(N / E)) void k_lmp(LmArgs a)
     const auto src = lm_order<LINES>(Src1<LmArgs>{a, a.s0.ntiles + a.s1.ntiles});
     lmp_body<N, E, LINES, MODE, LT, decltype(src), B::TW, B::TB>(src, lds, B::TW ? twl : a.tw,
                                                                    B::TB ? kpl : a.kinp, B::TB ? k2l : a.k2_p, sh);
+}
+
+// Two-butterfly persistent LM pass (16 points per thread, 8-point plan): up
+// to four waves per SIMD, so two 512-thread blocks share a CU.
+template <int N, int LINES, int MODE>
+__global__ __launch_bounds__(LINES *(N / 16), 4) void k_lmp2(LmArgs a)
+{
+    __shared__ float2 lds[LmTile<N, 16, LINES>::LDS];
+    __shared__ double2 twl[R8<N>::TWN];
+    __shared__ double2 kpl[MODE == LM_KIN ? N : 1];
+    __shared__ double k2l[MODE == LM_KERN ? N : 1];
+    __shared__ double sh[LmTile<N, 16, LINES>::NT / 64 + 1];
+    const auto src = lm_order<LINES>(Src1<LmArgs>{a, a.s0.ntiles + a.s1.ntiles});
+    lmp2_body<N, LINES, MODE>(src, lds, twl, kpl, k2l, sh);
 }
 
 template <int N, int E, int LINES, int S>

@@ -114,6 +114,10 @@ def load(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch ships its own HIP runtime; loading it first makes the library
+    # resolve libamdhip64 to that same copy (two runtimes in one process do
+    # not share the device: the second one's calls fail)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, args in _SIGNATURES.items():
         f = getattr(lib, name)

@@ -171,6 +171,40 @@ def test_chunked_steps_match_single_run():
     assert orc.rel_l2(a, b) < 1e-6
 
 
+LM_PASSES = ("kinetic_y", "kinetic", "y_fwd_rho", "kernel", "y_inv_phi")
+
+
+@pytest.mark.parametrize("n,mode", [((512, 8), 0), ((512, 32), 1), ((16, 512, 8), 0), ((512, 8, 8), 1),
+                                    ((64, 512, 512), 0)])
+def test_two_butterfly_pass_bitwise(n, mode):
+    """On 512-point strided lines schedule p8 runs the two-butterfly LM pass
+    (16 points per thread, two blocks per CU); it must equal, bit for bit, the
+    one-tile pass of the same 8-point plan (e8) on every strided pass, with
+    ragged tiles (8 lines of a 16-line tile; half spectra of 4 lines plus the
+    Nyquist segment), both nonlinear modes, and match the oracle."""
+    say("two-butterfly", n, "mode", mode)
+    psi0, L = lump_state(n, 23 + len(n))
+    kern, a, g, dz, steps = (1.0, 0.3, 0.4, 0.05), 0.5, -0.5, 2e-3, 6
+    names = gsn.variant_names()
+    outs = []
+    for lm_variant in ("p8", "e8"):
+        grid = gsn.Grid(n, L)
+        grid.set_kernel(*kern)
+        grid.set_coefficients(a, g, dz)
+        passes = grid.pass_names()
+        grid.set_schedule([names.index(lm_variant if p in LM_PASSES else "p8") for p in passes])
+        grid.set_nonlinear_mode(mode)
+        grid.set_psi(inputs.to_c64(psi0))
+        grid.step(steps)
+        outs.append((grid.get_psi(np.complex64), grid.mass(), grid.energy()))
+        del grid
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1] and outs[0][2] == outs[1][2]
+    if np.prod(n) <= 1 << 18:
+        ref = orc.evolve(inputs.as_oracle_input(psi0), L, kern, a, g, dz, steps)
+        assert orc.rel_l2(outs[0][0].astype(np.complex128), ref) < REL_L2
+
+
 def test_bitwise_determinism():
     n = (32, 64, 16)
     psi0, L = lump_state(n, 41)
