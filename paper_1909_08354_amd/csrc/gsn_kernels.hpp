@@ -1288,6 +1288,11 @@ __device__ __forceinline__ void lmp2_body(const Src &src, float2 *lds, double2 *
             for (int m = 0; m < 2; ++m) {
                 dc z[8];
                 r8_in<N, -1, LAST>(u, m, t, twl, z);
+                // kinetic factors: no LDS read moves above this point (hoisted
+                // next to the twiddles they need 3 VGPRs more than the 128 of
+                // two blocks per CU, and the spill reaches HBM); 0x27F lets
+                // every other kind of instruction cross
+                if constexpr (MODE == LM_KIN) __builtin_amdgcn_sched_barrier(0x27F);
                 const int j = t + TPL * m;
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
