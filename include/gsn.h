@@ -245,7 +245,7 @@ gsn_status gsn_autotune(gsn_grid grid, int iters);
    the density pass also writes real-space psi in place, and the phase pass
    reads it instead of transforming again (+8 bytes per point, two fewer FFTs
    per pair of rows).  Both give the same result up to rounding; gsn_autotune
-   picks one by timing whole sub-steps. */
+   picks one by timing whole steps (kinetic passes and nonlinear sub-step). */
 gsn_status gsn_set_nonlinear_mode(gsn_grid grid, int mode);
 gsn_status gsn_get_nonlinear_mode(gsn_grid grid, int *mode);
 /* Current variant of every pass (npass >= gsn_pass_count entries). */

@@ -1529,11 +1529,17 @@ static gsn_status time_launch(gsn_grid g, const Launch &L, int iters, double *ms
     return GSN_OK;
 }
 
-// Time the nonlinear sub-step (density .. phase) on the scratch buffer.
+// Time a whole merged step (the kinetic passes, then the nonlinear sub-step
+// density .. phase) on the scratch buffer.  The nonlinear mode changes what
+// the x passes leave in the caches for the strided passes around them, so the
+// sub-step timed alone can rank the modes the wrong way round (at 512^3 it
+// preferred mode 0, whose whole steps were 1.6% slower).
 static gsn_status time_nonlinear(gsn_grid g, int iters, double *ms)
 {
     std::vector<Launch> seq;
-    for (const Launch &L0 : g->nonlin) {
+    std::vector<Launch> step(g->kin_full);
+    step.insert(step.end(), g->nonlin.begin(), g->nonlin.end());
+    for (const Launch &L0 : step) {
         Launch L = L0;
         if (L.em) {
             if (L.ea.psi == g->psi) L.ea.psi = g->scratch;
@@ -1635,8 +1641,8 @@ extern "C" gsn_status gsn_autotune(gsn_grid g, int iters)
     }
     // nonlinear sub-step: recompute psi in the phase pass (mode 0), or store
     // real-space psi in the density pass (mode 1, with its own variants of the
-    // two x passes); whole sub-steps are timed because the two passes change
-    // together
+    // two x passes); whole steps are timed because the two passes change
+    // together and change the strided passes' cache state
     const std::string mkey = cache_key(g, P_COUNT);
     auto mit = cache.find(mkey);
     if (mit != cache.end()) {
