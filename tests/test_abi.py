@@ -72,3 +72,26 @@ def test_null_handles_are_rejected():
     m = ctypes.c_double()
     assert lib.gsn_mass(None, ctypes.byref(m)) == gsn.GSN_EINVAL
     assert lib.gsn_get_psi(None, None, 0, 0) == gsn.GSN_EINVAL
+
+
+def test_library_shares_torch_hip_runtime():
+    """The binding loads libgsn after torch, whose wheel carries its own HIP
+    runtime: the library then resolves libamdhip64 to that copy.  Loaded
+    first, it mapped the system runtime and torch, imported afterwards, a
+    second one, and the library's own HIP calls failed on the GPU.  Checked
+    in a fresh process: one libamdhip64 and one libhsa-runtime64 mapped after
+    load() and a later import of torch."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1909_08354_amd import gsn\n"
+            "gsn.load()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l or 'libhsa-runtime64' in l}\n"
+            "print(sorted(libs))\n"
+            "assert len([p for p in libs if 'libamdhip64' in p]) == 1, libs\n"
+            "assert len([p for p in libs if 'libhsa-runtime64' in p]) == 1, libs\n"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
