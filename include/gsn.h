@@ -228,7 +228,10 @@ double gsn_pass_bytes_per_point(gsn_grid grid, int i);
    (variant 0 "e16", variant 1 "e8"); variants 2 "p16" and 3 "p8" run the
    strided-axis, density and phase passes with persistent blocks that
    prefetch their next tile while transforming the current one (the
-   operations of e16 / e8); variant 4 "s8" uses 8 points per thread with the
+   operations of e16 / e8; on 512-point strided lines p8 runs the same
+   8-point plan with 16 points per thread in two blocks per compute unit,
+   loading its next tile after the stores, bitwise equal to e8); variant 4
+   "s8" uses 8 points per thread with the
    smallest tiles that fill a wavefront, for grids too small to give every
    compute unit a tile.  A variant changes the Stockham radix plan, the
    tile shape and the LDS footprint, never the result beyond rounding.
