@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "gsn_host.hpp"
@@ -627,41 +628,50 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const u16 *__restrict__ d
     }
 }
 
-// Data gradients of a 32 -> 32 layer on tiled shapes, in the forward
-// kernel's tiling: dX[p][ci] = sum_tap sum_co dZ[p - off(tap)][co]
+// Data gradients of a layer with 32 input channels on tiled shapes, in the
+// forward kernel's tiling: dX[p][ci] = sum_tap sum_co dZ[p - off(tap)][co]
 // W[tap][co][ci] is a forward convolution of dZ with the taps mirrored and
 // the weights transposed.  D^T = W^T dZ^T: lane (i16, q) ends with pixel i16
 // of an M-tile and the channels nb*16 + 4q .. +3, staged as 8 bytes in LDS;
 // each wave then writes its row of 64 pixels as 16-byte pieces, zeroed where
 // the layer below's ReLU was inactive (Aprev <= 0).  Taps accumulate in the
-// order 0 .. 8, each one K chunk of the 32 output channels.
+// order 0 .. 8, each one K chunk of the COUT output channels: 32 on
+// v_mfma_f32_16x16x32_bf16 (8 channels per lane), 16 (the last layer's 2,
+// padded) on v_mfma_f32_16x16x16_bf16 (4 per lane; same A, B and D lane
+// layout with half the K).
+template <int COUT>
 __global__ __launch_bounds__(256) void k_conv_bwd_data_t(const u16 *__restrict__ dZ, const u16 *__restrict__ Wb,
                                                          const u16 *__restrict__ Aprev, u16 *__restrict__ dX,
                                                          int H, int W, int ntiles)
 {
-    __shared__ u32x4v xin[kHP * kWP * 4];        // dZ halo, 16-byte quarters of 64-byte pixels
+    static_assert(COUT == 32 || COUT == 16, "32 or 16 output channels");
+    // one lane's K chunk of a pixel: 8 channels (16 bytes) or 4 (8 bytes)
+    using Q = std::conditional_t<COUT == 32, u32x4v, uint2>;
+    using KV = std::conditional_t<COUT == 32, bf16x8, bf16x4>;
+    constexpr int KL = COUT / 4;   // channels per lane and K chunk
+    __shared__ Q xin[kHP * kWP * 4];             // dZ halo, quarters of each pixel's channels
     __shared__ u32x4v yst[4][kTW * 64 / 16];     // per-wave output staging, 64 bytes per pixel
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i16 = lane & 15, q = lane >> 4;
-    // A fragments: rows ci = nb*16 + i16 of W[tap]^T, K = co 8q .. 8q + 7
-    bf16x8 wa[9][2];
+    // A fragments: rows ci = nb*16 + i16 of W[tap]^T, K = co KL q .. KL q + KL - 1
+    KV wa[9][2];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb)
-            wa[t][nb] = *(const bf16x8 *)(Wb + ((long long)(t * 32 + nb * 16 + i16)) * 32 + 8 * q);
+            wa[t][nb] = *(const KV *)(Wb + ((long long)(t * 32 + nb * 16 + i16)) * COUT + KL * q);
     const int tx = W / kTW, ty = H / kTH;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int img = tile / (tx * ty), r0 = tile - img * tx * ty;
         const int y0 = (r0 / tx) * kTH, x0 = (r0 % tx) * kTW;
-        const u16 *Zi = dZ + (long long)img * H * W * 32;
+        const u16 *Zi = dZ + (long long)img * H * W * COUT;
         __syncthreads();   // the previous tile's readers are done with xin
         for (int c = tid; c < kHP * kWP * 4; c += 256) {
             const int pq = c & 3, pix = c >> 2, rr = pix / kWP, cc = pix - rr * kWP;
             int ys = y0 + rr - 1, xs = x0 + cc - 1;
             ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
             xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
-            xin[c] = *(const u32x4v *)(Zi + ((long long)ys * W + xs) * 32 + pq * 8);
+            xin[c] = *(const Q *)(Zi + ((long long)ys * W + xs) * COUT + pq * KL);
         }
         __syncthreads();
         f32x4 acc[4][2];
@@ -675,10 +685,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_t(const u16 *__restrict__
             const int dy = 2 - t / 3, dx = 2 - t % 3;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const bf16x8 av = __builtin_bit_cast(bf16x8, xin[((wave + dy) * kWP + m * 16 + i16 + dx) * 4 + q]);
+                const KV av = __builtin_bit_cast(KV, xin[((wave + dy) * kWP + m * 16 + i16 + dx) * 4 + q]);
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb)
-                    acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nb], av, acc[m][nb], 0, 0, 0);
+                for (int nb = 0; nb < 2; ++nb) {
+                    if constexpr (COUT == 32)
+                        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nb], av, acc[m][nb], 0, 0, 0);
+                    else
+                        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t][nb], av, acc[m][nb], 0, 0, 0);
+                }
             }
         }
         uint2 *ys = (uint2 *)yst[wave];
@@ -1436,7 +1450,12 @@ static gsn_status gradients(gsn_corrector c, int B, float *loss)
                            np);
     hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 2 + 2 + 255) / 256), dim3(256), 0, c->stream, c->part,
                        kBwBlocks, 9 * 16 * 32 + 16, 32, 2, 32, 16, c->grad + offs[3]);
-    hipLaunchKernelGGL((k_conv_bwd_data<32, 16>), grid, block, 0, c->stream, c->dz4, c->wb[3], c->a[2], c->dza, H, W, np);
+    if (tl)
+        hipLaunchKernelGGL(k_conv_bwd_data_t<16>, tiled_grid(c, ntl), block, 0, c->stream, c->dz4, c->wb[3], c->a[2],
+                           c->dza, H, W, ntl);
+    else
+        hipLaunchKernelGGL((k_conv_bwd_data<32, 16>), grid, block, 0, c->stream, c->dz4, c->wb[3], c->a[2], c->dza, H,
+                           W, np);
     // layer 3
     if (tl)
         hipLaunchKernelGGL((k_conv_bwd_w_t<32, 32>), dim3(kBwBlocks), dim3(512), 0, c->stream, c->a[1], c->dza, c->part,
@@ -1447,7 +1466,7 @@ static gsn_status gradients(gsn_corrector c, int B, float *loss)
     hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
                        kBwBlocks, pstride_h, 32, 32, 32, 32, c->grad + offs[2]);
     if (tl)
-        hipLaunchKernelGGL(k_conv_bwd_data_t, tiled_grid(c, ntl), block, 0, c->stream, c->dza, c->wb[2], c->a[1], c->dzb,
+        hipLaunchKernelGGL(k_conv_bwd_data_t<32>, tiled_grid(c, ntl), block, 0, c->stream, c->dza, c->wb[2], c->a[1], c->dzb,
                            H, W, ntl);
     else
         hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dza, c->wb[2], c->a[1], c->dzb, H, W,
@@ -1462,7 +1481,7 @@ static gsn_status gradients(gsn_corrector c, int B, float *loss)
     hipLaunchKernelGGL(k_reduce_grad, dim3((9 * 32 * 32 + 32 + 255) / 256), dim3(256), 0, c->stream, c->part,
                        kBwBlocks, pstride_h, 32, 32, 32, 32, c->grad + offs[1]);
     if (tl)
-        hipLaunchKernelGGL(k_conv_bwd_data_t, tiled_grid(c, ntl), block, 0, c->stream, c->dzb, c->wb[1], c->a[0], c->dza,
+        hipLaunchKernelGGL(k_conv_bwd_data_t<32>, tiled_grid(c, ntl), block, 0, c->stream, c->dzb, c->wb[1], c->a[0], c->dza,
                            H, W, ntl);
     else
         hipLaunchKernelGGL((k_conv_bwd_data<32, 32>), grid, block, 0, c->stream, c->dzb, c->wb[1], c->a[0], c->dza, H, W,
